@@ -1,0 +1,108 @@
+"""The sampled latent J_t[R] by its definition (no cache).
+
+TEST INFRASTRUCTURE (oracle).
+
+* J_T(p, c) = sigma_0 G(seed, x, y, c, step=0) (seeds paragraph of the formal
+  appendix; G in oracle.noise).
+* For t < T, J_t on a region R is the InfiniteDiffusion update (Eq. 2): the
+  windows kappa(R) are run through Phi on J_{t+1}[R_i], each output is
+  weighted by W_i and placed at R_i (U_i), the placed sums are divided
+  pixel by pixel by the placed weights, with 0/0 := 0 (formal appendix).
+  Phi is one Euler step of the window (oracle.schedule).
+* The recursion is unrolled into the query's dependency cone (Alg. 1 is a
+  memoised evaluation of the same definition; the Parallelization theorem
+  gives one batched round per level): R_t = query, I_t = kappa(R_t),
+  R_{t+1} = bounding region of the windows of I_t; then levels are evaluated
+  on finite canvases from t = T-1 down to the query level.
+* Summation over the windows covering a pixel runs in canonical order
+  (iy ascending, then ix ascending).
+
+Outputs are float64 arrays [h, w, C] (row y, column x, channel).
+
+Pins (tests/test_oracle_sampler.py): closed form of the whole sampler under
+the linear-Gaussian denoiser; equality with brute-force bounded
+MultiDiffusion (Eq. 1) over a canvas holding the whole cone; crop and
+query-order independence.
+"""
+import numpy as np
+
+from .noise import noise_region
+from .schedule import euler_factor, sigma_pair, sigmas
+from .tdw import read_tdw
+from .unet import make_denoiser
+from .windows import cone, kappa_list, weight_map
+
+
+class Model:
+    """A weight file opened by the oracle: header, float64 tensors, denoiser."""
+
+    def __init__(self, path_or_header, tensors=None):
+        if isinstance(path_or_header, str):
+            self.header, self.tensors = read_tdw(path_or_header)
+        else:
+            self.header, self.tensors = path_or_header, (tensors or {})
+        h = self.header
+        self.C = h["denoiser"]["in_channels"]
+        self.K = h["sampler"]["steps"]
+        win = h["window"]
+        self.H, self.s, self.o, self.eps = win["size"], win["stride"], win["offset"], win["eps"]
+        sp = h["sampler"]
+        self.sched = sigmas(self.K, sp["sigma_max"], sp["sigma_min"], sp["rho"])
+        self.W = weight_map(self.H, self.eps)
+        self.denoiser = make_denoiser(h, self.tensors)
+        self.phi_calls = 0
+
+
+def _crop(canvas, canvas_region, sub):
+    cx, cy = canvas_region[0], canvas_region[1]
+    x0, y0, w, h = sub
+    return canvas[y0 - cy:y0 - cy + h, x0 - cx:x0 - cx + w]
+
+
+def level_step(model, j_next, region_next, region, windows, t):
+    """J_t on `region` from J_{t+1} on `region_next` using the given windows."""
+    H = model.H
+    sig, sig_next = sigma_pair(model.sched, model.K, t)
+    x0, y0, w, h = region
+    A = np.zeros((h, w, model.C))
+    B = np.zeros((h, w, 1))
+    if windows:
+        xs = np.stack([_crop(j_next, region_next, (ix * model.s + model.o, iy * model.s + model.o, H, H))
+                       for ix, iy in windows])
+        D = model.denoiser(xs, sig, windows)
+        model.phi_calls += len(windows)
+        phi = xs + euler_factor(sig, sig_next) * (xs - D)
+        for n, (ix, iy) in enumerate(windows):
+            ox, oy = ix * model.s + model.o, iy * model.s + model.o
+            ax0, ax1 = max(ox, x0), min(ox + H, x0 + w)
+            ay0, ay1 = max(oy, y0), min(oy + H, y0 + h)
+            if ax0 >= ax1 or ay0 >= ay1:
+                continue
+            wv = model.W[ay0 - oy:ay1 - oy, ax0 - ox:ax1 - ox, None]
+            A[ay0 - y0:ay1 - y0, ax0 - x0:ax1 - x0] += wv * phi[n, ay0 - oy:ay1 - oy, ax0 - ox:ax1 - ox]
+            B[ay0 - y0:ay1 - y0, ax0 - x0:ax1 - x0] += wv
+    out = np.zeros_like(A)
+    np.divide(A, B, out=out, where=B > 0)
+    return out
+
+
+def sample(model, seed, x0, y0, w, h, level):
+    """J_level on [x0, x0+w) x [y0, y0+h): float64 [h, w, C]."""
+    K = model.K
+    if not 0 <= level <= K:
+        raise ValueError("level out of range")
+    region = (x0, y0, w, h)
+    if level == K:
+        return model.sched[0] * noise_region(seed, x0, y0, w, h, model.C).astype(np.float64)
+    regions, kappas = cone(region, level, K, model.H, model.s, model.o)
+    top = level
+    while top < K and kappas[top] is not None:
+        top += 1
+    if top == K:
+        rK = regions[K]
+        j = model.sched[0] * noise_region(seed, rK[0], rK[1], rK[2], rK[3], model.C).astype(np.float64)
+    else:
+        j = np.zeros((regions[top][3], regions[top][2], model.C))
+    for t in range(top - 1, level - 1, -1):
+        j = level_step(model, j, regions[t + 1], regions[t], kappa_list(regions[t], model.H, model.s, model.o), t)
+    return j

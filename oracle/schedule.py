@@ -1,0 +1,48 @@
+"""EDM noise schedule, preconditioning and the per-level Euler step.
+
+TEST INFRASTRUCTURE (oracle).  The paper leaves Phi abstract ("a pretrained
+diffusion model", Sec. 3.1; "an arbitrary denoising function", Sec. 3.4).
+The reading used here is the EDM sampler of Karras et al. (2022):
+
+* sigma_k = (smax^(1/rho) + k/(K-1) (smin^(1/rho) - smax^(1/rho)))^rho for
+  k = 0..K-1 and sigma_K = 0; level t holds the state at sigma_{K-t}.
+* D(x; sigma) = c_skip x + c_out F(c_in x; c_noise) with
+  c_skip = sd^2/(sigma^2+sd^2), c_out = sigma sd / sqrt(sigma^2+sd^2),
+  c_in = 1/sqrt(sigma^2+sd^2), c_noise = ln(sigma)/4.
+* Phi for the step t+1 -> t is one deterministic Euler step of the window:
+  Phi(x) = x + (sigma' - sigma)/sigma (x - D(x; sigma)), sigma = sigma_{K-t-1},
+  sigma' = sigma_{K-t}.  At the last step sigma' = 0 and Phi(x) = D(x).
+
+Pins: the schedule's end points and monotonicity; the linear-Gaussian
+closed form of the whole sampler (tests/test_oracle_sampler.py) fixes the
+level indexing, the Euler factor and the preconditioning-free path.
+"""
+import math
+
+
+def sigmas(steps, sigma_max, sigma_min, rho):
+    """[sigma_0, ..., sigma_{K-1}, 0] in float64."""
+    if steps == 1:
+        return [float(sigma_max), 0.0]
+    a = sigma_max ** (1.0 / rho)
+    b = sigma_min ** (1.0 / rho)
+    s = [(a + k / (steps - 1) * (b - a)) ** rho for k in range(steps)]
+    return s + [0.0]
+
+
+def sigma_pair(sched, steps, t):
+    """(sigma, sigma') used by the step that produces level t from level t+1."""
+    return sched[steps - t - 1], sched[steps - t]
+
+
+def precond(sigma, sigma_data):
+    s2 = sigma * sigma + sigma_data * sigma_data
+    c_skip = sigma_data * sigma_data / s2
+    c_out = sigma * sigma_data / math.sqrt(s2)
+    c_in = 1.0 / math.sqrt(s2)
+    c_noise = 0.25 * math.log(sigma)
+    return c_skip, c_out, c_in, c_noise
+
+
+def euler_factor(sigma, sigma_next):
+    return (sigma_next - sigma) / sigma

@@ -1,0 +1,94 @@
+"""Pins of the oracle's noise hash G (no GPU)."""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from oracle import noise
+
+
+@pytest.mark.parametrize("key,ctr", [((1, 2), (5, 0, 0, 0)), ((0, 0), (0, 0, 0, 0)),
+                                     ((2 ** 64 - 1, 12345), (2 ** 64 - 1, 7, 2 ** 63, 99))])
+def test_generic_philox_matches_numpy_philox4x64(key, ctr):
+    # numpy's Philox4x64-10 emits block(counter + 1) first.
+    bg = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=np.array(ctr, dtype=np.uint64))
+    got = [int(v) for v in bg.random_raw(8)]
+    c = sum(int(v) << (64 * i) for i, v in enumerate(ctr))
+    for blk in range(2):
+        cc = (c + 1 + blk) % (1 << 256)
+        words = [(cc >> (64 * i)) & (2 ** 64 - 1) for i in range(4)]
+        assert noise.philox_generic(words, key, **noise.PHILOX4x64) == got[4 * blk:4 * blk + 4]
+
+
+def test_vectorised_philox4x32_matches_generic():
+    rng = np.random.default_rng(3)
+    c = rng.integers(0, 2 ** 32, size=(4, 300), dtype=np.uint64)
+    k = rng.integers(0, 2 ** 32, size=(2, 300), dtype=np.uint64)
+    v = noise.philox4x32(c[0], c[1], c[2], c[3], k[0], k[1])
+    for i in range(300):
+        ref = noise.philox4x32_scalar([int(c[j, i]) for j in range(4)], [int(k[0, i]), int(k[1, i])])
+        assert [int(v[j][i]) for j in range(4)] == ref
+
+
+def test_uniforms_exact_and_open_interval():
+    r = np.array([0, 1, 511, 512, 2 ** 32 - 1, 2 ** 31], dtype=np.uint64)
+    u = noise.uniform_from_word(r)
+    assert u.dtype == np.float32
+    k = (r >> np.uint64(9)) * 2 + 1
+    assert np.all(u.astype(np.float64) == k.astype(np.float64) * 2.0 ** -24)
+    assert u.min() == np.float32(2.0 ** -24) and u.max() == np.float32(1 - 2.0 ** -24)
+
+
+def _ulp(x):
+    return np.spacing(np.abs(x).astype(np.float32)).astype(np.float64)
+
+
+def test_ln_series_against_float64_log():
+    rng = np.random.default_rng(0)
+    r = np.concatenate([rng.integers(0, 2 ** 32, 200000, dtype=np.uint64),
+                        np.array([0, 1, 2 ** 32 - 1, 2 ** 31, 0x6A09E667 << 1], dtype=np.uint64)])
+    u = noise.uniform_from_word(r)
+    got = noise.ln_series(u).astype(np.float64)
+    ref = np.log(u.astype(np.float64))
+    err = np.abs(got - ref)
+    assert np.all(err <= 4 * _ulp(ref) + 2e-8)
+
+
+def test_sincos_against_float64():
+    rng = np.random.default_rng(1)
+    ub = noise.uniform_from_word(rng.integers(0, 2 ** 32, 200000, dtype=np.uint64))
+    s, c = noise.sincos_2pi(ub)
+    phi = 2 * np.pi * ub.astype(np.float64)
+    assert np.max(np.abs(s - np.sin(phi))) < 5e-7
+    assert np.max(np.abs(c - np.cos(phi))) < 5e-7
+
+
+def test_gaussian_is_standard_normal():
+    z = noise.noise_region(12345, -300, 77, 400, 300, 4).astype(np.float64).ravel()
+    n = z.size
+    assert abs(z.mean()) < 5 / math.sqrt(n)
+    assert abs(z.var() - 1) < 5 * math.sqrt(2 / n)
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    assert np.max(np.abs(z)) <= math.sqrt(48 * math.log(2)) + 1e-6
+    # channel pairs are independent coordinates of one Box-Muller draw
+    zz = z.reshape(-1, 4)
+    assert abs(np.corrcoef(zz[:, 0], zz[:, 1])[0, 1]) < 5 / math.sqrt(zz.shape[0])
+
+
+def test_counter_layout_and_channel_pairs():
+    seed = 0x00DEADBEEF123457
+    for (x, y, c, step) in [(0, 0, 0, 0), (-1, 5, 1, 0), (7, -2 ** 31, 2, 3), (2 ** 31 - 1, 3, 5, 0)]:
+        r = noise.philox4x32_scalar([x & 0xFFFFFFFF, y & 0xFFFFFFFF, step, c // 4],
+                                    [seed & 0xFFFFFFFF, seed >> 32])
+        pair = (r[2], r[3]) if (c % 4) // 2 else (r[0], r[1])
+        e, o = noise.box_muller(np.array([pair[0]], dtype=np.uint64), np.array([pair[1]], dtype=np.uint64))
+        want = o[0] if c % 2 else e[0]
+        assert noise.gaussian(seed, x, y, c, step) == want
+
+
+def test_negative_coordinates_wrap_to_u32():
+    a = noise.gaussian(9, -1, -2, 3, 0)
+    b = noise.gaussian(9, 2 ** 32 - 1, 2 ** 32 - 2, 3, 0)
+    assert a == b
+    assert noise.gaussian(9, 1, 2, 3, 0) != noise.gaussian(9, 2, 1, 3, 0)
