@@ -1,0 +1,167 @@
+/*
+ * td.h - lazy, seed-consistent windowed diffusion sampling of an unbounded
+ * latent plane (InfiniteDiffusion) on one AMD Instinct MI355X (gfx950).
+ *
+ * The library answers queries J_t[R] of the infinite image produced by the
+ * InfiniteDiffusion update (Sec. 3.2, Eq. 2; formal restatement in the
+ * appendix "Formal Properties") with the lazy, memoising query algorithm of
+ * Sec. 3.3 (Alg. 1), the window-range function kappa of the appendix's
+ * window-range algorithm, and the Laplacian decode of Sec. 5.2.
+ *
+ * Conventions for every call:
+ *  - Coordinates are int64 pixel indices; x is the column, y the row.  A
+ *    region [x0, x0+w) x [y0, y0+h) needs 1 <= w, h <= 2^20, w*h <= 2^26
+ *    and |x0|, |y0| < 2^31 - 2^22 (so every window index of its dependency
+ *    cone fits in int32 window units).
+ *  - Latent outputs are float32, planar [C][h][w] (C = latent channels);
+ *    height outputs are float32 [h][w] in metres.
+ *  - Every call returns td_status; nothing throws across the ABI.  On error,
+ *    td_last_error(ctx) describes the failure.
+ *  - A context is not thread-safe: one caller at a time.
+ *  - Buffers are owned by the caller; the context owns its weights, its
+ *    device cache and its workspaces, all freed by td_destroy.
+ *  - Device pointers are HIP device addresses on the context's device;
+ *    streams are hipStream_t passed as void* (NULL = the context's own
+ *    stream).
+ */
+#ifndef TD_H
+#define TD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct td_ctx td_ctx;
+
+typedef enum {
+  TD_OK = 0,
+  TD_E_INVAL = -1,   /* bad argument: size, level, buffer length, option   */
+  TD_E_NOMEM = -2,   /* device or host allocation failed                   */
+  TD_E_DEVICE = -3,  /* HIP runtime error                                  */
+  TD_E_IO = -4,      /* weight file missing or unreadable                  */
+  TD_E_FORMAT = -5,  /* weight file malformed or describes an unknown model */
+  TD_E_STATE = -6    /* call not valid now (e.g. query before weights)     */
+} td_status;
+
+/* Per-context counters.  windows_evaluated[t] counts denoiser (Phi)
+ * evaluations at level t since the last td_cache_clear / td_load_weights. */
+typedef struct {
+  uint64_t hits;          /* windows of a query's cone found in the cache  */
+  uint64_t misses;        /* windows that had to be evaluated              */
+  uint64_t evictions;     /* cache entries dropped by the LRU              */
+  uint64_t bytes_used;    /* device bytes held by cached contributions     */
+  uint64_t bytes_budget;  /* current budget                                */
+  uint64_t batches;       /* batched denoiser rounds launched              */
+  uint64_t queries;       /* td_sample_region* calls served                */
+  uint64_t windows_evaluated[64];
+} td_cache_stats_t;
+
+/* Elevation query level: decoded height in metres on full-resolution pixels
+ * (factor 8 finer than the latent), Sec. 5.2. */
+#define TD_LEVEL_HEIGHT (-1)
+
+/* Create a context on HIP device `hip_device`. */
+td_status td_create(int hip_device, td_ctx **out);
+
+/* Free every device and host resource of the context (NULL is a no-op). */
+void td_destroy(td_ctx *ctx);
+
+/* Load a .tdw weight file: 4-byte magic "TDW1", uint32 header length, JSON
+ * header (denoiser architecture or analytic kind, EDM sampler constants,
+ * window size/stride/offset/epsilon, decode constants, tensor table), zero
+ * padding to 64 bytes, then little-endian float32 tensors.  Replaces any
+ * previous model and clears the cache (cached contributions are
+ * model-specific).  TD_E_IO if unreadable, TD_E_FORMAT if malformed. */
+td_status td_load_weights(td_ctx *ctx, const char *path);
+
+/* J_level[R] for seed `seed` (Alg. 1 applied recursively from J_T = sigma_0 G).
+ * level in [0, K] (K = sampler steps; 0 = final latent, K = scaled noise),
+ * or TD_LEVEL_HEIGHT for decoded elevation on the full-resolution region.
+ * `out` is a host buffer of out_len floats, at least C*w*h (latent) or w*h
+ * (height); the call blocks until the result is in `out`.  Values depend
+ * only on (weights, seed, level, region), never on the cache or on earlier
+ * queries (seed consistency, Sec. 3.5). */
+td_status td_sample_region(td_ctx *ctx, uint64_t seed, int64_t x0, int64_t y0,
+                           int32_t w, int32_t h, int32_t level, float *out,
+                           size_t out_len);
+
+/* As td_sample_region, but `dev_out` is device memory and the work is
+ * enqueued on `hip_stream` (NULL: the context's stream).  Host-side planning
+ * runs synchronously; the result is ready when the stream reaches the end
+ * of the enqueued work. */
+td_status td_sample_region_async(td_ctx *ctx, uint64_t seed, int64_t x0,
+                                 int64_t y0, int32_t w, int32_t h,
+                                 int32_t level, float *dev_out, size_t out_len,
+                                 void *hip_stream);
+
+/* Byte budget of the device cache of window contributions (Sec. 3.3, the
+ * per-window contribution store with LRU eviction).  Entries beyond the
+ * budget are evicted least-recently-used first at the end of each query
+ * level; a query may exceed it transiently by its own working set.  Any
+ * budget, including 0, gives identical results. */
+td_status td_cache_set_budget(td_ctx *ctx, size_t bytes);
+
+/* Drop every cached contribution and reset the counters. */
+td_status td_cache_clear(td_ctx *ctx);
+
+/* Copy the counters into *out. */
+td_status td_cache_stats(td_ctx *ctx, td_cache_stats_t *out);
+
+/* Copy the cached contribution W_i (x) Phi(J_{t+1}[R_i]) of window
+ * (ix, iy) at level t for `seed` into the host buffer `out` ([H][H][C]
+ * float32, row-major, out_len >= H*H*C).  TD_E_INVAL if not cached. */
+td_status td_cache_peek(td_ctx *ctx, uint64_t seed, int32_t level, int64_t ix,
+                        int64_t iy, float *out, size_t out_len);
+
+/* Options: "batch" = max windows per batched denoiser round (>= 1);
+ * "cache_budget" = as td_cache_set_budget.  TD_E_INVAL for unknown keys. */
+td_status td_set_option(td_ctx *ctx, const char *key, int64_t value);
+
+/* Model facts: "channels", "steps", "window", "stride", "offset",
+ * "factor" (decode), "params".  TD_E_INVAL for unknown keys. */
+td_status td_get_info(td_ctx *ctx, const char *key, int64_t *value);
+
+/* Denoiser D(x; sigma_k) of the loaded model on `n` windows (EDM
+ * preconditioning, the definition of Phi's network call): x_dev and
+ * out_dev are device arrays [n][H][H][C] float32 (H = window size), k in
+ * [0, K-1] selects sigma_k of the schedule.  Synchronous.  For checking
+ * the network apart from the sampler. */
+td_status td_denoise_windows(td_ctx *ctx, const float *x_dev, int32_t n,
+                             int32_t k, float *out_dev);
+
+/* Laplacian decode (Sec. 5.2, with the signed-sqrt inverse of the
+ * signed-sqrt appendix) of a latent held in device memory, [lh][lw][C]
+ * float32 with latent origin (lx0, ly0), onto the full-resolution region
+ * [X0, X0+W) x [Y0, Y0+H): out_dev is [H][W] float32.  The latent must
+ * cover the 17-pixel apron; TD_E_INVAL otherwise.  Enqueued on hip_stream. */
+td_status td_lap_decode(td_ctx *ctx, const float *latent_dev, int64_t lx0,
+                        int64_t ly0, int32_t lw, int32_t lh, int64_t X0,
+                        int64_t Y0, int32_t W, int32_t H, float *out_dev,
+                        void *hip_stream);
+
+/* Window-range function kappa of the formal appendix for one axis pair:
+ * windows [ix*stride+offset, +size) meeting [x0,x0+w) x [y0,y0+h).
+ * Writes {ix_min, ix_max, iy_min, iy_max}; returns TD_OK, or TD_E_INVAL if
+ * the range is empty (region between windows) or an argument is invalid.
+ * Host-only; needs no context or device. */
+td_status td_kappa(int64_t x0, int64_t y0, int64_t w, int64_t h, int32_t size,
+                   int32_t stride, int32_t offset, int64_t out[4]);
+
+/* Number of denoiser evaluations a cold query of region R at level t needs
+ * with K steps: sum over levels of |kappa(R_l)| along the dependency cone
+ * (constant-time random access bound, appendix).  Host-only. */
+td_status td_cone_windows(int64_t x0, int64_t y0, int64_t w, int64_t h,
+                          int32_t level, int32_t steps, int32_t size,
+                          int32_t stride, int32_t offset, uint64_t *count);
+
+/* Description of the last error on ctx (owned by ctx, valid until the next
+ * call); "" if none.  Safe on NULL. */
+const char *td_last_error(const td_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TD_H */

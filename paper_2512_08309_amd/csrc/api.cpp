@@ -1,0 +1,777 @@
+// C-ABI of the lazy sampler: query planning (kappa and the dependency cone),
+// the device cache of per-window contributions with LRU eviction, and the
+// per-level execution order.
+//
+// A query J_t[R] (Alg. 1, Sec. 3.3) is served level by level:
+//   plan   : for l = t, t+1, ...: I_l = kappa(R_l) (window-range algorithm of
+//            the appendix, exact floor/ceil in int64); windows of I_l already
+//            in the cache are reused (they are the processed set P_l), the
+//            others are new; R_{l+1} = bounding region of the new windows,
+//            whose inputs J_{l+1}[R_i] are needed.  Planning stops at the
+//            first level without new windows, or at T (noise).
+//   run    : from the deepest planned level up: build J_{l+1} on R_{l+1}
+//            (seed noise at T, else the blend of level-(l+1) contributions),
+//            run the new windows through the batched denoiser, whose output
+//            epilogue stores V_i = W (x) Phi(J_{l+1}[R_i]) straight into the
+//            cache slots.  All windows of one level form one batched round
+//            (split only by workspace size), so a cold query needs at most
+//            T - t rounds (Parallelization theorem).
+//   output : J_t[R] = blend of the level-t contributions (0/0 := 0).
+// Evicting a contribution also removes it from the processed set (Sec. 3.3),
+// so it is simply recomputed when next needed: values never depend on cache
+// state (seed consistency).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <list>
+#include <memory>
+#include <unordered_map>
+
+#include "../../include/td.h"
+#include "model.h"
+
+namespace td {
+namespace {
+
+int64_t floordiv64(int64_t a, int64_t b) {
+  int64_t q = a / b;
+  return (q * b > a) ? q - 1 : q;
+}
+int64_t ceildiv64(int64_t a, int64_t b) { return -floordiv64(-a, b); }
+
+struct Region {
+  int64_t x0, y0, w, h;
+};
+
+struct Kappa {
+  bool empty = true;
+  int64_t ix0 = 0, ix1 = -1, iy0 = 0, iy1 = -1;
+  int64_t nx() const { return ix1 - ix0 + 1; }
+  int64_t ny() const { return iy1 - iy0 + 1; }
+  int64_t count() const { return empty ? 0 : nx() * ny(); }
+};
+
+Kappa kappa(const Region& r, int64_t H, int64_t S, int64_t O) {
+  Kappa k;
+  if (r.w <= 0 || r.h <= 0) return k;
+  k.ix0 = ceildiv64(r.x0 - O - H + 1, S);
+  k.ix1 = floordiv64(r.x0 + r.w - 1 - O, S);
+  k.iy0 = ceildiv64(r.y0 - O - H + 1, S);
+  k.iy1 = floordiv64(r.y0 + r.h - 1 - O, S);
+  k.empty = k.ix0 > k.ix1 || k.iy0 > k.iy1;
+  return k;
+}
+
+struct Key {
+  uint64_t seed;
+  int32_t level;
+  int64_t ix, iy;
+  bool operator==(const Key& o) const {
+    return seed == o.seed && level == o.level && ix == o.ix && iy == o.iy;
+  }
+};
+struct KeyHash {
+  size_t operator()(const Key& k) const {
+    uint64_t h = k.seed * 0x9E3779B97F4A7C15ull;
+    h ^= (uint64_t)k.level + 0x632BE59BD9B4E019ull + (h << 6) + (h >> 2);
+    h ^= (uint64_t)k.ix * 0xC2B2AE3D27D4EB4Full + (h << 6) + (h >> 2);
+    h ^= (uint64_t)k.iy * 0x165667B19E3779F9ull + (h << 6) + (h >> 2);
+    return (size_t)h;
+  }
+};
+
+// Device slab of fixed-size contribution slots.
+class SlotPool {
+ public:
+  ~SlotPool() { release(); }
+  void configure(size_t slot_floats) {
+    release();
+    slot_floats_ = slot_floats;
+    per_chunk_ = std::max<size_t>(1, (size_t)(256u << 20) / (slot_floats * 4));
+  }
+  void release() {
+    for (float* c : chunks_) (void)hipFree(c);
+    chunks_.clear();
+    free_.clear();
+    total_ = 0;
+  }
+  float* ptr(uint32_t s) const { return chunks_[s / per_chunk_] + (size_t)(s % per_chunk_) * slot_floats_; }
+  uint32_t take() {
+    if (free_.empty()) {
+      float* c = nullptr;
+      TD_HIP(hipMalloc(&c, per_chunk_ * slot_floats_ * sizeof(float)));
+      chunks_.push_back(c);
+      for (size_t i = per_chunk_; i-- > 0;) free_.push_back((uint32_t)(total_ + i));
+      total_ += per_chunk_;
+    }
+    uint32_t s = free_.back();
+    free_.pop_back();
+    return s;
+  }
+  void give(uint32_t s) { free_.push_back(s); }
+  size_t slot_bytes() const { return slot_floats_ * sizeof(float); }
+
+ private:
+  size_t slot_floats_ = 0, per_chunk_ = 1, total_ = 0;
+  std::vector<float*> chunks_;
+  std::vector<uint32_t> free_;
+};
+
+struct Entry {
+  uint32_t slot;
+  int pins;
+  std::list<Key>::iterator lru;
+};
+
+// Host staging (pinned) + device mirror for per-query metadata.
+class Arena {
+ public:
+  ~Arena() { release(); }
+  void release() {
+    if (h_) (void)hipHostFree(h_);
+    if (d_) (void)hipFree(d_);
+    h_ = nullptr;
+    d_ = nullptr;
+    cap_ = off_ = 0;
+  }
+  void reset() { off_ = 0; }
+  // Make room for `bytes` of reservations in the current query (only
+  // before the first reservation of a query).
+  void ensure(size_t bytes) {
+    if (bytes <= cap_) return;
+    TD_CHECK(off_ == 0, -2, "metadata arena resized within a query");
+    TD_HIP(hipDeviceSynchronize());
+    release();
+    cap_ = std::max<size_t>(bytes, 1 << 20);
+    TD_HIP(hipHostMalloc((void**)&h_, cap_, hipHostMallocDefault));
+    TD_HIP(hipMalloc((void**)&d_, cap_));
+  }
+  // Reserve n bytes; returns the host and device addresses.  Growing
+  // synchronises the device (only when an earlier query needed less).
+  std::pair<char*, char*> reserve(size_t n) {
+    n = (n + 255) / 256 * 256;
+    if (off_ + n > cap_) {
+      TD_CHECK(off_ == 0, -2, "metadata arena overflow within a query");
+      TD_HIP(hipDeviceSynchronize());
+      release();
+      cap_ = std::max<size_t>(n, 1 << 20);
+      TD_HIP(hipHostMalloc((void**)&h_, cap_, hipHostMallocDefault));
+      TD_HIP(hipMalloc((void**)&d_, cap_));
+    }
+    auto r = std::make_pair(h_ + off_, d_ + off_);
+    off_ += n;
+    return r;
+  }
+
+ private:
+  char* h_ = nullptr;
+  char* d_ = nullptr;
+  size_t cap_ = 0, off_ = 0;
+};
+
+struct Level {
+  int t;
+  Region region;      // R_t
+  Kappa k;            // kappa(R_t)
+  std::vector<std::pair<int64_t, int64_t>> fresh;  // new windows (ix, iy), canonical order
+  Region in_region{}; // bbox of the new windows = region at t+1
+};
+
+}  // namespace
+}  // namespace td
+
+struct td_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::unique_ptr<td::Model> model;
+  td::SlotPool pool;
+  std::unordered_map<td::Key, td::Entry, td::KeyHash> map;
+  std::list<td::Key> lru;  // front = most recent
+  size_t budget = (size_t)8 << 30;
+  int batch = 0;           // 0 = automatic
+  td_cache_stats_t stats{};
+  std::string err;
+  td::Arena arena;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+  float* canvas = nullptr;
+  size_t canvas_cap = 0;
+  float* tmp = nullptr;
+  size_t tmp_cap = 0;
+  float* dec = nullptr;
+  size_t dec_cap = 0;
+  float* outbuf = nullptr;
+  size_t outbuf_cap = 0;
+};
+
+namespace td {
+namespace {
+
+void grow(float*& p, size_t& cap, size_t n) {
+  if (n <= cap) return;
+  size_t want = std::max(n, cap * 3 / 2);
+  TD_HIP(hipDeviceSynchronize());
+  if (p) TD_HIP(hipFree(p));
+  p = nullptr;
+  cap = 0;
+  TD_HIP(hipMalloc(&p, want * sizeof(float)));
+  cap = want;
+}
+
+void need_model(td_ctx* c) { TD_CHECK(c->model, TD_E_STATE, "no weights loaded"); }
+
+void touch(td_ctx* c, Entry& e, const Key& k) {
+  c->lru.erase(e.lru);
+  c->lru.push_front(k);
+  e.lru = c->lru.begin();
+}
+
+void evict_to_budget(td_ctx* c) {
+  size_t sb = c->pool.slot_bytes();
+  auto it = c->lru.end();
+  while (c->map.size() * sb > c->budget && it != c->lru.begin()) {
+    --it;
+    auto m = c->map.find(*it);
+    if (m->second.pins > 0) continue;
+    c->pool.give(m->second.slot);
+    c->map.erase(m);
+    it = c->lru.erase(it);
+    c->stats.evictions++;
+  }
+  c->stats.bytes_used = c->map.size() * sb;
+}
+
+void unpin_level(td_ctx* c, uint64_t seed, const Level& lv) {
+  if (lv.k.empty) return;
+  for (int64_t iy = lv.k.iy0; iy <= lv.k.iy1; ++iy)
+    for (int64_t ix = lv.k.ix0; ix <= lv.k.ix1; ++ix) {
+      auto m = c->map.find(Key{seed, lv.t, ix, iy});
+      if (m != c->map.end() && m->second.pins > 0) m->second.pins--;
+    }
+}
+
+// Device pointer grid of level lv's contributions over lv.k (all present).
+const float* const* pointer_grid(td_ctx* c, uint64_t seed, const Level& lv) {
+  size_t n = (size_t)lv.k.count();
+  auto hd = c->arena.reserve(n * sizeof(float*));
+  const float** h = (const float**)hd.first;
+  size_t i = 0;
+  for (int64_t iy = lv.k.iy0; iy <= lv.k.iy1; ++iy)
+    for (int64_t ix = lv.k.ix0; ix <= lv.k.ix1; ++ix) {
+      auto m = c->map.find(Key{seed, lv.t, ix, iy});
+      TD_CHECK(m != c->map.end(), TD_E_DEVICE, "internal: contribution missing from cache");
+      h[i++] = c->pool.ptr(m->second.slot);
+    }
+  TD_HIP(hipMemcpyAsync(hd.second, hd.first, n * sizeof(float*), hipMemcpyHostToDevice, c->stream));
+  return (const float* const*)hd.second;
+}
+
+void blend_into(td_ctx* c, uint64_t seed, const Level& lv, const Region& r, int layout, float* out) {
+  const ModelDesc& d = c->model->d;
+  const float* const* grid = pointer_grid(c, seed, lv);
+  int64_t bx = lv.k.ix0 * d.S + d.O, by = lv.k.iy0 * d.S + d.O;
+  WinGeom g{d.H, d.S, d.C};
+  launch_blend(c->stream, g, (int)(r.x0 - bx), (int)(r.y0 - by), (int)r.w, (int)r.h, (int)lv.k.nx(),
+               (int)lv.k.ny(), grid, c->model->w1d(), layout, out);
+}
+
+int auto_batch(td_ctx* c) {
+  if (c->batch > 0) return c->batch;
+  size_t per = c->model->workspace_bytes_per_window();
+  if (!per) return 1 << 20;
+  size_t b = ((size_t)16 << 30) / per;
+  return (int)std::max<size_t>(1, std::min<size_t>(b, c->model->d.C == 4 ? 512 : 4096));
+}
+
+void check_region(int64_t x0, int64_t y0, int64_t w, int64_t h) {
+  const int64_t lim = (1LL << 31) - (1LL << 22);
+  TD_CHECK(w >= 1 && h >= 1 && w <= (1 << 20) && h <= (1 << 20) && w * h <= (1LL << 26), TD_E_INVAL,
+           "region sides must be in [1, 2^20] and its area at most 2^26 pixels");
+  TD_CHECK(x0 > -lim && y0 > -lim && x0 + w < lim && y0 + h < lim, TD_E_INVAL, "region coordinates out of range");
+}
+
+// J_level on region r written to dev_out (layout 0: [h][w][C], 1: [C][h][w]).
+void sample_latent(td_ctx* c, uint64_t seed, Region r, int level, int layout, float* dev_out) {
+  const ModelDesc& d = c->model->d;
+  hipStream_t st = c->stream;
+  c->stats.queries++;
+  if (level == d.K) {
+    launch_noise(st, seed, r.x0, r.y0, (int)r.w, (int)r.h, d.C, 0, (float)d.sched[0], layout, dev_out);
+    return;
+  }
+  // ---- plan
+  std::vector<Level> levels;
+  Region R = r;
+  for (int t = level; t < d.K; ++t) {
+    Level lv;
+    lv.t = t;
+    lv.region = R;
+    lv.k = kappa(R, d.H, d.S, d.O);
+    if (!lv.k.empty) {
+      TD_CHECK(lv.k.count() <= (1LL << 26), TD_E_INVAL, "query too large");
+      int64_t mnx = INT64_MAX, mxx = INT64_MIN, mny = INT64_MAX, mxy = INT64_MIN;
+      for (int64_t iy = lv.k.iy0; iy <= lv.k.iy1; ++iy)
+        for (int64_t ix = lv.k.ix0; ix <= lv.k.ix1; ++ix) {
+          Key key{seed, t, ix, iy};
+          auto m = c->map.find(key);
+          if (m != c->map.end()) {
+            m->second.pins++;
+            touch(c, m->second, key);
+            c->stats.hits++;
+          } else {
+            lv.fresh.push_back({ix, iy});
+            mnx = std::min(mnx, ix);
+            mxx = std::max(mxx, ix);
+            mny = std::min(mny, iy);
+            mxy = std::max(mxy, iy);
+          }
+        }
+      if (!lv.fresh.empty())
+        lv.in_region = Region{mnx * d.S + d.O, mny * d.S + d.O, (mxx - mnx) * d.S + d.H, (mxy - mny) * d.S + d.H};
+    }
+    levels.push_back(lv);
+    if (lv.k.empty || lv.fresh.empty()) break;
+    R = lv.in_region;
+  }
+  // ---- run, deepest level first
+  const int maxb = auto_batch(c);
+  size_t meta = 65536;
+  for (const Level& lv : levels) {
+    meta += (size_t)lv.k.count() * sizeof(float*) + 256;
+    size_t nbat = (lv.fresh.size() + maxb - 1) / maxb;
+    meta += lv.fresh.size() * (4 * sizeof(int) + sizeof(float*)) + nbat * 3 * 256;
+  }
+  c->arena.ensure(meta);
+  c->model->ensure_workspace(std::min<int>(maxb, 1 << 20));
+  for (int i = (int)levels.size() - 1; i >= 0; --i) {
+    Level& lv = levels[i];
+    if (lv.k.empty || lv.fresh.empty()) continue;
+    const Region& cr = lv.in_region;
+    size_t cn = (size_t)cr.w * cr.h * d.C;
+    grow(c->canvas, c->canvas_cap, cn);
+    const int tn = lv.t + 1;
+    if (tn == d.K) {
+      launch_noise(st, seed, cr.x0, cr.y0, (int)cr.w, (int)cr.h, d.C, 0, (float)d.sched[0], 0, c->canvas);
+    } else {
+      const Level& up = levels[i + 1];
+      if (up.k.empty) launch_fill(st, c->canvas, cn, 0.f);
+      else blend_into(c, seed, up, cr, 0, c->canvas);
+      unpin_level(c, seed, up);
+    }
+    // new windows -> slots, then batched denoiser rounds
+    const size_t nf = lv.fresh.size();
+    std::vector<uint32_t> slots(nf);
+    for (size_t j = 0; j < nf; ++j) {
+      Key key{seed, lv.t, lv.fresh[j].first, lv.fresh[j].second};
+      slots[j] = c->pool.take();
+      c->lru.push_front(key);
+      c->map[key] = Entry{slots[j], 1, c->lru.begin()};
+    }
+    c->stats.misses += nf;
+    if (lv.t < 64) c->stats.windows_evaluated[lv.t] += nf;
+    for (size_t b0 = 0; b0 < nf; b0 += (size_t)maxb) {
+      int nb = (int)std::min<size_t>(maxb, nf - b0);
+      auto o = c->arena.reserve((size_t)nb * 2 * sizeof(int));
+      auto w = c->arena.reserve((size_t)nb * 2 * sizeof(int));
+      auto s = c->arena.reserve((size_t)nb * sizeof(float*));
+      int* ho = (int*)o.first;
+      int* hw = (int*)w.first;
+      float** hs = (float**)s.first;
+      for (int j = 0; j < nb; ++j) {
+        auto ij = lv.fresh[b0 + j];
+        ho[2 * j] = (int)(ij.first * d.S + d.O - cr.x0);
+        ho[2 * j + 1] = (int)(ij.second * d.S + d.O - cr.y0);
+        hw[2 * j] = (int)ij.first;
+        hw[2 * j + 1] = (int)ij.second;
+        hs[j] = c->pool.ptr(slots[b0 + j]);
+      }
+      TD_HIP(hipMemcpyAsync(o.second, o.first, (size_t)nb * 2 * sizeof(int), hipMemcpyHostToDevice, st));
+      TD_HIP(hipMemcpyAsync(w.second, w.first, (size_t)nb * 2 * sizeof(int), hipMemcpyHostToDevice, st));
+      TD_HIP(hipMemcpyAsync(s.second, s.first, (size_t)nb * sizeof(float*), hipMemcpyHostToDevice, st));
+      WindowBatch wb;
+      wb.canvas = c->canvas;
+      wb.canvas_w = (int)cr.w;
+      wb.d_origins = (const int*)o.second;
+      wb.d_widx = (const int*)w.second;
+      wb.d_slots = (float* const*)s.second;
+      wb.n = nb;
+      wb.mode = 0;
+      c->model->run_batch(st, wb, d.K - lv.t - 1);
+      c->stats.batches++;
+    }
+    evict_to_budget(c);
+  }
+  // ---- output
+  const Level& top = levels[0];
+  if (top.k.empty) {
+    launch_fill(st, dev_out, (size_t)r.w * r.h * d.C, 0.f);
+  } else {
+    blend_into(c, seed, top, r, layout, dev_out);
+    unpin_level(c, seed, top);
+  }
+  evict_to_budget(c);
+}
+
+// Latent apron of a full-resolution region (decode reads 17 latent px).
+Region decode_apron(const ModelDesc& d, const Region& full) {
+  const int R = d.blur_radius;
+  int64_t xl = floordiv64(2 * full.x0 - 7, 16), xh = floordiv64(2 * (full.x0 + full.w - 1) - 7, 16) + 1;
+  int64_t yl = floordiv64(2 * full.y0 - 7, 16), yh = floordiv64(2 * (full.y0 + full.h - 1) - 7, 16) + 1;
+  return Region{xl - R - 1, yl - R - 1, xh - xl + 2 * R + 3, yh - yl + 2 * R + 3};
+}
+
+void decode_into(td_ctx* c, const float* latent, const Region& lat, const Region& full, float* out, hipStream_t st) {
+  const ModelDesc& d = c->model->d;
+  DecodeArgs a{};
+  a.latent = latent;
+  a.lx0 = lat.x0;
+  a.ly0 = lat.y0;
+  a.lw = (int)lat.w;
+  a.lh = (int)lat.h;
+  a.C = d.C;
+  a.X0 = full.x0;
+  a.Y0 = full.y0;
+  a.W = (int)full.w;
+  a.H = (int)full.h;
+  a.out = out;
+  a.sigma_low = (float)d.sigma_low;
+  a.sigma_res = (float)d.sigma_res;
+  a.taps = c->model->decode_taps();
+  a.radius = d.blur_radius;
+  a.atoms = c->model->decode_atoms();
+  size_t wf = decode_work_floats(a);
+  grow(c->dec, c->dec_cap, 2 * wf);
+  a.work0 = c->dec;
+  a.work1 = c->dec + wf;
+  launch_decode(st, a);
+}
+
+void sample_any(td_ctx* c, uint64_t seed, int64_t x0, int64_t y0, int32_t w, int32_t h, int32_t level,
+                float* dev_out, size_t out_len) {
+  need_model(c);
+  const ModelDesc& d = c->model->d;
+  check_region(x0, y0, w, h);
+  if (c->pending) {
+    TD_HIP(hipEventSynchronize(c->done));
+    c->pending = false;
+  }
+  c->arena.reset();
+  if (level == TD_LEVEL_HEIGHT) {
+    TD_CHECK(out_len >= (size_t)w * h, TD_E_INVAL, "output buffer too small");
+    Region full{x0, y0, w, h};
+    Region lat = decode_apron(d, full);
+    size_t n = (size_t)lat.w * lat.h * d.C;
+    grow(c->tmp, c->tmp_cap, n);
+    sample_latent(c, seed, lat, 0, 0, c->tmp);
+    decode_into(c, c->tmp, lat, full, dev_out, c->stream);
+  } else {
+    TD_CHECK(level >= 0 && level <= d.K, TD_E_INVAL, "level out of range");
+    TD_CHECK(out_len >= (size_t)w * h * d.C, TD_E_INVAL, "output buffer too small");
+    sample_latent(c, seed, Region{x0, y0, w, h}, level, 1, dev_out);
+  }
+  c->stats.bytes_budget = c->budget;
+  TD_HIP(hipEventRecord(c->done, c->stream));
+  c->pending = true;
+}
+
+template <class F>
+td_status guarded(td_ctx* c, F&& f) {
+  try {
+    if (c) c->err.clear();
+    f();
+    return TD_OK;
+  } catch (const Error& e) {
+    if (c) c->err = e.msg;
+    return (td_status)e.status;
+  } catch (const std::bad_alloc&) {
+    if (c) c->err = "host allocation failed";
+    return TD_E_NOMEM;
+  } catch (const std::exception& e) {
+    if (c) c->err = e.what();
+    return TD_E_DEVICE;
+  }
+}
+
+}  // namespace
+}  // namespace td
+
+using namespace td;
+
+extern "C" {
+
+td_status td_create(int hip_device, td_ctx** out) {
+  if (!out) return TD_E_INVAL;
+  *out = nullptr;
+  td_ctx* c = nullptr;
+  try {
+    c = new td_ctx();
+  } catch (...) {
+    return TD_E_NOMEM;
+  }
+  td_status s = guarded(c, [&] {
+    int n = 0;
+    TD_HIP(hipGetDeviceCount(&n));
+    TD_CHECK(hip_device >= 0 && hip_device < n, TD_E_INVAL, "no such HIP device");
+    c->device = hip_device;
+    TD_HIP(hipSetDevice(hip_device));
+    TD_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    TD_HIP(hipEventCreateWithFlags(&c->done, hipEventDisableTiming));
+  });
+  if (s != TD_OK) {
+    td_destroy(c);
+    return s;
+  }
+  *out = c;
+  return TD_OK;
+}
+
+void td_destroy(td_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  c->map.clear();
+  c->lru.clear();
+  c->pool.release();
+  c->model.reset();
+  c->arena.release();
+  for (float* p : {c->canvas, c->tmp, c->dec, c->outbuf})
+    if (p) (void)hipFree(p);
+  if (c->done) (void)hipEventDestroy(c->done);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+td_status td_load_weights(td_ctx* c, const char* path) {
+  if (!c) return TD_E_INVAL;
+  return guarded(c, [&] {
+    TD_CHECK(path, TD_E_INVAL, "null path");
+    TD_HIP(hipSetDevice(c->device));
+    TD_HIP(hipStreamSynchronize(c->stream));
+    c->map.clear();
+    c->lru.clear();
+    c->pool.release();
+    c->model.reset();
+    std::unique_ptr<Model> m(new Model());
+    m->load(path, c->stream);
+    c->pool.configure((size_t)m->d.H * m->d.H * m->d.C);
+    c->model = std::move(m);
+    c->stats = td_cache_stats_t{};
+    c->stats.bytes_budget = c->budget;
+  });
+}
+
+td_status td_sample_region_async(td_ctx* c, uint64_t seed, int64_t x0, int64_t y0, int32_t w, int32_t h,
+                                 int32_t level, float* dev_out, size_t out_len, void* hip_stream) {
+  if (!c) return TD_E_INVAL;
+  return guarded(c, [&] {
+    TD_CHECK(dev_out, TD_E_INVAL, "null output");
+    TD_HIP(hipSetDevice(c->device));
+    hipStream_t user = (hipStream_t)hip_stream;
+    if (user && user != c->stream) {
+      // order after the caller's stream, run on ours, then make theirs wait
+      hipEvent_t ev;
+      TD_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      TD_HIP(hipEventRecord(ev, user));
+      TD_HIP(hipStreamWaitEvent(c->stream, ev, 0));
+      sample_any(c, seed, x0, y0, w, h, level, dev_out, out_len);
+      TD_HIP(hipEventRecord(ev, c->stream));
+      TD_HIP(hipStreamWaitEvent(user, ev, 0));
+      TD_HIP(hipEventDestroy(ev));
+    } else {
+      sample_any(c, seed, x0, y0, w, h, level, dev_out, out_len);
+    }
+  });
+}
+
+td_status td_sample_region(td_ctx* c, uint64_t seed, int64_t x0, int64_t y0, int32_t w, int32_t h, int32_t level,
+                           float* out, size_t out_len) {
+  if (!c) return TD_E_INVAL;
+  return guarded(c, [&] {
+    TD_CHECK(out, TD_E_INVAL, "null output");
+    need_model(c);
+    TD_HIP(hipSetDevice(c->device));
+    size_t n = level == TD_LEVEL_HEIGHT ? (size_t)std::max(w, 0) * std::max(h, 0)
+                                        : (size_t)std::max(w, 0) * std::max(h, 0) * c->model->d.C;
+    TD_CHECK(out_len >= n, TD_E_INVAL, "output buffer too small");
+    grow(c->outbuf, c->outbuf_cap, std::max<size_t>(n, 1));
+    sample_any(c, seed, x0, y0, w, h, level, c->outbuf, n);
+    TD_HIP(hipMemcpyAsync(out, c->outbuf, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    TD_HIP(hipStreamSynchronize(c->stream));
+    c->pending = false;
+  });
+}
+
+td_status td_cache_set_budget(td_ctx* c, size_t bytes) {
+  if (!c) return TD_E_INVAL;
+  return guarded(c, [&] {
+    c->budget = bytes;
+    c->stats.bytes_budget = bytes;
+    if (c->model) evict_to_budget(c);
+  });
+}
+
+td_status td_cache_clear(td_ctx* c) {
+  if (!c) return TD_E_INVAL;
+  return guarded(c, [&] {
+    TD_HIP(hipSetDevice(c->device));
+    TD_HIP(hipStreamSynchronize(c->stream));
+    c->pending = false;
+    for (auto& kv : c->map) c->pool.give(kv.second.slot);
+    c->map.clear();
+    c->lru.clear();
+    c->stats = td_cache_stats_t{};
+    c->stats.bytes_budget = c->budget;
+  });
+}
+
+td_status td_cache_stats(td_ctx* c, td_cache_stats_t* out) {
+  if (!c || !out) return TD_E_INVAL;
+  c->stats.bytes_used = c->model ? c->map.size() * c->pool.slot_bytes() : 0;
+  c->stats.bytes_budget = c->budget;
+  *out = c->stats;
+  return TD_OK;
+}
+
+td_status td_cache_peek(td_ctx* c, uint64_t seed, int32_t level, int64_t ix, int64_t iy, float* out,
+                        size_t out_len) {
+  if (!c) return TD_E_INVAL;
+  return guarded(c, [&] {
+    need_model(c);
+    TD_CHECK(out, TD_E_INVAL, "null output");
+    const ModelDesc& d = c->model->d;
+    size_t n = (size_t)d.H * d.H * d.C;
+    TD_CHECK(out_len >= n, TD_E_INVAL, "output buffer too small");
+    auto m = c->map.find(Key{seed, level, ix, iy});
+    TD_CHECK(m != c->map.end(), TD_E_INVAL, "window not cached");
+    TD_HIP(hipSetDevice(c->device));
+    TD_HIP(hipMemcpyAsync(out, c->pool.ptr(m->second.slot), n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    TD_HIP(hipStreamSynchronize(c->stream));
+  });
+}
+
+td_status td_set_option(td_ctx* c, const char* key, int64_t value) {
+  if (!c) return TD_E_INVAL;
+  return guarded(c, [&] {
+    TD_CHECK(key, TD_E_INVAL, "null option key");
+    std::string k(key);
+    if (k == "batch") {
+      TD_CHECK(value >= 1 && value <= (1 << 20), TD_E_INVAL, "batch must be in [1, 2^20]");
+      c->batch = (int)value;
+    } else if (k == "cache_budget") {
+      TD_CHECK(value >= 0, TD_E_INVAL, "budget must be >= 0");
+      c->budget = (size_t)value;
+      if (c->model) evict_to_budget(c);
+    } else {
+      throw Error{TD_E_INVAL, "unknown option: " + k};
+    }
+  });
+}
+
+td_status td_get_info(td_ctx* c, const char* key, int64_t* value) {
+  if (!c || !value) return TD_E_INVAL;
+  return guarded(c, [&] {
+    need_model(c);
+    TD_CHECK(key, TD_E_INVAL, "null key");
+    const ModelDesc& d = c->model->d;
+    std::string k(key);
+    if (k == "channels") *value = d.C;
+    else if (k == "steps") *value = d.K;
+    else if (k == "window") *value = d.H;
+    else if (k == "stride") *value = d.S;
+    else if (k == "offset") *value = d.O;
+    else if (k == "factor") *value = d.factor;
+    else if (k == "params") *value = (int64_t)d.params;
+    else if (k == "batch") *value = auto_batch(c);
+    else throw Error{TD_E_INVAL, "unknown info key: " + k};
+  });
+}
+
+td_status td_denoise_windows(td_ctx* c, const float* x_dev, int32_t n, int32_t k, float* out_dev) {
+  if (!c) return TD_E_INVAL;
+  return guarded(c, [&] {
+    need_model(c);
+    const ModelDesc& d = c->model->d;
+    TD_CHECK(x_dev && out_dev && n >= 0, TD_E_INVAL, "bad arguments");
+    TD_CHECK(k >= 0 && k < d.K, TD_E_INVAL, "sigma index out of range");
+    TD_HIP(hipSetDevice(c->device));
+    if (c->pending) {
+      TD_HIP(hipEventSynchronize(c->done));
+      c->pending = false;
+    }
+    c->arena.reset();
+    int maxb = auto_batch(c);
+    c->model->ensure_workspace(maxb);
+    c->arena.ensure((size_t)(n / maxb + 1) * (256 + (size_t)std::min(n, maxb) * 2 * sizeof(int)));
+    for (int b0 = 0; b0 < n; b0 += maxb) {
+      int nb = std::min(maxb, n - b0);
+      auto o = c->arena.reserve((size_t)nb * 2 * sizeof(int));
+      int* ho = (int*)o.first;
+      for (int j = 0; j < nb; ++j) {
+        ho[2 * j] = 0;
+        ho[2 * j + 1] = j * d.H;
+      }
+      TD_HIP(hipMemcpyAsync(o.second, o.first, (size_t)nb * 2 * sizeof(int), hipMemcpyHostToDevice, c->stream));
+      WindowBatch wb;
+      wb.canvas = x_dev + (size_t)b0 * d.H * d.H * d.C;
+      wb.canvas_w = d.H;
+      wb.d_origins = (const int*)o.second;
+      wb.d_widx = (const int*)o.second;  // analytic kind: window index (0, j*H) is unused by the UNet
+      wb.n = nb;
+      wb.mode = 1;
+      wb.dout = out_dev + (size_t)b0 * d.H * d.H * d.C;
+      c->model->run_batch(c->stream, wb, k);
+    }
+    TD_HIP(hipStreamSynchronize(c->stream));
+  });
+}
+
+td_status td_lap_decode(td_ctx* c, const float* latent_dev, int64_t lx0, int64_t ly0, int32_t lw, int32_t lh,
+                        int64_t X0, int64_t Y0, int32_t W, int32_t H, float* out_dev, void* hip_stream) {
+  if (!c) return TD_E_INVAL;
+  return guarded(c, [&] {
+    need_model(c);
+    TD_CHECK(latent_dev && out_dev && lw > 0 && lh > 0, TD_E_INVAL, "bad arguments");
+    check_region(X0, Y0, W, H);
+    TD_HIP(hipSetDevice(c->device));
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : c->stream;
+    if (c->pending) {
+      TD_HIP(hipEventSynchronize(c->done));
+      c->pending = false;
+    }
+    Region need = decode_apron(c->model->d, Region{X0, Y0, W, H});
+    TD_CHECK(need.x0 >= lx0 && need.y0 >= ly0 && need.x0 + need.w <= lx0 + lw && need.y0 + need.h <= ly0 + lh,
+             TD_E_INVAL, "latent does not cover the 17-pixel decode apron");
+    decode_into(c, latent_dev, Region{lx0, ly0, lw, lh}, Region{X0, Y0, W, H}, out_dev, st);
+  });
+}
+
+td_status td_kappa(int64_t x0, int64_t y0, int64_t w, int64_t h, int32_t size, int32_t stride, int32_t offset,
+                   int64_t out[4]) {
+  if (!out || size < 1 || stride < 1 || w < 1 || h < 1) return TD_E_INVAL;
+  Kappa k = kappa(Region{x0, y0, w, h}, size, stride, offset);
+  out[0] = k.ix0;
+  out[1] = k.ix1;
+  out[2] = k.iy0;
+  out[3] = k.iy1;
+  return k.empty ? TD_E_INVAL : TD_OK;
+}
+
+td_status td_cone_windows(int64_t x0, int64_t y0, int64_t w, int64_t h, int32_t level, int32_t steps, int32_t size,
+                          int32_t stride, int32_t offset, uint64_t* count) {
+  if (!count || size < 1 || stride < 1 || w < 1 || h < 1 || level < 0 || level > steps) return TD_E_INVAL;
+  uint64_t n = 0;
+  Region R{x0, y0, w, h};
+  for (int t = level; t < steps; ++t) {
+    Kappa k = kappa(R, size, stride, offset);
+    if (k.empty) break;
+    n += (uint64_t)k.count();
+    R = Region{k.ix0 * stride + offset, k.iy0 * stride + offset, (k.ix1 - k.ix0) * stride + size,
+               (k.iy1 - k.iy0) * stride + size};
+  }
+  *count = n;
+  return TD_OK;
+}
+
+const char* td_last_error(const td_ctx* c) { return c ? c->err.c_str() : ""; }
+
+}  // extern "C"

@@ -1,0 +1,154 @@
+// Overlap blend of window contributions (InfiniteDiffusion update, Eq. 2):
+//   J_t(p) = sum_{i in kappa(p)} V_i(p - o_i) / sum_{i in kappa(p)} W(p - o_i),
+// V_i = W (x) Phi_i stored per window (Sec. 3.3), 0/0 := 0 (formal appendix).
+// The denominator is recomputed from the separable weight table instead of
+// being stored.  Windows are summed in canonical order (iy, then ix
+// ascending), so a pixel's value does not depend on the region it was
+// queried with.  One thread per pixel; all channels of a contribution pixel
+// are contiguous, so threads along x read consecutive addresses of the
+// same window.  HBM-bound: (H/s)^2 contribution reads + one write per value.
+//
+// Also here: the analytic linear-Gaussian window step (posterior mean of a
+// Gaussian prior, Euler step, weighting), used to check the sampler
+// machinery against a closed form.
+#include "td_internal.h"
+
+namespace td {
+namespace {
+
+__device__ __forceinline__ int ceil_div_i(int a, int s) { return a >= 0 ? (a + s - 1) / s : -((-a) / s); }
+__device__ __forceinline__ int floor_div_i(int a, int s) { return a >= 0 ? a / s : -((-a + s - 1) / s); }
+
+template <int CC>
+__global__ __launch_bounds__(256) void blend_kernel(int H, int S, int C, int rx0, int ry0, int w, int h,
+                                                    int nx, int ny, const float* const* __restrict__ ptrs,
+                                                    const float* __restrict__ w1d, int layout,
+                                                    float* __restrict__ out) {
+  const int nc = CC > 0 ? CC : C;
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= w * h) return;
+  int ry = idx / w, rx = idx - ry * w;
+  int px = rx0 + rx, py = ry0 + ry;
+  int xlo = max(0, ceil_div_i(px - H + 1, S)), xhi = min(nx - 1, floor_div_i(px, S));
+  int ylo = max(0, ceil_div_i(py - H + 1, S)), yhi = min(ny - 1, floor_div_i(py, S));
+  float acc[CC > 0 ? CC : 4];
+  float bsum = 0.f;
+  if (CC > 0) {
+#pragma unroll
+    for (int c = 0; c < (CC > 0 ? CC : 4); ++c) acc[c] = 0.f;
+  }
+  for (int c = 0; CC == 0 && c < 4; ++c) acc[c] = 0.f;
+  for (int iy = ylo; iy <= yhi; ++iy) {
+    int v = py - iy * S;
+    float wv = w1d[v];
+    for (int ix = xlo; ix <= xhi; ++ix) {
+      int u = px - ix * S;
+      bsum += w1d[u] * wv;
+      const float* p = ptrs[iy * nx + ix] + ((size_t)v * H + u) * nc;
+      if (CC == 4) {
+        float4 q = *reinterpret_cast<const float4*>(p);
+        acc[0] += q.x; acc[1] += q.y; acc[2] += q.z; acc[3] += q.w;
+      } else if (CC == 1) {
+        acc[0] += p[0];
+      }
+    }
+  }
+  if (CC > 0) {
+#pragma unroll
+    for (int c = 0; c < (CC > 0 ? CC : 4); ++c) {
+      float r = bsum > 0.f ? acc[c] / bsum : 0.f;
+      if (layout == 0) out[(size_t)idx * nc + c] = r;
+      else out[(size_t)c * w * h + idx] = r;
+    }
+  }
+}
+
+// Generic channel count: one pass per channel (C not 1 or 4).
+__global__ __launch_bounds__(256) void blend_generic(int H, int S, int C, int rx0, int ry0, int w, int h,
+                                                     int nx, int ny, const float* const* __restrict__ ptrs,
+                                                     const float* __restrict__ w1d, int layout,
+                                                     float* __restrict__ out) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= w * h) return;
+  int ry = idx / w, rx = idx - ry * w;
+  int px = rx0 + rx, py = ry0 + ry;
+  int xlo = max(0, ceil_div_i(px - H + 1, S)), xhi = min(nx - 1, floor_div_i(px, S));
+  int ylo = max(0, ceil_div_i(py - H + 1, S)), yhi = min(ny - 1, floor_div_i(py, S));
+  for (int c = 0; c < C; ++c) {
+    float acc = 0.f, bsum = 0.f;
+    for (int iy = ylo; iy <= yhi; ++iy) {
+      int v = py - iy * S;
+      for (int ix = xlo; ix <= xhi; ++ix) {
+        int u = px - ix * S;
+        bsum += w1d[u] * w1d[v];
+        acc += ptrs[iy * nx + ix][((size_t)v * H + u) * C + c];
+      }
+    }
+    float r = bsum > 0.f ? acc / bsum : 0.f;
+    if (layout == 0) out[(size_t)idx * C + c] = r;
+    else out[(size_t)c * w * h + idx] = r;
+  }
+}
+
+__device__ __forceinline__ int floor_mod(int a, int m) {
+  int r = a % m;
+  return r < 0 ? r + m : r;
+}
+
+__global__ __launch_bounds__(256) void lg_step_kernel(int H, int C, const float* __restrict__ canvas,
+                                                      int canvas_w, const int* __restrict__ origins,
+                                                      const int* __restrict__ widx, float a_post,
+                                                      float c_euler, const float* __restrict__ w1d,
+                                                      float* const* __restrict__ slots, int mode,
+                                                      float* __restrict__ dout) {
+  int b = blockIdx.y;
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= H * H * C) return;
+  int c = idx % C;
+  int pix = idx / C;
+  int v = pix / H, u = pix - v * H;
+  int ox = origins[2 * b], oy = origins[2 * b + 1];
+  float x = canvas[((size_t)(oy + v) * canvas_w + ox + u) * C + c];
+  int ix = widx[2 * b], iy = widx[2 * b + 1];
+  float mu = 0.1f * (float)(floor_mod(ix, 7) - 3) - 0.05f * (float)(floor_mod(iy, 5) - 2) + 0.01f * (float)c;
+  float d = mu + a_post * (x - mu);
+  if (mode == 1) {
+    dout[(size_t)b * H * H * C + idx] = d;
+    return;
+  }
+  float phi = x + c_euler * (x - d);
+  slots[b][idx] = (w1d[u] * w1d[v]) * phi;
+}
+
+}  // namespace
+
+void launch_blend(hipStream_t st, const WinGeom& g, int rx0, int ry0, int w, int h, int nx, int ny,
+                  const float* const* ptrs, const float* w1d, int layout, float* out) {
+  int n = w * h;
+  if (!n) return;
+  dim3 grid((n + 255) / 256);
+  if (g.channels == 4)
+    hipLaunchKernelGGL(blend_kernel<4>, grid, dim3(256), 0, st, g.size, g.stride, 4, rx0, ry0, w, h, nx,
+                       ny, ptrs, w1d, layout, out);
+  else if (g.channels == 1)
+    hipLaunchKernelGGL(blend_kernel<1>, grid, dim3(256), 0, st, g.size, g.stride, 1, rx0, ry0, w, h, nx,
+                       ny, ptrs, w1d, layout, out);
+  else
+    hipLaunchKernelGGL(blend_generic, grid, dim3(256), 0, st, g.size, g.stride, g.channels, rx0, ry0, w,
+                       h, nx, ny, ptrs, w1d, layout, out);
+  TD_LAUNCHED();
+}
+
+void launch_lg_step(hipStream_t st, const WinGeom& g, const float* canvas, int canvas_w,
+                    const int* origins, const int* widx, int nwin, double prior_std, double sigma,
+                    float c_euler, const float* w1d, float* const* slots, int mode, float* dout) {
+  if (!nwin) return;
+  int per = g.size * g.size * g.channels;
+  double s2 = prior_std * prior_std;
+  float a_post = (float)(s2 / (s2 + sigma * sigma));
+  hipLaunchKernelGGL(lg_step_kernel, dim3((per + 255) / 256, nwin), dim3(256), 0, st, g.size, g.channels,
+                     canvas, canvas_w, origins, widx, a_post, c_euler, w1d, slots, mode, dout);
+  TD_LAUNCHED();
+}
+
+}  // namespace td

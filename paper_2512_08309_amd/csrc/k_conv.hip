@@ -1,0 +1,257 @@
+// Implicit-GEMM convolution on CDNA4 matrix cores in FP32
+// (v_mfma_f32_16x16x4_f32, FP32 accumulation), batched over windows.
+//
+// GEMM view (activations NHWC, one image per window):
+//   M = windows * h * w output pixels, N = C_out, K = taps * C_in,
+//   out[m][n] = bias[n] + res[m][n] + sum_k act(A[m][k]) * Wt[k][n]
+// where A is the shifted input (3x3 with zero padding, or 1x1), read
+// through a virtual channel concat of two tensors (decoder skip
+// connections), with optional nearest 2x upsampling of the first
+// (decoder resolution change) and an optional GroupNorm affine + SiLU
+// prologue applied while staging into LDS (padding stays exactly zero).
+//
+// Tiling: 128 (M) x BN (N) per 256-thread workgroup, 4 waves of 64 lanes in
+// a WM x WN grid; K advances 16 input channels of one tap per stage, double
+// buffered in LDS.  Each lane of an MFMA reads its TM (resp. TN) operands
+// for all of its wave's tiles with one vector LDS read: tile r of a wave
+// owns rows {TM*i + r}, so the rows a lane needs are contiguous.  The
+// K-loop order is fixed (tap-major, then channel chunks), so every output
+// element is reduced in the same order whatever the batch composition:
+// results are batch-invariant, which the bit-exact seed consistency of the
+// sampler relies on.
+//
+// Workgroups are remapped so that each XCD (blockIdx % 8) walks a
+// contiguous range of tiles: neighbouring N tiles of one M tile share the
+// activation rows in that XCD's L2.
+#include "td_internal.h"
+
+namespace td {
+namespace {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float silu_f(float v) { return __fdividef(v, 1.0f + __expf(-v)); }
+
+template <int BN, int WM, int WN>
+__global__ __launch_bounds__(256, 2) void conv_kernel(ConvArgs a, int n_tiles_n) {
+  constexpr int BM = 128, BK = 16;
+  constexpr int TM = BM / WM / 16, TN = BN / WN / 16;
+  constexpr int AS = BM + 4, BS = BN + 4;
+  constexpr int NBL = (BK * BN / 4 + 255) / 256;  // float4 B loads per thread
+  __shared__ __attribute__((aligned(16))) float As[2][BK * AS];
+  __shared__ __attribute__((aligned(16))) float Bs[2][BK * BS];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WM, wn = wave / WM;
+
+  int bid = blockIdx.x;
+  const int nblk = gridDim.x;
+  const int tile = ((nblk & 7) == 0) ? (bid & 7) * (nblk >> 3) + (bid >> 3) : bid;
+  const int tn = tile % n_tiles_n, tm = tile / n_tiles_n;
+  const int m0 = tm * BM, n0 = tn * BN;
+
+  const int lw = a.lw, lh = a.lh;
+  const int W = 1 << lw, H = 1 << lh, lhw = lw + lh;
+  const int M = a.nb << lhw;
+  const int cin = a.c0 + a.c1;
+  const int cchunks = cin / BK;
+  const int nchunks = a.taps * cchunks;
+
+  // Per-thread A staging slots: 2 float4 (pixel am, channel quad akq).
+  int ab[2], ay[2], ax[2], akq[2], aml[2];
+  bool aval[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    int e = tid + 256 * i;
+    aml[i] = e % BM;
+    akq[i] = e / BM;
+    int m = m0 + aml[i];
+    aval[i] = m < M;
+    int mm = aval[i] ? m : 0;
+    ab[i] = mm >> lhw;
+    int r = mm & ((1 << lhw) - 1);
+    ay[i] = r >> lw;
+    ax[i] = r & (W - 1);
+  }
+
+  f4v ra[2], rb[NBL];
+
+  auto load_chunk = [&](int c) {
+    int tap = c / cchunks;
+    int ci0 = (c - tap * cchunks) * BK;
+    int dy = 0, dx = 0;
+    if (a.taps == 9) { dy = tap / 3 - 1; dx = tap % 3 - 1; }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      int yy = ay[i] + dy, xx = ax[i] + dx;
+      bool ok = aval[i] && yy >= 0 && yy < H && xx >= 0 && xx < W;
+      int ci = ci0 + 4 * akq[i];
+      f4v v = {0.f, 0.f, 0.f, 0.f};
+      if (ok) {
+        const float* p;
+        if (ci < a.c0) {
+          if (a.up0)
+            p = a.src0 + ((((size_t)ab[i] << (lhw - 2)) + ((size_t)(yy >> 1) << (lw - 1)) + (xx >> 1)) * a.c0 + ci);
+          else
+            p = a.src0 + ((((size_t)ab[i] << lhw) + ((size_t)yy << lw) + xx) * a.c0 + ci);
+        } else {
+          p = a.src1 + ((((size_t)ab[i] << lhw) + ((size_t)yy << lw) + xx) * a.c1 + (ci - a.c0));
+        }
+        v = *reinterpret_cast<const f4v*>(p);
+      }
+      ra[i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < NBL; ++i) {
+      int e = tid + 256 * i;
+      if (e < BK * BN / 4) {
+        int row = e / (BN / 4), c4 = e % (BN / 4);
+        rb[i] = *reinterpret_cast<const f4v*>(a.wt + ((size_t)(tap * cin + ci0 + row) * a.cout + n0 + 4 * c4));
+      }
+    }
+  };
+
+  auto store_chunk = [&](int c, int buf) {
+    int tap = c / cchunks;
+    int ci0 = (c - tap * cchunks) * BK;
+    int dy = 0, dx = 0;
+    if (a.taps == 9) { dy = tap / 3 - 1; dx = tap % 3 - 1; }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      f4v v = ra[i];
+      if (a.act) {
+        int yy = ay[i] + dy, xx = ax[i] + dx;
+        bool ok = aval[i] && yy >= 0 && yy < H && xx >= 0 && xx < W;
+        if (ok) {
+          int ci = ci0 + 4 * akq[i];
+          f4v s = *reinterpret_cast<const f4v*>(a.gn_scale + (size_t)ab[i] * cin + ci);
+          f4v t = *reinterpret_cast<const f4v*>(a.gn_shift + (size_t)ab[i] * cin + ci);
+          v = v * s + t;
+          if (a.act == 2) {
+            v.x = silu_f(v.x); v.y = silu_f(v.y); v.z = silu_f(v.z); v.w = silu_f(v.w);
+          }
+        }
+      }
+      float* dst = &As[buf][(4 * akq[i]) * AS + aml[i]];
+      dst[0] = v.x;
+      dst[AS] = v.y;
+      dst[2 * AS] = v.z;
+      dst[3 * AS] = v.w;
+    }
+#pragma unroll
+    for (int i = 0; i < NBL; ++i) {
+      int e = tid + 256 * i;
+      if (e < BK * BN / 4) {
+        int row = e / (BN / 4), c4 = e % (BN / 4);
+        *reinterpret_cast<f4v*>(&Bs[buf][row * BS + 4 * c4]) = rb[i];
+      }
+    }
+  };
+
+  f4v acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = (f4v){0.f, 0.f, 0.f, 0.f};
+
+  load_chunk(0);
+  store_chunk(0, 0);
+  __syncthreads();
+
+  const int arow = wm * (BM / WM) + TM * (lane & 15);
+  const int brow = wn * (BN / WN) + TN * (lane & 15);
+  const int kl = lane >> 4;
+
+  for (int c = 0; c < nchunks; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nchunks) load_chunk(c + 1);
+    const float* Ab = As[buf];
+    const float* Bb = Bs[buf];
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      const int krow = kk * 4 + kl;
+      float av[TM], bv[TN];
+      if constexpr (TM == 4) {
+        f4v t = *reinterpret_cast<const f4v*>(&Ab[krow * AS + arow]);
+        av[0] = t.x; av[1] = t.y; av[2] = t.z; av[3] = t.w;
+      } else {
+#pragma unroll
+        for (int r = 0; r < TM; ++r) av[r] = Ab[krow * AS + arow + r];
+      }
+      if constexpr (TN == 4) {
+        f4v t = *reinterpret_cast<const f4v*>(&Bb[krow * BS + brow]);
+        bv[0] = t.x; bv[1] = t.y; bv[2] = t.z; bv[3] = t.w;
+      } else {
+#pragma unroll
+        for (int r = 0; r < TN; ++r) bv[r] = Bb[krow * BS + brow + r];
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    if (c + 1 < nchunks) store_chunk(c + 1, buf ^ 1);
+    __syncthreads();
+  }
+
+  // Epilogue: lane holds D[4*(lane/16)+v][lane%16] of every tile.
+  const int nb0 = n0 + brow;
+  float bias_v[TN];
+#pragma unroll
+  for (int j = 0; j < TN; ++j) bias_v[j] = a.bias ? a.bias[nb0 + j] : 0.f;
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int m = m0 + wm * (BM / WM) + TM * (4 * kl + v) + i;
+      if (m >= M) continue;
+      float o[TN];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) o[j] = acc[i][j][v] + bias_v[j];
+      const size_t off = (size_t)m * a.cout + nb0;
+      if (a.res) {
+        if constexpr (TN == 4) {
+          f4v r = *reinterpret_cast<const f4v*>(a.res + off);
+          o[0] += r.x; o[1] += r.y; o[2] += r.z; o[3] += r.w;
+        } else {
+#pragma unroll
+          for (int j = 0; j < TN; ++j) o[j] += a.res[off + j];
+        }
+      }
+      if constexpr (TN == 4) {
+        *reinterpret_cast<f4v*>(a.out + off) = (f4v){o[0], o[1], o[2], o[3]};
+      } else {
+#pragma unroll
+        for (int j = 0; j < TN; ++j) a.out[off + j] = o[j];
+      }
+    }
+  }
+}
+
+template <int BN, int WM, int WN>
+void launch_cfg(hipStream_t st, const ConvArgs& a) {
+  int M = a.nb << (a.lh + a.lw);
+  int mt = (M + 127) / 128;
+  int nt = a.cout / BN;
+  hipLaunchKernelGGL((conv_kernel<BN, WM, WN>), dim3(mt * nt), dim3(256), 0, st, a, nt);
+  TD_LAUNCHED();
+}
+
+}  // namespace
+
+void launch_conv(hipStream_t st, const ConvArgs& a) {
+  int cin = a.c0 + a.c1;
+  TD_CHECK(cin % 16 == 0 && (a.c1 == 0 || a.c0 % 16 == 0), -5, "conv: input channels must be multiples of 16");
+  TD_CHECK(a.taps == 9 || a.taps == 1, -5, "conv: taps must be 9 or 1");
+  TD_CHECK(!a.up0 || (a.lh >= 1 && a.lw >= 1), -5, "conv: upsampled source needs h, w >= 2");
+  TD_CHECK(a.lh + a.lw <= 20, -5, "conv: image too large");
+  if (a.nb == 0) return;
+  if (a.cout % 128 == 0) launch_cfg<128, 2, 2>(st, a);
+  else if (a.cout == 64) launch_cfg<64, 2, 2>(st, a);
+  else if (a.cout == 32) launch_cfg<32, 4, 1>(st, a);
+  else if (a.cout == 16) launch_cfg<16, 4, 1>(st, a);
+  else TD_CHECK(false, -5, "conv: unsupported output channel count");
+}
+
+}  // namespace td

@@ -1,0 +1,129 @@
+// GroupNorm statistics per (window, group), turned into a per-channel
+// affine (scale = gamma * rstd, shift = beta - mean * scale) that the
+// consuming convolution applies while staging its input.
+//
+// Input is the same virtual tensor the convolution reads: concat of src0
+// (optionally stored at half resolution and nearest-upsampled; its pixels
+// then count four times, which leaves mean and biased variance unchanged)
+// and src1.  Sums and sums of squares are accumulated in FP64 in a fixed
+// order (per thread, then per channel over threads, then per group, then
+// over pixel chunks), so the statistics are deterministic and free of the
+// cancellation that FP32 E[x^2] - E[x]^2 would suffer.  The pass reads the
+// tensor once: HBM-bound.
+#include "td_internal.h"
+
+namespace td {
+namespace {
+
+constexpr int kMaxCin = 1024;
+
+__host__ __device__ inline int gn_nchunk(int lh, int lw, int cin, int up0) {
+  long hw = 1L << (lh + lw);
+  int n = 1;
+  while (n < 16 && hw * cin / (2L * n) >= 32768 && hw / (2L * n) >= (up0 ? 4 : 1)) n *= 2;
+  return n;
+}
+
+__global__ __launch_bounds__(256) void gn_partial_kernel(GnArgs a, int nchunk) {
+  __shared__ double ls[256 * 4];
+  __shared__ double lq[256 * 4];
+  __shared__ double cs[kMaxCin];
+  __shared__ double cq[kMaxCin];
+  const int tid = threadIdx.x;
+  const int b = blockIdx.y, chunk = blockIdx.x;
+  const int hw = 1 << (a.lh + a.lw);
+  const int cin = a.c0 + a.c1;
+  for (int seg = 0; seg < 2; ++seg) {
+    const int Cs = seg == 0 ? a.c0 : a.c1;
+    if (Cs == 0) continue;
+    const float* src = seg == 0 ? a.src0 : a.src1;
+    const int up = (seg == 0 && a.up0) ? 1 : 0;
+    const int npix_img = up ? hw >> 2 : hw;
+    const int per = npix_img / nchunk;
+    const int p0 = chunk * per;
+    const int nq = Cs / 4, npl = 256 / nq;
+    const int q = tid % nq, pl = tid / nq;
+    double s[4] = {0, 0, 0, 0}, sq[4] = {0, 0, 0, 0};
+    const float* base = src + ((size_t)b * npix_img + p0) * Cs + 4 * q;
+    for (int p = pl; p < per; p += npl) {
+      float4 v = *reinterpret_cast<const float4*>(base + (size_t)p * Cs);
+      double d0 = v.x, d1 = v.y, d2 = v.z, d3 = v.w;
+      s[0] += d0; s[1] += d1; s[2] += d2; s[3] += d3;
+      sq[0] += d0 * d0; sq[1] += d1 * d1; sq[2] += d2 * d2; sq[3] += d3 * d3;
+    }
+    for (int j = 0; j < 4; ++j) {
+      ls[tid * 4 + j] = s[j];
+      lq[tid * 4 + j] = sq[j];
+    }
+    __syncthreads();
+    const double wgt = up ? 4.0 : 1.0;
+    for (int c = tid; c < Cs; c += 256) {
+      double ts = 0, tq = 0;
+      for (int l = 0; l < npl; ++l) {
+        ts += ls[(l * nq + c / 4) * 4 + (c & 3)];
+        tq += lq[(l * nq + c / 4) * 4 + (c & 3)];
+      }
+      const int cg = (seg == 0 ? 0 : a.c0) + c;
+      cs[cg] = ts * wgt;
+      cq[cg] = tq * wgt;
+    }
+    __syncthreads();
+  }
+  const int cgp = cin / a.groups;
+  for (int g = tid; g < a.groups; g += 256) {
+    double ts = 0, tq = 0;
+    for (int c = g * cgp; c < (g + 1) * cgp; ++c) {
+      ts += cs[c];
+      tq += cq[c];
+    }
+    double* o = a.partial + (((size_t)b * nchunk + chunk) * a.groups + g) * 2;
+    o[0] = ts;
+    o[1] = tq;
+  }
+}
+
+__global__ __launch_bounds__(256) void gn_finalize_kernel(GnArgs a, int nchunk) {
+  const int b = blockIdx.x;
+  const int cin = a.c0 + a.c1;
+  const int cgp = cin / a.groups;
+  const double n = (double)(1L << (a.lh + a.lw)) * cgp;
+  for (int c = threadIdx.x; c < cin; c += blockDim.x) {
+    const int g = c / cgp;
+    double ts = 0, tq = 0;
+    for (int k = 0; k < nchunk; ++k) {
+      const double* p = a.partial + (((size_t)b * nchunk + k) * a.groups + g) * 2;
+      ts += p[0];
+      tq += p[1];
+    }
+    double mean = ts / n;
+    double var = tq / n - mean * mean;
+    if (var < 0) var = 0;
+    double rstd = 1.0 / sqrt(var + (double)a.eps);
+    double sc = (double)a.gamma[c] * rstd;
+    a.scale[(size_t)b * cin + c] = (float)sc;
+    a.shift[(size_t)b * cin + c] = (float)((double)a.beta[c] - mean * sc);
+  }
+}
+
+}  // namespace
+
+size_t gn_partial_doubles(int nb, int lh, int lw, int cin, int groups) {
+  return (size_t)nb * 16 * groups * 2;
+}
+
+void launch_gn(hipStream_t st, const GnArgs& a) {
+  const int cin = a.c0 + a.c1;
+  TD_CHECK(cin <= kMaxCin && cin % a.groups == 0, -5, "groupnorm: bad channel/group count");
+  for (int cs : {a.c0, a.c1}) {
+    if (!cs) continue;
+    TD_CHECK(cs % 4 == 0 && 256 % (cs / 4) == 0, -5, "groupnorm: segment channels must divide 1024 in quads");
+  }
+  if (!a.nb) return;
+  const int nchunk = gn_nchunk(a.lh, a.lw, cin, a.up0);
+  hipLaunchKernelGGL(gn_partial_kernel, dim3(nchunk, a.nb), dim3(256), 0, st, a, nchunk);
+  TD_LAUNCHED();
+  hipLaunchKernelGGL(gn_finalize_kernel, dim3(a.nb), dim3(256), 0, st, a, nchunk);
+  TD_LAUNCHED();
+}
+
+}  // namespace td

@@ -1,0 +1,162 @@
+// Laplacian decode of a terrain latent (Sec. 5.2) with the signed-sqrt
+// inverse (signed-sqrt appendix).
+//
+//   L = sigma_low * J0[.., 0]                   low band (signed-sqrt metres)
+//   Hres(X, Y) = sum_k sigma_res * J0[Y/8, X/8, k] * beta_k(X mod 8, Y mod 8)
+//                (orthonormal 8x8 DCT-II atoms (1,0), (0,1), (1,1); k = 1..3)
+//   P = up8(L) + Hres,  L_hat = G5 * down8(P),  z = up8(L_hat) + Hres,
+//   elevation = sign(z) z^2
+// up8 is bilinear with half-pixel centres (xi = (X + 0.5)/8 - 0.5), down8 the
+// 8x8 block mean, G5 the separable sigma = 5 Gaussian (radius 15) at latent
+// resolution.  There is no padding: the latent covers a 17-pixel apron.
+//
+// Stages: (1) down8(P) per latent block, evaluating its 64 pixels in
+// registers; (2) vertical then (3) horizontal 31-tap blur at latent
+// resolution; (4) the full-resolution pass, one thread per output pixel,
+// which is the HBM-bound one (4 B written per pixel, the latent read once
+// through the caches).
+#include "td_internal.h"
+
+namespace td {
+namespace {
+
+struct Span {
+  int64_t xl, xh, yl, yh;   // latent range of L_hat read by up8
+};
+
+__host__ __device__ inline int64_t floordiv(int64_t a, int64_t b) {
+  int64_t q = a / b;
+  return (q * b > a) ? q - 1 : q;
+}
+
+inline Span span_of(const DecodeArgs& a) {
+  Span s;
+  s.xl = floordiv(2 * a.X0 - 7, 16);
+  s.xh = floordiv(2 * (a.X0 + a.W - 1) - 7, 16) + 1;
+  s.yl = floordiv(2 * a.Y0 - 7, 16);
+  s.yh = floordiv(2 * (a.Y0 + a.H - 1) - 7, 16) + 1;
+  return s;
+}
+
+// bilinear sample of L (= sigma_low * channel 0) at full-res pixel with
+// coordinates relative to 8*lx0, 8*ly0 (both >= 8 by the apron).
+__device__ __forceinline__ float up8_latent(const float* lat, int lw, int C, float sl, int Xr, int Yr) {
+  int ix = (2 * Xr - 7) >> 4, iy = (2 * Yr - 7) >> 4;
+  float fx = (float)((2 * Xr - 7) - 16 * ix) * 0.0625f;
+  float fy = (float)((2 * Yr - 7) - 16 * iy) * 0.0625f;
+  const float* r0 = lat + ((size_t)iy * lw + ix) * C;
+  const float* r1 = r0 + (size_t)lw * C;
+  float a0 = (1.f - fy) * r0[0] + fy * r1[0];
+  float a1 = (1.f - fy) * r0[C] + fy * r1[C];
+  return sl * ((1.f - fx) * a0 + fx * a1);
+}
+
+__device__ __forceinline__ float residual_at(const float* lat, int lw, int C, float sr, const float* atoms,
+                                             int Xr, int Yr) {
+  if (C < 2) return 0.f;
+  const float* p = lat + ((size_t)(Yr >> 3) * lw + (Xr >> 3)) * C;
+  int a = (Yr & 7) * 8 + (Xr & 7);
+  float h = 0.f;
+  int nk = C - 1 < 3 ? C - 1 : 3;
+  for (int k = 0; k < nk; ++k) h += p[1 + k] * atoms[k * 64 + a];
+  return sr * h;
+}
+
+// (1) D(bx, by) = mean of P over latent block (bx, by); block origin
+// relative to the latent origin is (bx0 + i, by0 + j).
+__global__ __launch_bounds__(256) void down_p_kernel(const float* __restrict__ lat, int lw, int C, float sl,
+                                                     float sr, const float* __restrict__ atoms, int bx0,
+                                                     int by0, int nx, int ny, float* __restrict__ D) {
+  int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= nx * ny) return;
+  int j = e / nx, i = e % nx;
+  int X0r = (bx0 + i) * 8, Y0r = (by0 + j) * 8;
+  float s = 0.f;
+  for (int yy = 0; yy < 8; ++yy) {
+    float row = 0.f;
+    for (int xx = 0; xx < 8; ++xx) {
+      int Xr = X0r + xx, Yr = Y0r + yy;
+      row += up8_latent(lat, lw, C, sl, Xr, Yr) + residual_at(lat, lw, C, sr, atoms, Xr, Yr);
+    }
+    s += row;
+  }
+  D[e] = s * (1.0f / 64.0f);
+}
+
+// (2) vertical blur: out[j][i] = sum_t g[t] in[j + t][i], out rows ny_out
+__global__ __launch_bounds__(256) void blur_v_kernel(const float* __restrict__ in, int nx, int ny_out,
+                                                     const float* __restrict__ g, int R, float* __restrict__ out) {
+  int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= nx * ny_out) return;
+  int j = e / nx, i = e % nx;
+  float s = 0.f;
+  for (int t = 0; t <= 2 * R; ++t) s += g[t] * in[(size_t)(j + t) * nx + i];
+  out[e] = s;
+}
+
+// (3) horizontal blur: out[j][i] = sum_t g[t] in[j][i + t], in width nx_in
+__global__ __launch_bounds__(256) void blur_h_kernel(const float* __restrict__ in, int nx_in, int nx_out, int ny,
+                                                     const float* __restrict__ g, int R, float* __restrict__ out) {
+  int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= nx_out * ny) return;
+  int j = e / nx_out, i = e % nx_out;
+  float s = 0.f;
+  for (int t = 0; t <= 2 * R; ++t) s += g[t] * in[(size_t)j * nx_in + i + t];
+  out[e] = s;
+}
+
+// (4) full resolution: z = up8(L_hat) + Hres, elevation = sign(z) z^2.
+__global__ __launch_bounds__(256) void decode_out_kernel(const float* __restrict__ lat, int lw, int C, float sr,
+                                                         const float* __restrict__ atoms,
+                                                         const float* __restrict__ lhat, int nlx, int hx0,
+                                                         int hy0, int xo, int yo, int W, int H,
+                                                         float* __restrict__ out) {
+  int X = blockIdx.x * 256 + threadIdx.x;
+  int Y = blockIdx.y;
+  if (X >= W) return;
+  int Xr = xo + X, Yr = yo + Y;   // relative to 8*lx0, 8*ly0
+  int ix = ((2 * Xr - 7) >> 4) - hx0, iy = ((2 * Yr - 7) >> 4) - hy0;
+  float fx = (float)((2 * Xr - 7) - 16 * ((2 * Xr - 7) >> 4)) * 0.0625f;
+  float fy = (float)((2 * Yr - 7) - 16 * ((2 * Yr - 7) >> 4)) * 0.0625f;
+  const float* r0 = lhat + (size_t)iy * nlx + ix;
+  float a0 = (1.f - fy) * r0[0] + fy * r0[nlx];
+  float a1 = (1.f - fy) * r0[1] + fy * r0[nlx + 1];
+  float z = (1.f - fx) * a0 + fx * a1 + residual_at(lat, lw, C, sr, atoms, Xr, Yr);
+  out[(size_t)Y * W + X] = (z < 0.f ? -z : z) * z;
+}
+
+}  // namespace
+
+size_t decode_work_floats(const DecodeArgs& a) {
+  Span s = span_of(a);
+  size_t nx = (size_t)(s.xh - s.xl + 1 + 2 * a.radius), ny = (size_t)(s.yh - s.yl + 1 + 2 * a.radius);
+  return nx * ny;
+}
+
+void launch_decode(hipStream_t st, const DecodeArgs& a) {
+  Span s = span_of(a);
+  const int R = a.radius;
+  // latent needed: [xl - R - 1, xh + R + 1] (bilinear inside P) and blocks of the output
+  TD_CHECK(s.xl - R - 1 >= a.lx0 && s.yl - R - 1 >= a.ly0 && s.xh + R + 1 < a.lx0 + a.lw &&
+               s.yh + R + 1 < a.ly0 + a.lh,
+           -1, "decode: latent does not cover the 17-pixel apron");
+  const int nxD = (int)(s.xh - s.xl + 1 + 2 * R), nyD = (int)(s.yh - s.yl + 1 + 2 * R);
+  const int nx = (int)(s.xh - s.xl + 1), ny = (int)(s.yh - s.yl + 1);
+  const int bx0 = (int)(s.xl - R - a.lx0), by0 = (int)(s.yl - R - a.ly0);
+  hipLaunchKernelGGL(down_p_kernel, dim3((nxD * nyD + 255) / 256), dim3(256), 0, st, a.latent, a.lw, a.C,
+                     a.sigma_low, a.sigma_res, a.atoms, bx0, by0, nxD, nyD, a.work0);
+  TD_LAUNCHED();
+  hipLaunchKernelGGL(blur_v_kernel, dim3((nxD * ny + 255) / 256), dim3(256), 0, st, a.work0, nxD, ny, a.taps, R,
+                     a.work1);
+  TD_LAUNCHED();
+  hipLaunchKernelGGL(blur_h_kernel, dim3((nx * ny + 255) / 256), dim3(256), 0, st, a.work1, nxD, nx, ny, a.taps, R,
+                     a.work0);
+  TD_LAUNCHED();
+  const int xo = (int)(a.X0 - 8 * a.lx0), yo = (int)(a.Y0 - 8 * a.ly0);
+  hipLaunchKernelGGL(decode_out_kernel, dim3((a.W + 255) / 256, a.H), dim3(256), 0, st, a.latent, a.lw, a.C,
+                     a.sigma_res, a.atoms, a.work0, nx, (int)(s.xl - a.lx0), (int)(s.yl - a.ly0), xo, yo, a.W,
+                     a.H, a.out);
+  TD_LAUNCHED();
+}
+
+}  // namespace td

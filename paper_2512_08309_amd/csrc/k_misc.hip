@@ -1,0 +1,286 @@
+// The thin layers of the window denoiser, which do not map onto matrix
+// cores: the 3x3 input conv (4 or 1 input channels, K = 36 or 9) with the
+// window gather and EDM input scaling fused in; the 3x3 output conv (4 or 1
+// output channels) fused with GroupNorm + SiLU on its input, the EDM output
+// preconditioning, the Euler step and the window weighting; 2x2 average
+// pooling; the noise-level embedding MLP; and 64-token window attention.
+// Together they are well under 1% of the denoiser's FLOPs.
+#include "td_internal.h"
+
+namespace td {
+namespace {
+
+__device__ __forceinline__ float silu_f(float v) { return __fdividef(v, 1.0f + __expf(-v)); }
+
+// ---------------------------------------------------------------- conv_in
+// One workgroup per (window, 16x16 output tile).  LDS: (16+2)^2 x cimg
+// scaled inputs (zero outside the window: the network pads with zeros),
+// and the 9 x cimg x c0 weights.
+template <int CI>
+__global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ canvas, int canvas_w,
+                                                      const int* __restrict__ origins, int H, int c0,
+                                                      float c_in, const float* __restrict__ wt,
+                                                      const float* __restrict__ bias, float* __restrict__ out) {
+  extern __shared__ float sm[];
+  float* halo = sm;                 // [18*18][CI]
+  float* wl = sm + 18 * 18 * CI;    // [9][CI][c0]
+  const int b = blockIdx.y;
+  const int tiles_x = H / 16;
+  const int tx0 = (blockIdx.x % tiles_x) * 16, ty0 = (blockIdx.x / tiles_x) * 16;
+  const int ox = origins[2 * b], oy = origins[2 * b + 1];
+  for (int e = threadIdx.x; e < 18 * 18 * CI; e += 256) {
+    int c = e % CI, p = e / CI;
+    int hy = p / 18, hx = p % 18;
+    int y = ty0 + hy - 1, x = tx0 + hx - 1;
+    float v = 0.f;
+    if (y >= 0 && y < H && x >= 0 && x < H) v = c_in * canvas[((size_t)(oy + y) * canvas_w + ox + x) * CI + c];
+    halo[e] = v;
+  }
+  for (int e = threadIdx.x; e < 9 * CI * c0; e += 256) wl[e] = wt[e];
+  __syncthreads();
+  for (int e = threadIdx.x; e < 256 * c0; e += 256) {
+    int co = e % c0, p = e / c0;
+    int py = p / 16, px = p % 16;
+    float acc = bias[co];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      int dy = t / 3, dx = t % 3;
+      const float* hp = halo + ((py + dy) * 18 + px + dx) * CI;
+#pragma unroll
+      for (int c = 0; c < CI; ++c) acc += hp[c] * wl[(t * CI + c) * c0 + co];
+    }
+    out[(((size_t)b * H + ty0 + py) * H + tx0 + px) * c0 + co] = acc;
+  }
+}
+
+// ---------------------------------------------------------------- conv_out
+template <int CO, int CK>
+__global__ __launch_bounds__(256) void conv_out_kernel(OutArgs a) {
+  __shared__ float halo[18 * 18 * (CK + 1)];
+  __shared__ float wl[9 * CK * CO];
+  const int b = blockIdx.y;
+  const int H = a.H, c0 = a.c0;
+  const int tiles_x = H / 16;
+  const int tx0 = (blockIdx.x % tiles_x) * 16, ty0 = (blockIdx.x / tiles_x) * 16;
+  const int py = threadIdx.x / 16, px = threadIdx.x % 16;
+  float acc[CO];
+#pragma unroll
+  for (int o = 0; o < CO; ++o) acc[o] = 0.f;
+  const float* hb = a.h + (size_t)b * H * H * c0;
+  const float* sc = a.gn_scale + (size_t)b * c0;
+  const float* sh = a.gn_shift + (size_t)b * c0;
+  for (int ci0 = 0; ci0 < c0; ci0 += CK) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < 18 * 18 * CK; e += 256) {
+      int c = e % CK, p = e / CK;
+      int hy = p / 18, hx = p % 18;
+      int y = ty0 + hy - 1, x = tx0 + hx - 1;
+      float v = 0.f;
+      if (y >= 0 && y < H && x >= 0 && x < H) {
+        float r = hb[((size_t)y * H + x) * c0 + ci0 + c];
+        v = silu_f(r * sc[ci0 + c] + sh[ci0 + c]);
+      }
+      halo[p * (CK + 1) + c] = v;
+    }
+    for (int e = threadIdx.x; e < 9 * CK * CO; e += 256) {
+      int o = e % CO, r = e / CO;
+      int c = r % CK, t = r / CK;
+      wl[e] = a.wt[((size_t)t * c0 + ci0 + c) * CO + o];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const float* hp = halo + ((py + t / 3) * 18 + px + t % 3) * (CK + 1);
+      const float* wp = wl + t * CK * CO;
+#pragma unroll 8
+      for (int c = 0; c < CK; ++c) {
+        float v = hp[c];
+#pragma unroll
+        for (int o = 0; o < CO; ++o) acc[o] += v * wp[c * CO + o];
+      }
+    }
+  }
+  const int u = tx0 + px, v = ty0 + py;
+  const int ox = a.origins[2 * b], oy = a.origins[2 * b + 1];
+  const float* xin = a.canvas + ((size_t)(oy + v) * a.canvas_w + ox + u) * CO;
+  const float wuv = a.w1d[u] * a.w1d[v];
+#pragma unroll
+  for (int o = 0; o < CO; ++o) {
+    float x = xin[o];
+    float F = acc[o] + a.bias[o];
+    float d = a.c_skip * x + a.c_out * F;
+    if (a.mode == 1) {
+      a.dout[(((size_t)b * H + v) * H + u) * CO + o] = d;
+    } else {
+      float phi = x + a.c_euler * (x - d);
+      a.slots[b][((size_t)v * H + u) * CO + o] = wuv * phi;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- avgpool
+__global__ __launch_bounds__(256) void avgpool_kernel(const float* __restrict__ in, float* __restrict__ out,
+                                                      int nb, int h, int w, int C) {
+  const int ho = h / 2, wo = w / 2, cq = C / 4;
+  size_t n = (size_t)nb * ho * wo * cq;
+  size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  int q = (int)(e % cq);
+  size_t p = e / cq;
+  int x = (int)(p % wo);
+  size_t r = p / wo;
+  int y = (int)(r % ho);
+  size_t b = r / ho;
+  const float* s = in + (((b * h + 2 * y) * w + 2 * x) * C) + 4 * q;
+  float4 a0 = *reinterpret_cast<const float4*>(s);
+  float4 a1 = *reinterpret_cast<const float4*>(s + C);
+  float4 a2 = *reinterpret_cast<const float4*>(s + (size_t)w * C);
+  float4 a3 = *reinterpret_cast<const float4*>(s + (size_t)w * C + C);
+  float4 o;
+  o.x = 0.25f * ((a0.x + a1.x) + (a2.x + a3.x));
+  o.y = 0.25f * ((a0.y + a1.y) + (a2.y + a3.y));
+  o.z = 0.25f * ((a0.z + a1.z) + (a2.z + a3.z));
+  o.w = 0.25f * ((a0.w + a1.w) + (a2.w + a3.w));
+  *reinterpret_cast<float4*>(out + p * C + 4 * q) = o;
+}
+
+// ---------------------------------------------------------------- embedding
+__global__ void gemv_kernel(const float* __restrict__ W, const float* __restrict__ b,
+                            const float* __restrict__ add, const float* __restrict__ in,
+                            float* __restrict__ out, int nk, int nin, int nout, int act) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nk * nout) return;
+  int k = e / nout, o = e % nout;
+  float acc = 0.f;
+  for (int i = 0; i < nin; ++i) acc += W[(size_t)o * nin + i] * in[(size_t)k * nin + i];
+  acc += b[o];
+  if (add) acc += add[o];
+  if (act) acc = acc / (1.0f + expf(-acc));
+  out[e] = acc;
+}
+
+__global__ void pos_emb_kernel(const float* __restrict__ cn, int nk, int dim, float log_period,
+                               float* __restrict__ out) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nk * dim) return;
+  int k = e / dim, j = e % dim, half = dim / 2;
+  int jj = j < half ? j : j - half;
+  float f = expf(-log_period * (float)jj / (float)half);
+  float arg = cn[k] * f;
+  out[e] = j < half ? cosf(arg) : sinf(arg);
+}
+
+// ---------------------------------------------------------------- attention
+// One workgroup per (window, head); T <= 64 tokens, head dim d <= 64.
+__global__ __launch_bounds__(256) void attention_kernel(const float* __restrict__ qkv, float* __restrict__ out,
+                                                        int T, int C, int heads) {
+  __shared__ float Q[64 * 65], Kt[64 * 65], V[64 * 65], S[64 * 65];
+  const int b = blockIdx.x, h = blockIdx.y;
+  const int d = C / heads;
+  const float* base = qkv + (size_t)b * T * 3 * C;
+  for (int e = threadIdx.x; e < T * d; e += 256) {
+    int t = e / d, i = e % d;
+    const float* row = base + (size_t)t * 3 * C + h * d + i;
+    Q[t * 65 + i] = row[0];
+    Kt[t * 65 + i] = row[C];
+    V[t * 65 + i] = row[2 * C];
+  }
+  __syncthreads();
+  const float scale = 1.0f / sqrtf((float)d);
+  for (int e = threadIdx.x; e < T * T; e += 256) {
+    int i = e / T, j = e % T;
+    float acc = 0.f;
+    for (int k = 0; k < d; ++k) acc += Q[i * 65 + k] * Kt[j * 65 + k];
+    S[i * 65 + j] = acc * scale;
+  }
+  __syncthreads();
+  if (threadIdx.x < T) {
+    float* r = S + threadIdx.x * 65;
+    float m = r[0];
+    for (int j = 1; j < T; ++j) m = fmaxf(m, r[j]);
+    float s = 0.f;
+    for (int j = 0; j < T; ++j) {
+      float ev = expf(r[j] - m);
+      r[j] = ev;
+      s += ev;
+    }
+    float inv = 1.0f / s;
+    for (int j = 0; j < T; ++j) r[j] *= inv;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < T * d; e += 256) {
+    int i = e / d, k = e % d;
+    float acc = 0.f;
+    for (int j = 0; j < T; ++j) acc += S[i * 65 + j] * V[j * 65 + k];
+    out[((size_t)b * T + i) * C + h * d + k] = acc;
+  }
+}
+
+}  // namespace
+
+void launch_conv_in(hipStream_t st, const float* canvas, int canvas_w, const int* origins, int nwin, int H,
+                    int cimg, int c0, float c_in, const float* wt, const float* bias, float* out) {
+  if (!nwin) return;
+  TD_CHECK(H % 16 == 0, -5, "conv_in: window size must be a multiple of 16");
+  dim3 grid((H / 16) * (H / 16), nwin);
+  size_t shm = (18 * 18 * cimg + 9 * cimg * c0) * sizeof(float);
+  TD_CHECK(shm <= 64 * 1024, -5, "conv_in: too many channels");
+  if (cimg == 4)
+    hipLaunchKernelGGL(conv_in_kernel<4>, grid, dim3(256), shm, st, canvas, canvas_w, origins, H, c0, c_in, wt,
+                       bias, out);
+  else if (cimg == 1)
+    hipLaunchKernelGGL(conv_in_kernel<1>, grid, dim3(256), shm, st, canvas, canvas_w, origins, H, c0, c_in, wt,
+                       bias, out);
+  else
+    TD_CHECK(false, -5, "conv_in: latent channels must be 1 or 4");
+  TD_LAUNCHED();
+}
+
+void launch_conv_out(hipStream_t st, const OutArgs& a) {
+  if (!a.nb) return;
+  TD_CHECK(a.H % 16 == 0, -5, "conv_out: window size must be a multiple of 16");
+  dim3 grid((a.H / 16) * (a.H / 16), a.nb);
+  if (a.cimg == 4 && a.c0 % 32 == 0)
+    hipLaunchKernelGGL((conv_out_kernel<4, 32>), grid, dim3(256), 0, st, a);
+  else if (a.cimg == 4 && a.c0 % 16 == 0)
+    hipLaunchKernelGGL((conv_out_kernel<4, 16>), grid, dim3(256), 0, st, a);
+  else if (a.cimg == 1 && a.c0 % 16 == 0)
+    hipLaunchKernelGGL((conv_out_kernel<1, 16>), grid, dim3(256), 0, st, a);
+  else
+    TD_CHECK(false, -5, "conv_out: unsupported channel counts");
+  TD_LAUNCHED();
+}
+
+void launch_avgpool(hipStream_t st, const float* in, float* out, int nb, int h, int w, int C) {
+  TD_CHECK(C % 4 == 0, -5, "avgpool: channels must be a multiple of 4");
+  size_t n = (size_t)nb * (h / 2) * (w / 2) * (C / 4);
+  if (!n) return;
+  hipLaunchKernelGGL(avgpool_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, out, nb, h, w, C);
+  TD_LAUNCHED();
+}
+
+void launch_gemv(hipStream_t st, const float* W, const float* b, const float* add, const float* in, float* out,
+                 int nk, int nin, int nout, int act_silu) {
+  int n = nk * nout;
+  if (!n) return;
+  hipLaunchKernelGGL(gemv_kernel, dim3((n + 255) / 256), dim3(256), 0, st, W, b, add, in, out, nk, nin, nout,
+                     act_silu);
+  TD_LAUNCHED();
+}
+
+void launch_pos_emb(hipStream_t st, const float* c_noise, int nk, int dim, float max_period, float* out) {
+  int n = nk * dim;
+  if (!n) return;
+  hipLaunchKernelGGL(pos_emb_kernel, dim3((n + 255) / 256), dim3(256), 0, st, c_noise, nk, dim,
+                     logf(max_period), out);
+  TD_LAUNCHED();
+}
+
+void launch_attention(hipStream_t st, const float* qkv, float* out, int nb, int T, int C, int heads) {
+  TD_CHECK(T <= 64 && C / heads <= 64 && C % heads == 0, -5, "attention: at most 64 tokens and head dim 64");
+  if (!nb) return;
+  hipLaunchKernelGGL(attention_kernel, dim3(nb, heads), dim3(256), 0, st, qkv, out, T, C, heads);
+  TD_LAUNCHED();
+}
+
+}  // namespace td

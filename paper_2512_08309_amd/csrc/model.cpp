@@ -1,0 +1,560 @@
+// Weight-file parsing, device weight layouts and the batched window
+// denoiser D(x; sigma) = c_skip x + c_out F(c_in x; c_noise) (EDM
+// preconditioning) with F a GroupNorm/SiLU UNet.  One call runs one
+// batched round of Phi evaluations for a level (Parallelization theorem of
+// the appendix: all windows of a level are independent).
+#include "model.h"
+
+#include <cmath>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+
+#include "json.h"
+
+namespace td {
+
+namespace {
+
+int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return (1 << l) == v ? l : -1;
+}
+
+std::vector<double> edm_sigmas(int K, double smax, double smin, double rho) {
+  std::vector<double> s;
+  if (K == 1) {
+    s = {smax, 0.0};
+    return s;
+  }
+  double a = std::pow(smax, 1.0 / rho), b = std::pow(smin, 1.0 / rho);
+  for (int k = 0; k < K; ++k) s.push_back(std::pow(a + (double)k / (K - 1) * (b - a), rho));
+  s.push_back(0.0);
+  return s;
+}
+
+}  // namespace
+
+Model::~Model() {
+  for (void* p : allocs_) (void)hipFree(p);
+  if (ws_) (void)hipFree(ws_);
+}
+
+float* Model::dalloc(size_t n) {
+  void* p = nullptr;
+  TD_HIP(hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(float)));
+  allocs_.push_back(p);
+  return (float*)p;
+}
+
+const float* Model::upload(const std::vector<float>& v) {
+  float* p = dalloc(v.size());
+  TD_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(float), hipMemcpyHostToDevice));
+  return p;
+}
+
+void Model::load(const std::string& path, hipStream_t st) {
+  std::ifstream f(path, std::ios::binary);
+  TD_CHECK(f.good(), -4, "cannot open weight file: " + path);
+  std::stringstream ss;
+  ss << f.rdbuf();
+  std::string raw = ss.str();
+  TD_CHECK(raw.size() >= 8 && raw.compare(0, 4, "TDW1") == 0, -5, "not a TDW1 weight file: " + path);
+  uint32_t n = 0;
+  std::memcpy(&n, raw.data() + 4, 4);
+  TD_CHECK((size_t)n + 8 <= raw.size(), -5, "weight file header truncated");
+  std::string htxt = raw.substr(8, n);
+  Json h = JsonParser(htxt).parse();
+  size_t data_start = (8 + (size_t)n + 63) / 64 * 64;
+
+  const Json& dn = h.at("denoiser");
+  d.kind = dn.at("kind").str();
+  d.C = (int)dn.at("in_channels").integer();
+  const Json& sp = h.at("sampler");
+  d.K = (int)sp.at("steps").integer();
+  d.smax = sp.at("sigma_max").num();
+  d.smin = sp.at("sigma_min").num();
+  d.rho = sp.at("rho").num();
+  d.sigma_data = sp.at("sigma_data").num();
+  const Json& wn = h.at("window");
+  d.H = (int)wn.at("size").integer();
+  d.S = (int)wn.at("stride").integer();
+  d.O = (int)wn.at("offset").integer();
+  d.win_eps = wn.at("eps").num();
+  const Json& dc = h.at("decode");
+  d.factor = (int)dc.at("factor").integer();
+  d.sigma_low = dc.at("sigma_low").num();
+  d.sigma_res = dc.at("sigma_res").num();
+  d.blur_sigma = dc.at("blur_sigma").num();
+  d.blur_radius = (int)dc.at("blur_radius").integer();
+  TD_CHECK(d.C >= 1 && d.K >= 1 && d.K <= 64 && d.H >= 1 && d.S >= 1 && d.H <= 4096, -5,
+           "weight header: bad sampler/window constants");
+  TD_CHECK(d.factor == 8 && d.blur_radius >= 0 && d.blur_radius <= 64, -5, "weight header: unsupported decode");
+  TD_CHECK(d.smax > d.smin && d.smin > 0 && d.rho > 0 && d.sigma_data > 0, -5, "weight header: bad schedule");
+  d.sched = edm_sigmas(d.K, d.smax, d.smin, d.rho);
+
+  // tensors
+  std::map<std::string, std::vector<float>> host;
+  std::map<std::string, std::vector<int>> shapes;
+  if (h.has("tensors")) {
+    for (const Json& e : h.at("tensors").arr()) {
+      std::vector<int> shp;
+      size_t cnt = 1;
+      for (const Json& x : e.at("shape").arr()) {
+        long long v = x.integer();
+        TD_CHECK(v >= 0 && v < (1LL << 31), -5, "weight header: bad tensor shape");
+        shp.push_back((int)v);
+        cnt *= (size_t)v;
+      }
+      long long off = e.at("offset").integer();
+      TD_CHECK(off >= 0 && data_start + (size_t)off + cnt * 4 <= raw.size(), -5,
+               "weight file truncated at tensor " + e.at("name").str());
+      std::vector<float> v(cnt);
+      std::memcpy(v.data(), raw.data() + data_start + off, cnt * 4);
+      host[e.at("name").str()] = std::move(v);
+      shapes[e.at("name").str()] = shp;
+      d.params += cnt;
+    }
+  }
+
+  // window weights w(u) = eps + (1-eps)(1 - |2u-(H-1)|/(H-1))  (Sec. 6 setup)
+  std::vector<float> w1(d.H);
+  for (int u = 0; u < d.H; ++u) {
+    double v = d.H == 1 ? 1.0 : d.win_eps + (1.0 - d.win_eps) * (1.0 - std::fabs(2.0 * u - (d.H - 1)) / (d.H - 1));
+    w1[u] = (float)v;
+  }
+  w1d_ = (float*)upload(w1);
+  // decode tables: Gaussian taps and DCT atoms
+  {
+    int R = d.blur_radius;
+    std::vector<double> g(2 * R + 1);
+    double s = 0;
+    for (int j = -R; j <= R; ++j) s += (g[j + R] = std::exp(-0.5 * (j / d.blur_sigma) * (j / d.blur_sigma)));
+    std::vector<float> gf(2 * R + 1);
+    for (int j = 0; j <= 2 * R; ++j) gf[j] = (float)(g[j] / s);
+    taps_ = (float*)upload(gf);
+    const double PI = 3.14159265358979323846;
+    double b0 = 1.0 / std::sqrt(8.0);
+    std::vector<float> at(3 * 64);
+    for (int y = 0; y < 8; ++y)
+      for (int x = 0; x < 8; ++x) {
+        double bx = 0.5 * std::cos(PI * (2 * x + 1) / 16.0), by = 0.5 * std::cos(PI * (2 * y + 1) / 16.0);
+        at[0 * 64 + y * 8 + x] = (float)(bx * b0);   // atom (1,0): varies along x
+        at[1 * 64 + y * 8 + x] = (float)(b0 * by);   // atom (0,1): varies along y
+        at[2 * 64 + y * 8 + x] = (float)(bx * by);   // atom (1,1)
+      }
+    atoms_ = (float*)upload(at);
+  }
+
+  if (d.kind == "linear_gaussian") {
+    d.prior_std = dn.at("prior_std").num();
+    TD_CHECK(d.prior_std > 0, -5, "weight header: prior_std must be positive");
+  } else if (d.kind == "unet") {
+    for (const Json& c : dn.at("channels").arr()) d.ch.push_back((int)c.integer());
+    d.nres = (int)dn.at("num_res_blocks").integer();
+    for (const Json& a : dn.at("attn_levels").arr()) d.attn_levels.push_back((int)a.integer());
+    d.mid_attn = dn.at("mid_attn").boolean();
+    d.heads = (int)dn.at("num_heads").integer();
+    d.groups = (int)dn.at("gn_groups").integer();
+    d.gn_eps = (float)dn.at("gn_eps").num();
+    d.emb_mult = (int)dn.at("emb_mult").integer();
+    d.pe_max_period = dn.at("pe_max_period").num();
+    TD_CHECK(!d.ch.empty() && d.nres >= 1 && d.heads >= 1 && d.groups >= 1, -5, "weight header: bad UNet");
+    TD_CHECK(ilog2(d.H) >= 4 && (d.H >> (d.ch.size() - 1)) >= 1, -5,
+             "UNet windows must be a power of two >= 16 and divisible by 2^(levels-1)");
+    build_unet(host, shapes, st);
+  } else {
+    throw Error{-5, "unknown denoiser kind: " + d.kind};
+  }
+  TD_HIP(hipStreamSynchronize(st));
+}
+
+void Model::build_unet(const std::map<std::string, std::vector<float>>& host,
+                       const std::map<std::string, std::vector<int>>& shapes, hipStream_t st) {
+  auto get = [&](const std::string& name, std::vector<int> shape) -> const std::vector<float>& {
+    auto it = host.find(name);
+    TD_CHECK(it != host.end(), -5, "weight file lacks tensor " + name);
+    TD_CHECK(shapes.at(name) == shape, -5, "tensor " + name + " has an unexpected shape");
+    return it->second;
+  };
+  // [co][ci][k][k] -> [tap][ci][co]
+  auto conv_layout = [&](const std::string& name, int co, int ci, int k) {
+    const std::vector<float>& w = get(name, {co, ci, k, k});
+    std::vector<float> r((size_t)k * k * ci * co);
+    for (int o = 0; o < co; ++o)
+      for (int i = 0; i < ci; ++i)
+        for (int t = 0; t < k * k; ++t) r[((size_t)t * ci + i) * co + o] = w[((size_t)o * ci + i) * k * k + t];
+    return upload(r);
+  };
+  auto vec = [&](const std::string& name, int n) { return upload(get(name, {n})); };
+
+  const int nl = (int)d.ch.size();
+  const int c0 = d.ch[0];
+  const int emb = d.emb_mult * c0;
+  conv_in_w_ = conv_layout("conv_in.weight", c0, d.C, 3);
+  conv_in_b_ = vec("conv_in.bias", c0);
+
+  // per-level embedding: pe -> lin1 -> SiLU -> lin2 -> SiLU, for every sigma_k
+  std::vector<float> cn(d.K);
+  for (int k = 0; k < d.K; ++k) cn[k] = (float)(0.25 * std::log(d.sched[k]));
+  const float* d_cn = upload(cn);
+  float* pe = dalloc((size_t)d.K * c0);
+  float* e1 = dalloc((size_t)d.K * emb);
+  float* e2 = dalloc((size_t)d.K * emb);
+  launch_pos_emb(st, d_cn, d.K, c0, (float)d.pe_max_period, pe);
+  const float* l1w = upload(get("emb.lin1.weight", {emb, c0}));
+  const float* l1b = vec("emb.lin1.bias", emb);
+  const float* l2w = upload(get("emb.lin2.weight", {emb, emb}));
+  const float* l2b = vec("emb.lin2.bias", emb);
+  launch_gemv(st, l1w, l1b, nullptr, pe, e1, d.K, c0, emb, 1);
+  launch_gemv(st, l2w, l2b, nullptr, e1, e2, d.K, emb, emb, 1);
+
+  std::vector<std::pair<std::string, int>> order;  // (prefix, cout) for bias table
+  auto make_rb = [&](const std::string& p, int cin, int cout) {
+    ResBlockW w;
+    w.cin = cin;
+    w.cout = cout;
+    w.gn1_g = vec(p + "gn1.weight", cin);
+    w.gn1_b = vec(p + "gn1.bias", cin);
+    w.w1 = conv_layout(p + "conv1.weight", cout, cin, 3);
+    w.gn2_g = vec(p + "gn2.weight", cout);
+    w.gn2_b = vec(p + "gn2.bias", cout);
+    w.w2 = conv_layout(p + "conv2.weight", cout, cout, 3);
+    w.b2 = vec(p + "conv2.bias", cout);
+    w.has_skip = cin != cout;
+    if (w.has_skip) {
+      w.wskip = conv_layout(p + "skip.weight", cout, cin, 1);
+      w.bskip = vec(p + "skip.bias", cout);
+    }
+    TD_CHECK(cin % d.groups == 0 && cout % d.groups == 0, -5, "GroupNorm groups must divide channels");
+    rb_[p] = w;
+    order.push_back({p, cout});
+  };
+  auto make_at = [&](const std::string& p, int C) {
+    AttnW w;
+    w.C = C;
+    w.gn_g = vec(p + "gn.weight", C);
+    w.gn_b = vec(p + "gn.bias", C);
+    w.wqkv = conv_layout(p + "qkv.weight", 3 * C, C, 1);
+    w.bqkv = vec(p + "qkv.bias", 3 * C);
+    w.wproj = conv_layout(p + "proj.weight", C, C, 1);
+    w.bproj = vec(p + "proj.bias", C);
+    at_[p] = w;
+  };
+  std::vector<int> skipc;
+  int c = c0;
+  for (int l = 0; l < nl; ++l)
+    for (int j = 0; j < d.nres; ++j) {
+      std::string p = "enc." + std::to_string(l) + "." + std::to_string(j) + ".";
+      make_rb(p, c, d.ch[l]);
+      c = d.ch[l];
+      if (d.attn_at(l)) make_at(p + "attn.", c);
+      skipc.push_back(c);
+    }
+  make_rb("mid.0.", c, c);
+  if (d.mid_attn) make_at("mid.attn.", c);
+  make_rb("mid.1.", c, c);
+  for (int l = nl - 1; l >= 0; --l)
+    for (int j = 0; j < d.nres; ++j) {
+      std::string p = "dec." + std::to_string(l) + "." + std::to_string(j) + ".";
+      int cs = skipc.back();
+      skipc.pop_back();
+      make_rb(p, c + cs, d.ch[l]);
+      c = d.ch[l];
+      if (d.attn_at(l)) make_at(p + "attn.", c);
+    }
+  out_gn_g_ = vec("out.gn.weight", c);
+  out_gn_b_ = vec("out.gn.bias", c);
+  out_w_ = conv_layout("out.conv.weight", d.C, c, 3);
+  out_b_ = vec("out.conv.bias", d.C);
+
+  // bias_eff[block][k][cout] = conv1.bias + Lin_emb(emb_k)
+  size_t total = 0;
+  for (auto& o : order) total += (size_t)d.K * o.second;
+  bias_eff_ = dalloc(total);
+  size_t off = 0;
+  for (auto& o : order) {
+    ResBlockW& w = rb_[o.first];
+    w.bias_off = off;
+    const float* ew = upload(get(o.first + "emb.weight", {o.second, emb}));
+    const float* eb = vec(o.first + "emb.bias", o.second);
+    const float* b1 = vec(o.first + "conv1.bias", o.second);
+    launch_gemv(st, ew, eb, b1, e2, bias_eff_ + off, d.K, emb, o.second, 0);
+    off += (size_t)d.K * o.second;
+  }
+}
+
+size_t Model::workspace_bytes_per_window() const {
+  if (d.kind != "unet") return 0;
+  size_t f = 0;
+  const int nl = (int)d.ch.size();
+  for (int l = 0; l < nl; ++l) {
+    size_t r2 = (size_t)(d.H >> l) * (d.H >> l);
+    size_t c = d.ch[l];
+    f += r2 * c * (4 + d.nres);                   // T R X Y + skips
+    if (l > 0) f += r2 * d.ch[l - 1];             // pooled input
+    if (d.attn_at(l) || (l == nl - 1 && d.mid_attn)) f += r2 * c * 4;  // qkv + attn out
+  }
+  f += 2 * 1024;                                  // GN scale/shift
+  return f * sizeof(float) + (size_t)16 * d.groups * 2 * sizeof(double);
+}
+
+void Model::ensure_workspace(int max_batch) {
+  if (d.kind != "unet" || max_batch <= ws_batch_) return;
+  if (ws_) {
+    TD_HIP(hipDeviceSynchronize());
+    TD_HIP(hipFree(ws_));
+    ws_ = nullptr;
+    ws_batch_ = 0;
+  }
+  size_t bytes = workspace_bytes_per_window() * (size_t)max_batch + 4096 * 64;
+  TD_HIP(hipMalloc(&ws_, bytes));
+  char* p = (char*)ws_;
+  auto take = [&](size_t nfloat) {
+    float* r = (float*)p;
+    p += (nfloat * sizeof(float) + 255) / 256 * 256;
+    return r;
+  };
+  const int nl = (int)d.ch.size();
+  lb_.assign(nl, LevelBufs{});
+  for (int l = 0; l < nl; ++l) {
+    size_t r2 = (size_t)(d.H >> l) * (d.H >> l) * max_batch;
+    size_t c = d.ch[l];
+    LevelBufs& b = lb_[l];
+    b.T = take(r2 * c);
+    b.R = take(r2 * c);
+    b.X = take(r2 * c);
+    b.Y = take(r2 * c);
+    b.S.clear();
+    for (int j = 0; j < d.nres; ++j) b.S.push_back(take(r2 * c));
+    b.P = l > 0 ? take(r2 * d.ch[l - 1]) : nullptr;
+    if (d.attn_at(l) || (l == nl - 1 && d.mid_attn)) {
+      b.Q = take(r2 * 3 * c);
+      b.O = take(r2 * c);
+    } else {
+      b.Q = b.O = nullptr;
+    }
+  }
+  gn_scale_ = take((size_t)max_batch * 1024);
+  gn_shift_ = take((size_t)max_batch * 1024);
+  gn_part_ = (double*)take((size_t)max_batch * 16 * d.groups * 2 * 2);
+  TD_CHECK((size_t)(p - (char*)ws_) <= bytes, -2, "workspace layout overflow");
+  ws_batch_ = max_batch;
+}
+
+void Model::gn(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int nb, int lh, int lw,
+               const float* g, const float* b) {
+  GnArgs a;
+  a.src0 = s0;
+  a.src1 = s1;
+  a.c0 = c0;
+  a.c1 = c1;
+  a.up0 = up0;
+  a.nb = nb;
+  a.lh = lh;
+  a.lw = lw;
+  a.groups = d.groups;
+  a.eps = d.gn_eps;
+  a.gamma = g;
+  a.beta = b;
+  a.partial = gn_part_;
+  a.scale = gn_scale_;
+  a.shift = gn_shift_;
+  launch_gn(st, a);
+}
+
+void Model::resblock(hipStream_t st, const ResBlockW& w, int k, const float* s0, int c0, int up0, const float* s1,
+                     int c1, int nb, int lvl, float* out) {
+  const int lr = ilog2(d.H >> lvl);
+  LevelBufs& B = lb_[lvl];
+  TD_CHECK(c0 + c1 == w.cin, -5, "resblock: channel mismatch");
+  gn(st, s0, c0, up0, s1, c1, nb, lr, lr, w.gn1_g, w.gn1_b);
+  ConvArgs a{};
+  a.src0 = s0;
+  a.src1 = s1;
+  a.c0 = c0;
+  a.c1 = c1;
+  a.up0 = up0;
+  a.gn_scale = gn_scale_;
+  a.gn_shift = gn_shift_;
+  a.act = 2;
+  a.nb = nb;
+  a.lh = lr;
+  a.lw = lr;
+  a.cout = w.cout;
+  a.taps = 9;
+  a.wt = w.w1;
+  a.bias = bias_eff_ + w.bias_off + (size_t)k * w.cout;
+  a.res = nullptr;
+  a.out = B.T;
+  launch_conv(st, a);
+  const float* res = s0;
+  if (w.has_skip) {
+    ConvArgs s = a;
+    s.gn_scale = s.gn_shift = nullptr;
+    s.act = 0;
+    s.taps = 1;
+    s.wt = w.wskip;
+    s.bias = w.bskip;
+    s.out = B.R;
+    launch_conv(st, s);
+    res = B.R;
+  } else {
+    TD_CHECK(c1 == 0 && !up0, -5, "identity skip needs a plain input");
+  }
+  gn(st, B.T, w.cout, 0, nullptr, 0, nb, lr, lr, w.gn2_g, w.gn2_b);
+  ConvArgs b2{};
+  b2.src0 = B.T;
+  b2.c0 = w.cout;
+  b2.gn_scale = gn_scale_;
+  b2.gn_shift = gn_shift_;
+  b2.act = 2;
+  b2.nb = nb;
+  b2.lh = lr;
+  b2.lw = lr;
+  b2.cout = w.cout;
+  b2.taps = 9;
+  b2.wt = w.w2;
+  b2.bias = w.b2;
+  b2.res = res;
+  b2.out = out;
+  launch_conv(st, b2);
+}
+
+void Model::attention(hipStream_t st, const AttnW& w, const float* in, int nb, int lvl, float* out) {
+  const int lr = ilog2(d.H >> lvl);
+  LevelBufs& B = lb_[lvl];
+  gn(st, in, w.C, 0, nullptr, 0, nb, lr, lr, w.gn_g, w.gn_b);
+  ConvArgs q{};
+  q.src0 = in;
+  q.c0 = w.C;
+  q.gn_scale = gn_scale_;
+  q.gn_shift = gn_shift_;
+  q.act = 1;
+  q.nb = nb;
+  q.lh = lr;
+  q.lw = lr;
+  q.cout = 3 * w.C;
+  q.taps = 1;
+  q.wt = w.wqkv;
+  q.bias = w.bqkv;
+  q.out = B.Q;
+  launch_conv(st, q);
+  launch_attention(st, B.Q, B.O, nb, 1 << (2 * lr), w.C, d.heads);
+  ConvArgs p{};
+  p.src0 = B.O;
+  p.c0 = w.C;
+  p.nb = nb;
+  p.lh = lr;
+  p.lw = lr;
+  p.cout = w.C;
+  p.taps = 1;
+  p.wt = w.wproj;
+  p.bias = w.bproj;
+  p.res = in;
+  p.out = out;
+  launch_conv(st, p);
+}
+
+void Model::run_batch(hipStream_t st, const WindowBatch& wb, int k) {
+  TD_CHECK(k >= 0 && k < d.K, -1, "sigma index out of range");
+  const double sigma = d.sched[k], sigma_next = d.sched[k + 1];
+  const double sd = d.sigma_data;
+  const double s2 = sigma * sigma + sd * sd;
+  const float c_skip = (float)(sd * sd / s2), c_out = (float)(sigma * sd / std::sqrt(s2));
+  const float c_in = (float)(1.0 / std::sqrt(s2)), c_euler = (float)((sigma_next - sigma) / sigma);
+  WinGeom g{d.H, d.S, d.C};
+  if (d.kind == "linear_gaussian") {
+    launch_lg_step(st, g, wb.canvas, wb.canvas_w, wb.d_origins, wb.d_widx, wb.n, d.prior_std, sigma,
+                   c_euler, w1d_, wb.d_slots, wb.mode, wb.dout);
+    return;
+  }
+  TD_CHECK(wb.n <= ws_batch_, -1, "batch larger than workspace");
+  const int nl = (int)d.ch.size();
+  const int nb = wb.n;
+  LevelBufs& L0 = lb_[0];
+  launch_conv_in(st, wb.canvas, wb.canvas_w, wb.d_origins, nb, d.H, d.C, d.ch[0], c_in, conv_in_w_, conv_in_b_,
+                 L0.X);
+  const float* h = L0.X;
+  int hc = d.ch[0];
+  for (int l = 0; l < nl; ++l) {
+    LevelBufs& B = lb_[l];
+    if (l > 0) {
+      int r = d.H >> (l - 1);
+      launch_avgpool(st, h, B.P, nb, r, r, hc);
+      h = B.P;
+    }
+    for (int j = 0; j < d.nres; ++j) {
+      std::string p = "enc." + std::to_string(l) + "." + std::to_string(j) + ".";
+      const ResBlockW& w = rb_.at(p);
+      if (d.attn_at(l)) {
+        resblock(st, w, k, h, hc, 0, nullptr, 0, nb, l, B.X);
+        attention(st, at_.at(p + "attn."), B.X, nb, l, B.S[j]);
+      } else {
+        resblock(st, w, k, h, hc, 0, nullptr, 0, nb, l, B.S[j]);
+      }
+      h = B.S[j];
+      hc = w.cout;
+    }
+  }
+  {
+    LevelBufs& B = lb_[nl - 1];
+    resblock(st, rb_.at("mid.0."), k, h, hc, 0, nullptr, 0, nb, nl - 1, B.X);
+    const float* m = B.X;
+    if (d.mid_attn) {
+      attention(st, at_.at("mid.attn."), B.X, nb, nl - 1, B.Y);
+      m = B.Y;
+    }
+    float* o = (m == B.X) ? B.Y : B.X;
+    resblock(st, rb_.at("mid.1."), k, m, hc, 0, nullptr, 0, nb, nl - 1, o);
+    h = o;
+  }
+  int hl = nl - 1;  // level h lives at
+  for (int l = nl - 1; l >= 0; --l) {
+    LevelBufs& B = lb_[l];
+    for (int j = 0; j < d.nres; ++j) {
+      std::string p = "dec." + std::to_string(l) + "." + std::to_string(j) + ".";
+      const ResBlockW& w = rb_.at(p);
+      const float* skip = B.S[d.nres - 1 - j];
+      int up0 = hl != l ? 1 : 0;
+      float* o = (h == B.X) ? B.Y : B.X;
+      if (d.attn_at(l)) {
+        float* tmp = (o == B.X) ? B.Y : B.X;
+        // attention input must not alias its output: resblock -> o, attention o -> tmp
+        resblock(st, w, k, h, hc, up0, skip, w.cin - hc, nb, l, o);
+        attention(st, at_.at(p + "attn."), o, nb, l, tmp);
+        h = tmp;
+      } else {
+        resblock(st, w, k, h, hc, up0, skip, w.cin - hc, nb, l, o);
+        h = o;
+      }
+      hc = w.cout;
+      hl = l;
+    }
+  }
+  gn(st, h, hc, 0, nullptr, 0, nb, ilog2(d.H), ilog2(d.H), out_gn_g_, out_gn_b_);
+  OutArgs oa{};
+  oa.h = h;
+  oa.gn_scale = gn_scale_;
+  oa.gn_shift = gn_shift_;
+  oa.nb = nb;
+  oa.H = d.H;
+  oa.c0 = hc;
+  oa.cimg = d.C;
+  oa.wt = out_w_;
+  oa.bias = out_b_;
+  oa.canvas = wb.canvas;
+  oa.canvas_w = wb.canvas_w;
+  oa.origins = wb.d_origins;
+  oa.c_skip = c_skip;
+  oa.c_out = c_out;
+  oa.c_euler = c_euler;
+  oa.w1d = w1d_;
+  oa.slots = wb.d_slots;
+  oa.mode = wb.mode;
+  oa.dout = wb.dout;
+  launch_conv_out(st, oa);
+}
+
+}  // namespace td

@@ -1,0 +1,120 @@
+// Loaded model: header constants, device weights in kernel layouts, the
+// window-denoiser executor and its workspace.
+#pragma once
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "td_internal.h"
+
+namespace td {
+
+struct ModelDesc {
+  std::string kind;        // "unet" or "linear_gaussian"
+  int C = 0;               // latent channels
+  // UNet
+  std::vector<int> ch;
+  int nres = 0;
+  std::vector<int> attn_levels;
+  bool mid_attn = false;
+  int heads = 1, groups = 1, emb_mult = 4;
+  float gn_eps = 1e-5f;
+  double pe_max_period = 10000.0;
+  // analytic denoiser
+  double prior_std = 0.5;
+  // sampler
+  int K = 0;
+  double smax = 80, smin = 0.002, rho = 7, sigma_data = 0.5;
+  std::vector<double> sched;  // sigma_0..sigma_{K-1}, 0
+  // windows
+  int H = 0, S = 0, O = 0;
+  double win_eps = 0.01;
+  // decode
+  int factor = 8, blur_radius = 15;
+  double sigma_low = 20, sigma_res = 2, blur_sigma = 5;
+  size_t params = 0;
+  bool attn_at(int l) const {
+    for (int a : attn_levels)
+      if (a == l) return true;
+    return false;
+  }
+};
+
+struct ResBlockW {
+  int cin = 0, cout = 0;
+  bool has_skip = false;
+  const float *gn1_g = nullptr, *gn1_b = nullptr, *w1 = nullptr, *gn2_g = nullptr, *gn2_b = nullptr;
+  const float *w2 = nullptr, *b2 = nullptr, *wskip = nullptr, *bskip = nullptr;
+  size_t bias_off = 0;     // offset of this block's [K][cout] table in bias_eff
+};
+
+struct AttnW {
+  int C = 0;
+  const float *gn_g = nullptr, *gn_b = nullptr, *wqkv = nullptr, *bqkv = nullptr, *wproj = nullptr,
+              *bproj = nullptr;
+};
+
+// Batch of windows for one denoiser round: inputs are read from a dense
+// canvas ([rows][canvas_w][C]) at per-window origins.
+struct WindowBatch {
+  const float* canvas = nullptr;
+  int canvas_w = 0;
+  const int* d_origins = nullptr;   // [n][2] device
+  const int* d_widx = nullptr;      // [n][2] device (window indices, analytic kind)
+  float* const* d_slots = nullptr;  // [n] device pointers, mode 0
+  float* dout = nullptr;            // mode 1: [n][H][H][C]
+  int n = 0;
+  int mode = 0;                     // 0: contributions W (x) Phi, 1: raw D
+};
+
+class Model {
+ public:
+  ModelDesc d;
+  ~Model();
+  void load(const std::string& path, hipStream_t st);
+  // Evaluate one batch (n <= max_batch) at schedule index k (sigma = sched[k]),
+  // Euler target sched[k+1].
+  void run_batch(hipStream_t st, const WindowBatch& b, int k);
+  size_t workspace_bytes_per_window() const;
+  void ensure_workspace(int max_batch);
+  int max_batch() const { return ws_batch_; }
+  const float* w1d() const { return w1d_; }
+  const float* decode_taps() const { return taps_; }
+  const float* decode_atoms() const { return atoms_; }
+
+ private:
+  std::vector<void*> allocs_;
+  std::map<std::string, const float*> t_;
+  float* w1d_ = nullptr;
+  float* taps_ = nullptr;
+  float* atoms_ = nullptr;
+  // unet
+  const float *conv_in_w_ = nullptr, *conv_in_b_ = nullptr, *out_gn_g_ = nullptr, *out_gn_b_ = nullptr;
+  const float *out_w_ = nullptr, *out_b_ = nullptr;
+  std::map<std::string, ResBlockW> rb_;
+  std::map<std::string, AttnW> at_;
+  float* bias_eff_ = nullptr;
+  // workspace
+  int ws_batch_ = 0;
+  void* ws_ = nullptr;
+  struct LevelBufs {
+    float *T, *R, *X, *Y, *P, *Q, *O;
+    std::vector<float*> S;
+  };
+  std::vector<LevelBufs> lb_;
+  float *gn_scale_ = nullptr, *gn_shift_ = nullptr;
+  double* gn_part_ = nullptr;
+
+  float* dalloc(size_t n);
+  const float* upload(const std::vector<float>& v);
+  void build_unet(const std::map<std::string, std::vector<float>>& host,
+                  const std::map<std::string, std::vector<int>>& shapes, hipStream_t st);
+  void gn(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int nb, int lh, int lw,
+          const float* g, const float* b);
+  void resblock(hipStream_t st, const ResBlockW& w, int k, const float* s0, int c0, int up0, const float* s1,
+                int c1, int nb, int lvl, float* out);
+  void attention(hipStream_t st, const AttnW& w, const float* in, int nb, int lvl, float* out);
+};
+
+}  // namespace td

@@ -1,0 +1,162 @@
+// Internal declarations shared by the host runtime and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+namespace td {
+
+// ---------------------------------------------------------------- errors --
+
+struct Error {
+  int status;
+  std::string msg;
+};
+
+#define TD_HIP(expr)                                                          \
+  do {                                                                        \
+    hipError_t e_ = (expr);                                                   \
+    if (e_ != hipSuccess) {                                                   \
+      throw ::td::Error{e_ == hipErrorOutOfMemory ? -2 : -3,                  \
+                        std::string(#expr) + ": " + hipGetErrorString(e_)};   \
+    }                                                                         \
+  } while (0)
+
+#define TD_CHECK(cond, status, msg)                                           \
+  do {                                                                        \
+    if (!(cond)) throw ::td::Error{(status), (msg)};                          \
+  } while (0)
+
+// Launch check: catches bad launch configurations immediately.
+#define TD_LAUNCHED() TD_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------- kernels --
+
+// Geometry of one level's window set relative to a dense canvas.
+struct WinGeom {
+  int size;       // window side H
+  int stride;     // s
+  int channels;   // C
+};
+
+// Counter-hash Gaussian noise scaled by `scale` on a region.  layout 0:
+// [h][w][C] with row pitch w*C; layout 1: planar [C][h][w].
+void launch_noise(hipStream_t st, uint64_t seed, int64_t x0, int64_t y0,
+                  int w, int h, int C, uint32_t step, float scale, int layout,
+                  float* out);
+
+// Blend of cached window contributions:
+//   out(p) = sum_i V_i(p - o_i) / sum_i W(p - o_i)   (0 where no window covers p)
+// Pixel p = (bx + rx, by + ry) for rx in [0,w), ry in [0,h); (bx, by) is the
+// origin of window (ix0, iy0).  ptrs[(iy-iy0)*nx + (ix-ix0)] -> [H][H][C].
+void launch_blend(hipStream_t st, const WinGeom& g, int rx0, int ry0, int w,
+                  int h, int nx, int ny, const float* const* ptrs,
+                  const float* w1d, int layout, float* out);
+
+void launch_fill(hipStream_t st, float* p, size_t n, float v);
+
+// Analytic linear-Gaussian denoiser + Euler step + weighting (see kernels).
+void launch_lg_step(hipStream_t st, const WinGeom& g, const float* canvas,
+                    int canvas_w, const int* origins, const int* widx,
+                    int nwin, double prior_std, double sigma, float c_euler,
+                    const float* w1d, float* const* slots, int mode,
+                    float* dout);
+
+struct ConvArgs {
+  const float* src0;
+  const float* src1;
+  int c0, c1;            // channels of src0 / src1 (input = concat)
+  int up0;               // src0 stored at half resolution (nearest 2x)
+  const float* gn_scale; // [nb][cin] (act != 0)
+  const float* gn_shift;
+  int act;               // 0 none, 1 affine, 2 affine + SiLU
+  int nb, lh, lw;        // batch, log2(height), log2(width)
+  int cout;
+  int taps;              // 9 (3x3, zero pad 1) or 1
+  const float* wt;       // [taps][cin][cout]
+  const float* bias;     // [cout]
+  const float* res;      // [nb][h][w][cout] or null
+  float* out;            // [nb][h][w][cout]
+};
+void launch_conv(hipStream_t st, const ConvArgs& a);
+
+struct GnArgs {
+  const float* src0;
+  const float* src1;
+  int c0, c1, up0;
+  int nb, lh, lw;
+  int groups;
+  float eps;
+  const float* gamma;
+  const float* beta;
+  double* partial;       // workspace [nb][nchunk][groups][2]
+  float* scale;          // [nb][cin]
+  float* shift;
+};
+size_t gn_partial_doubles(int nb, int lh, int lw, int cin, int groups);
+void launch_gn(hipStream_t st, const GnArgs& a);
+
+void launch_avgpool(hipStream_t st, const float* in, float* out, int nb, int h,
+                    int w, int C);
+
+// conv_in: gathers each window from the canvas, scales by c_in and applies
+// the 3x3 input conv.  origins: [nwin][2] canvas-relative (x, y).
+void launch_conv_in(hipStream_t st, const float* canvas, int canvas_w,
+                    const int* origins, int nwin, int H, int cimg, int c0,
+                    float c_in, const float* wt, const float* bias,
+                    float* out);
+
+// Output conv (GN + SiLU + 3x3 to cimg channels) fused with EDM
+// preconditioning, the Euler step and the window weighting.  mode 0 writes
+// V = W (x) Phi into slots[b]; mode 1 writes D to dout [nwin][H][H][cimg].
+struct OutArgs {
+  const float* h;        // [nb][H][H][c0]
+  const float* gn_scale;
+  const float* gn_shift;
+  int nb, H, c0, cimg;
+  const float* wt;       // [9][c0][cimg]
+  const float* bias;     // [cimg]
+  const float* canvas;   // window inputs x (un-preconditioned)
+  int canvas_w;
+  const int* origins;
+  float c_skip, c_out, c_euler;
+  const float* w1d;
+  float* const* slots;
+  int mode;
+  float* dout;
+};
+void launch_conv_out(hipStream_t st, const OutArgs& a);
+
+void launch_attention(hipStream_t st, const float* qkv, float* out, int nb,
+                      int T, int C, int heads);
+
+// out[k][o] = act(sum_i W[o][i] in[k][i] + b[o] + add[o]) for k < nk.
+void launch_gemv(hipStream_t st, const float* W, const float* b,
+                 const float* add, const float* in, float* out, int nk,
+                 int nin, int nout, int act_silu);
+void launch_pos_emb(hipStream_t st, const float* c_noise, int nk, int dim,
+                    float max_period, float* out);
+
+// Laplacian decode (see kernels file for the exact definition).
+struct DecodeArgs {
+  const float* latent;   // [lh][lw][C]
+  int64_t lx0, ly0;
+  int lw, lh, C;
+  int64_t X0, Y0;
+  int W, H;
+  float* out;            // [H][W]
+  float sigma_low, sigma_res;
+  const float* taps;     // 2R+1 Gaussian taps
+  int radius;
+  const float* atoms;    // [3][8][8]
+  float* work0;          // latent-resolution scratch
+  float* work1;
+};
+size_t decode_work_floats(const DecodeArgs& a);
+void launch_decode(hipStream_t st, const DecodeArgs& a);
+
+}  // namespace td

@@ -1,0 +1,251 @@
+"""ctypes binding of libtd.so: the C-ABI of include/td.h under the same names.
+
+Argument marshalling only: every step of sampling, the cache and the decode
+run inside the native library.  Torch tensors supply device memory and
+streams for the device-side calls.  The library must have been built
+(``paper_2512_08309_amd.build``); importing this module without it raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtd.so")
+
+TD_OK, TD_E_INVAL, TD_E_NOMEM, TD_E_DEVICE, TD_E_IO, TD_E_FORMAT, TD_E_STATE = 0, -1, -2, -3, -4, -5, -6
+TD_LEVEL_HEIGHT = -1
+STATUS_NAMES = {0: "TD_OK", -1: "TD_E_INVAL", -2: "TD_E_NOMEM", -3: "TD_E_DEVICE", -4: "TD_E_IO",
+                -5: "TD_E_FORMAT", -6: "TD_E_STATE"}
+
+# Every symbol include/td.h declares.
+EXPORTS = ["td_create", "td_destroy", "td_load_weights", "td_sample_region", "td_sample_region_async",
+           "td_cache_set_budget", "td_cache_clear", "td_cache_stats", "td_cache_peek", "td_set_option",
+           "td_get_info", "td_denoise_windows", "td_lap_decode", "td_kappa", "td_cone_windows", "td_last_error"]
+
+
+class td_cache_stats_t(ctypes.Structure):
+    _fields_ = [("hits", ctypes.c_uint64), ("misses", ctypes.c_uint64), ("evictions", ctypes.c_uint64),
+                ("bytes_used", ctypes.c_uint64), ("bytes_budget", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("queries", ctypes.c_uint64), ("windows_evaluated", ctypes.c_uint64 * 64)]
+
+
+class TDError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libtd.so is not built (run __graft_entry__.build() or paper_2512_08309_amd/build.py)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
+    fp = ctypes.POINTER(ctypes.c_float)
+    sig = {
+        "td_create": ([ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
+        "td_destroy": ([vp], None),
+        "td_load_weights": ([vp, ctypes.c_char_p], ctypes.c_int),
+        "td_sample_region": ([vp, u64, i64, i64, i32, i32, i32, fp, sz], ctypes.c_int),
+        "td_sample_region_async": ([vp, u64, i64, i64, i32, i32, i32, vp, sz, vp], ctypes.c_int),
+        "td_cache_set_budget": ([vp, sz], ctypes.c_int),
+        "td_cache_clear": ([vp], ctypes.c_int),
+        "td_cache_stats": ([vp, ctypes.POINTER(td_cache_stats_t)], ctypes.c_int),
+        "td_cache_peek": ([vp, u64, i32, i64, i64, fp, sz], ctypes.c_int),
+        "td_set_option": ([vp, ctypes.c_char_p, i64], ctypes.c_int),
+        "td_get_info": ([vp, ctypes.c_char_p, ctypes.POINTER(i64)], ctypes.c_int),
+        "td_denoise_windows": ([vp, vp, i32, i32, vp], ctypes.c_int),
+        "td_lap_decode": ([vp, vp, i64, i64, i32, i32, i64, i64, i32, i32, vp, vp], ctypes.c_int),
+        "td_kappa": ([i64, i64, i64, i64, i32, i32, i32, ctypes.POINTER(i64)], ctypes.c_int),
+        "td_cone_windows": ([i64, i64, i64, i64, i32, i32, i32, i32, i32, ctypes.POINTER(u64)], ctypes.c_int),
+        "td_last_error": ([vp], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+lib = _load()
+
+
+def _check(ctx, status):
+    if status != TD_OK:
+        msg = lib.td_last_error(ctx)
+        raise TDError(status, msg.decode() if msg else "")
+
+
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+# ---------------------------------------------------------------- raw calls
+
+def td_create(device=0):
+    p = ctypes.c_void_p()
+    _check(None, lib.td_create(device, ctypes.byref(p)))
+    return p
+
+
+def td_destroy(ctx):
+    lib.td_destroy(ctx)
+
+
+def td_load_weights(ctx, path):
+    _check(ctx, lib.td_load_weights(ctx, os.fsencode(path)))
+
+
+def td_get_info(ctx, key):
+    v = ctypes.c_int64()
+    _check(ctx, lib.td_get_info(ctx, key.encode(), ctypes.byref(v)))
+    return v.value
+
+
+def td_sample_region(ctx, seed, x0, y0, w, h, level, out=None):
+    """Host result: float32 [C][h][w] (latent) or [h][w] (height)."""
+    shape = (h, w) if level == TD_LEVEL_HEIGHT else (td_get_info(ctx, "channels"), h, w)
+    if out is None:
+        out = np.empty(shape, dtype=np.float32)
+    assert out.dtype == np.float32 and out.flags.c_contiguous
+    _check(ctx, lib.td_sample_region(ctx, seed & (2 ** 64 - 1), x0, y0, w, h, level, _fptr(out), out.size))
+    return out
+
+
+def td_sample_region_async(ctx, seed, x0, y0, w, h, level, dev_out, stream=None):
+    """dev_out: contiguous float32 torch tensor on the context's device."""
+    assert dev_out.dtype.is_floating_point and dev_out.element_size() == 4 and dev_out.is_contiguous()
+    _check(ctx, lib.td_sample_region_async(ctx, seed & (2 ** 64 - 1), x0, y0, w, h, level,
+                                           ctypes.c_void_p(dev_out.data_ptr()), dev_out.numel(), _stream(stream)))
+    return dev_out
+
+
+def td_cache_set_budget(ctx, nbytes):
+    _check(ctx, lib.td_cache_set_budget(ctx, nbytes))
+
+
+def td_cache_clear(ctx):
+    _check(ctx, lib.td_cache_clear(ctx))
+
+
+def td_cache_stats(ctx):
+    s = td_cache_stats_t()
+    _check(ctx, lib.td_cache_stats(ctx, ctypes.byref(s)))
+    d = {k: getattr(s, k) for k, _ in td_cache_stats_t._fields_ if k != "windows_evaluated"}
+    d["windows_evaluated"] = list(s.windows_evaluated)
+    return d
+
+
+def td_cache_peek(ctx, seed, level, ix, iy):
+    H = td_get_info(ctx, "window")
+    C = td_get_info(ctx, "channels")
+    out = np.empty((H, H, C), dtype=np.float32)
+    _check(ctx, lib.td_cache_peek(ctx, seed & (2 ** 64 - 1), level, ix, iy, _fptr(out), out.size))
+    return out
+
+
+def td_set_option(ctx, key, value):
+    _check(ctx, lib.td_set_option(ctx, key.encode(), value))
+
+
+def td_denoise_windows(ctx, x_dev, k, out_dev):
+    """x_dev, out_dev: contiguous float32 torch tensors [n][H][H][C] on the device."""
+    assert x_dev.is_contiguous() and out_dev.is_contiguous() and x_dev.shape == out_dev.shape
+    _check(ctx, lib.td_denoise_windows(ctx, ctypes.c_void_p(x_dev.data_ptr()), x_dev.shape[0], k,
+                                       ctypes.c_void_p(out_dev.data_ptr())))
+    return out_dev
+
+
+def td_lap_decode(ctx, latent_dev, lx0, ly0, X0, Y0, W, H, out_dev, stream=None):
+    """latent_dev: float32 [lh][lw][C] tensor; out_dev: float32 [H][W] tensor."""
+    lh, lw = latent_dev.shape[0], latent_dev.shape[1]
+    assert latent_dev.is_contiguous() and out_dev.is_contiguous() and out_dev.numel() >= W * H
+    _check(ctx, lib.td_lap_decode(ctx, ctypes.c_void_p(latent_dev.data_ptr()), lx0, ly0, lw, lh, X0, Y0, W, H,
+                                  ctypes.c_void_p(out_dev.data_ptr()), _stream(stream)))
+    return out_dev
+
+
+def td_kappa(x0, y0, w, h, size, stride, offset=0):
+    """(ix_min, ix_max, iy_min, iy_max), or None if no window meets the region."""
+    out = (ctypes.c_int64 * 4)()
+    s = lib.td_kappa(x0, y0, w, h, size, stride, offset, out)
+    if s == TD_E_INVAL and w >= 1 and h >= 1 and size >= 1 and stride >= 1:
+        return None
+    _check(None, s)
+    return tuple(out)
+
+
+def td_cone_windows(x0, y0, w, h, level, steps, size, stride, offset=0):
+    n = ctypes.c_uint64()
+    _check(None, lib.td_cone_windows(x0, y0, w, h, level, steps, size, stride, offset, ctypes.byref(n)))
+    return n.value
+
+
+def td_last_error(ctx):
+    return lib.td_last_error(ctx).decode()
+
+
+# ---------------------------------------------------------------- convenience
+
+class Context:
+    """Owning wrapper: Context(device).load_weights(path).sample_region(...)."""
+
+    def __init__(self, device=0):
+        self.ctx = td_create(device)
+
+    def close(self):
+        if self.ctx:
+            td_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load_weights(self, path):
+        td_load_weights(self.ctx, path)
+        return self
+
+    def info(self, key):
+        return td_get_info(self.ctx, key)
+
+    def sample_region(self, seed, x0, y0, w, h, level):
+        return td_sample_region(self.ctx, seed, x0, y0, w, h, level)
+
+    def sample_region_async(self, seed, x0, y0, w, h, level, dev_out, stream=None):
+        return td_sample_region_async(self.ctx, seed, x0, y0, w, h, level, dev_out, stream)
+
+    def cache_set_budget(self, nbytes):
+        td_cache_set_budget(self.ctx, nbytes)
+
+    def cache_clear(self):
+        td_cache_clear(self.ctx)
+
+    def cache_stats(self):
+        return td_cache_stats(self.ctx)
+
+    def cache_peek(self, seed, level, ix, iy):
+        return td_cache_peek(self.ctx, seed, level, ix, iy)
+
+    def set_option(self, key, value):
+        td_set_option(self.ctx, key, value)
+
+    def denoise_windows(self, x_dev, k, out_dev):
+        return td_denoise_windows(self.ctx, x_dev, k, out_dev)
+
+    def lap_decode(self, latent_dev, lx0, ly0, X0, Y0, W, H, out_dev, stream=None):
+        return td_lap_decode(self.ctx, latent_dev, lx0, ly0, X0, Y0, W, H, out_dev, stream)

@@ -1,0 +1,71 @@
+"""The C-ABI library: loads, exports every declared symbol, host-only logic
+(no GPU needed)."""
+import os
+import re
+
+import pytest
+from hypothesis import given, settings, strategies as st
+
+from oracle import windows as wn
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _td():
+    from paper_2512_08309_amd import td
+    return td
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "td.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(td_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    td = _td()
+    decl = declared_symbols()
+    assert len(decl) >= 16
+    assert sorted(td.EXPORTS) == decl
+    for name in decl:
+        assert hasattr(td.lib, name), name
+
+
+@settings(max_examples=300, deadline=None)
+@given(x0=st.integers(-2 ** 30, 2 ** 30), y0=st.integers(-2 ** 30, 2 ** 30), w=st.integers(1, 300),
+       h=st.integers(1, 300), H=st.integers(1, 80), s=st.integers(1, 90), o=st.integers(-100, 100))
+def test_kappa_matches_oracle(x0, y0, w, h, H, s, o):
+    td = _td()
+    k = wn.kappa((x0, y0, w, h), H, s, o)
+    got = td.td_kappa(x0, y0, w, h, H, s, o)
+    if k is None:
+        assert got is None
+    else:
+        assert got == (k[0][0], k[0][1], k[1][0], k[1][1])
+
+
+@pytest.mark.parametrize("region,level,K,H,s", [
+    ((0, 0, 64, 64), 0, 8, 32, 16), ((5, -7, 64, 64), 0, 8, 32, 16), ((13, -1000001, 1024, 1024), 0, 20, 64, 32),
+    ((-1000003, 999983, 64, 64), 0, 8, 32, 16), ((3, 9, 128, 128), 0, 8, 32, 16), ((0, 0, 7, 3), 5, 8, 32, 16),
+    ((10, 0, 5, 5), 0, 4, 8, 20)])
+def test_cone_counts_match_oracle(region, level, K, H, s):
+    td = _td()
+    assert td.td_cone_windows(*region, level, K, H, s) == wn.cone_window_count(region, level, K, H, s)
+
+
+def test_argument_errors_without_device():
+    td = _td()
+    with pytest.raises(td.TDError):
+        td.td_cone_windows(0, 0, 0, 5, 0, 8, 32, 16)
+    assert td.td_last_error(None) == ""
+    assert td.lib.td_sample_region(None, 0, 0, 0, 1, 1, 0, None, 0) == td.TD_E_INVAL
+    assert td.lib.td_cache_clear(None) == td.TD_E_INVAL
+
+
+def test_create_fails_cleanly_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    td = _td()
+    with pytest.raises(td.TDError):
+        td.td_create(0)

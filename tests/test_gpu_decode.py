@@ -1,0 +1,62 @@
+"""GPU parity of the Laplacian decode against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from gpu_common import rel_l2, require_gpu
+from oracle import laplace
+from oracle.sampler import Model, sample
+from synth.fbm import terrain_latent
+
+pytestmark = pytest.mark.gpu
+
+DEC = {"factor": 8, "sigma_low": 20.0, "sigma_res": 2.0, "blur_sigma": 5.0, "blur_radius": 15}
+
+
+@pytest.fixture(scope="module")
+def ctx(weights):
+    require_gpu()
+    from paper_2512_08309_amd import td
+    c = td.Context(0).load_weights(weights("lg"))
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("out_region", [(0, 0, 256, 192), (-803, 517, 203, 77), (8 * 1000001, -8 * 999, 64, 64)])
+def test_decode_fbm_latent_matches_oracle(ctx, out_region):
+    import torch
+    lx0, ly0, lw, lh = laplace.required_latent(out_region, DEC)
+    lx0, ly0 = lx0 - 3, ly0 - 2          # a larger latent than needed
+    lw, lh = lw + 7, lh + 5
+    lat = terrain_latent(21, lx0, ly0, lw, lh, 4)
+    X0, Y0, W, H = out_region
+    out = torch.empty((H, W), dtype=torch.float32, device="cuda")
+    ctx.lap_decode(torch.from_numpy(lat).cuda(), lx0, ly0, X0, Y0, W, H, out)
+    torch.cuda.synchronize()
+    ref = laplace.decode(lat.astype(np.float64), (lx0, ly0), out_region, DEC)
+    got = out.cpu().numpy()
+    assert rel_l2(got, ref) <= 1e-5
+    assert np.max(np.abs(got - ref)) <= 1e-4 * np.max(np.abs(ref)) + 1e-3
+
+
+def test_decode_rejects_short_apron(ctx):
+    import torch
+    from paper_2512_08309_amd import td
+    lat = torch.zeros((20, 20, 4), device="cuda")
+    out = torch.empty((8, 8), device="cuda")
+    with pytest.raises(td.TDError):
+        ctx.lap_decode(lat, 0, 0, 64, 64, 8, 8, out)
+
+
+def test_height_query_matches_oracle(weights):
+    require_gpu()
+    from paper_2512_08309_amd import td
+    with td.Context(0) as c:
+        c.load_weights(weights("lg"))
+        region = (-50, 77, 48, 40)
+        got = c.sample_region(3, *region, td.TD_LEVEL_HEIGHT)
+        m = Model(weights("lg"))
+        lx0, ly0, lw, lh = laplace.required_latent(region, DEC)
+        lat = sample(m, 3, lx0, ly0, lw, lh, 0)
+        ref = laplace.decode(lat, (lx0, ly0), region, DEC)
+        assert got.shape == (40, 48)
+        assert rel_l2(got, ref) <= 1e-4
