@@ -1,0 +1,213 @@
+"""Throughput benchmark of lazy windowed sampling on one MI355X.
+
+A step is one cold query through the C-ABI: the decoded elevation of a
+full-resolution region (default 8192 x 8192 px, i.e. a 1024 x 1024 latent
+region plus the 17-pixel decode apron) of the 4-channel latent plane, with
+the 4-level UNet (128/256/256/512, 8-head attention at 8x8), windows 64 at
+stride 32 and 20 EDM steps: noise, every window of the dependency cone
+through the batched denoiser, blend + Euler per level, the device cache,
+the Laplacian decode and the result in device memory.  The cache is cleared
+before every step, so every step does the full cold work.
+
+Reported: window-denoises/s (denoiser evaluations per second of the timed
+steps), the roofline of the dominant kernel (the FP32 MFMA 3x3 convolution)
+from event timing of every launch inside the timed steps, the other kernel
+classes, p50/p99 latency of a stream of small queries (first query and its
+neighbour, as in time-to-first/second-tile), and the FP64 oracle timed on
+the host cores on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=1)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--config", default="c2")
+    p.add_argument("--size", type=int, default=1024, help="latent side of the query (full-res = 8x)")
+    p.add_argument("--workload", choices=["height", "latent"], default="height")
+    p.add_argument("--batch", type=int, default=0)
+    p.add_argument("--seed", type=int, default=7)
+    p.add_argument("--latency-pairs", type=int, default=100)
+    p.add_argument("--cpu-windows", type=int, default=16)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    return p.parse_args()
+
+
+def cpu_baseline(weights_path, n):
+    """Oracle (FP64 NumPy) denoiser on n windows at sigma_0, timed on host cores."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle.sampler import Model
+    m = Model(weights_path)
+    x = 80.0 * np.random.default_rng(0).standard_normal((n, m.H, m.H, m.C))
+    m.denoiser(x[:1], m.sched[0], None)          # warm BLAS
+    t0 = time.perf_counter()
+    m.denoiser(x, m.sched[0], None)
+    dt = time.perf_counter() - t0
+    threads = max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"] or [1])
+    return {"value": n / dt, "unit": "window-denoises/s", "cores": threads, "kind": "oracle",
+            "sample": "%d windows of the same model through the FP64 oracle denoiser at sigma_0 (one batched "
+                      "level round; the sampler's blend/Euler is <0.1%% of its work), %.1f s" % (n, dt)}
+
+
+def latency_stream(td, torch, weights_path, pairs, seed=11):
+    """TTFT/TTST-style stream: random 64x64 queries in [-1e6, 1e6) and their right neighbours."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    xs = rng.integers(-10 ** 6, 10 ** 6, size=(pairs, 2))
+    first, second = [], []
+    with td.Context(0) as c:
+        c.load_weights(weights_path)
+        C = c.info("channels")
+        out = torch.empty((C, 64, 64), dtype=torch.float32, device="cuda")
+        st = torch.cuda.current_stream()
+        c.sample_region_async(seed, 0, 0, 64, 64, 0, out, st)      # warm kernels / workspace
+        torch.cuda.synchronize()
+        for x, y in xs:
+            for dx, sink in ((0, first), (64, second)):
+                t0 = time.perf_counter()
+                c.sample_region_async(seed, int(x) + dx, int(y), 64, 64, 0, out, st)
+                torch.cuda.synchronize()
+                sink.append(1e3 * (time.perf_counter() - t0))
+    def pct(v):
+        return {"p50_ms": float(np.percentile(v, 50)), "p99_ms": float(np.percentile(v, 99)), "n": len(v)}
+    return {"workload": "1-channel model, windows 32/16, K=8, 2-level UNet 16/32; %d random 64x64 latent queries "
+                        "in [-1e6,1e6) seed %d, each followed by its right neighbour; end-to-end through "
+                        "td_sample_region_async incl. planning" % (pairs, seed),
+            "first": pct(first), "neighbour": pct(second)}
+
+
+def main():
+    a = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if a.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: this build measures the per-GPU share of the sampling path "
+              "(sharding across GPUs is described in DESIGN.md but not built); got --gpus %d" % a.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2512_08309_amd import td
+    from synth.models import cached_weights
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    wdir = os.path.join(ROOT, ".td_weights")
+    wpath = cached_weights(a.config, wdir, 0)
+    ctx = td.Context(0).load_weights(wpath)
+    if a.batch:
+        ctx.set_option("batch", a.batch)
+    K, C = ctx.info("steps"), ctx.info("channels")
+    H, S = ctx.info("window"), ctx.info("stride")
+    lx, ly = 13, -1000001
+    if a.workload == "height":
+        region = (8 * lx, 8 * ly, 8 * a.size, 8 * a.size)
+        level = td.TD_LEVEL_HEIGHT
+        out = torch.empty((region[3], region[2]), dtype=torch.float32, device="cuda")
+    else:
+        region = (lx, ly, a.size, a.size)
+        level = 0
+        out = torch.empty((C, a.size, a.size), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        ctx.cache_clear()
+        ctx.sample_region_async(a.seed, *region, level, out, stream)
+        torch.cuda.synchronize()
+        return ctx.cache_stats()["misses"]
+
+    for i in range(a.warmup):
+        print("[bench] warmup step %d" % i, file=sys.stderr, flush=True)
+        step()
+    ctx.set_option("timing", 1)
+    ctx.kernel_stats(reset=True)
+    torch.cuda.synchronize()
+    windows = 0
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        windows += step()
+        print("[bench] step %d done" % i, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ks = ctx.kernel_stats()
+    ctx.set_option("timing", 0)
+    finite = bool(torch.isfinite(out).all().item())
+    ctx.close()
+
+    conv = ks.get("conv3x3_mfma_f32", {"launches": 0, "ms": 0.0, "flops": 0.0})
+    achieved = conv["flops"] / (conv["ms"] * 1e-3) / 1e12 if conv["ms"] else 0.0
+    kernels = {}
+    for name, v in sorted(ks.items(), key=lambda kv: -kv[1]["ms"]):
+        e = {"launches": v["launches"], "ms_total": round(v["ms"], 3),
+             "avg_us": round(1e3 * v["ms"] / max(v["launches"], 1), 2)}
+        if v["ms"] > 0:
+            e["TFLOP/s"] = round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 2)
+            e["GB/s"] = round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1)
+        kernels[name] = e
+
+    lat = None
+    if a.latency_pairs > 0:
+        print("[bench] latency stream", file=sys.stderr, flush=True)
+        lat = latency_stream(td, torch, cached_weights("c1", wdir, 0), a.latency_pairs)
+    cpu = None
+    if not a.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(wpath, a.cpu_windows)
+
+    res = {
+        "metric": "window-denoises/s",
+        "value": windows / dt,
+        "unit": "window-denoises/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * dt / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": ("cold %s query, full-res %dx%d px (latent %d^2 + 17 px apron) at latent (%d, %d), seed %d"
+                         % ("elevation" if level == td.TD_LEVEL_HEIGHT else "latent", region[2], region[3],
+                            a.size, lx, ly, a.seed)) if level == td.TD_LEVEL_HEIGHT else
+                        ("cold latent query %dx%d at (%d, %d), seed %d" % (a.size, a.size, lx, ly, a.seed)),
+            "latent_channels": C, "steps_K": K, "window": H, "stride": S,
+            "unet": "4-level 128/256/256/512, 2 res-blocks, 8-head attention at 8x8, random init"
+            if a.config.startswith("c2") else a.config,
+            "windows_per_step": windows // max(a.steps, 1),
+            "batch": a.batch or "auto",
+        },
+        "roofline": {
+            "kernel": "conv3x3_mfma_f32",
+            "bound": "mfma",
+            "achieved": round(achieved, 2),
+            "peak": PEAK_FP32_MFMA_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4),
+            "traffic": None,
+            "avg_launch_us": round(1e3 * conv["ms"] / max(conv["launches"], 1), 2),
+            "launches": conv["launches"],
+        },
+        "kernels": kernels,
+        "latency": lat,
+        "cpu_baseline": cpu,
+        "output_finite": finite,
+    }
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

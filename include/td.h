@@ -117,7 +117,9 @@ td_status td_cache_peek(td_ctx *ctx, uint64_t seed, int32_t level, int64_t ix,
                         int64_t iy, float *out, size_t out_len);
 
 /* Options: "batch" = max windows per batched denoiser round (>= 1);
- * "cache_budget" = as td_cache_set_budget.  TD_E_INVAL for unknown keys. */
+ * "cache_budget" = as td_cache_set_budget; "timing" = 1 records every kernel
+ * launch between HIP events on its stream (see td_kernel_stats), 0 stops.
+ * TD_E_INVAL for unknown keys. */
 td_status td_set_option(td_ctx *ctx, const char *key, int64_t value);
 
 /* Model facts: "channels", "steps", "window", "stride", "offset",
@@ -156,6 +158,24 @@ td_status td_kappa(int64_t x0, int64_t y0, int64_t w, int64_t h, int32_t size,
 td_status td_cone_windows(int64_t x0, int64_t y0, int64_t w, int64_t h,
                           int32_t level, int32_t steps, int32_t size,
                           int32_t stride, int32_t offset, uint64_t *count);
+
+/* Per kernel class, totals over the launches recorded while "timing" was
+ * on: launch count, summed event-measured duration, and the algorithmic
+ * FLOPs and HBM bytes the launches had to do (what the method requires, not
+ * what the hardware counted). */
+typedef struct {
+  char name[32];      /* e.g. "conv3x3_mfma_f32", "blend", "noise_philox" */
+  uint64_t launches;
+  double ms;
+  double flops;
+  double bytes;
+} td_kernel_stat_t;
+
+/* Copy up to `cap` class totals into out, set *count to the number of
+ * classes with launches; reset != 0 clears the totals afterwards.  Waits for
+ * the recorded launches to finish.  TD_E_STATE if timing is off. */
+td_status td_kernel_stats(td_ctx *ctx, td_kernel_stat_t *out, int32_t cap,
+                          int32_t *count, int32_t reset);
 
 /* Description of the last error on ctx (owned by ctx, valid until the next
  * call); "" if none.  Safe on NULL. */

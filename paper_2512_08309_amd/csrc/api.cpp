@@ -29,6 +29,7 @@
 
 #include "../../include/td.h"
 #include "model.h"
+#include "profile.h"
 
 namespace td {
 namespace {
@@ -202,6 +203,7 @@ struct td_ctx {
   size_t dec_cap = 0;
   float* outbuf = nullptr;
   size_t outbuf_cap = 0;
+  std::unique_ptr<td::Profiler> prof;
 };
 
 namespace td {
@@ -474,10 +476,17 @@ void sample_any(td_ctx* c, uint64_t seed, int64_t x0, int64_t y0, int32_t w, int
   c->pending = true;
 }
 
+// Installs the context's profiler (if timing is on) for the launches of one call.
+struct ProfScope {
+  explicit ProfScope(td_ctx* c) { g_prof = c ? c->prof.get() : nullptr; }
+  ~ProfScope() { g_prof = nullptr; }
+};
+
 template <class F>
 td_status guarded(td_ctx* c, F&& f) {
   try {
     if (c) c->err.clear();
+    ProfScope scope(c);
     f();
     return TD_OK;
   } catch (const Error& e) {
@@ -534,6 +543,7 @@ void td_destroy(td_ctx* c) {
   c->pool.release();
   c->model.reset();
   c->arena.release();
+  c->prof.reset();
   for (float* p : {c->canvas, c->tmp, c->dec, c->outbuf})
     if (p) (void)hipFree(p);
   if (c->done) (void)hipEventDestroy(c->done);
@@ -657,6 +667,12 @@ td_status td_set_option(td_ctx* c, const char* key, int64_t value) {
     if (k == "batch") {
       TD_CHECK(value >= 1 && value <= (1 << 20), TD_E_INVAL, "batch must be in [1, 2^20]");
       c->batch = (int)value;
+    } else if (k == "timing") {
+      if (value && !c->prof) c->prof.reset(new Profiler());
+      if (!value && c->prof) {
+        TD_HIP(hipStreamSynchronize(c->stream));
+        c->prof.reset();
+      }
     } else if (k == "cache_budget") {
       TD_CHECK(value >= 0, TD_E_INVAL, "budget must be >= 0");
       c->budget = (size_t)value;
@@ -770,6 +786,32 @@ td_status td_cone_windows(int64_t x0, int64_t y0, int64_t w, int64_t h, int32_t 
   }
   *count = n;
   return TD_OK;
+}
+
+td_status td_kernel_stats(td_ctx* c, td_kernel_stat_t* out, int32_t cap, int32_t* count, int32_t reset) {
+  if (!c || !count || cap < 0 || (cap > 0 && !out)) return TD_E_INVAL;
+  return guarded(c, [&] {
+    TD_CHECK(c->prof, TD_E_STATE, "timing is off (td_set_option \"timing\" 1)");
+    TD_HIP(hipSetDevice(c->device));
+    c->prof->resolve();
+    int n = 0;
+    for (int k = 0; k < K_NCLASS; ++k) {
+      const Profiler::Total& t = c->prof->tot[k];
+      if (!t.launches) continue;
+      if (n < cap) {
+        td_kernel_stat_t& o = out[n];
+        std::memset(&o, 0, sizeof(o));
+        std::strncpy(o.name, kclass_name(k), sizeof(o.name) - 1);
+        o.launches = t.launches;
+        o.ms = t.ms;
+        o.flops = t.flops;
+        o.bytes = t.bytes;
+      }
+      ++n;
+    }
+    *count = n;
+    if (reset) c->prof->reset();
+  });
 }
 
 const char* td_last_error(const td_ctx* c) { return c ? c->err.c_str() : ""; }

@@ -127,6 +127,7 @@ void launch_blend(hipStream_t st, const WinGeom& g, int rx0, int ry0, int w, int
   int n = w * h;
   if (!n) return;
   dim3 grid((n + 255) / 256);
+  prof_begin(st);
   if (g.channels == 4)
     hipLaunchKernelGGL(blend_kernel<4>, grid, dim3(256), 0, st, g.size, g.stride, 4, rx0, ry0, w, h, nx,
                        ny, ptrs, w1d, layout, out);
@@ -137,6 +138,8 @@ void launch_blend(hipStream_t st, const WinGeom& g, int rx0, int ry0, int w, int
     hipLaunchKernelGGL(blend_generic, grid, dim3(256), 0, st, g.size, g.stride, g.channels, rx0, ry0, w,
                        h, nx, ny, ptrs, w1d, layout, out);
   TD_LAUNCHED();
+  const double cov = (double)((g.size + g.stride - 1) / g.stride) * ((g.size + g.stride - 1) / g.stride);
+  prof_end(st, K_BLEND, (double)n * g.channels * (cov + 1), 4.0 * n * g.channels * (cov + 1));
 }
 
 void launch_lg_step(hipStream_t st, const WinGeom& g, const float* canvas, int canvas_w,
@@ -146,9 +149,11 @@ void launch_lg_step(hipStream_t st, const WinGeom& g, const float* canvas, int c
   int per = g.size * g.size * g.channels;
   double s2 = prior_std * prior_std;
   float a_post = (float)(s2 / (s2 + sigma * sigma));
+  prof_begin(st);
   hipLaunchKernelGGL(lg_step_kernel, dim3((per + 255) / 256, nwin), dim3(256), 0, st, g.size, g.channels,
                      canvas, canvas_w, origins, widx, a_post, c_euler, w1d, slots, mode, dout);
   TD_LAUNCHED();
+  prof_end(st, K_LG, 6.0 * per * nwin, 8.0 * per * nwin);
 }
 
 }  // namespace td

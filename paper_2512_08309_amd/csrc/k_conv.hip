@@ -32,7 +32,7 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float silu_f(float v) { return __fdividef(v, 1.0f + __expf(-v)); }
 
-template <int BN, int WM, int WN>
+template <int TAPS, int BN, int WM, int WN>
 __global__ __launch_bounds__(256, 2) void conv_kernel(ConvArgs a, int n_tiles_n) {
   constexpr int BM = 128, BK = 16;
   constexpr int TM = BM / WM / 16, TN = BN / WN / 16;
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256, 2) void conv_kernel(ConvArgs a, int n_tiles_n)
   const int M = a.nb << lhw;
   const int cin = a.c0 + a.c1;
   const int cchunks = cin / BK;
-  const int nchunks = a.taps * cchunks;
+  const int nchunks = TAPS * cchunks;
 
   // Per-thread A staging slots: 2 float4 (pixel am, channel quad akq).
   int ab[2], ay[2], ax[2], akq[2], aml[2];
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(256, 2) void conv_kernel(ConvArgs a, int n_tiles_n)
     int tap = c / cchunks;
     int ci0 = (c - tap * cchunks) * BK;
     int dy = 0, dx = 0;
-    if (a.taps == 9) { dy = tap / 3 - 1; dx = tap % 3 - 1; }
+    if (TAPS == 9) { dy = tap / 3 - 1; dx = tap % 3 - 1; }
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       int yy = ay[i] + dy, xx = ax[i] + dx;
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(256, 2) void conv_kernel(ConvArgs a, int n_tiles_n)
     int tap = c / cchunks;
     int ci0 = (c - tap * cchunks) * BK;
     int dy = 0, dx = 0;
-    if (a.taps == 9) { dy = tap / 3 - 1; dx = tap % 3 - 1; }
+    if (TAPS == 9) { dy = tap / 3 - 1; dx = tap % 3 - 1; }
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       f4v v = ra[i];
@@ -234,7 +234,10 @@ void launch_cfg(hipStream_t st, const ConvArgs& a) {
   int M = a.nb << (a.lh + a.lw);
   int mt = (M + 127) / 128;
   int nt = a.cout / BN;
-  hipLaunchKernelGGL((conv_kernel<BN, WM, WN>), dim3(mt * nt), dim3(256), 0, st, a, nt);
+  if (a.taps == 9)
+    hipLaunchKernelGGL((conv_kernel<9, BN, WM, WN>), dim3(mt * nt), dim3(256), 0, st, a, nt);
+  else
+    hipLaunchKernelGGL((conv_kernel<1, BN, WM, WN>), dim3(mt * nt), dim3(256), 0, st, a, nt);
   TD_LAUNCHED();
 }
 
@@ -247,11 +250,17 @@ void launch_conv(hipStream_t st, const ConvArgs& a) {
   TD_CHECK(!a.up0 || (a.lh >= 1 && a.lw >= 1), -5, "conv: upsampled source needs h, w >= 2");
   TD_CHECK(a.lh + a.lw <= 20, -5, "conv: image too large");
   if (a.nb == 0) return;
+  TD_CHECK(a.cout % 128 == 0 || a.cout == 64 || a.cout == 32 || a.cout == 16, -5,
+           "conv: unsupported output channel count");
+  const double M = (double)a.nb * (1 << (a.lh + a.lw));
+  const double in_bytes = 4.0 * (a.up0 ? M / 4 * a.c0 + M * a.c1 : M * cin);
+  const double bytes = in_bytes + 4.0 * a.taps * cin * a.cout + 4.0 * M * a.cout * (a.res ? 2 : 1);
+  prof_begin(st);
   if (a.cout % 128 == 0) launch_cfg<128, 2, 2>(st, a);
   else if (a.cout == 64) launch_cfg<64, 2, 2>(st, a);
   else if (a.cout == 32) launch_cfg<32, 4, 1>(st, a);
-  else if (a.cout == 16) launch_cfg<16, 4, 1>(st, a);
-  else TD_CHECK(false, -5, "conv: unsupported output channel count");
+  else launch_cfg<16, 4, 1>(st, a);
+  prof_end(st, a.taps == 9 ? K_CONV3 : K_CONV1, 2.0 * M * a.cout * a.taps * cin, bytes);
 }
 
 }  // namespace td

@@ -120,10 +120,14 @@ void launch_gn(hipStream_t st, const GnArgs& a) {
   }
   if (!a.nb) return;
   const int nchunk = gn_nchunk(a.lh, a.lw, cin, a.up0);
+  const double hw = (double)(1 << (a.lh + a.lw));
+  prof_begin(st);
   hipLaunchKernelGGL(gn_partial_kernel, dim3(nchunk, a.nb), dim3(256), 0, st, a, nchunk);
   TD_LAUNCHED();
   hipLaunchKernelGGL(gn_finalize_kernel, dim3(a.nb), dim3(256), 0, st, a, nchunk);
   TD_LAUNCHED();
+  const double elems = a.nb * hw * ((a.up0 ? a.c0 / 4.0 : a.c0) + a.c1);
+  prof_end(st, K_GN, 3.0 * elems, 4.0 * elems + 8.0 * a.nb * cin);
 }
 
 }  // namespace td

@@ -143,6 +143,7 @@ void launch_decode(hipStream_t st, const DecodeArgs& a) {
   const int nxD = (int)(s.xh - s.xl + 1 + 2 * R), nyD = (int)(s.yh - s.yl + 1 + 2 * R);
   const int nx = (int)(s.xh - s.xl + 1), ny = (int)(s.yh - s.yl + 1);
   const int bx0 = (int)(s.xl - R - a.lx0), by0 = (int)(s.yl - R - a.ly0);
+  prof_begin(st);
   hipLaunchKernelGGL(down_p_kernel, dim3((nxD * nyD + 255) / 256), dim3(256), 0, st, a.latent, a.lw, a.C,
                      a.sigma_low, a.sigma_res, a.atoms, bx0, by0, nxD, nyD, a.work0);
   TD_LAUNCHED();
@@ -157,6 +158,7 @@ void launch_decode(hipStream_t st, const DecodeArgs& a) {
                      a.sigma_res, a.atoms, a.work0, nx, (int)(s.xl - a.lx0), (int)(s.yl - a.ly0), xo, yo, a.W,
                      a.H, a.out);
   TD_LAUNCHED();
+  prof_end(st, K_DECODE, 20.0 * a.W * a.H, 4.0 * (double)a.W * a.H + 4.0 * (double)nxD * nyD * a.C);
 }
 
 }  // namespace td

@@ -225,6 +225,7 @@ void launch_conv_in(hipStream_t st, const float* canvas, int canvas_w, const int
   dim3 grid((H / 16) * (H / 16), nwin);
   size_t shm = (18 * 18 * cimg + 9 * cimg * c0) * sizeof(float);
   TD_CHECK(shm <= 64 * 1024, -5, "conv_in: too many channels");
+  prof_begin(st);
   if (cimg == 4)
     hipLaunchKernelGGL(conv_in_kernel<4>, grid, dim3(256), shm, st, canvas, canvas_w, origins, H, c0, c_in, wt,
                        bias, out);
@@ -234,12 +235,15 @@ void launch_conv_in(hipStream_t st, const float* canvas, int canvas_w, const int
   else
     TD_CHECK(false, -5, "conv_in: latent channels must be 1 or 4");
   TD_LAUNCHED();
+  const double px = (double)nwin * H * H;
+  prof_end(st, K_CONV_IN, 2.0 * px * c0 * 9 * cimg, 4.0 * px * (cimg + c0));
 }
 
 void launch_conv_out(hipStream_t st, const OutArgs& a) {
   if (!a.nb) return;
   TD_CHECK(a.H % 16 == 0, -5, "conv_out: window size must be a multiple of 16");
   dim3 grid((a.H / 16) * (a.H / 16), a.nb);
+  prof_begin(st);
   if (a.cimg == 4 && a.c0 % 32 == 0)
     hipLaunchKernelGGL((conv_out_kernel<4, 32>), grid, dim3(256), 0, st, a);
   else if (a.cimg == 4 && a.c0 % 16 == 0)
@@ -249,14 +253,18 @@ void launch_conv_out(hipStream_t st, const OutArgs& a) {
   else
     TD_CHECK(false, -5, "conv_out: unsupported channel counts");
   TD_LAUNCHED();
+  const double px = (double)a.nb * a.H * a.H;
+  prof_end(st, K_CONV_OUT, 2.0 * px * a.cimg * 9 * a.c0, 4.0 * px * (a.c0 + 2 * a.cimg));
 }
 
 void launch_avgpool(hipStream_t st, const float* in, float* out, int nb, int h, int w, int C) {
   TD_CHECK(C % 4 == 0, -5, "avgpool: channels must be a multiple of 4");
   size_t n = (size_t)nb * (h / 2) * (w / 2) * (C / 4);
   if (!n) return;
+  prof_begin(st);
   hipLaunchKernelGGL(avgpool_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, out, nb, h, w, C);
   TD_LAUNCHED();
+  prof_end(st, K_POOL, 4.0 * n * 4, 4.0 * 4 * n * 5);
 }
 
 void launch_gemv(hipStream_t st, const float* W, const float* b, const float* add, const float* in, float* out,
@@ -279,8 +287,10 @@ void launch_pos_emb(hipStream_t st, const float* c_noise, int nk, int dim, float
 void launch_attention(hipStream_t st, const float* qkv, float* out, int nb, int T, int C, int heads) {
   TD_CHECK(T <= 64 && C / heads <= 64 && C % heads == 0, -5, "attention: at most 64 tokens and head dim 64");
   if (!nb) return;
+  prof_begin(st);
   hipLaunchKernelGGL(attention_kernel, dim3(nb, heads), dim3(256), 0, st, qkv, out, T, C, heads);
   TD_LAUNCHED();
+  prof_end(st, K_ATTN, 4.0 * nb * T * T * C, 4.0 * nb * T * 4 * C);
 }
 
 }  // namespace td

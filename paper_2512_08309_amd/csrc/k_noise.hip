@@ -142,9 +142,11 @@ void launch_noise(hipStream_t st, uint64_t seed, int64_t x0, int64_t y0, int w, 
   int64_t n = (int64_t)w * h;
   if (n == 0) return;
   int blocks = (int)((n + 255) / 256);
+  prof_begin(st);
   hipLaunchKernelGGL(noise_kernel, dim3(blocks), dim3(256), 0, st, (uint32_t)(seed & 0xFFFFFFFFu),
                      (uint32_t)(seed >> 32), x0, y0, w, h, C, step, scale, layout, out);
   TD_LAUNCHED();
+  prof_end(st, K_NOISE, 0.0, 4.0 * n * C);
 }
 
 void launch_fill(hipStream_t st, float* p, size_t n, float v) {

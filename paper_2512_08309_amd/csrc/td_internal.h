@@ -34,6 +34,19 @@ struct Error {
 // Launch check: catches bad launch configurations immediately.
 #define TD_LAUNCHED() TD_HIP(hipGetLastError())
 
+// ------------------------------------------------------------- profiling --
+// Opt-in per-launch event timing (kernel class, algorithmic FLOPs and HBM
+// bytes of the launch).  When no profiler is installed the hooks are no-ops.
+enum KClass {
+  K_CONV3 = 0, K_CONV1, K_GN, K_CONV_IN, K_CONV_OUT, K_ATTN, K_POOL, K_NOISE, K_BLEND, K_DECODE, K_LG, K_EMB,
+  K_NCLASS
+};
+const char* kclass_name(int k);
+struct Profiler;
+extern thread_local Profiler* g_prof;
+void prof_begin(hipStream_t st);
+void prof_end(hipStream_t st, int cls, double flops, double bytes);
+
 // ---------------------------------------------------------------- kernels --
 
 // Geometry of one level's window set relative to a dense canvas.

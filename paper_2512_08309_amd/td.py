@@ -21,13 +21,19 @@ STATUS_NAMES = {0: "TD_OK", -1: "TD_E_INVAL", -2: "TD_E_NOMEM", -3: "TD_E_DEVICE
 # Every symbol include/td.h declares.
 EXPORTS = ["td_create", "td_destroy", "td_load_weights", "td_sample_region", "td_sample_region_async",
            "td_cache_set_budget", "td_cache_clear", "td_cache_stats", "td_cache_peek", "td_set_option",
-           "td_get_info", "td_denoise_windows", "td_lap_decode", "td_kappa", "td_cone_windows", "td_last_error"]
+           "td_get_info", "td_denoise_windows", "td_lap_decode", "td_kappa", "td_cone_windows", "td_kernel_stats",
+           "td_last_error"]
 
 
 class td_cache_stats_t(ctypes.Structure):
     _fields_ = [("hits", ctypes.c_uint64), ("misses", ctypes.c_uint64), ("evictions", ctypes.c_uint64),
                 ("bytes_used", ctypes.c_uint64), ("bytes_budget", ctypes.c_uint64), ("batches", ctypes.c_uint64),
                 ("queries", ctypes.c_uint64), ("windows_evaluated", ctypes.c_uint64 * 64)]
+
+
+class td_kernel_stat_t(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64), ("ms", ctypes.c_double),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
 class TDError(RuntimeError):
@@ -58,6 +64,7 @@ def _load():
         "td_lap_decode": ([vp, vp, i64, i64, i32, i32, i64, i64, i32, i32, vp, vp], ctypes.c_int),
         "td_kappa": ([i64, i64, i64, i64, i32, i32, i32, ctypes.POINTER(i64)], ctypes.c_int),
         "td_cone_windows": ([i64, i64, i64, i64, i32, i32, i32, i32, i32, ctypes.POINTER(u64)], ctypes.c_int),
+        "td_kernel_stats": ([vp, ctypes.POINTER(td_kernel_stat_t), i32, ctypes.POINTER(i32), i32], ctypes.c_int),
         "td_last_error": ([vp], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -187,6 +194,15 @@ def td_cone_windows(x0, y0, w, h, level, steps, size, stride, offset=0):
     return n.value
 
 
+def td_kernel_stats(ctx, reset=False):
+    """{class name: {"launches", "ms", "flops", "bytes"}} while timing is on."""
+    arr = (td_kernel_stat_t * 32)()
+    n = ctypes.c_int32()
+    _check(ctx, lib.td_kernel_stats(ctx, arr, 32, ctypes.byref(n), 1 if reset else 0))
+    return {arr[i].name.decode(): {"launches": arr[i].launches, "ms": arr[i].ms, "flops": arr[i].flops,
+                                   "bytes": arr[i].bytes} for i in range(min(n.value, 32))}
+
+
 def td_last_error(ctx):
     return lib.td_last_error(ctx).decode()
 
@@ -246,6 +262,9 @@ class Context:
 
     def denoise_windows(self, x_dev, k, out_dev):
         return td_denoise_windows(self.ctx, x_dev, k, out_dev)
+
+    def kernel_stats(self, reset=False):
+        return td_kernel_stats(self.ctx, reset)
 
     def lap_decode(self, latent_dev, lx0, ly0, X0, Y0, W, H, out_dev, stream=None):
         return td_lap_decode(self.ctx, latent_dev, lx0, ly0, X0, Y0, W, H, out_dev, stream)
