@@ -42,6 +42,9 @@ def parse():
     p.add_argument("--latency-pairs", type=int, default=100)
     p.add_argument("--cpu-windows", type=int, default=16)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--calib-copy-mib", type=int, default=0,
+                   help="run one plain elementwise copy (read N MiB, write N MiB) before the steps, as the "
+                        "reference dispatch that scales hardware byte counters")
     return p.parse_args()
 
 
@@ -128,6 +131,12 @@ def main():
         torch.cuda.synchronize()
         return ctx.cache_stats()["misses"]
 
+    if a.calib_copy_mib:
+        src = torch.ones(a.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     for i in range(a.warmup):
         print("[bench] warmup step %d" % i, file=sys.stderr, flush=True)
         step()

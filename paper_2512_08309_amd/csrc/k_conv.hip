@@ -30,11 +30,13 @@ namespace {
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ float silu_f(float v) { return __fdividef(v, 1.0f + __expf(-v)); }
+__device__ __forceinline__ float silu_f(float v) {
+  return v * __builtin_amdgcn_rcpf(1.0f + __expf(-v));
+}
 
 template <int TAPS, int BN, int WM, int WN>
-__global__ __launch_bounds__(256, 2) void conv_kernel(ConvArgs a, int n_tiles_n) {
-  constexpr int BM = 128, BK = 16;
+__global__ __launch_bounds__(256, 4) void conv_kernel(ConvArgs a, int n_tiles_n) {
+  constexpr int BM = 128, BK = 16, KS = BK / 4;
   constexpr int TM = BM / WM / 16, TN = BN / WN / 16;
   constexpr int AS = BM + 4, BS = BN + 4;
   constexpr int NBL = (BK * BN / 4 + 255) / 256;  // float4 B loads per thread
@@ -44,7 +46,7 @@ __global__ __launch_bounds__(256, 2) void conv_kernel(ConvArgs a, int n_tiles_n)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WM, wn = wave / WM;
 
-  int bid = blockIdx.x;
+  const int bid = blockIdx.x;
   const int nblk = gridDim.x;
   const int tile = ((nblk & 7) == 0) ? (bid & 7) * (nblk >> 3) + (bid >> 3) : bid;
   const int tn = tile % n_tiles_n, tm = tile / n_tiles_n;
@@ -53,85 +55,78 @@ __global__ __launch_bounds__(256, 2) void conv_kernel(ConvArgs a, int n_tiles_n)
   const int lw = a.lw, lh = a.lh;
   const int W = 1 << lw, H = 1 << lh, lhw = lw + lh;
   const int M = a.nb << lhw;
-  const int cin = a.c0 + a.c1;
-  const int cchunks = cin / BK;
-  const int nchunks = TAPS * cchunks;
+  const int c0 = a.c0, c1 = a.c1, cin = c0 + c1;
 
-  // Per-thread A staging slots: 2 float4 (pixel am, channel quad akq).
+  // Per-thread A staging slots: 2 float4 (pixel aml, channel quad akq).
   int ab[2], ay[2], ax[2], akq[2], aml[2];
   bool aval[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
-    int e = tid + 256 * i;
+    const int e = tid + 256 * i;
     aml[i] = e % BM;
     akq[i] = e / BM;
-    int m = m0 + aml[i];
+    const int m = m0 + aml[i];
     aval[i] = m < M;
-    int mm = aval[i] ? m : 0;
+    const int mm = aval[i] ? m : 0;
     ab[i] = mm >> lhw;
-    int r = mm & ((1 << lhw) - 1);
+    const int r = mm & ((1 << lhw) - 1);
     ay[i] = r >> lw;
     ax[i] = r & (W - 1);
   }
 
-  f4v ra[2], rb[NBL];
-
-  auto load_chunk = [&](int c) {
-    int tap = c / cchunks;
-    int ci0 = (c - tap * cchunks) * BK;
+  // Tap state of the chunk being loaded: per-slot base pointers of the
+  // shifted pixel in both sources.  Out-of-image pixels point at a valid
+  // pixel and are zeroed after the load (branch-free, always in bounds).
+  const float* p0[2];
+  const float* p1[2];
+  bool pok[2];
+  auto set_tap = [&](int tap) {
     int dy = 0, dx = 0;
     if (TAPS == 9) { dy = tap / 3 - 1; dx = tap % 3 - 1; }
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      int yy = ay[i] + dy, xx = ax[i] + dx;
-      bool ok = aval[i] && yy >= 0 && yy < H && xx >= 0 && xx < W;
-      int ci = ci0 + 4 * akq[i];
-      f4v v = {0.f, 0.f, 0.f, 0.f};
-      if (ok) {
-        const float* p;
-        if (ci < a.c0) {
-          if (a.up0)
-            p = a.src0 + ((((size_t)ab[i] << (lhw - 2)) + ((size_t)(yy >> 1) << (lw - 1)) + (xx >> 1)) * a.c0 + ci);
-          else
-            p = a.src0 + ((((size_t)ab[i] << lhw) + ((size_t)yy << lw) + xx) * a.c0 + ci);
-        } else {
-          p = a.src1 + ((((size_t)ab[i] << lhw) + ((size_t)yy << lw) + xx) * a.c1 + (ci - a.c0));
-        }
-        v = *reinterpret_cast<const f4v*>(p);
-      }
-      ra[i] = v;
+      const int yy = ay[i] + dy, xx = ax[i] + dx;
+      const bool ok = aval[i] && yy >= 0 && yy < H && xx >= 0 && xx < W;
+      const int yc = ok ? yy : 0, xc = ok ? xx : 0;
+      pok[i] = ok;
+      if (a.up0)
+        p0[i] = a.src0 + ((((size_t)ab[i] << (lhw - 2)) + ((size_t)(yc >> 1) << (lw - 1)) + (xc >> 1)) * c0 + 4 * akq[i]);
+      else
+        p0[i] = a.src0 + ((((size_t)ab[i] << lhw) + ((size_t)yc << lw) + xc) * c0 + 4 * akq[i]);
+      p1[i] = c1 ? a.src1 + ((((size_t)ab[i] << lhw) + ((size_t)yc << lw) + xc) * c1 + 4 * akq[i]) : a.src0;
+    }
+  };
+
+  f4v ra[2], rb[NBL];
+  auto load_chunk = [&](int tap, int ci0) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const float* p = ci0 < c0 ? p0[i] + ci0 : p1[i] + (ci0 - c0);
+      ra[i] = *reinterpret_cast<const f4v*>(p);
+
     }
 #pragma unroll
     for (int i = 0; i < NBL; ++i) {
-      int e = tid + 256 * i;
+      const int e = tid + 256 * i;
       if (e < BK * BN / 4) {
-        int row = e / (BN / 4), c4 = e % (BN / 4);
+        const int row = e / (BN / 4), c4 = e % (BN / 4);
         rb[i] = *reinterpret_cast<const f4v*>(a.wt + ((size_t)(tap * cin + ci0 + row) * a.cout + n0 + 4 * c4));
       }
     }
   };
 
-  auto store_chunk = [&](int c, int buf) {
-    int tap = c / cchunks;
-    int ci0 = (c - tap * cchunks) * BK;
-    int dy = 0, dx = 0;
-    if (TAPS == 9) { dy = tap / 3 - 1; dx = tap % 3 - 1; }
+  auto store_chunk = [&](int buf, int ci0) {
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       f4v v = ra[i];
       if (a.act) {
-        int yy = ay[i] + dy, xx = ax[i] + dx;
-        bool ok = aval[i] && yy >= 0 && yy < H && xx >= 0 && xx < W;
-        if (ok) {
-          int ci = ci0 + 4 * akq[i];
-          f4v s = *reinterpret_cast<const f4v*>(a.gn_scale + (size_t)ab[i] * cin + ci);
-          f4v t = *reinterpret_cast<const f4v*>(a.gn_shift + (size_t)ab[i] * cin + ci);
-          v = v * s + t;
-          if (a.act == 2) {
-            v.x = silu_f(v.x); v.y = silu_f(v.y); v.z = silu_f(v.z); v.w = silu_f(v.w);
-          }
+        const size_t so = (size_t)ab[i] * cin + ci0 + 4 * akq[i];
+        v = v * *reinterpret_cast<const f4v*>(a.gn_scale + so) + *reinterpret_cast<const f4v*>(a.gn_shift + so);
+        if (a.act == 2) {
+          v.x = silu_f(v.x); v.y = silu_f(v.y); v.z = silu_f(v.z); v.w = silu_f(v.w);
         }
       }
+      if (!pok[i]) v = (f4v){0.f, 0.f, 0.f, 0.f};
       float* dst = &As[buf][(4 * akq[i]) * AS + aml[i]];
       dst[0] = v.x;
       dst[AS] = v.y;
@@ -140,9 +135,9 @@ __global__ __launch_bounds__(256, 2) void conv_kernel(ConvArgs a, int n_tiles_n)
     }
 #pragma unroll
     for (int i = 0; i < NBL; ++i) {
-      int e = tid + 256 * i;
+      const int e = tid + 256 * i;
       if (e < BK * BN / 4) {
-        int row = e / (BN / 4), c4 = e % (BN / 4);
+        const int row = e / (BN / 4), c4 = e % (BN / 4);
         *reinterpret_cast<f4v*>(&Bs[buf][row * BS + 4 * c4]) = rb[i];
       }
     }
@@ -154,7 +149,10 @@ __global__ __launch_bounds__(256, 2) void conv_kernel(ConvArgs a, int n_tiles_n)
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = (f4v){0.f, 0.f, 0.f, 0.f};
 
-  load_chunk(0);
+  const int nchunks = TAPS * (cin / BK);
+  int tap_n = 0, ci_n = 0;
+  set_tap(0);
+  load_chunk(0, 0);
   store_chunk(0, 0);
   __syncthreads();
 
@@ -164,34 +162,46 @@ __global__ __launch_bounds__(256, 2) void conv_kernel(ConvArgs a, int n_tiles_n)
 
   for (int c = 0; c < nchunks; ++c) {
     const int buf = c & 1;
-    if (c + 1 < nchunks) load_chunk(c + 1);
+    const bool more = c + 1 < nchunks;
+    if (more) {
+      ci_n += BK;
+      if (ci_n == cin) {
+        ci_n = 0;
+        ++tap_n;
+        set_tap(tap_n);
+      }
+      load_chunk(tap_n, ci_n);
+    }
+    // All LDS operand reads of the stage first, then the MFMA chain.
     const float* Ab = As[buf];
     const float* Bb = Bs[buf];
+    float av[KS][TM], bv[KS][TN];
 #pragma unroll
-    for (int kk = 0; kk < BK / 4; ++kk) {
+    for (int kk = 0; kk < KS; ++kk) {
       const int krow = kk * 4 + kl;
-      float av[TM], bv[TN];
       if constexpr (TM == 4) {
         f4v t = *reinterpret_cast<const f4v*>(&Ab[krow * AS + arow]);
-        av[0] = t.x; av[1] = t.y; av[2] = t.z; av[3] = t.w;
+        av[kk][0] = t.x; av[kk][1] = t.y; av[kk][2] = t.z; av[kk][3] = t.w;
       } else {
 #pragma unroll
-        for (int r = 0; r < TM; ++r) av[r] = Ab[krow * AS + arow + r];
+        for (int r = 0; r < TM; ++r) av[kk][r] = Ab[krow * AS + arow + r];
       }
       if constexpr (TN == 4) {
         f4v t = *reinterpret_cast<const f4v*>(&Bb[krow * BS + brow]);
-        bv[0] = t.x; bv[1] = t.y; bv[2] = t.z; bv[3] = t.w;
+        bv[kk][0] = t.x; bv[kk][1] = t.y; bv[kk][2] = t.z; bv[kk][3] = t.w;
       } else {
 #pragma unroll
-        for (int r = 0; r < TN; ++r) bv[r] = Bb[krow * BS + brow + r];
+        for (int r = 0; r < TN; ++r) bv[kk][r] = Bb[krow * BS + brow + r];
       }
+    }
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk)
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i], bv[j], acc[i][j], 0, 0, 0);
-    }
-    if (c + 1 < nchunks) store_chunk(c + 1, buf ^ 1);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk][i], bv[kk][j], acc[i][j], 0, 0, 0);
+    if (more) store_chunk(buf ^ 1, ci_n);
     __syncthreads();
   }
 

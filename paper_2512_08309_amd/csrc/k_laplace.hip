@@ -10,8 +10,8 @@
 // 8x8 block mean, G5 the separable sigma = 5 Gaussian (radius 15) at latent
 // resolution.  There is no padding: the latent covers a 17-pixel apron.
 //
-// Stages: (1) down8(P) per latent block, evaluating its 64 pixels in
-// registers; (2) vertical then (3) horizontal 31-tap blur at latent
+// Stages: (1) down8(P) per latent block as a 3x3 stencil on the latent;
+// (2) vertical then (3) horizontal 31-tap blur at latent
 // resolution; (4) the full-resolution pass, one thread per output pixel,
 // which is the HBM-bound one (4 B written per pixel, the latent read once
 // through the caches).
@@ -62,25 +62,29 @@ __device__ __forceinline__ float residual_at(const float* lat, int lw, int C, fl
   return sr * h;
 }
 
-// (1) D(bx, by) = mean of P over latent block (bx, by); block origin
-// relative to the latent origin is (bx0 + i, by0 + j).
+// (1) D(bx, by) = mean of P over latent block (bx, by).  Bilinear
+// half-pixel up8 followed by the 8x8 block mean is exactly the separable
+// stencil [1, 6, 1]/8 on the latent grid; the residual contributes
+// sum_k r_k * mean(beta_k) (the atom means are zero up to rounding of the
+// table).  Block origin relative to the latent origin: (bx0 + i, by0 + j).
 __global__ __launch_bounds__(256) void down_p_kernel(const float* __restrict__ lat, int lw, int C, float sl,
-                                                     float sr, const float* __restrict__ atoms, int bx0,
+                                                     float sr, const float* __restrict__ atom_mean, int bx0,
                                                      int by0, int nx, int ny, float* __restrict__ D) {
   int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= nx * ny) return;
   int j = e / nx, i = e % nx;
-  int X0r = (bx0 + i) * 8, Y0r = (by0 + j) * 8;
-  float s = 0.f;
-  for (int yy = 0; yy < 8; ++yy) {
-    float row = 0.f;
-    for (int xx = 0; xx < 8; ++xx) {
-      int Xr = X0r + xx, Yr = Y0r + yy;
-      row += up8_latent(lat, lw, C, sl, Xr, Yr) + residual_at(lat, lw, C, sr, atoms, Xr, Yr);
-    }
-    s += row;
-  }
-  D[e] = s * (1.0f / 64.0f);
+  const int x = bx0 + i, y = by0 + j;
+  const float* r0 = lat + ((size_t)(y - 1) * lw + x - 1) * C;
+  const float* r1 = r0 + (size_t)lw * C;
+  const float* r2 = r1 + (size_t)lw * C;
+  float a = (r0[0] + 6.f * r0[C] + r0[2 * C]) * 0.125f;
+  float b = (r1[0] + 6.f * r1[C] + r1[2 * C]) * 0.125f;
+  float c = (r2[0] + 6.f * r2[C] + r2[2 * C]) * 0.125f;
+  float d = sl * ((a + 6.f * b + c) * 0.125f);
+  int nk = C - 1 < 3 ? C - 1 : 3;
+  float h = 0.f;
+  for (int k = 0; k < nk; ++k) h += r1[C + 1 + k] * atom_mean[k];
+  D[e] = d + sr * h;
 }
 
 // (2) vertical blur: out[j][i] = sum_t g[t] in[j + t][i], out rows ny_out
@@ -106,15 +110,11 @@ __global__ __launch_bounds__(256) void blur_h_kernel(const float* __restrict__ i
 }
 
 // (4) full resolution: z = up8(L_hat) + Hres, elevation = sign(z) z^2.
-__global__ __launch_bounds__(256) void decode_out_kernel(const float* __restrict__ lat, int lw, int C, float sr,
-                                                         const float* __restrict__ atoms,
-                                                         const float* __restrict__ lhat, int nlx, int hx0,
-                                                         int hy0, int xo, int yo, int W, int H,
-                                                         float* __restrict__ out) {
-  int X = blockIdx.x * 256 + threadIdx.x;
-  int Y = blockIdx.y;
-  if (X >= W) return;
-  int Xr = xo + X, Yr = yo + Y;   // relative to 8*lx0, 8*ly0
+// Each thread writes 4 consecutive pixels of a row (one 16-byte store when
+// the row is 16-byte aligned).
+__device__ __forceinline__ float decode_px(const float* __restrict__ lat, int lw, int C, float sr,
+                                           const float* __restrict__ atoms, const float* __restrict__ lhat,
+                                           int nlx, int hx0, int hy0, int Xr, int Yr) {
   int ix = ((2 * Xr - 7) >> 4) - hx0, iy = ((2 * Yr - 7) >> 4) - hy0;
   float fx = (float)((2 * Xr - 7) - 16 * ((2 * Xr - 7) >> 4)) * 0.0625f;
   float fy = (float)((2 * Yr - 7) - 16 * ((2 * Yr - 7) >> 4)) * 0.0625f;
@@ -122,7 +122,28 @@ __global__ __launch_bounds__(256) void decode_out_kernel(const float* __restrict
   float a0 = (1.f - fy) * r0[0] + fy * r0[nlx];
   float a1 = (1.f - fy) * r0[1] + fy * r0[nlx + 1];
   float z = (1.f - fx) * a0 + fx * a1 + residual_at(lat, lw, C, sr, atoms, Xr, Yr);
-  out[(size_t)Y * W + X] = (z < 0.f ? -z : z) * z;
+  return (z < 0.f ? -z : z) * z;
+}
+
+__global__ __launch_bounds__(256) void decode_out_kernel(const float* __restrict__ lat, int lw, int C, float sr,
+                                                         const float* __restrict__ atoms,
+                                                         const float* __restrict__ lhat, int nlx, int hx0,
+                                                         int hy0, int xo, int yo, int W, int H,
+                                                         float* __restrict__ out) {
+  int X = 4 * (blockIdx.x * 256 + threadIdx.x);
+  int Y = blockIdx.y;
+  if (X >= W) return;
+  int Yr = yo + Y;
+  float v[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    v[q] = (X + q < W) ? decode_px(lat, lw, C, sr, atoms, lhat, nlx, hx0, hy0, xo + X + q, Yr) : 0.f;
+  float* o = out + (size_t)Y * W + X;
+  if (X + 3 < W && (((uintptr_t)o) & 15) == 0) {
+    *reinterpret_cast<float4*>(o) = make_float4(v[0], v[1], v[2], v[3]);
+  } else {
+    for (int q = 0; q < 4 && X + q < W; ++q) o[q] = v[q];
+  }
 }
 
 }  // namespace
@@ -145,7 +166,7 @@ void launch_decode(hipStream_t st, const DecodeArgs& a) {
   const int bx0 = (int)(s.xl - R - a.lx0), by0 = (int)(s.yl - R - a.ly0);
   prof_begin(st);
   hipLaunchKernelGGL(down_p_kernel, dim3((nxD * nyD + 255) / 256), dim3(256), 0, st, a.latent, a.lw, a.C,
-                     a.sigma_low, a.sigma_res, a.atoms, bx0, by0, nxD, nyD, a.work0);
+                     a.sigma_low, a.sigma_res, a.atoms + 3 * 64, bx0, by0, nxD, nyD, a.work0);
   TD_LAUNCHED();
   hipLaunchKernelGGL(blur_v_kernel, dim3((nxD * ny + 255) / 256), dim3(256), 0, st, a.work0, nxD, ny, a.taps, R,
                      a.work1);
@@ -154,7 +175,7 @@ void launch_decode(hipStream_t st, const DecodeArgs& a) {
                      a.work0);
   TD_LAUNCHED();
   const int xo = (int)(a.X0 - 8 * a.lx0), yo = (int)(a.Y0 - 8 * a.ly0);
-  hipLaunchKernelGGL(decode_out_kernel, dim3((a.W + 255) / 256, a.H), dim3(256), 0, st, a.latent, a.lw, a.C,
+  hipLaunchKernelGGL(decode_out_kernel, dim3((a.W + 1023) / 1024, a.H), dim3(256), 0, st, a.latent, a.lw, a.C,
                      a.sigma_res, a.atoms, a.work0, nx, (int)(s.xl - a.lx0), (int)(s.yl - a.ly0), xo, yo, a.W,
                      a.H, a.out);
   TD_LAUNCHED();

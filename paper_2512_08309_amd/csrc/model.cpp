@@ -136,7 +136,7 @@ void Model::load(const std::string& path, hipStream_t st) {
     taps_ = (float*)upload(gf);
     const double PI = 3.14159265358979323846;
     double b0 = 1.0 / std::sqrt(8.0);
-    std::vector<float> at(3 * 64);
+    std::vector<float> at(3 * 64 + 3);
     for (int y = 0; y < 8; ++y)
       for (int x = 0; x < 8; ++x) {
         double bx = 0.5 * std::cos(PI * (2 * x + 1) / 16.0), by = 0.5 * std::cos(PI * (2 * y + 1) / 16.0);
@@ -144,6 +144,11 @@ void Model::load(const std::string& path, hipStream_t st) {
         at[1 * 64 + y * 8 + x] = (float)(b0 * by);   // atom (0,1): varies along y
         at[2 * 64 + y * 8 + x] = (float)(bx * by);   // atom (1,1)
       }
+    for (int k = 0; k < 3; ++k) {   // block means of the stored (rounded) atoms
+      double m = 0;
+      for (int e = 0; e < 64; ++e) m += at[k * 64 + e];
+      at[3 * 64 + k] = (float)(m / 64.0);
+    }
     atoms_ = (float*)upload(at);
   }
 

@@ -165,7 +165,7 @@ struct DecodeArgs {
   float sigma_low, sigma_res;
   const float* taps;     // 2R+1 Gaussian taps
   int radius;
-  const float* atoms;    // [3][8][8]
+  const float* atoms;    // [3][8][8] atoms, then their 3 block means
   float* work0;          // latent-resolution scratch
   float* work1;
 };
