@@ -117,13 +117,17 @@ td_status td_cache_peek(td_ctx *ctx, uint64_t seed, int32_t level, int64_t ix,
                         int64_t iy, float *out, size_t out_len);
 
 /* Options: "batch" = max windows per batched denoiser round (>= 1);
- * "cache_budget" = as td_cache_set_budget; "timing" = 1 records every kernel
+ * "cache_budget" = as td_cache_set_budget; "precision" = 0 FP32 network
+ * (default), 1 BF16 convolution operands with FP32 accumulation (GroupNorm
+ * statistics, attention, the input/output layers, blend, Euler update and
+ * decode stay FP32); changing it clears the cache; "timing" = 1 records every kernel
  * launch between HIP events on its stream (see td_kernel_stats), 0 stops.
  * TD_E_INVAL for unknown keys. */
 td_status td_set_option(td_ctx *ctx, const char *key, int64_t value);
 
 /* Model facts: "channels", "steps", "window", "stride", "offset",
- * "factor" (decode), "params".  TD_E_INVAL for unknown keys. */
+ * "factor" (decode), "params", "batch", "precision".  TD_E_INVAL for
+ * unknown keys. */
 td_status td_get_info(td_ctx *ctx, const char *key, int64_t *value);
 
 /* Denoiser D(x; sigma_k) of the loaded model on `n` windows (EDM

@@ -106,3 +106,20 @@ def sample(model, seed, x0, y0, w, h, level):
     for t in range(top - 1, level - 1, -1):
         j = level_step(model, j, regions[t + 1], regions[t], kappa_list(regions[t], model.H, model.s, model.o), t)
     return j
+
+
+def sample_levels(model, seed, x0, y0, w, h, level=0):
+    """{t: J_t on [x0, x0+w) x [y0, y0+h)} for t = level..K from one evaluation
+    of the cone (each level's canvas contains the query region)."""
+    K = model.K
+    region = (x0, y0, w, h)
+    regions, kappas = cone(region, level, K, model.H, model.s, model.o)
+    if any(kappas[t] is None for t in range(level, K)):
+        raise ValueError("sample_levels needs a layout without gaps")
+    rK = regions[K]
+    j = model.sched[0] * noise_region(seed, rK[0], rK[1], rK[2], rK[3], model.C).astype(np.float64)
+    out = {K: _crop(j, rK, region).copy()}
+    for t in range(K - 1, level - 1, -1):
+        j = level_step(model, j, regions[t + 1], regions[t], kappa_list(regions[t], model.H, model.s, model.o), t)
+        out[t] = _crop(j, regions[t], region).copy()
+    return out

@@ -667,6 +667,14 @@ td_status td_set_option(td_ctx* c, const char* key, int64_t value) {
     if (k == "batch") {
       TD_CHECK(value >= 1 && value <= (1 << 20), TD_E_INVAL, "batch must be in [1, 2^20]");
       c->batch = (int)value;
+    } else if (k == "precision") {
+      need_model(c);
+      TD_HIP(hipStreamSynchronize(c->stream));
+      c->model->set_precision((int)value);
+      // cached contributions were computed at the previous precision
+      for (auto& kv : c->map) c->pool.give(kv.second.slot);
+      c->map.clear();
+      c->lru.clear();
     } else if (k == "timing") {
       if (value && !c->prof) c->prof.reset(new Profiler());
       if (!value && c->prof) {
@@ -698,6 +706,7 @@ td_status td_get_info(td_ctx* c, const char* key, int64_t* value) {
     else if (k == "factor") *value = d.factor;
     else if (k == "params") *value = (int64_t)d.params;
     else if (k == "batch") *value = auto_batch(c);
+    else if (k == "precision") *value = c->model->precision();
     else throw Error{TD_E_INVAL, "unknown info key: " + k};
   });
 }

@@ -1,0 +1,236 @@
+// Reduced-precision implicit-GEMM convolution: BF16 operands on CDNA4
+// matrix cores (v_mfma_f32_16x16x32_bf16), FP32 accumulation, FP32 output
+// with bias and residual added in FP32.
+//
+// Operands are prepared outside: activations by the GroupNorm-apply kernel
+// (NHWC BF16, the virtual concat / upsample / GN / SiLU already applied),
+// weights at load time as [C_out][Kp] BF16 with K = tap * C_in + c_in
+// flattened and zero-padded to a multiple of the stage depth.  With no
+// per-element transform left, staging is plain 16-byte copies: one
+// (pixel, 8-channel) segment per load.
+//
+// Tile 128 x 128 per 256-thread workgroup (4 waves, 2 x 2, 64 x 64 each),
+// K advances BK per stage through double-buffered LDS.  LDS rows hold BK
+// BF16 values of one pixel (A) or one output channel (B); the 16-byte
+// segments of a row are XOR-swizzled by the row index so that the MFMA
+// operand reads (16 consecutive rows, same segment) are bank-conflict free.
+// A K-group g of an MFMA lane pairs the same 8 K indices for A and B, so
+// the product is the plain dot product whatever order the hardware sums
+// the 32 terms in; that order is fixed, keeping results batch-invariant.
+//
+// FAST (C_in a multiple of BK = 64): a stage never straddles a tap, so the
+// shifted pixel address is computed once per tap.  Otherwise (small C_in)
+// BK = 32 and every segment resolves its own (tap, channel).
+#include "td_internal.h"
+
+namespace td {
+namespace {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
+
+template <int BK>
+__device__ __forceinline__ int swz(int row, int seg) {
+  return BK == 64 ? (seg ^ (row & 7)) : (seg ^ ((row >> 1) & 3));
+}
+
+template <int TAPS, bool FAST, int BN, int WM, int WN>
+__global__ __launch_bounds__(256, 2) void conv_bf16_kernel(ConvLpArgs a, int n_tiles_n) {
+  constexpr int BM = 128;
+  constexpr int BK = FAST ? 64 : 32;
+  constexpr int SEGS = BK / 8;             // 16-byte segments per row
+  constexpr int AL = BM * SEGS / 256;      // A segment loads per thread
+  constexpr int BL = (BN * SEGS + 255) / 256;
+  constexpr int KS = BK / 32;              // MFMA k-steps per stage
+  constexpr int TM = BM / WM / 16, TN = BN / WN / 16;
+  __shared__ __attribute__((aligned(16))) u4v As[2][BM * SEGS];
+  __shared__ __attribute__((aligned(16))) u4v Bs[2][BN * SEGS];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WM, wn = wave / WM;
+  const int bid = blockIdx.x, nblk = gridDim.x;
+  const int tile = ((nblk & 7) == 0) ? (bid & 7) * (nblk >> 3) + (bid >> 3) : bid;
+  const int tn = tile % n_tiles_n, tm = tile / n_tiles_n;
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int lw = a.lw, lh = a.lh, W = 1 << lw, H = 1 << lh, lhw = lw + lh;
+  const int M = a.nb << lhw;
+  const int cin = a.cin, Kp = a.kp, K = TAPS * cin;
+  const __bf16* act = reinterpret_cast<const __bf16*>(a.act);
+  const __bf16* wts = reinterpret_cast<const __bf16*>(a.wt);
+
+  // this thread's A pixel (fixed) and segments s = tid/128 + 2j
+  const int am = tid & (BM - 1), s0 = tid >> 7;
+  const int mrow = m0 + am;
+  const bool mval = mrow < M;
+  const int mm = mval ? mrow : 0;
+  const int ab = mm >> lhw, ay = (mm >> lw) & (H - 1), ax = mm & (W - 1);
+
+  u4v ra[AL], rb[BL];
+  const u4v zero = {0u, 0u, 0u, 0u};
+  const __bf16* pix = act;   // shifted pixel base (FAST)
+  bool pok = false;
+  auto set_tap = [&](int tap) {
+    int dy = 0, dx = 0;
+    if (TAPS == 9) { dy = tap / 3 - 1; dx = tap % 3 - 1; }
+    const int yy = ay + dy, xx = ax + dx;
+    pok = mval && yy >= 0 && yy < H && xx >= 0 && xx < W;
+    const int yc = pok ? yy : 0, xc = pok ? xx : 0;
+    pix = act + ((((size_t)ab << lhw) + ((size_t)yc << lw) + xc) * cin);
+  };
+  auto load_stage = [&](int k0, int ci0) {
+#pragma unroll
+    for (int j = 0; j < AL; ++j) {
+      const int s = s0 + 2 * j;
+      if (FAST) {
+        u4v v = *reinterpret_cast<const u4v*>(pix + ci0 + 8 * s);
+        ra[j] = pok ? v : zero;
+      } else {
+        const int k = k0 + 8 * s;
+        const int t = k / cin, ci = k - t * cin;
+        int dy = 0, dx = 0;
+        if (TAPS == 9) { dy = t / 3 - 1; dx = t % 3 - 1; }
+        const int yy = ay + dy, xx = ax + dx;
+        const bool ok = mval && k < K && yy >= 0 && yy < H && xx >= 0 && xx < W;
+        const int yc = ok ? yy : 0, xc = ok ? xx : 0;
+        u4v v = *reinterpret_cast<const u4v*>(
+            act + ((((size_t)ab << lhw) + ((size_t)yc << lw) + xc) * cin + (ok ? ci : 0)));
+        ra[j] = ok ? v : zero;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < BL; ++j) {
+      const int e = tid + 256 * j;
+      if (e < BN * SEGS) {
+        const int n = e % BN, s = e / BN;
+        rb[j] = *reinterpret_cast<const u4v*>(wts + (size_t)(n0 + n) * Kp + k0 + 8 * s);
+      }
+    }
+  };
+  auto store_stage = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < AL; ++j) {
+      const int s = s0 + 2 * j;
+      As[buf][am * SEGS + swz<BK>(am, s)] = ra[j];
+    }
+#pragma unroll
+    for (int j = 0; j < BL; ++j) {
+      const int e = tid + 256 * j;
+      if (e < BN * SEGS) {
+        const int n = e % BN, s = e / BN;
+        Bs[buf][n * SEGS + swz<BK>(n, s)] = rb[j];
+      }
+    }
+  };
+
+  f4v acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = (f4v){0.f, 0.f, 0.f, 0.f};
+
+  const int nst = Kp / BK;
+  int tap = 0, ci = 0;
+  if (FAST) set_tap(0);
+  load_stage(0, 0);
+  store_stage(0);
+  __syncthreads();
+
+  const int g = lane >> 4, r16 = lane & 15;
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    const bool more = st + 1 < nst;
+    if (more) {
+      if (FAST) {
+        ci += BK;
+        if (ci == cin) {
+          ci = 0;
+          ++tap;
+          set_tap(tap);
+        }
+      }
+      load_stage((st + 1) * BK, ci);
+    }
+    bf8v av[KS][TM], bv[KS][TN];
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      const int seg = 4 * kk + g;
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int row = wm * (BM / WM) + 16 * i + r16;
+        u4v u = As[buf][row * SEGS + swz<BK>(row, seg)];
+        av[kk][i] = __builtin_bit_cast(bf8v, u);
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int col = wn * (BN / WN) + 16 * j + r16;
+        u4v w = Bs[buf][col * SEGS + swz<BK>(col, seg)];
+        bv[kk][j] = __builtin_bit_cast(bf8v, w);
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk)
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[kk][i], bv[kk][j], acc[i][j], 0, 0, 0);
+    if (more) store_stage(buf ^ 1);
+    __syncthreads();
+  }
+
+  // Epilogue: tile (i, j), lane holds rows 4g+v, column r16.
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const int n = n0 + wn * (BN / WN) + 16 * j + r16;
+    const float bias = a.bias ? a.bias[n] : 0.f;
+    const float scl = a.wscale ? a.wscale[n] : 1.f;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = m0 + wm * (BM / WM) + 16 * i + 4 * g + v;
+        if (m >= M) continue;
+        const size_t off = (size_t)m * a.cout + n;
+        float o = acc[i][j][v] * scl + bias;
+        if (a.res) o += a.res[off];
+        a.out[off] = o;
+      }
+  }
+}
+
+template <int BN, int WM, int WN>
+void launch_lp_cfg(hipStream_t st, const ConvLpArgs& a, bool fast) {
+  const int M = a.nb << (a.lh + a.lw);
+  const int mt = (M + 127) / 128, nt = a.cout / BN;
+  if (a.taps == 9 && fast)
+    hipLaunchKernelGGL((conv_bf16_kernel<9, true, BN, WM, WN>), dim3(mt * nt), dim3(256), 0, st, a, nt);
+  else if (a.taps == 9)
+    hipLaunchKernelGGL((conv_bf16_kernel<9, false, BN, WM, WN>), dim3(mt * nt), dim3(256), 0, st, a, nt);
+  else if (fast)
+    hipLaunchKernelGGL((conv_bf16_kernel<1, true, BN, WM, WN>), dim3(mt * nt), dim3(256), 0, st, a, nt);
+  else
+    hipLaunchKernelGGL((conv_bf16_kernel<1, false, BN, WM, WN>), dim3(mt * nt), dim3(256), 0, st, a, nt);
+  TD_LAUNCHED();
+}
+
+}  // namespace
+
+void launch_conv_lp(hipStream_t st, const ConvLpArgs& a) {
+  TD_CHECK(a.cin % 8 == 0 && (a.cout % 128 == 0 || a.cout == 32 || a.cout == 16), -5,
+           "bf16 conv: needs C_in % 8 == 0 and C_out in {16, 32, 128k}");
+  TD_CHECK(a.taps == 9 || a.taps == 1, -5, "bf16 conv: taps must be 9 or 1");
+  if (!a.nb) return;
+  const bool fast = a.cin % 64 == 0;
+  const int BK = fast ? 64 : 32;
+  TD_CHECK(a.kp % BK == 0 && a.kp >= a.taps * a.cin, -5, "bf16 conv: bad padded K");
+  const double Md = (double)(a.nb << (a.lh + a.lw));
+  prof_begin(st);
+  if (a.cout % 128 == 0) launch_lp_cfg<128, 2, 2>(st, a, fast);
+  else if (a.cout == 32) launch_lp_cfg<32, 4, 1>(st, a, fast);
+  else launch_lp_cfg<16, 4, 1>(st, a, fast);
+  prof_end(st, a.taps == 9 ? K_CONV3_LP : K_CONV1_LP, 2.0 * Md * a.cout * a.taps * a.cin,
+           2.0 * Md * a.cin + 2.0 * a.kp * a.cout + 4.0 * Md * a.cout * (a.res ? 2 : 1));
+}
+
+}  // namespace td

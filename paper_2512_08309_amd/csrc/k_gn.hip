@@ -105,7 +105,65 @@ __global__ __launch_bounds__(256) void gn_finalize_kernel(GnArgs a, int nchunk) 
   }
 }
 
+__device__ __forceinline__ float silu_f(float v) { return v * __builtin_amdgcn_rcpf(1.0f + __expf(-v)); }
+
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
+  typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+  bf2 p = {(__bf16)lo, (__bf16)hi};
+  return __builtin_bit_cast(uint32_t, p);
+}
+
+// One thread per (pixel, 8 channels): reads the virtual conv input in FP32,
+// applies the GroupNorm affine (and SiLU), writes 16 bytes of BF16.
+__global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
+  const int cin = a.c0 + a.c1, q8 = cin / 8;
+  const int lhw = a.lh + a.lw;
+  const size_t n = ((size_t)a.nb << lhw) * q8;
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const int q = (int)(e % q8);
+  const size_t p = e / q8;
+  const int b = (int)(p >> lhw);
+  const int y = (int)((p >> a.lw) & ((1 << a.lh) - 1)), x = (int)(p & ((1 << a.lw) - 1));
+  const int c = 8 * q;
+  const float* s;
+  if (c < a.c0) {
+    if (a.up0)
+      s = a.src0 + ((((size_t)b << (lhw - 2)) + ((size_t)(y >> 1) << (a.lw - 1)) + (x >> 1)) * a.c0 + c);
+    else
+      s = a.src0 + (p * a.c0 + c);
+  } else {
+    s = a.src1 + (p * a.c1 + (c - a.c0));
+  }
+  float4 v0 = *reinterpret_cast<const float4*>(s);
+  float4 v1 = *reinterpret_cast<const float4*>(s + 4);
+  float v[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+  if (a.act) {
+    const float* sc = a.scale + (size_t)b * cin + c;
+    const float* sh = a.shift + (size_t)b * cin + c;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      v[j] = v[j] * sc[j] + sh[j];
+      if (a.act == 2) v[j] = silu_f(v[j]);
+    }
+  }
+  uint4 o = {pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]), pack_bf16(v[4], v[5]), pack_bf16(v[6], v[7])};
+  *reinterpret_cast<uint4*>(a.out + p * cin + c) = o;
+}
+
 }  // namespace
+
+void launch_apply(hipStream_t st, const ApplyArgs& a) {
+  const int cin = a.c0 + a.c1;
+  TD_CHECK(cin % 8 == 0 && a.c0 % 8 == 0, -5, "apply: channels must be multiples of 8");
+  const size_t n = ((size_t)a.nb << (a.lh + a.lw)) * (cin / 8);
+  if (!n) return;
+  prof_begin(st);
+  hipLaunchKernelGGL(apply_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+  TD_LAUNCHED();
+  const double el = 8.0 * n;
+  prof_end(st, K_APPLY, 4.0 * el, el * (2.0 + (a.up0 ? 4.0 * a.c1 / cin + 1.0 * a.c0 / cin : 4.0)));
+}
 
 size_t gn_partial_doubles(int nb, int lh, int lw, int cin, int groups) {
   return (size_t)nb * 16 * groups * 2;

@@ -54,6 +54,52 @@ const float* Model::upload(const std::vector<float>& v) {
   return p;
 }
 
+namespace {
+// float -> bfloat16, round to nearest even (NaN kept quiet).
+uint16_t to_bf16(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+}  // namespace
+
+// File layout [co][ci][k][k] -> [co][kp] BF16 with K = tap * ci + c, zero padded.
+const uint16_t* Model::upload_lp(const std::vector<float>& w, int co, int ci, int k, int* kp) {
+  const int taps = k * k;
+  *kp = conv_lp_kp(taps, ci);
+  std::vector<uint16_t> r((size_t)co * *kp, 0);
+  for (int o = 0; o < co; ++o)
+    for (int i = 0; i < ci; ++i)
+      for (int t = 0; t < taps; ++t) r[(size_t)o * *kp + t * ci + i] = to_bf16(w[((size_t)o * ci + i) * taps + t]);
+  void* p = nullptr;
+  TD_HIP(hipMalloc(&p, std::max<size_t>(r.size(), 1) * sizeof(uint16_t)));
+  allocs_.push_back(p);
+  TD_HIP(hipMemcpy(p, r.data(), r.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+  return (const uint16_t*)p;
+}
+
+int Model::cin_max(int l) const {
+  const int nl = (int)d.ch.size();
+  int c = d.ch[l];
+  if (l > 0) c = std::max(c, d.ch[l - 1]);
+  int up = l < nl - 1 ? d.ch[l + 1] : d.ch[l];
+  c = std::max(c, up + d.ch[l]);
+  return c;
+}
+
+void Model::set_precision(int p) {
+  TD_CHECK(p == 0 || p == 1, -1, "precision must be 0 (fp32) or 1 (bf16)");
+  if (p != 0) TD_CHECK(d.kind == "unet", -1, "reduced precision applies to the network denoiser only");
+  if (p != prec_ && ws_) {
+    TD_HIP(hipDeviceSynchronize());
+    TD_HIP(hipFree(ws_));
+    ws_ = nullptr;
+    ws_batch_ = 0;
+  }
+  prec_ = p;
+}
+
 void Model::load(const std::string& path, hipStream_t st) {
   std::ifstream f(path, std::ios::binary);
   TD_CHECK(f.good(), -4, "cannot open weight file: " + path);
@@ -193,6 +239,9 @@ void Model::build_unet(const std::map<std::string, std::vector<float>>& host,
     return upload(r);
   };
   auto vec = [&](const std::string& name, int n) { return upload(get(name, {n})); };
+  auto lp = [&](const std::string& name, int co, int ci, int k, int* kp) {
+    return upload_lp(get(name, {co, ci, k, k}), co, ci, k, kp);
+  };
 
   const int nl = (int)d.ch.size();
   const int c0 = d.ch[0];
@@ -227,10 +276,13 @@ void Model::build_unet(const std::map<std::string, std::vector<float>>& host,
     w.gn2_b = vec(p + "gn2.bias", cout);
     w.w2 = conv_layout(p + "conv2.weight", cout, cout, 3);
     w.b2 = vec(p + "conv2.bias", cout);
+    w.w1_lp = lp(p + "conv1.weight", cout, cin, 3, &w.kp1);
+    w.w2_lp = lp(p + "conv2.weight", cout, cout, 3, &w.kp2);
     w.has_skip = cin != cout;
     if (w.has_skip) {
       w.wskip = conv_layout(p + "skip.weight", cout, cin, 1);
       w.bskip = vec(p + "skip.bias", cout);
+      w.wskip_lp = lp(p + "skip.weight", cout, cin, 1, &w.kps);
     }
     TD_CHECK(cin % d.groups == 0 && cout % d.groups == 0, -5, "GroupNorm groups must divide channels");
     rb_[p] = w;
@@ -245,6 +297,8 @@ void Model::build_unet(const std::map<std::string, std::vector<float>>& host,
     w.bqkv = vec(p + "qkv.bias", 3 * C);
     w.wproj = conv_layout(p + "proj.weight", C, C, 1);
     w.bproj = vec(p + "proj.bias", C);
+    w.wqkv_lp = lp(p + "qkv.weight", 3 * C, C, 1, &w.kpq);
+    w.wproj_lp = lp(p + "proj.weight", C, C, 1, &w.kpp);
     at_[p] = w;
   };
   std::vector<int> skipc;
@@ -302,7 +356,10 @@ size_t Model::workspace_bytes_per_window() const {
     if (d.attn_at(l) || (l == nl - 1 && d.mid_attn)) f += r2 * c * 4;  // qkv + attn out
   }
   f += 2 * 1024;                                  // GN scale/shift
-  return f * sizeof(float) + (size_t)16 * d.groups * 2 * sizeof(double);
+  size_t lp = 0;
+  if (prec_)
+    for (int l = 0; l < nl; ++l) lp += 2 * (size_t)(d.H >> l) * (d.H >> l) * cin_max(l);   // A, A0 (BF16)
+  return f * sizeof(float) + lp * sizeof(uint16_t) + (size_t)16 * d.groups * 2 * sizeof(double) + 64 * 256;
 }
 
 void Model::ensure_workspace(int max_batch) {
@@ -340,6 +397,12 @@ void Model::ensure_workspace(int max_batch) {
     } else {
       b.Q = b.O = nullptr;
     }
+    if (prec_) {
+      b.A = (uint16_t*)take((r2 * cin_max(l) + 1) / 2);
+      b.A0 = (uint16_t*)take((r2 * cin_max(l) + 1) / 2);
+    } else {
+      b.A = b.A0 = nullptr;
+    }
   }
   gn_scale_ = take((size_t)max_batch * 1024);
   gn_shift_ = take((size_t)max_batch * 1024);
@@ -369,11 +432,65 @@ void Model::gn(hipStream_t st, const float* s0, int c0, int up0, const float* s1
   launch_gn(st, a);
 }
 
+void Model::conv_lp(hipStream_t st, const uint16_t* act, int cin, int nb, int lr, int cout, int taps,
+                    const uint16_t* wt, int kp, const float* bias, const float* res, float* out) {
+  ConvLpArgs a{};
+  a.act = act;
+  a.cin = cin;
+  a.nb = nb;
+  a.lh = lr;
+  a.lw = lr;
+  a.cout = cout;
+  a.taps = taps;
+  a.kp = kp;
+  a.wt = wt;
+  a.bias = bias;
+  a.res = res;
+  a.out = out;
+  launch_conv_lp(st, a);
+}
+
+void Model::apply(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int act, int nb, int lr,
+                  uint16_t* out) {
+  ApplyArgs a{};
+  a.src0 = s0;
+  a.src1 = s1;
+  a.c0 = c0;
+  a.c1 = c1;
+  a.up0 = up0;
+  a.scale = gn_scale_;
+  a.shift = gn_shift_;
+  a.act = act;
+  a.nb = nb;
+  a.lh = lr;
+  a.lw = lr;
+  a.out = out;
+  launch_apply(st, a);
+}
+
 void Model::resblock(hipStream_t st, const ResBlockW& w, int k, const float* s0, int c0, int up0, const float* s1,
                      int c1, int nb, int lvl, float* out) {
   const int lr = ilog2(d.H >> lvl);
   LevelBufs& B = lb_[lvl];
   TD_CHECK(c0 + c1 == w.cin, -5, "resblock: channel mismatch");
+  if (prec_) {
+    const float* bias1 = bias_eff_ + w.bias_off + (size_t)k * w.cout;
+    gn(st, s0, c0, up0, s1, c1, nb, lr, lr, w.gn1_g, w.gn1_b);
+    apply(st, s0, c0, up0, s1, c1, 2, nb, lr, B.A);
+    conv_lp(st, B.A, w.cin, nb, lr, w.cout, 9, w.w1_lp, w.kp1, bias1, nullptr, B.T);
+    const float* res = s0;
+    if (w.has_skip) {
+      apply(st, s0, c0, up0, s1, c1, 0, nb, lr, B.A0);
+      conv_lp(st, B.A0, w.cin, nb, lr, w.cout, 1, w.wskip_lp, w.kps, w.bskip, nullptr, B.R);
+      res = B.R;
+    } else {
+      TD_CHECK(c1 == 0 && !up0, -5, "identity skip needs a plain input");
+    }
+    gn(st, B.T, w.cout, 0, nullptr, 0, nb, lr, lr, w.gn2_g, w.gn2_b);
+    apply(st, B.T, w.cout, 0, nullptr, 0, 2, nb, lr, B.A);
+    conv_lp(st, B.A, w.cout, nb, lr, w.cout, 9, w.w2_lp, w.kp2, w.b2, res, out);
+    return;
+  }
   gn(st, s0, c0, up0, s1, c1, nb, lr, lr, w.gn1_g, w.gn1_b);
   ConvArgs a{};
   a.src0 = s0;
@@ -431,6 +548,14 @@ void Model::attention(hipStream_t st, const AttnW& w, const float* in, int nb, i
   const int lr = ilog2(d.H >> lvl);
   LevelBufs& B = lb_[lvl];
   gn(st, in, w.C, 0, nullptr, 0, nb, lr, lr, w.gn_g, w.gn_b);
+  if (prec_) {
+    apply(st, in, w.C, 0, nullptr, 0, 1, nb, lr, B.A);
+    conv_lp(st, B.A, w.C, nb, lr, 3 * w.C, 1, w.wqkv_lp, w.kpq, w.bqkv, nullptr, B.Q);
+    launch_attention(st, B.Q, B.O, nb, 1 << (2 * lr), w.C, d.heads);
+    apply(st, B.O, w.C, 0, nullptr, 0, 0, nb, lr, B.A);
+    conv_lp(st, B.A, w.C, nb, lr, w.C, 1, w.wproj_lp, w.kpp, w.bproj, in, out);
+    return;
+  }
   ConvArgs q{};
   q.src0 = in;
   q.c0 = w.C;

@@ -47,12 +47,17 @@ struct ResBlockW {
   const float *gn1_g = nullptr, *gn1_b = nullptr, *w1 = nullptr, *gn2_g = nullptr, *gn2_b = nullptr;
   const float *w2 = nullptr, *b2 = nullptr, *wskip = nullptr, *bskip = nullptr;
   size_t bias_off = 0;     // offset of this block's [K][cout] table in bias_eff
+  // reduced precision: [cout][kp] BF16 weights (K = tap * cin + c_in)
+  const uint16_t *w1_lp = nullptr, *w2_lp = nullptr, *wskip_lp = nullptr;
+  int kp1 = 0, kp2 = 0, kps = 0;
 };
 
 struct AttnW {
   int C = 0;
   const float *gn_g = nullptr, *gn_b = nullptr, *wqkv = nullptr, *bqkv = nullptr, *wproj = nullptr,
               *bproj = nullptr;
+  const uint16_t *wqkv_lp = nullptr, *wproj_lp = nullptr;
+  int kpq = 0, kpp = 0;
 };
 
 // Batch of windows for one denoiser round: inputs are read from a dense
@@ -82,8 +87,12 @@ class Model {
   const float* w1d() const { return w1d_; }
   const float* decode_taps() const { return taps_; }
   const float* decode_atoms() const { return atoms_; }
+  // 0: FP32 (FP32 MFMA); 1: BF16 operands, FP32 accumulation.
+  void set_precision(int p);
+  int precision() const { return prec_; }
 
  private:
+  int prec_ = 0;
   std::vector<void*> allocs_;
   std::map<std::string, const float*> t_;
   float* w1d_ = nullptr;
@@ -101,6 +110,7 @@ class Model {
   struct LevelBufs {
     float *T, *R, *X, *Y, *P, *Q, *O;
     std::vector<float*> S;
+    uint16_t *A, *A0;      // BF16 operand buffers (reduced precision)
   };
   std::vector<LevelBufs> lb_;
   float *gn_scale_ = nullptr, *gn_shift_ = nullptr;
@@ -108,6 +118,12 @@ class Model {
 
   float* dalloc(size_t n);
   const float* upload(const std::vector<float>& v);
+  const uint16_t* upload_lp(const std::vector<float>& w, int co, int ci, int k, int* kp);
+  int cin_max(int lvl) const;
+  void conv_lp(hipStream_t st, const uint16_t* act, int cin, int nb, int lr, int cout, int taps,
+               const uint16_t* wt, int kp, const float* bias, const float* res, float* out);
+  void apply(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int act, int nb,
+             int lr, uint16_t* out);
   void build_unet(const std::map<std::string, std::vector<float>>& host,
                   const std::map<std::string, std::vector<int>>& shapes, hipStream_t st);
   void gn(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int nb, int lh, int lw,

@@ -39,7 +39,7 @@ struct Error {
 // bytes of the launch).  When no profiler is installed the hooks are no-ops.
 enum KClass {
   K_CONV3 = 0, K_CONV1, K_GN, K_CONV_IN, K_CONV_OUT, K_ATTN, K_POOL, K_NOISE, K_BLEND, K_DECODE, K_LG, K_EMB,
-  K_NCLASS
+  K_CONV3_LP, K_CONV1_LP, K_APPLY, K_NCLASS
 };
 const char* kclass_name(int k);
 struct Profiler;
@@ -96,6 +96,41 @@ struct ConvArgs {
   float* out;            // [nb][h][w][cout]
 };
 void launch_conv(hipStream_t st, const ConvArgs& a);
+
+// Reduced-precision conv: BF16 operands, FP32 accumulation and output.
+struct ConvLpArgs {
+  const uint16_t* act;   // [nb][h][w][cin] BF16, activation already applied
+  int cin;
+  int nb, lh, lw;
+  int cout;
+  int taps;              // 9 (3x3, zero pad 1) or 1
+  int kp;                // padded K = round_up(taps * cin, 64 or 32)
+  const uint16_t* wt;    // [cout][kp] BF16, K = tap * cin + c_in
+  const float* wscale;   // per-output-channel weight scale or null
+  const float* bias;     // [cout]
+  const float* res;      // [nb][h][w][cout] FP32 or null
+  float* out;            // [nb][h][w][cout] FP32
+};
+void launch_conv_lp(hipStream_t st, const ConvLpArgs& a);
+// K padding a weight matrix for launch_conv_lp needs.
+inline int conv_lp_kp(int taps, int cin) {
+  int bk = cin % 64 == 0 ? 64 : 32;
+  return (taps * cin + bk - 1) / bk * bk;
+}
+
+// GroupNorm apply (+ SiLU) of the virtual conv input, written as BF16 NHWC:
+// act 0 = convert only, 1 = affine, 2 = affine + SiLU.
+struct ApplyArgs {
+  const float* src0;
+  const float* src1;
+  int c0, c1, up0;
+  const float* scale;
+  const float* shift;
+  int act;
+  int nb, lh, lw;
+  uint16_t* out;         // [nb][h][w][c0 + c1]
+};
+void launch_apply(hipStream_t st, const ApplyArgs& a);
 
 struct GnArgs {
   const float* src0;

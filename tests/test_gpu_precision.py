@@ -1,0 +1,98 @@
+"""Reduced precision (BF16 convolution operands, FP32 accumulation) against
+the FP64 oracle.
+
+The bars are the precision target of the workload (relative heightfield
+error <= 2e-2); the tests print the measured errors so they can be quoted.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import planar, rel_l2, require_gpu
+from oracle import laplace
+from oracle.sampler import Model, sample_levels
+
+pytestmark = pytest.mark.gpu
+
+DEC = {"factor": 8, "sigma_low": 20.0, "sigma_res": 2.0, "blur_sigma": 5.0, "blur_radius": 15}
+
+
+@pytest.fixture(scope="module")
+def lp_ctx(weights):
+    require_gpu()
+    from paper_2512_08309_amd import td
+    made = {}
+
+    def get(config, precision):
+        key = (config, precision)
+        if key not in made:
+            c = td.Context(0).load_weights(weights(config))
+            c.set_option("precision", precision)
+            assert c.info("precision") == precision
+            made[key] = c
+        return made[key]
+    yield get
+    for c in made.values():
+        c.close()
+
+
+@pytest.mark.parametrize("config,k,n", [("c1", 0, 8), ("c1", 5, 8), ("c2", 0, 2), ("c2", 15, 2)])
+def test_bf16_denoiser_close_to_oracle(lp_ctx, weights, config, k, n):
+    import torch
+    from oracle.tdw import read_tdw
+    from oracle.unet import UNetDenoiser
+    c = lp_ctx(config, 1)
+    hdr, t = read_tdw(weights(config))
+    m = Model(weights(config))
+    H, C = m.H, m.C
+    x = (m.sched[k] * np.random.default_rng(20 + k).standard_normal((n, H, H, C))).astype(np.float32)
+    xd = torch.from_numpy(x).cuda()
+    out = torch.empty_like(xd)
+    c.denoise_windows(xd, k, out)
+    ref = UNetDenoiser(hdr, t)(x.astype(np.float64), m.sched[k], None)
+    err = rel_l2(out.cpu().numpy(), ref)
+    print("bf16 denoiser %s sigma_%d rel L2 %.3e" % (config, k, err))
+    assert err <= 2e-2
+
+
+def test_bf16_c1_crop_error_every_level(lp_ctx, weights):
+    """128x128 C1 crop at (3, 9): error of every level J_t and of the heightfield."""
+    m = Model(weights("c1"))
+    region = (3, 9, 128, 128)
+    ref = sample_levels(m, 5, *region, 0)
+    c32 = lp_ctx("c1", 0)
+    c16 = lp_ctx("c1", 1)
+    errs16, errs32 = {}, {}
+    for t in range(m.K, -1, -1):
+        r = planar(ref[t])
+        errs16[t] = rel_l2(c16.sample_region(5, *region, t), r)
+        errs32[t] = rel_l2(c32.sample_region(5, *region, t), r)
+    print("per-level rel L2 vs FP64 oracle, bf16:", {t: "%.2e" % e for t, e in errs16.items()})
+    print("per-level rel L2 vs FP64 oracle, fp32:", {t: "%.2e" % e for t, e in errs32.items()})
+    assert errs16[m.K] < 1e-7 and errs32[m.K] < 1e-7    # the noise level (FP32 rounding of sigma_0 * G)
+    assert max(errs32.values()) <= 1e-4
+    assert max(errs16.values()) <= 2e-2
+    # heightfield of the interior (decode needs the 17 px apron inside the crop)
+    out = (8 * 20, 8 * 26, 8 * 90, 8 * 90)
+    lx0, ly0, lw, lh = laplace.required_latent(out, DEC)
+    assert lx0 >= 3 and ly0 >= 9 and lx0 + lw <= 131 and ly0 + lh <= 137
+    lat = ref[0][ly0 - 9:ly0 - 9 + lh, lx0 - 3:lx0 - 3 + lw]
+    href = laplace.decode(lat, (lx0, ly0), out, DEC)
+    from paper_2512_08309_amd import td
+    h16 = c16.sample_region(5, *out, td.TD_LEVEL_HEIGHT)
+    h32 = c32.sample_region(5, *out, td.TD_LEVEL_HEIGHT)
+    e16, e32 = rel_l2(h16, href), rel_l2(h32, href)
+    print("heightfield rel RMSE vs FP64 oracle: bf16 %.3e, fp32 %.3e" % (e16, e32))
+    assert e32 <= 1e-4 and e16 <= 2e-2
+
+
+def test_bf16_seed_consistency_bit_exact(lp_ctx):
+    c = lp_ctx("c1", 1)
+    c.cache_clear()
+    big = c.sample_region(4, 0, 0, 96, 80, 0)
+    c.cache_clear()
+    c.set_option("batch", 7)
+    try:
+        small = c.sample_region(4, 33, 21, 29, 30, 0)
+    finally:
+        c.set_option("batch", 4096)
+    assert np.array_equal(small, big[:, 21:51, 33:62])
