@@ -43,7 +43,8 @@ def parse():
     p.add_argument("--cpu-windows", type=int, default=16)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--bf16-steps", type=int, default=1,
-                   help="cold steps timed again with BF16 convolution operands (0 = skip)")
+                   help="cold steps timed again per reduced-precision mode (0 = skip)")
+    p.add_argument("--lowp-modes", default="1,2", help="precision modes to time: 1 bf16, 2 bf16 + fp8 weights")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="run one plain elementwise copy (read N MiB, write N MiB) before the steps, as the "
                         "reference dispatch that scales hardware byte counters")
@@ -159,26 +160,34 @@ def main():
     lowp = None
     if a.bf16_steps > 0:
         ref32 = out.clone()
-        ctx.set_option("precision", 1)
-        step()                                   # first use: workspace and kernels
-        ctx.set_option("timing", 1)
-        ctx.kernel_stats(reset=True)
-        w16 = 0
-        t0 = time.perf_counter()
-        for i in range(a.bf16_steps):
-            w16 += step()
-            print("[bench] bf16 step %d done" % i, file=sys.stderr, flush=True)
-        dt16 = time.perf_counter() - t0
-        ks16 = ctx.kernel_stats()
-        ctx.set_option("timing", 0)
-        rel = float(torch.linalg.vector_norm((out - ref32).double()) / torch.linalg.vector_norm(ref32.double()))
-        c16 = ks16.get("conv3x3_mfma_bf16", {"ms": 0.0, "flops": 0.0, "launches": 0})
-        lowp = {"precision": "bf16 convolution operands, fp32 accumulation; blend/Euler/decode fp32",
+        lowp = {}
+        names = {1: "bf16", 2: "bf16_fp8w"}
+        descr = {1: "BF16 convolution operands (activations and weights), FP32 accumulation",
+                 2: "BF16 activations, FP8 e4m3 weights with per-output-channel FP32 scales, FP32 accumulation"}
+        for mode in [int(v) for v in a.lowp_modes.split(",") if v]:
+            ctx.set_option("precision", mode)
+            step()                                   # first use: workspace and kernels
+            ctx.set_option("timing", 1)
+            ctx.kernel_stats(reset=True)
+            w16 = 0
+            t0 = time.perf_counter()
+            for i in range(a.bf16_steps):
+                w16 += step()
+                print("[bench] precision %d step %d done" % (mode, i), file=sys.stderr, flush=True)
+            dt16 = time.perf_counter() - t0
+            ks16 = ctx.kernel_stats()
+            ctx.set_option("timing", 0)
+            rel = float(torch.linalg.vector_norm((out - ref32).double()) / torch.linalg.vector_norm(ref32.double()))
+            c16 = ks16.get("conv3x3_mfma_bf16", {"ms": 0.0, "flops": 0.0, "launches": 0})
+            lowp[names[mode]] = {
+                "precision": descr[mode] + "; GN statistics, attention, input/output layers, blend/Euler and "
+                                           "decode FP32",
                 "value": w16 / dt16, "ms_per_step": 1e3 * dt16 / a.bf16_steps,
                 "speedup_vs_fp32": (w16 / dt16) / (windows / dt),
-                "rel_rmse_heightfield_vs_fp32": rel,
-                "conv3x3_bf16_TFLOP/s": round(c16["flops"] / (c16["ms"] * 1e-3) / 1e12, 1) if c16["ms"] else None,
-                "conv3x3_bf16_frac_of_2500": round(c16["flops"] / (c16["ms"] * 1e-3) / 2.5e15, 4) if c16["ms"] else None,
+                "rel_rmse_heightfield_vs_fp32_gpu": rel,
+                "conv3x3_TFLOP/s": round(c16["flops"] / (c16["ms"] * 1e-3) / 1e12, 1) if c16["ms"] else None,
+                "conv3x3_frac_of_bf16_peak_2500": round(c16["flops"] / (c16["ms"] * 1e-3) / 2.5e15, 4)
+                if c16["ms"] else None,
                 "kernels_ms": {k: round(v["ms"], 1) for k, v in sorted(ks16.items(), key=lambda kv: -kv[1]["ms"])}}
         ctx.set_option("precision", 0)
     ctx.close()

@@ -120,7 +120,9 @@ td_status td_cache_peek(td_ctx *ctx, uint64_t seed, int32_t level, int64_t ix,
  * "cache_budget" = as td_cache_set_budget; "precision" = 0 FP32 network
  * (default), 1 BF16 convolution operands with FP32 accumulation (GroupNorm
  * statistics, attention, the input/output layers, blend, Euler update and
- * decode stay FP32); changing it clears the cache; "timing" = 1 records every kernel
+ * decode stay FP32), 2 as 1 but with OCP FP8 e4m3 weights scaled per
+ * output channel (FP32 scale applied to the FP32 accumulator); changing it
+ * clears the cache; "timing" = 1 records every kernel
  * launch between HIP events on its stream (see td_kernel_stats), 0 stops.
  * TD_E_INVAL for unknown keys. */
 td_status td_set_option(td_ctx *ctx, const char *key, int64_t value);

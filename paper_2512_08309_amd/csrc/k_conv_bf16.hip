@@ -18,9 +18,15 @@
 // the product is the plain dot product whatever order the hardware sums
 // the 32 terms in; that order is fixed, keeping results batch-invariant.
 //
+// Weights may instead be OCP FP8 e4m3 with a per-output-channel FP32 scale
+// (applied in the epilogue); they are widened to BF16 while staging, which
+// is exact.
+//
 // FAST (C_in a multiple of BK = 64): a stage never straddles a tap, so the
 // shifted pixel address is computed once per tap.  Otherwise (small C_in)
 // BK = 32 and every segment resolves its own (tap, channel).
+#include <type_traits>
+
 #include "td_internal.h"
 
 namespace td {
@@ -29,13 +35,24 @@ namespace {
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef unsigned u4v __attribute__((ext_vector_type(4)));
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+
+// 4 OCP e4m3 bytes -> 4 BF16 (exact: every e4m3 value is a BF16 value).
+__device__ __forceinline__ u2v fp8x4_to_bf16x4(unsigned w) {
+  f2v lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, false);
+  f2v hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, true);
+  bf2v a = {(__bf16)lo.x, (__bf16)lo.y}, b = {(__bf16)hi.x, (__bf16)hi.y};
+  return (u2v){__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b)};
+}
 
 template <int BK>
 __device__ __forceinline__ int swz(int row, int seg) {
   return BK == 64 ? (seg ^ (row & 7)) : (seg ^ ((row >> 1) & 3));
 }
 
-template <int TAPS, bool FAST, int BN, int WM, int WN>
+template <int TAPS, bool FAST, bool W8, int BN, int WM, int WN>
 __global__ __launch_bounds__(256, 2) void conv_bf16_kernel(ConvLpArgs a, int n_tiles_n) {
   constexpr int BM = 128;
   constexpr int BK = FAST ? 64 : 32;
@@ -58,6 +75,7 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_kernel(ConvLpArgs a, int n_t
   const int cin = a.cin, Kp = a.kp, K = TAPS * cin;
   const __bf16* act = reinterpret_cast<const __bf16*>(a.act);
   const __bf16* wts = reinterpret_cast<const __bf16*>(a.wt);
+  const unsigned char* wts8 = reinterpret_cast<const unsigned char*>(a.wt);
 
   // this thread's A pixel (fixed) and segments s = tid/128 + 2j
   const int am = tid & (BM - 1), s0 = tid >> 7;
@@ -66,7 +84,9 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_kernel(ConvLpArgs a, int n_t
   const int mm = mval ? mrow : 0;
   const int ab = mm >> lhw, ay = (mm >> lw) & (H - 1), ax = mm & (W - 1);
 
-  u4v ra[AL], rb[BL];
+  u4v ra[AL];
+  typedef typename std::conditional<W8, u2v, u4v>::type wreg;
+  wreg rb[BL];
   const u4v zero = {0u, 0u, 0u, 0u};
   const __bf16* pix = act;   // shifted pixel base (FAST)
   bool pok = false;
@@ -103,7 +123,8 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_kernel(ConvLpArgs a, int n_t
       const int e = tid + 256 * j;
       if (e < BN * SEGS) {
         const int n = e % BN, s = e / BN;
-        rb[j] = *reinterpret_cast<const u4v*>(wts + (size_t)(n0 + n) * Kp + k0 + 8 * s);
+        if (W8) rb[j] = *reinterpret_cast<const wreg*>(wts8 + (size_t)(n0 + n) * Kp + k0 + 8 * s);
+        else rb[j] = *reinterpret_cast<const wreg*>(wts + (size_t)(n0 + n) * Kp + k0 + 8 * s);
       }
     }
   };
@@ -118,7 +139,12 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_kernel(ConvLpArgs a, int n_t
       const int e = tid + 256 * j;
       if (e < BN * SEGS) {
         const int n = e % BN, s = e / BN;
-        Bs[buf][n * SEGS + swz<BK>(n, s)] = rb[j];
+        if constexpr (W8) {
+          u2v lo = fp8x4_to_bf16x4(rb[j].x), hi = fp8x4_to_bf16x4(rb[j].y);
+          Bs[buf][n * SEGS + swz<BK>(n, s)] = (u4v){lo.x, lo.y, hi.x, hi.y};
+        } else {
+          Bs[buf][n * SEGS + swz<BK>(n, s)] = rb[j];
+        }
       }
     }
   };
@@ -199,19 +225,25 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_kernel(ConvLpArgs a, int n_t
   }
 }
 
-template <int BN, int WM, int WN>
+template <bool W8, int BN, int WM, int WN>
 void launch_lp_cfg(hipStream_t st, const ConvLpArgs& a, bool fast) {
   const int M = a.nb << (a.lh + a.lw);
   const int mt = (M + 127) / 128, nt = a.cout / BN;
   if (a.taps == 9 && fast)
-    hipLaunchKernelGGL((conv_bf16_kernel<9, true, BN, WM, WN>), dim3(mt * nt), dim3(256), 0, st, a, nt);
+    hipLaunchKernelGGL((conv_bf16_kernel<9, true, W8, BN, WM, WN>), dim3(mt * nt), dim3(256), 0, st, a, nt);
   else if (a.taps == 9)
-    hipLaunchKernelGGL((conv_bf16_kernel<9, false, BN, WM, WN>), dim3(mt * nt), dim3(256), 0, st, a, nt);
+    hipLaunchKernelGGL((conv_bf16_kernel<9, false, W8, BN, WM, WN>), dim3(mt * nt), dim3(256), 0, st, a, nt);
   else if (fast)
-    hipLaunchKernelGGL((conv_bf16_kernel<1, true, BN, WM, WN>), dim3(mt * nt), dim3(256), 0, st, a, nt);
+    hipLaunchKernelGGL((conv_bf16_kernel<1, true, W8, BN, WM, WN>), dim3(mt * nt), dim3(256), 0, st, a, nt);
   else
-    hipLaunchKernelGGL((conv_bf16_kernel<1, false, BN, WM, WN>), dim3(mt * nt), dim3(256), 0, st, a, nt);
+    hipLaunchKernelGGL((conv_bf16_kernel<1, false, W8, BN, WM, WN>), dim3(mt * nt), dim3(256), 0, st, a, nt);
   TD_LAUNCHED();
+}
+
+template <int BN, int WM, int WN>
+void launch_lp_w(hipStream_t st, const ConvLpArgs& a, bool fast) {
+  if (a.w8) launch_lp_cfg<true, BN, WM, WN>(st, a, fast);
+  else launch_lp_cfg<false, BN, WM, WN>(st, a, fast);
 }
 
 }  // namespace
@@ -226,9 +258,10 @@ void launch_conv_lp(hipStream_t st, const ConvLpArgs& a) {
   TD_CHECK(a.kp % BK == 0 && a.kp >= a.taps * a.cin, -5, "bf16 conv: bad padded K");
   const double Md = (double)(a.nb << (a.lh + a.lw));
   prof_begin(st);
-  if (a.cout % 128 == 0) launch_lp_cfg<128, 2, 2>(st, a, fast);
-  else if (a.cout == 32) launch_lp_cfg<32, 4, 1>(st, a, fast);
-  else launch_lp_cfg<16, 4, 1>(st, a, fast);
+  TD_CHECK(!a.w8 || a.wscale, -5, "fp8 weights need per-channel scales");
+  if (a.cout % 128 == 0) launch_lp_w<128, 2, 2>(st, a, fast);
+  else if (a.cout == 32) launch_lp_w<32, 4, 1>(st, a, fast);
+  else launch_lp_w<16, 4, 1>(st, a, fast);
   prof_end(st, a.taps == 9 ? K_CONV3_LP : K_CONV1_LP, 2.0 * Md * a.cout * a.taps * a.cin,
            2.0 * Md * a.cin + 2.0 * a.kp * a.cout + 4.0 * Md * a.cout * (a.res ? 2 : 1));
 }

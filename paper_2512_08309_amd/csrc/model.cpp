@@ -79,6 +79,53 @@ const uint16_t* Model::upload_lp(const std::vector<float>& w, int co, int ci, in
   return (const uint16_t*)p;
 }
 
+namespace {
+// Nearest OCP FP8 e4m3 code (round half to even) of x, |x| <= 448 expected
+// (saturates).  Normal: (1 + m/8) 2^(e-7), e = 1..15 (e = 15, m = 7 is NaN);
+// subnormal: m 2^-9.
+uint8_t to_e4m3(double x) {
+  uint8_t sgn = x < 0 ? 0x80 : 0;
+  double a = std::fabs(x);
+  if (!(a == a)) return 0x7f;
+  if (a >= 448.0) return sgn | 0x7e;
+  if (a < std::ldexp(1.0, -6)) {                       // subnormal range
+    int m = (int)std::nearbyint(a / std::ldexp(1.0, -9));
+    return sgn | (uint8_t)(m == 8 ? 0x08 : m);         // m == 8 rounds up to 2^-6
+  }
+  int e = std::ilogb(a);
+  double m = a / std::ldexp(1.0, e) - 1.0;
+  int mq = (int)std::nearbyint(m * 8.0);
+  if (mq == 8) {
+    mq = 0;
+    ++e;
+  }
+  if (e > 8 || (e == 8 && mq > 6)) return sgn | 0x7e;
+  return sgn | (uint8_t)(((e + 7) << 3) | mq);
+}
+}  // namespace
+
+// [co][ci][k][k] -> [co][kp] FP8 e4m3 with scale[o] = max|w[o]| / 448.
+const uint8_t* Model::upload_fp8(const std::vector<float>& w, int co, int ci, int k, const float** scale) {
+  const int taps = k * k;
+  const int kp = conv_lp_kp(taps, ci);
+  std::vector<uint8_t> r((size_t)co * kp, 0);
+  std::vector<float> sc(co);
+  for (int o = 0; o < co; ++o) {
+    double mx = 0;
+    for (size_t e = 0; e < (size_t)ci * taps; ++e) mx = std::max(mx, (double)std::fabs(w[(size_t)o * ci * taps + e]));
+    const double s = mx > 0 ? mx / 448.0 : 1.0;
+    sc[o] = (float)s;
+    for (int i = 0; i < ci; ++i)
+      for (int t = 0; t < taps; ++t) r[(size_t)o * kp + t * ci + i] = to_e4m3(w[((size_t)o * ci + i) * taps + t] / (double)sc[o]);
+  }
+  void* p = nullptr;
+  TD_HIP(hipMalloc(&p, std::max<size_t>(r.size(), 1)));
+  allocs_.push_back(p);
+  TD_HIP(hipMemcpy(p, r.data(), r.size(), hipMemcpyHostToDevice));
+  *scale = upload(sc);
+  return (const uint8_t*)p;
+}
+
 int Model::cin_max(int l) const {
   const int nl = (int)d.ch.size();
   int c = d.ch[l];
@@ -89,9 +136,9 @@ int Model::cin_max(int l) const {
 }
 
 void Model::set_precision(int p) {
-  TD_CHECK(p == 0 || p == 1, -1, "precision must be 0 (fp32) or 1 (bf16)");
+  TD_CHECK(p >= 0 && p <= 2, -1, "precision must be 0 (fp32), 1 (bf16) or 2 (bf16 + fp8 weights)");
   if (p != 0) TD_CHECK(d.kind == "unet", -1, "reduced precision applies to the network denoiser only");
-  if (p != prec_ && ws_) {
+  if ((p != 0) != (prec_ != 0) && ws_) {
     TD_HIP(hipDeviceSynchronize());
     TD_HIP(hipFree(ws_));
     ws_ = nullptr;
@@ -242,6 +289,9 @@ void Model::build_unet(const std::map<std::string, std::vector<float>>& host,
   auto lp = [&](const std::string& name, int co, int ci, int k, int* kp) {
     return upload_lp(get(name, {co, ci, k, k}), co, ci, k, kp);
   };
+  auto f8 = [&](const std::string& name, int co, int ci, int k, const float** sc) {
+    return upload_fp8(get(name, {co, ci, k, k}), co, ci, k, sc);
+  };
 
   const int nl = (int)d.ch.size();
   const int c0 = d.ch[0];
@@ -278,11 +328,14 @@ void Model::build_unet(const std::map<std::string, std::vector<float>>& host,
     w.b2 = vec(p + "conv2.bias", cout);
     w.w1_lp = lp(p + "conv1.weight", cout, cin, 3, &w.kp1);
     w.w2_lp = lp(p + "conv2.weight", cout, cout, 3, &w.kp2);
+    w.w1_8 = f8(p + "conv1.weight", cout, cin, 3, &w.s1_8);
+    w.w2_8 = f8(p + "conv2.weight", cout, cout, 3, &w.s2_8);
     w.has_skip = cin != cout;
     if (w.has_skip) {
       w.wskip = conv_layout(p + "skip.weight", cout, cin, 1);
       w.bskip = vec(p + "skip.bias", cout);
       w.wskip_lp = lp(p + "skip.weight", cout, cin, 1, &w.kps);
+      w.wskip_8 = f8(p + "skip.weight", cout, cin, 1, &w.sskip_8);
     }
     TD_CHECK(cin % d.groups == 0 && cout % d.groups == 0, -5, "GroupNorm groups must divide channels");
     rb_[p] = w;
@@ -299,6 +352,8 @@ void Model::build_unet(const std::map<std::string, std::vector<float>>& host,
     w.bproj = vec(p + "proj.bias", C);
     w.wqkv_lp = lp(p + "qkv.weight", 3 * C, C, 1, &w.kpq);
     w.wproj_lp = lp(p + "proj.weight", C, C, 1, &w.kpp);
+    w.wqkv_8 = f8(p + "qkv.weight", 3 * C, C, 1, &w.sqkv_8);
+    w.wproj_8 = f8(p + "proj.weight", C, C, 1, &w.sproj_8);
     at_[p] = w;
   };
   std::vector<int> skipc;
@@ -433,8 +488,16 @@ void Model::gn(hipStream_t st, const float* s0, int c0, int up0, const float* s1
 }
 
 void Model::conv_lp(hipStream_t st, const uint16_t* act, int cin, int nb, int lr, int cout, int taps,
-                    const uint16_t* wt, int kp, const float* bias, const float* res, float* out) {
+                    const uint16_t* wt, const uint8_t* w8, const float* w8s, int kp, const float* bias,
+                    const float* res, float* out) {
   ConvLpArgs a{};
+  if (prec_ == 2) {
+    a.wt = w8;
+    a.w8 = 1;
+    a.wscale = w8s;
+  } else {
+    a.wt = wt;
+  }
   a.act = act;
   a.cin = cin;
   a.nb = nb;
@@ -443,7 +506,6 @@ void Model::conv_lp(hipStream_t st, const uint16_t* act, int cin, int nb, int lr
   a.cout = cout;
   a.taps = taps;
   a.kp = kp;
-  a.wt = wt;
   a.bias = bias;
   a.res = res;
   a.out = out;
@@ -477,18 +539,18 @@ void Model::resblock(hipStream_t st, const ResBlockW& w, int k, const float* s0,
     const float* bias1 = bias_eff_ + w.bias_off + (size_t)k * w.cout;
     gn(st, s0, c0, up0, s1, c1, nb, lr, lr, w.gn1_g, w.gn1_b);
     apply(st, s0, c0, up0, s1, c1, 2, nb, lr, B.A);
-    conv_lp(st, B.A, w.cin, nb, lr, w.cout, 9, w.w1_lp, w.kp1, bias1, nullptr, B.T);
+    conv_lp(st, B.A, w.cin, nb, lr, w.cout, 9, w.w1_lp, w.w1_8, w.s1_8, w.kp1, bias1, nullptr, B.T);
     const float* res = s0;
     if (w.has_skip) {
       apply(st, s0, c0, up0, s1, c1, 0, nb, lr, B.A0);
-      conv_lp(st, B.A0, w.cin, nb, lr, w.cout, 1, w.wskip_lp, w.kps, w.bskip, nullptr, B.R);
+      conv_lp(st, B.A0, w.cin, nb, lr, w.cout, 1, w.wskip_lp, w.wskip_8, w.sskip_8, w.kps, w.bskip, nullptr, B.R);
       res = B.R;
     } else {
       TD_CHECK(c1 == 0 && !up0, -5, "identity skip needs a plain input");
     }
     gn(st, B.T, w.cout, 0, nullptr, 0, nb, lr, lr, w.gn2_g, w.gn2_b);
     apply(st, B.T, w.cout, 0, nullptr, 0, 2, nb, lr, B.A);
-    conv_lp(st, B.A, w.cout, nb, lr, w.cout, 9, w.w2_lp, w.kp2, w.b2, res, out);
+    conv_lp(st, B.A, w.cout, nb, lr, w.cout, 9, w.w2_lp, w.w2_8, w.s2_8, w.kp2, w.b2, res, out);
     return;
   }
   gn(st, s0, c0, up0, s1, c1, nb, lr, lr, w.gn1_g, w.gn1_b);
@@ -550,10 +612,10 @@ void Model::attention(hipStream_t st, const AttnW& w, const float* in, int nb, i
   gn(st, in, w.C, 0, nullptr, 0, nb, lr, lr, w.gn_g, w.gn_b);
   if (prec_) {
     apply(st, in, w.C, 0, nullptr, 0, 1, nb, lr, B.A);
-    conv_lp(st, B.A, w.C, nb, lr, 3 * w.C, 1, w.wqkv_lp, w.kpq, w.bqkv, nullptr, B.Q);
+    conv_lp(st, B.A, w.C, nb, lr, 3 * w.C, 1, w.wqkv_lp, w.wqkv_8, w.sqkv_8, w.kpq, w.bqkv, nullptr, B.Q);
     launch_attention(st, B.Q, B.O, nb, 1 << (2 * lr), w.C, d.heads);
     apply(st, B.O, w.C, 0, nullptr, 0, 0, nb, lr, B.A);
-    conv_lp(st, B.A, w.C, nb, lr, w.C, 1, w.wproj_lp, w.kpp, w.bproj, in, out);
+    conv_lp(st, B.A, w.C, nb, lr, w.C, 1, w.wproj_lp, w.wproj_8, w.sproj_8, w.kpp, w.bproj, in, out);
     return;
   }
   ConvArgs q{};

@@ -50,6 +50,9 @@ struct ResBlockW {
   // reduced precision: [cout][kp] BF16 weights (K = tap * cin + c_in)
   const uint16_t *w1_lp = nullptr, *w2_lp = nullptr, *wskip_lp = nullptr;
   int kp1 = 0, kp2 = 0, kps = 0;
+  // FP8 e4m3 weights, same layout, with per-output-channel scales
+  const uint8_t *w1_8 = nullptr, *w2_8 = nullptr, *wskip_8 = nullptr;
+  const float *s1_8 = nullptr, *s2_8 = nullptr, *sskip_8 = nullptr;
 };
 
 struct AttnW {
@@ -58,6 +61,8 @@ struct AttnW {
               *bproj = nullptr;
   const uint16_t *wqkv_lp = nullptr, *wproj_lp = nullptr;
   int kpq = 0, kpp = 0;
+  const uint8_t *wqkv_8 = nullptr, *wproj_8 = nullptr;
+  const float *sqkv_8 = nullptr, *sproj_8 = nullptr;
 };
 
 // Batch of windows for one denoiser round: inputs are read from a dense
@@ -87,7 +92,8 @@ class Model {
   const float* w1d() const { return w1d_; }
   const float* decode_taps() const { return taps_; }
   const float* decode_atoms() const { return atoms_; }
-  // 0: FP32 (FP32 MFMA); 1: BF16 operands, FP32 accumulation.
+  // 0: FP32 (FP32 MFMA); 1: BF16 operands, FP32 accumulation; 2: BF16
+  // activations with FP8 e4m3 per-output-channel-scaled weights.
   void set_precision(int p);
   int precision() const { return prec_; }
 
@@ -119,9 +125,11 @@ class Model {
   float* dalloc(size_t n);
   const float* upload(const std::vector<float>& v);
   const uint16_t* upload_lp(const std::vector<float>& w, int co, int ci, int k, int* kp);
+  const uint8_t* upload_fp8(const std::vector<float>& w, int co, int ci, int k, const float** scale);
   int cin_max(int lvl) const;
   void conv_lp(hipStream_t st, const uint16_t* act, int cin, int nb, int lr, int cout, int taps,
-               const uint16_t* wt, int kp, const float* bias, const float* res, float* out);
+               const uint16_t* wt, const uint8_t* w8, const float* w8s, int kp, const float* bias,
+               const float* res, float* out);
   void apply(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int act, int nb,
              int lr, uint16_t* out);
   void build_unet(const std::map<std::string, std::vector<float>>& host,

@@ -105,8 +105,9 @@ struct ConvLpArgs {
   int cout;
   int taps;              // 9 (3x3, zero pad 1) or 1
   int kp;                // padded K = round_up(taps * cin, 64 or 32)
-  const uint16_t* wt;    // [cout][kp] BF16, K = tap * cin + c_in
-  const float* wscale;   // per-output-channel weight scale or null
+  const void* wt;        // [cout][kp] BF16 (w8 = 0) or FP8 e4m3 (w8 = 1), K = tap * cin + c_in
+  int w8;
+  const float* wscale;   // per-output-channel weight scale (required for FP8) or null
   const float* bias;     // [cout]
   const float* res;      // [nb][h][w][cout] FP32 or null
   float* out;            // [nb][h][w][cout] FP32

@@ -35,12 +35,21 @@ def lp_ctx(weights):
         c.close()
 
 
+# Relative error bars vs the FP64 oracle.  BF16 is held to the workload's
+# target (heightfield RMSE <= 2e-2).  FP8 e4m3 weights (3 mantissa bits)
+# measure ~5e-2 on this random-init network and do NOT meet that target; the
+# bar below only guards against regressions of the measured level.
+BARS = {1: 2e-2, 2: 8e-2}
+HEIGHT_BARS = {1: 2e-2, 2: 8e-2}
+
+
+@pytest.mark.parametrize("prec", [1, 2])
 @pytest.mark.parametrize("config,k,n", [("c1", 0, 8), ("c1", 5, 8), ("c2", 0, 2), ("c2", 15, 2)])
-def test_bf16_denoiser_close_to_oracle(lp_ctx, weights, config, k, n):
+def test_lowp_denoiser_close_to_oracle(lp_ctx, weights, config, k, n, prec):
     import torch
     from oracle.tdw import read_tdw
     from oracle.unet import UNetDenoiser
-    c = lp_ctx(config, 1)
+    c = lp_ctx(config, prec)
     hdr, t = read_tdw(weights(config))
     m = Model(weights(config))
     H, C = m.H, m.C
@@ -50,27 +59,28 @@ def test_bf16_denoiser_close_to_oracle(lp_ctx, weights, config, k, n):
     c.denoise_windows(xd, k, out)
     ref = UNetDenoiser(hdr, t)(x.astype(np.float64), m.sched[k], None)
     err = rel_l2(out.cpu().numpy(), ref)
-    print("bf16 denoiser %s sigma_%d rel L2 %.3e" % (config, k, err))
-    assert err <= 2e-2
+    print("precision %d denoiser %s sigma_%d rel L2 %.3e" % (prec, config, k, err))
+    assert err <= BARS[prec]
 
 
-def test_bf16_c1_crop_error_every_level(lp_ctx, weights):
+@pytest.mark.parametrize("prec", [1, 2])
+def test_lowp_c1_crop_error_every_level(lp_ctx, weights, prec):
     """128x128 C1 crop at (3, 9): error of every level J_t and of the heightfield."""
     m = Model(weights("c1"))
     region = (3, 9, 128, 128)
     ref = sample_levels(m, 5, *region, 0)
     c32 = lp_ctx("c1", 0)
-    c16 = lp_ctx("c1", 1)
+    c16 = lp_ctx("c1", prec)
     errs16, errs32 = {}, {}
     for t in range(m.K, -1, -1):
         r = planar(ref[t])
         errs16[t] = rel_l2(c16.sample_region(5, *region, t), r)
         errs32[t] = rel_l2(c32.sample_region(5, *region, t), r)
-    print("per-level rel L2 vs FP64 oracle, bf16:", {t: "%.2e" % e for t, e in errs16.items()})
+    print("per-level rel L2 vs FP64 oracle, precision %d:" % prec, {t: "%.2e" % e for t, e in errs16.items()})
     print("per-level rel L2 vs FP64 oracle, fp32:", {t: "%.2e" % e for t, e in errs32.items()})
     assert errs16[m.K] < 1e-7 and errs32[m.K] < 1e-7    # the noise level (FP32 rounding of sigma_0 * G)
     assert max(errs32.values()) <= 1e-4
-    assert max(errs16.values()) <= 2e-2
+    assert max(errs16.values()) <= HEIGHT_BARS[prec]
     # heightfield of the interior (decode needs the 17 px apron inside the crop)
     out = (8 * 20, 8 * 26, 8 * 90, 8 * 90)
     lx0, ly0, lw, lh = laplace.required_latent(out, DEC)
@@ -81,8 +91,8 @@ def test_bf16_c1_crop_error_every_level(lp_ctx, weights):
     h16 = c16.sample_region(5, *out, td.TD_LEVEL_HEIGHT)
     h32 = c32.sample_region(5, *out, td.TD_LEVEL_HEIGHT)
     e16, e32 = rel_l2(h16, href), rel_l2(h32, href)
-    print("heightfield rel RMSE vs FP64 oracle: bf16 %.3e, fp32 %.3e" % (e16, e32))
-    assert e32 <= 1e-4 and e16 <= 2e-2
+    print("heightfield rel RMSE vs FP64 oracle: precision %d %.3e, fp32 %.3e" % (prec, e16, e32))
+    assert e32 <= 1e-4 and e16 <= HEIGHT_BARS[prec]
 
 
 def test_bf16_seed_consistency_bit_exact(lp_ctx):
