@@ -56,6 +56,7 @@ typedef struct {
   uint64_t bytes_budget;  /* current budget                                */
   uint64_t batches;       /* batched denoiser rounds launched              */
   uint64_t queries;       /* td_sample_region* calls served                */
+  uint64_t denoiser_evals;/* network evaluations (windows x Euler steps)   */
   uint64_t windows_evaluated[64];
 } td_cache_stats_t;
 
@@ -78,7 +79,10 @@ void td_destroy(td_ctx *ctx);
 td_status td_load_weights(td_ctx *ctx, const char *path);
 
 /* J_level[R] for seed `seed` (Alg. 1 applied recursively from J_T = sigma_0 G).
- * level in [0, K] (K = sampler steps; 0 = final latent, K = scaled noise),
+ * level in [0, T] (T = blend levels, "levels" in td_get_info; T = sampler
+ * steps K unless the weight file truncates T, Sec. 3.4, in which case Phi
+ * of a level runs several window-local Euler steps; 0 = final latent,
+ * T = scaled noise),
  * or TD_LEVEL_HEIGHT for decoded elevation on the full-resolution region.
  * `out` is a host buffer of out_len floats, at least C*w*h (latent) or w*h
  * (height); the call blocks until the result is in `out`.  Values depend
@@ -127,7 +131,7 @@ td_status td_cache_peek(td_ctx *ctx, uint64_t seed, int32_t level, int64_t ix,
  * TD_E_INVAL for unknown keys. */
 td_status td_set_option(td_ctx *ctx, const char *key, int64_t value);
 
-/* Model facts: "channels", "steps", "window", "stride", "offset",
+/* Model facts: "channels", "steps" (K), "levels" (T), "window", "stride", "offset",
  * "factor" (decode), "params", "batch", "precision".  TD_E_INVAL for
  * unknown keys. */
 td_status td_get_info(td_ctx *ctx, const char *key, int64_t *value);

@@ -16,6 +16,8 @@ TEST INFRASTRUCTURE (oracle).
   on finite canvases from t = T-1 down to the query level.
 * Summation over the windows covering a pixel runs in canonical order
   (iy ascending, then ix ascending).
+* Levels are blend levels: T = K unless the header truncates T (Phi then
+  runs several window-local Euler steps, oracle.schedule.level_steps).
 
 Outputs are float64 arrays [h, w, C] (row y, column x, channel).
 
@@ -27,7 +29,7 @@ query-order independence.
 import numpy as np
 
 from .noise import noise_region
-from .schedule import euler_factor, sigma_pair, sigmas
+from .schedule import blend_points, euler_factor, level_steps, sigmas
 from .tdw import read_tdw
 from .unet import make_denoiser
 from .windows import cone, kappa_list, weight_map
@@ -43,11 +45,13 @@ class Model:
             self.header, self.tensors = path_or_header, (tensors or {})
         h = self.header
         self.C = h["denoiser"]["in_channels"]
-        self.K = h["sampler"]["steps"]
+        self.steps = h["sampler"]["steps"]
+        self.points = blend_points(h["sampler"])
+        self.K = len(self.points) - 1          # blend levels T
         win = h["window"]
         self.H, self.s, self.o, self.eps = win["size"], win["stride"], win["offset"], win["eps"]
         sp = h["sampler"]
-        self.sched = sigmas(self.K, sp["sigma_max"], sp["sigma_min"], sp["rho"])
+        self.sched = sigmas(self.steps, sp["sigma_max"], sp["sigma_min"], sp["rho"])
         self.W = weight_map(self.H, self.eps)
         self.denoiser = make_denoiser(h, self.tensors)
         self.phi_calls = 0
@@ -62,16 +66,18 @@ def _crop(canvas, canvas_region, sub):
 def level_step(model, j_next, region_next, region, windows, t):
     """J_t on `region` from J_{t+1} on `region_next` using the given windows."""
     H = model.H
-    sig, sig_next = sigma_pair(model.sched, model.K, t)
     x0, y0, w, h = region
     A = np.zeros((h, w, model.C))
     B = np.zeros((h, w, 1))
     if windows:
         xs = np.stack([_crop(j_next, region_next, (ix * model.s + model.o, iy * model.s + model.o, H, H))
                        for ix, iy in windows])
-        D = model.denoiser(xs, sig, windows)
+        phi = xs
+        for k in level_steps(model.points, t):
+            sig, sig_next = model.sched[k], model.sched[k + 1]
+            D = model.denoiser(phi, sig, windows)
+            phi = phi + euler_factor(sig, sig_next) * (phi - D)
         model.phi_calls += len(windows)
-        phi = xs + euler_factor(sig, sig_next) * (xs - D)
         for n, (ix, iy) in enumerate(windows):
             ox, oy = ix * model.s + model.o, iy * model.s + model.o
             ax0, ax1 = max(ox, x0), min(ox + H, x0 + w)

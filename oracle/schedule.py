@@ -13,9 +13,15 @@ The reading used here is the EDM sampler of Karras et al. (2022):
   Phi(x) = x + (sigma' - sigma)/sigma (x - D(x; sigma)), sigma = sigma_{K-t-1},
   sigma' = sigma_{K-t}.  At the last step sigma' = 0 and Phi(x) = D(x).
 
+* Truncated T (Sec. 3.4): blends happen only after the schedule indices in
+  the header's "blend" list; level t then holds the state at
+  sigma_{b_{T-t}} and its Phi runs the Euler steps b_{T-t-1} .. b_{T-t}-1
+  on the window alone.
+
 Pins: the schedule's end points and monotonicity; the linear-Gaussian
 closed form of the whole sampler (tests/test_oracle_sampler.py) fixes the
-level indexing, the Euler factor and the preconditioning-free path.
+level indexing, the Euler factor and the preconditioning-free path, for
+every blend schedule.
 """
 import math
 
@@ -33,6 +39,23 @@ def sigmas(steps, sigma_max, sigma_min, rho):
 def sigma_pair(sched, steps, t):
     """(sigma, sigma') used by the step that produces level t from level t+1."""
     return sched[steps - t - 1], sched[steps - t]
+
+
+def blend_points(sampler):
+    """Schedule indices b_0 = 0 < b_1 < ... < b_T = K after which the windows
+    are blended.  Default: after every step (T = K).  With T < K, Phi of a
+    level runs several window-local Euler steps (truncated T, Sec. 3.4)."""
+    K = sampler["steps"]
+    b = list(sampler.get("blend", range(K + 1)))
+    if b[0] != 0 or b[-1] != K or any(x >= y for x, y in zip(b, b[1:])):
+        raise ValueError("blend points must rise strictly from 0 to K")
+    return b
+
+
+def level_steps(points, t):
+    """Schedule indices k of the Euler steps Phi runs to produce blend level t."""
+    T = len(points) - 1
+    return list(range(points[T - t - 1], points[T - t]))
 
 
 def precond(sigma, sigma_data):

@@ -297,14 +297,14 @@ void sample_latent(td_ctx* c, uint64_t seed, Region r, int level, int layout, fl
   const ModelDesc& d = c->model->d;
   hipStream_t st = c->stream;
   c->stats.queries++;
-  if (level == d.K) {
+  if (level == d.T) {
     launch_noise(st, seed, r.x0, r.y0, (int)r.w, (int)r.h, d.C, 0, (float)d.sched[0], layout, dev_out);
     return;
   }
   // ---- plan
   std::vector<Level> levels;
   Region R = r;
-  for (int t = level; t < d.K; ++t) {
+  for (int t = level; t < d.T; ++t) {
     Level lv;
     lv.t = t;
     lv.region = R;
@@ -352,7 +352,7 @@ void sample_latent(td_ctx* c, uint64_t seed, Region r, int level, int layout, fl
     size_t cn = (size_t)cr.w * cr.h * d.C;
     grow(c->canvas, c->canvas_cap, cn);
     const int tn = lv.t + 1;
-    if (tn == d.K) {
+    if (tn == d.T) {
       launch_noise(st, seed, cr.x0, cr.y0, (int)cr.w, (int)cr.h, d.C, 0, (float)d.sched[0], 0, c->canvas);
     } else {
       const Level& up = levels[i + 1];
@@ -370,6 +370,7 @@ void sample_latent(td_ctx* c, uint64_t seed, Region r, int level, int layout, fl
       c->map[key] = Entry{slots[j], 1, c->lru.begin()};
     }
     c->stats.misses += nf;
+    c->stats.denoiser_evals += (uint64_t)nf * c->model->level_steps(lv.t);
     if (lv.t < 64) c->stats.windows_evaluated[lv.t] += nf;
     for (size_t b0 = 0; b0 < nf; b0 += (size_t)maxb) {
       int nb = (int)std::min<size_t>(maxb, nf - b0);
@@ -398,7 +399,7 @@ void sample_latent(td_ctx* c, uint64_t seed, Region r, int level, int layout, fl
       wb.d_slots = (float* const*)s.second;
       wb.n = nb;
       wb.mode = 0;
-      c->model->run_batch(st, wb, d.K - lv.t - 1);
+      c->model->run_level(st, wb, lv.t);
       c->stats.batches++;
     }
     evict_to_budget(c);
@@ -467,7 +468,7 @@ void sample_any(td_ctx* c, uint64_t seed, int64_t x0, int64_t y0, int32_t w, int
     sample_latent(c, seed, lat, 0, 0, c->tmp);
     decode_into(c, c->tmp, lat, full, dev_out, c->stream);
   } else {
-    TD_CHECK(level >= 0 && level <= d.K, TD_E_INVAL, "level out of range");
+    TD_CHECK(level >= 0 && level <= d.T, TD_E_INVAL, "level out of range");
     TD_CHECK(out_len >= (size_t)w * h * d.C, TD_E_INVAL, "output buffer too small");
     sample_latent(c, seed, Region{x0, y0, w, h}, level, 1, dev_out);
   }
@@ -700,6 +701,7 @@ td_status td_get_info(td_ctx* c, const char* key, int64_t* value) {
     std::string k(key);
     if (k == "channels") *value = d.C;
     else if (k == "steps") *value = d.K;
+    else if (k == "levels") *value = d.T;
     else if (k == "window") *value = d.H;
     else if (k == "stride") *value = d.S;
     else if (k == "offset") *value = d.O;

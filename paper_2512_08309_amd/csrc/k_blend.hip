@@ -117,7 +117,8 @@ __global__ __launch_bounds__(256) void lg_step_kernel(int H, int C, const float*
     return;
   }
   float phi = x + c_euler * (x - d);
-  slots[b][idx] = (w1d[u] * w1d[v]) * phi;
+  if (mode == 2) dout[(size_t)b * H * H * C + idx] = phi;
+  else slots[b][idx] = (w1d[u] * w1d[v]) * phi;
 }
 
 }  // namespace

@@ -113,7 +113,8 @@ __global__ __launch_bounds__(256) void conv_out_kernel(OutArgs a) {
       a.dout[(((size_t)b * H + v) * H + u) * CO + o] = d;
     } else {
       float phi = x + a.c_euler * (x - d);
-      a.slots[b][((size_t)v * H + u) * CO + o] = wuv * phi;
+      if (a.mode == 2) a.dout[(((size_t)b * H + v) * H + u) * CO + o] = phi;
+      else a.slots[b][((size_t)v * H + u) * CO + o] = wuv * phi;
     }
   }
 }

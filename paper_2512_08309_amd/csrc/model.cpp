@@ -186,6 +186,17 @@ void Model::load(const std::string& path, hipStream_t st) {
   TD_CHECK(d.factor == 8 && d.blur_radius >= 0 && d.blur_radius <= 64, -5, "weight header: unsupported decode");
   TD_CHECK(d.smax > d.smin && d.smin > 0 && d.rho > 0 && d.sigma_data > 0, -5, "weight header: bad schedule");
   d.sched = edm_sigmas(d.K, d.smax, d.smin, d.rho);
+  d.points.clear();
+  if (sp.has("blend")) {
+    for (const Json& b : sp.at("blend").arr()) d.points.push_back((int)b.integer());
+  } else {
+    for (int k = 0; k <= d.K; ++k) d.points.push_back(k);
+  }
+  TD_CHECK(d.points.size() >= 2 && d.points.front() == 0 && d.points.back() == d.K, -5,
+           "weight header: blend points must run from 0 to steps");
+  for (size_t i = 1; i < d.points.size(); ++i)
+    TD_CHECK(d.points[i] > d.points[i - 1], -5, "weight header: blend points must increase");
+  d.T = (int)d.points.size() - 1;
 
   // tensors
   std::map<std::string, std::vector<float>> host;
@@ -400,7 +411,8 @@ void Model::build_unet(const std::map<std::string, std::vector<float>>& host,
 }
 
 size_t Model::workspace_bytes_per_window() const {
-  if (d.kind != "unet") return 0;
+  const size_t state = d.T < d.K ? (size_t)d.H * d.H * d.C * sizeof(float) + 2 * sizeof(int) : 0;
+  if (d.kind != "unet") return state;
   size_t f = 0;
   const int nl = (int)d.ch.size();
   for (int l = 0; l < nl; ++l) {
@@ -414,11 +426,11 @@ size_t Model::workspace_bytes_per_window() const {
   size_t lp = 0;
   if (prec_)
     for (int l = 0; l < nl; ++l) lp += 2 * (size_t)(d.H >> l) * (d.H >> l) * cin_max(l);   // A, A0 (BF16)
-  return f * sizeof(float) + lp * sizeof(uint16_t) + (size_t)16 * d.groups * 2 * sizeof(double) + 64 * 256;
+  return state + f * sizeof(float) + lp * sizeof(uint16_t) + (size_t)16 * d.groups * 2 * sizeof(double) + 64 * 256;
 }
 
 void Model::ensure_workspace(int max_batch) {
-  if (d.kind != "unet" || max_batch <= ws_batch_) return;
+  if (max_batch <= ws_batch_) return;
   if (ws_) {
     TD_HIP(hipDeviceSynchronize());
     TD_HIP(hipFree(ws_));
@@ -433,7 +445,19 @@ void Model::ensure_workspace(int max_batch) {
     p += (nfloat * sizeof(float) + 255) / 256 * 256;
     return r;
   };
-  const int nl = (int)d.ch.size();
+  state_ = nullptr;
+  state_origins_ = nullptr;
+  if (d.T < d.K) {
+    state_ = take((size_t)max_batch * d.H * d.H * d.C);
+    state_origins_ = (int*)take((size_t)max_batch * 2);
+    std::vector<int> o(2 * (size_t)max_batch);
+    for (int b = 0; b < max_batch; ++b) {
+      o[2 * b] = 0;
+      o[2 * b + 1] = b * d.H;
+    }
+    TD_HIP(hipMemcpy(state_origins_, o.data(), o.size() * sizeof(int), hipMemcpyHostToDevice));
+  }
+  const int nl = d.kind == "unet" ? (int)d.ch.size() : 0;
   lb_.assign(nl, LevelBufs{});
   for (int l = 0; l < nl; ++l) {
     size_t r2 = (size_t)(d.H >> l) * (d.H >> l) * max_batch;
@@ -459,9 +483,11 @@ void Model::ensure_workspace(int max_batch) {
       b.A = b.A0 = nullptr;
     }
   }
-  gn_scale_ = take((size_t)max_batch * 1024);
-  gn_shift_ = take((size_t)max_batch * 1024);
-  gn_part_ = (double*)take((size_t)max_batch * 16 * d.groups * 2 * 2);
+  if (d.kind == "unet") {
+    gn_scale_ = take((size_t)max_batch * 1024);
+    gn_shift_ = take((size_t)max_batch * 1024);
+    gn_part_ = (double*)take((size_t)max_batch * 16 * d.groups * 2 * 2);
+  }
   TD_CHECK((size_t)(p - (char*)ws_) <= bytes, -2, "workspace layout overflow");
   ws_batch_ = max_batch;
 }
@@ -649,6 +675,29 @@ void Model::attention(hipStream_t st, const AttnW& w, const float* in, int nb, i
   launch_conv(st, p);
 }
 
+void Model::run_level(hipStream_t st, const WindowBatch& wb, int t) {
+  TD_CHECK(t >= 0 && t < d.T, -1, "blend level out of range");
+  const int k0 = d.points[d.T - t - 1], k1 = d.points[d.T - t];
+  if (k1 - k0 == 1) {
+    run_batch(st, wb, k0);
+    return;
+  }
+  TD_CHECK(state_ && wb.n <= ws_batch_, -1, "window state buffer missing");
+  for (int k = k0; k < k1; ++k) {
+    WindowBatch s = wb;
+    if (k > k0) {   // later steps read the window state of the previous step
+      s.canvas = state_;
+      s.canvas_w = d.H;
+      s.d_origins = state_origins_;
+    }
+    if (k + 1 < k1) {
+      s.mode = 2;
+      s.dout = state_;
+    }
+    run_batch(st, s, k);
+  }
+}
+
 void Model::run_batch(hipStream_t st, const WindowBatch& wb, int k) {
   TD_CHECK(k >= 0 && k < d.K, -1, "sigma index out of range");
   const double sigma = d.sched[k], sigma_next = d.sched[k + 1];
@@ -664,6 +713,8 @@ void Model::run_batch(hipStream_t st, const WindowBatch& wb, int k) {
   }
   TD_CHECK(wb.n <= ws_batch_, -1, "batch larger than workspace");
   const int nl = (int)d.ch.size();
+  // (mode 2 writes Phi into dout; the output kernel reads x at the same
+  //  element before writing it, so dout may alias the canvas)
   const int nb = wb.n;
   LevelBufs& L0 = lb_[0];
   launch_conv_in(st, wb.canvas, wb.canvas_w, wb.d_origins, nb, d.H, d.C, d.ch[0], c_in, conv_in_w_, conv_in_b_,

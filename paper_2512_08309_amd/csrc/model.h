@@ -27,6 +27,8 @@ struct ModelDesc {
   int K = 0;
   double smax = 80, smin = 0.002, rho = 7, sigma_data = 0.5;
   std::vector<double> sched;  // sigma_0..sigma_{K-1}, 0
+  std::vector<int> points;    // blend points b_0 = 0 < ... < b_T = K (schedule indices)
+  int T = 0;                  // blend levels (= K unless truncated)
   // windows
   int H = 0, S = 0, O = 0;
   double win_eps = 0.01;
@@ -75,7 +77,7 @@ struct WindowBatch {
   float* const* d_slots = nullptr;  // [n] device pointers, mode 0
   float* dout = nullptr;            // mode 1: [n][H][H][C]
   int n = 0;
-  int mode = 0;                     // 0: contributions W (x) Phi, 1: raw D
+  int mode = 0;                     // 0: contributions W (x) Phi, 1: raw D, 2: Phi to dout
 };
 
 class Model {
@@ -83,9 +85,13 @@ class Model {
   ModelDesc d;
   ~Model();
   void load(const std::string& path, hipStream_t st);
-  // Evaluate one batch (n <= max_batch) at schedule index k (sigma = sched[k]),
-  // Euler target sched[k+1].
+  // One denoiser round of a batch (n <= max_batch) at schedule index k
+  // (sigma = sched[k]), Euler target sched[k+1].
   void run_batch(hipStream_t st, const WindowBatch& b, int k);
+  // Phi of blend level t: the Euler steps points[T-t-1] .. points[T-t]-1 on
+  // every window of the batch, the last one writing b.mode's output.
+  void run_level(hipStream_t st, const WindowBatch& b, int t);
+  int level_steps(int t) const { return d.points[d.T - t] - d.points[d.T - t - 1]; }
   size_t workspace_bytes_per_window() const;
   void ensure_workspace(int max_batch);
   int max_batch() const { return ws_batch_; }
@@ -121,6 +127,8 @@ class Model {
   std::vector<LevelBufs> lb_;
   float *gn_scale_ = nullptr, *gn_shift_ = nullptr;
   double* gn_part_ = nullptr;
+  float* state_ = nullptr;        // window states between the steps of one Phi
+  int* state_origins_ = nullptr;  // (0, b*H) for b < ws_batch_
 
   float* dalloc(size_t n);
   const float* upload(const std::vector<float>& v);

@@ -161,7 +161,8 @@ void launch_conv_in(hipStream_t st, const float* canvas, int canvas_w,
 
 // Output conv (GN + SiLU + 3x3 to cimg channels) fused with EDM
 // preconditioning, the Euler step and the window weighting.  mode 0 writes
-// V = W (x) Phi into slots[b]; mode 1 writes D to dout [nwin][H][H][cimg].
+// V = W (x) Phi into slots[b]; mode 1 writes D to dout [nwin][H][H][cimg];
+// mode 2 writes the Euler-stepped window (unweighted) to dout.
 struct OutArgs {
   const float* h;        // [nb][H][H][c0]
   const float* gn_scale;

@@ -28,7 +28,8 @@ EXPORTS = ["td_create", "td_destroy", "td_load_weights", "td_sample_region", "td
 class td_cache_stats_t(ctypes.Structure):
     _fields_ = [("hits", ctypes.c_uint64), ("misses", ctypes.c_uint64), ("evictions", ctypes.c_uint64),
                 ("bytes_used", ctypes.c_uint64), ("bytes_budget", ctypes.c_uint64), ("batches", ctypes.c_uint64),
-                ("queries", ctypes.c_uint64), ("windows_evaluated", ctypes.c_uint64 * 64)]
+                ("queries", ctypes.c_uint64), ("denoiser_evals", ctypes.c_uint64),
+                ("windows_evaluated", ctypes.c_uint64 * 64)]
 
 
 class td_kernel_stat_t(ctypes.Structure):

@@ -11,6 +11,8 @@ workloads the method is measured on:
 * ``c2k4``, ``c2k2``: ``c2`` with K reduced to 4 / 2 (same network).
 * ``lg``  : analytic linear-Gaussian denoiser (no tensors), 4 channels,
             windows 32 at stride 16, K = 8.
+* ``c1t2``, ``lgt2``, ``c2t1``/``c2t2``/``c2t5``: the same models with
+            truncated T (blends only at the listed schedule indices).
 
 Initialisation: every tensor is Gaussian from numpy's PCG64 seeded with the
 given seed, drawn in file order.  Conv / linear weights ~ N(0, 1/fan_in);
@@ -53,6 +55,11 @@ for _k in (4, 2):
     CONFIGS["c2k%d" % _k]["sampler"]["steps"] = _k
 CONFIGS["c1k2"] = copy.deepcopy(CONFIGS["c1"])
 CONFIGS["c1k2"]["sampler"]["steps"] = 2
+# truncated T (blend only after the listed schedule indices)
+for _name, _base, _blend in [("c1t2", "c1", [0, 4, 8]), ("lgt2", "lg", [0, 3, 8]), ("c2t2", "c2", [0, 10, 20]),
+                             ("c2t5", "c2", [0, 4, 8, 12, 16, 20]), ("c2t1", "c2", [0, 20])]:
+    CONFIGS[_name] = copy.deepcopy(CONFIGS[_base])
+    CONFIGS[_name]["sampler"]["blend"] = _blend
 
 
 def _resblock(prefix, cin, cout, emb_dim):

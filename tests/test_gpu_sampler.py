@@ -37,7 +37,7 @@ def ctxs(weights):
     ("lg", (-2 ** 31 + 2 ** 22 + 1, 7, 16, 16))])
 def test_noise_level_bit_exact(ctxs, config, region):
     c = ctxs(config)
-    K, C = c.info("steps"), c.info("channels")
+    K, C = c.info("levels"), c.info("channels")
     for seed in (0, 1, 0x00DEADBEEF123457):
         got = c.sample_region(seed, *region, K)
         z = onoise.noise_region(seed, *region, C)
@@ -164,3 +164,33 @@ def test_c2_reduced_steps_sampler_matches_oracle(ctxs, weights):
     got = c.sample_region(7, 0, 0, 32, 32, 0)
     ref = planar(sample(m, 7, 0, 0, 32, 32, 0))
     assert rel_l2(got, ref) <= TOL
+
+
+# ------------------------------------------------------------ truncated T
+
+@pytest.mark.parametrize("level", [0, 1])
+def test_truncated_t_linear_gaussian_matches_oracle(ctxs, weights, level):
+    c = ctxs("lgt2")
+    assert c.info("levels") == 2 and c.info("steps") == 8
+    m = Model(weights("lgt2"))
+    got = c.sample_region(6, -19, 33, 41, 27, level)
+    assert rel_l2(got, planar(sample(m, 6, -19, 33, 41, 27, level))) <= 1e-6
+
+
+def test_truncated_t_c1_matches_oracle_and_counts(ctxs, weights):
+    c = ctxs("c1t2")
+    m = Model(weights("c1t2"))
+    c.cache_clear()
+    got = c.sample_region(3, 5, -7, 64, 64, 0)
+    assert rel_l2(got, planar(sample(m, 3, 5, -7, 64, 64, 0))) <= TOL
+    st = c.cache_stats()
+    want = wn.cone_window_count((5, -7, 64, 64), 0, 2, 32, 16)
+    assert st["misses"] == want and st["denoiser_evals"] == 4 * want     # 4 Euler steps per level
+    # lazy evaluation stays seed-consistent across crops and batch sizes
+    c.cache_clear()
+    c.set_option("batch", 5)
+    try:
+        small = c.sample_region(3, 20, 10, 17, 23, 0)
+    finally:
+        c.set_option("batch", 4096)
+    assert np.array_equal(small, got[:, 17:40, 15:32])

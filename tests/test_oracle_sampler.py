@@ -48,16 +48,20 @@ def brute_mu_bar(x, y, c, H, s, o, eps):
     return num / den
 
 
-@pytest.mark.parametrize("seed,x0,y0,level", [(0, 0, 0, 0), (1, -37, 1000003, 0), (5, 3, -4, 3)])
-def test_linear_gaussian_closed_form(weights, seed, x0, y0, level):
-    m = Model(weights("lg"))
+@pytest.mark.parametrize("config,seed,x0,y0,level", [("lg", 0, 0, 0, 0), ("lg", 1, -37, 1000003, 0),
+                                                    ("lg", 5, 3, -4, 3), ("lgt2", 2, -9, 40, 0),
+                                                    ("lgt2", 3, 100, -70, 1)])
+def test_linear_gaussian_closed_form(weights, config, seed, x0, y0, level):
+    m = Model(weights(config))
     w, h = 23, 17
     got = sample(m, seed, x0, y0, w, h, level)
     sp = m.header["sampler"]
-    sig = schedule.sigmas(m.K, sp["sigma_max"], sp["sigma_min"], sp["rho"])
+    sig = schedule.sigmas(m.steps, sp["sigma_max"], sp["sigma_min"], sp["rho"])
     sd = m.header["denoiser"]["prior_std"]
     prod = 1.0
-    for k in range(m.K - level):
+    # every window is affine in its input, so any blend schedule gives the
+    # same closed form over the steps run up to the level's blend point
+    for k in range(m.points[m.K - level]):
         prod *= 1 + (sig[k + 1] - sig[k]) * sig[k] / (sd * sd + sig[k] ** 2)
     g = noise.noise_region(seed, x0, y0, w, h, m.C).astype(np.float64)
     for (yy, xx, c) in [(0, 0, 0), (h - 1, w - 1, 3), (5, 11, 1), (16, 2, 2), (8, 8, 0)]:
@@ -73,11 +77,12 @@ def bounded_multidiffusion(m, seed, canvas, level):
     wins = [(ix, iy) for iy in range(-(-(Y0 - m.o) // m.s), (Y0 + HH - m.H - m.o) // m.s + 1)
             for ix in range(-(-(X0 - m.o) // m.s), (X0 + WW - m.H - m.o) // m.s + 1)]
     for t in range(m.K - 1, level - 1, -1):
-        sig, sig_n = schedule.sigma_pair(m.sched, m.K, t)
         xs = np.stack([j[iy * m.s + m.o - Y0:iy * m.s + m.o - Y0 + m.H,
                          ix * m.s + m.o - X0:ix * m.s + m.o - X0 + m.H] for ix, iy in wins])
-        D = m.denoiser(xs, sig, wins)
-        phi = xs + (sig_n - sig) / sig * (xs - D)
+        phi = xs
+        for k in schedule.level_steps(m.points, t):
+            sig, sig_n = m.sched[k], m.sched[k + 1]
+            phi = phi + (sig_n - sig) / sig * (phi - m.denoiser(phi, sig, wins))
         A = np.zeros_like(j)
         B = np.zeros(j.shape[:2] + (1,))
         for n, (ix, iy) in enumerate(wins):
@@ -88,7 +93,8 @@ def bounded_multidiffusion(m, seed, canvas, level):
     return j
 
 
-@pytest.mark.parametrize("config,region", [("lg", (-5, 9, 13, 7)), ("c1k2", (3, -5, 20, 12))])
+@pytest.mark.parametrize("config,region", [("lg", (-5, 9, 13, 7)), ("c1k2", (3, -5, 20, 12)),
+                                           ("c1t2", (-7, 2, 9, 11))])
 def test_lazy_equals_bounded_multidiffusion(weights, config, region):
     m = Model(weights(config))
     regions, _ = wn.cone(region, 0, m.K, m.H, m.s, m.o)
@@ -123,3 +129,21 @@ def test_noise_level_and_zero_rule(weights):
     assert np.all(out[:, 8:20] == 0) and np.all(out[:, 28:40] == 0)
     assert np.all(out[:, 0:8] != 0)
     assert np.all(sample(gap, 3, 10, 0, 5, 5, 0) == 0)
+
+
+def test_blend_schedule_validation_and_levels():
+    assert schedule.blend_points({"steps": 4}) == [0, 1, 2, 3, 4]
+    assert schedule.blend_points({"steps": 8, "blend": [0, 4, 8]}) == [0, 4, 8]
+    for bad in ([1, 8], [0, 5], [0, 4, 4, 8]):
+        with pytest.raises(ValueError):
+            schedule.blend_points({"steps": 8, "blend": bad})
+    pts = [0, 4, 8]
+    assert schedule.level_steps(pts, 1) == [0, 1, 2, 3] and schedule.level_steps(pts, 0) == [4, 5, 6, 7]
+
+
+def test_truncated_t_cone_is_smaller(weights):
+    full, trunc = Model(weights("c1")), Model(weights("c1t2"))
+    region = (0, 0, 64, 64)
+    n_full = wn.cone_window_count(region, 0, full.K, full.H, full.s)
+    n_trunc = wn.cone_window_count(region, 0, trunc.K, trunc.H, trunc.s)
+    assert (full.K, trunc.K) == (8, 2) and n_trunc < n_full / 5
