@@ -45,6 +45,7 @@ def parse():
     p.add_argument("--bf16-steps", type=int, default=1,
                    help="cold steps timed again per reduced-precision mode (0 = skip)")
     p.add_argument("--lowp-modes", default="1,2", help="precision modes to time: 1 bf16, 2 bf16 + fp8 weights")
+    p.add_argument("--truncated", default="c2t2", help="truncated-T config timed cold ('' = skip)")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="run one plain elementwise copy (read N MiB, write N MiB) before the steps, as the "
                         "reference dispatch that scales hardware byte counters")
@@ -203,6 +204,32 @@ def main():
             e["GB/s"] = round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1)
         kernels[name] = e
 
+    trunc = None
+    if a.truncated:
+        # cost of the same query when the windows are blended at T < K levels
+        # (Sec. 3.4): analytic cone counts, and one timed cold step for a.truncated
+        def cone(size, T):
+            return td.td_cone_windows(lx, ly, size, size, 0, T, H, S)
+        trunc = {"cone_windows_by_T": {str(T): {str(sz): cone(sz, T) for sz in (128, 512, 1024)}
+                                       for T in (1, 2, 5, 20)},
+                 "note": "window evaluations of a cold latent query of side 128/512/1024 at (13,-1000001); "
+                         "each evaluation runs K/T = 20/T Euler steps of the network"}
+        tctx = td.Context(0).load_weights(cached_weights(a.truncated, wdir, 0))
+        tctx.set_option("timing", 1)
+        tctx.sample_region_async(a.seed, *region, level, out, stream)     # first use
+        torch.cuda.synchronize()
+        tctx.cache_clear()
+        t0 = time.perf_counter()
+        tctx.sample_region_async(a.seed, *region, level, out, stream)
+        torch.cuda.synchronize()
+        dtt = time.perf_counter() - t0
+        stt = tctx.cache_stats()
+        trunc["timed"] = {"config": a.truncated, "T": tctx.info("levels"), "ms_per_step": 1e3 * dtt,
+                          "windows": stt["misses"], "denoiser_evals": stt["denoiser_evals"],
+                          "denoiser_evals_per_s": stt["denoiser_evals"] / dtt,
+                          "speedup_vs_T20_step": (1e3 * dt / a.steps) / (1e3 * dtt)}
+        tctx.close()
+
     lat = None
     if a.latency_pairs > 0:
         print("[bench] latency stream", file=sys.stderr, flush=True)
@@ -250,6 +277,7 @@ def main():
         "kernels": kernels,
         "latency": lat,
         "reduced_precision": lowp,
+        "truncated_T": trunc,
         "cpu_baseline": cpu,
         "output_finite": finite,
     }

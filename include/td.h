@@ -187,6 +187,55 @@ typedef struct {
 td_status td_kernel_stats(td_ctx *ctx, td_kernel_stat_t *out, int32_t cap,
                           int32_t *count, int32_t reset);
 
+/* ------------------------------------------------------------- serving --
+ * A request loop over one context with continuous batching.  Queries are
+ * admitted in arrival order while fewer than max_inflight are in flight and
+ * their worst-case device footprint (cone contributions + level canvases)
+ * fits hbm_budget bytes (a query that alone exceeds it is admitted when
+ * nothing else is in flight).  Each td_server_progress round builds the
+ * level inputs that are ready and runs one batched denoiser call over ready
+ * windows of one level, taken from any in-flight queries (windows shared by
+ * several queries are evaluated once).  Results equal those of the same
+ * queries made one at a time (seed consistency, Sec. 3.5; Parallelization
+ * theorem of the appendix).  The server uses the context's model, cache
+ * and stream; one thread drives it. */
+typedef struct td_server td_server;
+
+typedef struct {
+  uint64_t seed;
+  int64_t x0, y0;
+  int32_t w, h;
+  int32_t level;      /* latent level 0..T-1 */
+  float *dev_out;     /* device buffer [C][h][w], owned by the caller */
+  size_t out_len;
+} td_request;
+
+typedef struct {
+  uint64_t submitted, admitted, completed;
+  uint64_t rounds;           /* batched denoiser rounds */
+  uint64_t batched_windows;  /* windows evaluated by the server */
+  uint64_t in_flight, queued;
+  uint64_t mem_in_flight;    /* admitted footprint (bytes) */
+  uint64_t canvas_bytes;     /* device bytes of the canvas pool */
+} td_server_stats_t;
+
+td_status td_server_create(td_ctx *ctx, size_t hbm_budget, int32_t max_inflight,
+                           td_server **out);
+/* Waits for the device, releases unfinished queries, frees the server. */
+void td_server_destroy(td_server *srv);
+/* Queue a query (copied); *ticket identifies it.  Non-blocking. */
+td_status td_server_submit(td_server *srv, const td_request *req,
+                           uint64_t *ticket);
+/* Run `rounds` scheduling rounds; *in_flight = admitted + queued queries
+ * not yet complete.  Enqueues work and returns without waiting for it. */
+td_status td_server_progress(td_server *srv, int32_t rounds, int32_t *in_flight);
+/* *done = 1 once the query's result is in its buffer (then *latency_ms is
+ * the time from submission to observed completion and the ticket is
+ * released); TD_E_INVAL for an unknown ticket. */
+td_status td_server_poll(td_server *srv, uint64_t ticket, int32_t *done,
+                         double *latency_ms);
+td_status td_server_stats(td_server *srv, td_server_stats_t *out);
+
 /* Description of the last error on ctx (owned by ctx, valid until the next
  * call); "" if none.  Safe on NULL. */
 const char *td_last_error(const td_ctx *ctx);

@@ -21,6 +21,9 @@
 // so it is simply recomputed when next needed: values never depend on cache
 // state (seed consistency).
 #include <algorithm>
+#include <chrono>
+#include <deque>
+#include <map>
 #include <cmath>
 #include <cstring>
 #include <list>
@@ -253,9 +256,9 @@ void unpin_level(td_ctx* c, uint64_t seed, const Level& lv) {
 }
 
 // Device pointer grid of level lv's contributions over lv.k (all present).
-const float* const* pointer_grid(td_ctx* c, uint64_t seed, const Level& lv) {
+const float* const* pointer_grid(td_ctx* c, Arena& arena, uint64_t seed, const Level& lv) {
   size_t n = (size_t)lv.k.count();
-  auto hd = c->arena.reserve(n * sizeof(float*));
+  auto hd = arena.reserve(n * sizeof(float*));
   const float** h = (const float**)hd.first;
   size_t i = 0;
   for (int64_t iy = lv.k.iy0; iy <= lv.k.iy1; ++iy)
@@ -268,9 +271,9 @@ const float* const* pointer_grid(td_ctx* c, uint64_t seed, const Level& lv) {
   return (const float* const*)hd.second;
 }
 
-void blend_into(td_ctx* c, uint64_t seed, const Level& lv, const Region& r, int layout, float* out) {
+void blend_into(td_ctx* c, Arena& arena, uint64_t seed, const Level& lv, const Region& r, int layout, float* out) {
   const ModelDesc& d = c->model->d;
-  const float* const* grid = pointer_grid(c, seed, lv);
+  const float* const* grid = pointer_grid(c, arena, seed, lv);
   int64_t bx = lv.k.ix0 * d.S + d.O, by = lv.k.iy0 * d.S + d.O;
   WinGeom g{d.H, d.S, d.C};
   launch_blend(c->stream, g, (int)(r.x0 - bx), (int)(r.y0 - by), (int)r.w, (int)r.h, (int)lv.k.nx(),
@@ -357,7 +360,7 @@ void sample_latent(td_ctx* c, uint64_t seed, Region r, int level, int layout, fl
     } else {
       const Level& up = levels[i + 1];
       if (up.k.empty) launch_fill(st, c->canvas, cn, 0.f);
-      else blend_into(c, seed, up, cr, 0, c->canvas);
+      else blend_into(c, c->arena, seed, up, cr, 0, c->canvas);
       unpin_level(c, seed, up);
     }
     // new windows -> slots, then batched denoiser rounds
@@ -409,7 +412,7 @@ void sample_latent(td_ctx* c, uint64_t seed, Region r, int level, int layout, fl
   if (top.k.empty) {
     launch_fill(st, dev_out, (size_t)r.w * r.h * d.C, 0.f);
   } else {
-    blend_into(c, seed, top, r, layout, dev_out);
+    blend_into(c, c->arena, seed, top, r, layout, dev_out);
     unpin_level(c, seed, top);
   }
   evict_to_budget(c);
@@ -826,5 +829,490 @@ td_status td_kernel_stats(td_ctx* c, td_kernel_stat_t* out, int32_t cap, int32_t
 }
 
 const char* td_last_error(const td_ctx* c) { return c ? c->err.c_str() : ""; }
+
+}  // extern "C"
+
+// ====================================================================== serving
+//
+// Continuous batching of region queries.  A query is planned when admitted
+// (HBM budget, in-flight limit): its cone's windows are looked up in the
+// cache; windows another in-flight query is already going to evaluate are
+// shared, the rest become tasks owned by this query.  Every scheduling round
+// (td_server_progress) builds the level canvases whose inputs have been
+// enqueued, then runs ONE batched denoiser round over ready tasks of one
+// level, drawn from any number of queries (the window gather copies each
+// task's input out of its owner's canvas), so queries admitted while others
+// are in flight share the GPU with them.  Everything runs on the context's
+// stream in enqueue order, which is the only synchronisation the data needs;
+// the host tracks completion with one event per query.  Results equal the
+// same queries run alone, bit for bit: every window is evaluated with the
+// same batch-invariant kernels and blended in canonical order.
+
+namespace td {
+namespace {
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct SrvTask {
+  Key key;
+  uint32_t slot;
+  uint64_t q;       // owning query (its canvas holds the input)
+  int li;           // owning level index
+  int ox, oy;       // window origin relative to the owner's canvas
+  bool enq = false;
+};
+
+struct SrvLevel {
+  Level L;                 // t, region, kappa, in_region (fresh = owned windows)
+  std::vector<int> own;    // owned task ids
+  float* canvas = nullptr;
+  size_t canvas_n = 0;
+  bool built = false;
+  size_t n_enq = 0;
+};
+
+struct SrvQuery {
+  uint64_t ticket = 0;
+  td_request r{};
+  double t_sub = 0, t_done = 0;
+  int state = 0;           // 0 queued, 1 active, 2 result enqueued, 3 done
+  std::vector<SrvLevel> lv;
+  int cur = -1;
+  hipEvent_t ev = nullptr;
+  size_t mem = 0;
+};
+
+constexpr int kRing = 8;
+
+}  // namespace
+}  // namespace td
+
+struct td_server {
+  td_ctx* c = nullptr;
+  size_t budget = 0;
+  int max_inflight = 1;
+  int maxb = 1;
+  uint64_t next_ticket = 1;
+  std::deque<uint64_t> queued;
+  std::vector<uint64_t> active;
+  std::unordered_map<uint64_t, td::SrvQuery> q;
+  std::unordered_map<int, td::SrvTask> tasks;
+  int next_task = 0;
+  std::unordered_map<td::Key, int, td::KeyHash> pending;   // not yet enqueued
+  std::map<int, std::deque<int>> ready;                    // level -> ready task ids (FIFO)
+  size_t mem_used = 0;
+  td::Arena ring[td::kRing];
+  hipEvent_t ring_ev[td::kRing] = {};
+  bool ring_used[td::kRing] = {};
+  uint64_t round = 0;
+  float* batch_in = nullptr;
+  size_t batch_cap = 0;
+  std::multimap<size_t, float*> free_canvas;   // capacity -> free canvas
+  std::vector<float*> all_canvas;
+  std::unordered_map<float*, size_t> canvas_cap;
+  td_server_stats_t stats{};
+};
+
+namespace td {
+namespace {
+
+float* take_canvas(td_server* s, size_t n) {
+  auto it = s->free_canvas.lower_bound(n);
+  if (it != s->free_canvas.end() && it->first <= 2 * n + (1 << 20)) {
+    float* p = it->second;
+    s->free_canvas.erase(it);
+    return p;
+  }
+  size_t cap = std::max<size_t>(n, 1 << 18);
+  float* p = nullptr;
+  TD_HIP(hipMalloc(&p, cap * sizeof(float)));
+  s->all_canvas.push_back(p);
+  s->canvas_cap[p] = cap;
+  s->stats.canvas_bytes += cap * sizeof(float);
+  return p;
+}
+
+void give_canvas(td_server* s, float* p) {
+  if (p) s->free_canvas.emplace(s->canvas_cap[p], p);
+}
+
+// Upper bound of the device bytes a query needs while in flight.
+size_t query_bytes(td_ctx* c, const td_request& r) {
+  const ModelDesc& d = c->model->d;
+  size_t slot = c->pool.slot_bytes();
+  size_t bytes = 0;
+  Region R{r.x0, r.y0, r.w, r.h};
+  for (int t = r.level; t < d.T; ++t) {
+    Kappa k = kappa(R, d.H, d.S, d.O);
+    if (k.empty) break;
+    bytes += (size_t)k.count() * slot;
+    R = Region{k.ix0 * d.S + d.O, k.iy0 * d.S + d.O, (k.ix1 - k.ix0) * d.S + d.H, (k.iy1 - k.iy0) * d.S + d.H};
+    bytes += (size_t)R.w * R.h * d.C * sizeof(float);
+  }
+  return bytes;
+}
+
+void plan_query(td_server* s, SrvQuery& Q) {
+  td_ctx* c = s->c;
+  const ModelDesc& d = c->model->d;
+  Region R{Q.r.x0, Q.r.y0, Q.r.w, Q.r.h};
+  for (int t = Q.r.level; t < d.T; ++t) {
+    SrvLevel S;
+    S.L.t = t;
+    S.L.region = R;
+    S.L.k = kappa(R, d.H, d.S, d.O);
+    if (!S.L.k.empty) {
+      int64_t mnx = INT64_MAX, mxx = INT64_MIN, mny = INT64_MAX, mxy = INT64_MIN;
+      for (int64_t iy = S.L.k.iy0; iy <= S.L.k.iy1; ++iy)
+        for (int64_t ix = S.L.k.ix0; ix <= S.L.k.ix1; ++ix) {
+          Key key{Q.r.seed, t, ix, iy};
+          auto m = c->map.find(key);
+          if (m != c->map.end()) {
+            m->second.pins++;
+            touch(c, m->second, key);
+            c->stats.hits++;
+            continue;
+          }
+          int id = s->next_task++;
+          SrvTask T;
+          T.key = key;
+          T.slot = c->pool.take();
+          T.q = Q.ticket;
+          T.li = (int)Q.lv.size();
+          c->lru.push_front(key);
+          c->map[key] = Entry{T.slot, 1, c->lru.begin()};
+          s->pending[key] = id;
+          s->tasks[id] = T;
+          S.own.push_back(id);
+          S.L.fresh.push_back({ix, iy});
+          mnx = std::min(mnx, ix);
+          mxx = std::max(mxx, ix);
+          mny = std::min(mny, iy);
+          mxy = std::max(mxy, iy);
+        }
+      if (!S.own.empty()) {
+        S.L.in_region = Region{mnx * d.S + d.O, mny * d.S + d.O, (mxx - mnx) * d.S + d.H, (mxy - mny) * d.S + d.H};
+        for (int id : S.own) {
+          SrvTask& T = s->tasks[id];
+          T.ox = (int)(T.key.ix * d.S + d.O - S.L.in_region.x0);
+          T.oy = (int)(T.key.iy * d.S + d.O - S.L.in_region.y0);
+        }
+        c->stats.misses += S.own.size();
+        c->stats.denoiser_evals += (uint64_t)S.own.size() * c->model->level_steps(t);
+        if (t < 64) c->stats.windows_evaluated[t] += S.own.size();
+      }
+    }
+    Q.lv.push_back(std::move(S));
+    const SrvLevel& B = Q.lv.back();
+    if (B.L.k.empty || B.own.empty()) break;
+    R = B.L.in_region;
+  }
+  Q.cur = (int)Q.lv.size() - 1;
+}
+
+bool all_enqueued(td_server* s, uint64_t seed, const Level& L) {
+  if (L.k.empty) return true;
+  for (int64_t iy = L.k.iy0; iy <= L.k.iy1; ++iy)
+    for (int64_t ix = L.k.ix0; ix <= L.k.ix1; ++ix)
+      if (s->pending.count(Key{seed, L.t, ix, iy})) return false;
+  return true;
+}
+
+// Advance one query as far as the enqueued work allows.
+void advance(td_server* s, SrvQuery& Q, Arena& arena) {
+  td_ctx* c = s->c;
+  const ModelDesc& d = c->model->d;
+  hipStream_t st = c->stream;
+  while (Q.state == 1) {
+    if (Q.cur >= 0) {
+      SrvLevel& S = Q.lv[Q.cur];
+      if (S.own.empty()) {
+        Q.cur--;
+        continue;
+      }
+      if (!S.built) {
+        const int tn = S.L.t + 1;
+        const bool below = Q.cur + 1 < (int)Q.lv.size();
+        if (tn != d.T && below && !all_enqueued(s, Q.r.seed, Q.lv[Q.cur + 1].L)) return;
+        const Region& cr = S.L.in_region;
+        S.canvas_n = (size_t)cr.w * cr.h * d.C;
+        S.canvas = take_canvas(s, S.canvas_n);
+        if (tn == d.T) {
+          launch_noise(st, Q.r.seed, cr.x0, cr.y0, (int)cr.w, (int)cr.h, d.C, 0, (float)d.sched[0], 0, S.canvas);
+        } else if (!below || Q.lv[Q.cur + 1].L.k.empty) {
+          launch_fill(st, S.canvas, S.canvas_n, 0.f);
+        } else {
+          blend_into(c, arena, Q.r.seed, Q.lv[Q.cur + 1].L, cr, 0, S.canvas);
+          unpin_level(c, Q.r.seed, Q.lv[Q.cur + 1].L);
+        }
+        S.built = true;
+        for (int id : S.own) s->ready[S.L.t].push_back(id);
+      }
+      if (S.n_enq < S.own.size()) return;
+      give_canvas(s, S.canvas);       // later users are stream-ordered after its readers
+      S.canvas = nullptr;
+      Q.cur--;
+      continue;
+    }
+    // every level evaluated: the result is the blend of the query level
+    const Level& top = Q.lv[0].L;
+    if (!all_enqueued(s, Q.r.seed, top)) return;
+    const size_t n = (size_t)Q.r.w * Q.r.h * d.C;
+    if (top.k.empty) {
+      launch_fill(st, Q.r.dev_out, n, 0.f);
+    } else {
+      blend_into(c, arena, Q.r.seed, top, Region{Q.r.x0, Q.r.y0, Q.r.w, Q.r.h}, 1, Q.r.dev_out);
+      unpin_level(c, Q.r.seed, top);
+    }
+    TD_HIP(hipEventRecord(Q.ev, st));
+    Q.state = 2;
+    s->mem_used -= Q.mem;
+    c->stats.queries++;
+  }
+}
+
+// One batched denoiser round over ready tasks of a single level.
+bool run_round_batch(td_server* s, Arena& arena) {
+  td_ctx* c = s->c;
+  const ModelDesc& d = c->model->d;
+  hipStream_t st = c->stream;
+  int best = -1;
+  size_t bestn = 0;
+  for (auto& kv : s->ready)
+    if (kv.second.size() > bestn || (kv.second.size() == bestn && bestn && kv.first > best)) {
+      best = kv.first;
+      bestn = kv.second.size();
+    }
+  if (best < 0 || bestn == 0) return false;
+  std::deque<int>& dq = s->ready[best];
+  const int nb = (int)std::min<size_t>(dq.size(), (size_t)s->maxb);
+  const size_t per = (size_t)d.H * d.H * d.C;
+  if ((size_t)nb * per > s->batch_cap) {
+    TD_HIP(hipStreamSynchronize(st));
+    if (s->batch_in) TD_HIP(hipFree(s->batch_in));
+    s->batch_cap = (size_t)s->maxb * per;
+    TD_HIP(hipMalloc(&s->batch_in, s->batch_cap * sizeof(float)));
+  }
+  auto src = arena.reserve((size_t)nb * sizeof(float*));
+  auto pit = arena.reserve((size_t)nb * sizeof(int));
+  auto org = arena.reserve((size_t)nb * 2 * sizeof(int));
+  auto wix = arena.reserve((size_t)nb * 2 * sizeof(int));
+  auto slo = arena.reserve((size_t)nb * sizeof(float*));
+  const float** hs = (const float**)src.first;
+  int* hp = (int*)pit.first;
+  int* ho = (int*)org.first;
+  int* hw = (int*)wix.first;
+  float** hsl = (float**)slo.first;
+  std::vector<int> ids(nb);
+  for (int j = 0; j < nb; ++j) {
+    ids[j] = dq.front();
+    dq.pop_front();
+    SrvTask& T = s->tasks[ids[j]];
+    SrvQuery& O = s->q[T.q];
+    SrvLevel& S = O.lv[T.li];
+    hs[j] = S.canvas + ((size_t)T.oy * S.L.in_region.w + T.ox) * d.C;
+    hp[j] = (int)S.L.in_region.w;
+    ho[2 * j] = 0;
+    ho[2 * j + 1] = j * d.H;
+    hw[2 * j] = (int)T.key.ix;
+    hw[2 * j + 1] = (int)T.key.iy;
+    hsl[j] = c->pool.ptr(T.slot);
+  }
+  TD_HIP(hipMemcpyAsync(src.second, src.first, (size_t)nb * sizeof(float*), hipMemcpyHostToDevice, st));
+  TD_HIP(hipMemcpyAsync(pit.second, pit.first, (size_t)nb * sizeof(int), hipMemcpyHostToDevice, st));
+  TD_HIP(hipMemcpyAsync(org.second, org.first, (size_t)nb * 2 * sizeof(int), hipMemcpyHostToDevice, st));
+  TD_HIP(hipMemcpyAsync(wix.second, wix.first, (size_t)nb * 2 * sizeof(int), hipMemcpyHostToDevice, st));
+  TD_HIP(hipMemcpyAsync(slo.second, slo.first, (size_t)nb * sizeof(float*), hipMemcpyHostToDevice, st));
+  launch_gather(st, (const float* const*)src.second, (const int*)pit.second, nb, d.H, d.C, s->batch_in);
+  WindowBatch wb;
+  wb.canvas = s->batch_in;
+  wb.canvas_w = d.H;
+  wb.d_origins = (const int*)org.second;
+  wb.d_widx = (const int*)wix.second;
+  wb.d_slots = (float* const*)slo.second;
+  wb.n = nb;
+  wb.mode = 0;
+  c->model->run_level(st, wb, best);
+  c->stats.batches++;
+  s->stats.batched_windows += nb;
+  for (int id : ids) {
+    SrvTask& T = s->tasks[id];
+    T.enq = true;
+    s->pending.erase(T.key);
+    s->q[T.q].lv[T.li].n_enq++;
+  }
+  for (int id : ids) s->tasks.erase(id);
+  if (dq.empty()) s->ready.erase(best);
+  return true;
+}
+
+void admit(td_server* s) {
+  while (!s->queued.empty() && (int)s->active.size() < s->max_inflight) {
+    SrvQuery& Q = s->q[s->queued.front()];
+    size_t need = query_bytes(s->c, Q.r);
+    if (!s->active.empty() && s->mem_used + need > s->budget) break;
+    s->queued.pop_front();
+    Q.mem = need;
+    s->mem_used += need;
+    plan_query(s, Q);
+    Q.state = 1;
+    s->active.push_back(Q.ticket);
+    s->stats.admitted++;
+  }
+}
+
+void server_round(td_server* s) {
+  td_ctx* c = s->c;
+  const int slot = (int)(s->round % kRing);
+  if (s->ring_used[slot]) TD_HIP(hipEventSynchronize(s->ring_ev[slot]));
+  Arena& arena = s->ring[slot];
+  arena.reset();
+  admit(s);
+  size_t need = 65536;   // metadata of this round: pointer grids + one batch
+  for (uint64_t t : s->active) {
+    const SrvQuery& Q = s->q[t];
+    for (const SrvLevel& S : Q.lv) need += (size_t)S.L.k.count() * sizeof(float*) + 256;
+  }
+  need += (size_t)s->maxb * 48 + 5 * 256;
+  arena.ensure(need);
+  for (uint64_t t : s->active) advance(s, s->q[t], arena);
+  if (run_round_batch(s, arena)) s->stats.rounds++;
+  for (uint64_t t : s->active) advance(s, s->q[t], arena);
+  TD_HIP(hipEventRecord(s->ring_ev[slot], c->stream));
+  s->ring_used[slot] = true;
+  s->round++;
+  // completions
+  std::vector<uint64_t> still;
+  for (uint64_t t : s->active) {
+    SrvQuery& Q = s->q[t];
+    if (Q.state == 2) {
+      hipError_t e = hipEventQuery(Q.ev);
+      if (e == hipSuccess) {
+        Q.state = 3;
+        Q.t_done = now_ms();
+        s->stats.completed++;
+      } else if (e != hipErrorNotReady) {
+        TD_HIP(e);
+      }
+      (void)hipGetLastError();   // "not ready" is a status, not an error
+    }
+    if (Q.state != 3) still.push_back(t);
+  }
+  s->active.swap(still);
+  evict_to_budget(c);
+}
+
+}  // namespace
+}  // namespace td
+
+extern "C" {
+
+td_status td_server_create(td_ctx* c, size_t hbm_budget, int32_t max_inflight, td_server** out) {
+  if (!c || !out || max_inflight < 1) return TD_E_INVAL;
+  *out = nullptr;
+  td_server* s = nullptr;
+  td_status st = guarded(c, [&] {
+    need_model(c);
+    TD_HIP(hipSetDevice(c->device));
+    s = new td_server();
+    s->c = c;
+    s->budget = hbm_budget;
+    s->max_inflight = max_inflight;
+    s->maxb = std::min(auto_batch(c), 4096);
+    c->model->ensure_workspace(s->maxb);
+    for (int i = 0; i < kRing; ++i) TD_HIP(hipEventCreateWithFlags(&s->ring_ev[i], hipEventDisableTiming));
+  });
+  if (st != TD_OK) {
+    td_server_destroy(s);
+    return st;
+  }
+  *out = s;
+  return TD_OK;
+}
+
+void td_server_destroy(td_server* s) {
+  if (!s) return;
+  td_ctx* c = s->c;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  // release what unfinished queries hold: pins and not-yet-evaluated slots
+  for (auto& kv : s->pending) {
+    auto m = c->map.find(kv.first);
+    if (m != c->map.end()) {
+      c->pool.give(m->second.slot);
+      c->lru.erase(m->second.lru);
+      c->map.erase(m);
+    }
+  }
+  for (auto& kv : s->q) {
+    SrvQuery& Q = kv.second;
+    if (Q.state == 1) {
+      for (int i = std::max(Q.cur, 0); i < (int)Q.lv.size(); ++i) unpin_level(c, Q.r.seed, Q.lv[i].L);
+    }
+    if (Q.ev) (void)hipEventDestroy(Q.ev);
+  }
+  for (float* p : s->all_canvas) (void)hipFree(p);
+  if (s->batch_in) (void)hipFree(s->batch_in);
+  for (int i = 0; i < kRing; ++i)
+    if (s->ring_ev[i]) (void)hipEventDestroy(s->ring_ev[i]);
+  delete s;
+}
+
+td_status td_server_submit(td_server* s, const td_request* r, uint64_t* ticket) {
+  if (!s || !r || !ticket) return TD_E_INVAL;
+  td_ctx* c = s->c;
+  return guarded(c, [&] {
+    need_model(c);
+    const ModelDesc& d = c->model->d;
+    check_region(r->x0, r->y0, r->w, r->h);
+    TD_CHECK(r->level >= 0 && r->level < d.T, TD_E_INVAL, "server queries take latent levels 0..T-1");
+    TD_CHECK(r->dev_out && r->out_len >= (size_t)r->w * r->h * d.C, TD_E_INVAL, "output buffer too small");
+    SrvQuery Q;
+    Q.ticket = s->next_ticket++;
+    Q.r = *r;
+    Q.t_sub = now_ms();
+    TD_HIP(hipEventCreateWithFlags(&Q.ev, hipEventDisableTiming));
+    const uint64_t t = Q.ticket;
+    s->q[t] = std::move(Q);
+    s->queued.push_back(t);
+    s->stats.submitted++;
+    *ticket = t;
+  });
+}
+
+td_status td_server_progress(td_server* s, int32_t rounds, int32_t* in_flight) {
+  if (!s || rounds < 0) return TD_E_INVAL;
+  td_ctx* c = s->c;
+  return guarded(c, [&] {
+    TD_HIP(hipSetDevice(c->device));
+    for (int i = 0; i < rounds; ++i) server_round(s);
+    if (in_flight) *in_flight = (int32_t)(s->active.size() + s->queued.size());
+  });
+}
+
+td_status td_server_poll(td_server* s, uint64_t ticket, int32_t* done, double* latency_ms) {
+  if (!s || !done) return TD_E_INVAL;
+  auto it = s->q.find(ticket);
+  if (it == s->q.end()) return TD_E_INVAL;
+  SrvQuery& Q = it->second;
+  *done = Q.state == 3;
+  if (Q.state == 3) {
+    if (latency_ms) *latency_ms = Q.t_done - Q.t_sub;
+    if (Q.ev) (void)hipEventDestroy(Q.ev);
+    s->q.erase(it);
+  }
+  return TD_OK;
+}
+
+td_status td_server_stats(td_server* s, td_server_stats_t* out) {
+  if (!s || !out) return TD_E_INVAL;
+  s->stats.in_flight = s->active.size();
+  s->stats.queued = s->queued.size();
+  s->stats.mem_in_flight = s->mem_used;
+  *out = s->stats;
+  return TD_OK;
+}
 
 }  // extern "C"

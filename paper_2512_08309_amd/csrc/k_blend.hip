@@ -121,7 +121,29 @@ __global__ __launch_bounds__(256) void lg_step_kernel(int H, int C, const float*
   else slots[b][idx] = (w1d[u] * w1d[v]) * phi;
 }
 
+// Window gather: out[b][v][u][c] = src[b][(v * pitch[b] + u) * C + c].
+__global__ __launch_bounds__(256) void gather_kernel(const float* const* __restrict__ src,
+                                                     const int* __restrict__ pitch, int H, int C,
+                                                     float* __restrict__ out) {
+  const int b = blockIdx.y;
+  const int per = H * H * C;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= per) return;
+  const int c = e % C, p = e / C;
+  const int v = p / H, u = p - v * H;
+  out[(size_t)b * per + e] = src[b][((size_t)v * pitch[b] + u) * C + c];
+}
+
 }  // namespace
+
+void launch_gather(hipStream_t st, const float* const* src, const int* pitch, int nb, int H, int C, float* out) {
+  if (!nb) return;
+  const int per = H * H * C;
+  prof_begin(st);
+  hipLaunchKernelGGL(gather_kernel, dim3((per + 255) / 256, nb), dim3(256), 0, st, src, pitch, H, C, out);
+  TD_LAUNCHED();
+  prof_end(st, K_GATHER, 0.0, 8.0 * per * nb);
+}
 
 void launch_blend(hipStream_t st, const WinGeom& g, int rx0, int ry0, int w, int h, int nx, int ny,
                   const float* const* ptrs, const float* w1d, int layout, float* out) {

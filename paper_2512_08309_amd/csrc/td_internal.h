@@ -39,7 +39,7 @@ struct Error {
 // bytes of the launch).  When no profiler is installed the hooks are no-ops.
 enum KClass {
   K_CONV3 = 0, K_CONV1, K_GN, K_CONV_IN, K_CONV_OUT, K_ATTN, K_POOL, K_NOISE, K_BLEND, K_DECODE, K_LG, K_EMB,
-  K_CONV3_LP, K_CONV1_LP, K_APPLY, K_NCLASS
+  K_CONV3_LP, K_CONV1_LP, K_APPLY, K_GATHER, K_NCLASS
 };
 const char* kclass_name(int k);
 struct Profiler;
@@ -71,6 +71,11 @@ void launch_blend(hipStream_t st, const WinGeom& g, int rx0, int ry0, int w,
                   const float* w1d, int layout, float* out);
 
 void launch_fill(hipStream_t st, float* p, size_t n, float v);
+
+// Window gather (Alg. 1's J_{t+1}[R_i]) from per-window canvases into a
+// dense batch [nb][H][H][C]; src[b] points at the window's first pixel,
+// pitch[b] is its canvas row length in pixels.
+void launch_gather(hipStream_t st, const float* const* src, const int* pitch, int nb, int H, int C, float* out);
 
 // Analytic linear-Gaussian denoiser + Euler step + weighting (see kernels).
 void launch_lg_step(hipStream_t st, const WinGeom& g, const float* canvas,

@@ -22,7 +22,8 @@ STATUS_NAMES = {0: "TD_OK", -1: "TD_E_INVAL", -2: "TD_E_NOMEM", -3: "TD_E_DEVICE
 EXPORTS = ["td_create", "td_destroy", "td_load_weights", "td_sample_region", "td_sample_region_async",
            "td_cache_set_budget", "td_cache_clear", "td_cache_stats", "td_cache_peek", "td_set_option",
            "td_get_info", "td_denoise_windows", "td_lap_decode", "td_kappa", "td_cone_windows", "td_kernel_stats",
-           "td_last_error"]
+           "td_server_create", "td_server_destroy", "td_server_submit", "td_server_progress", "td_server_poll",
+           "td_server_stats", "td_last_error"]
 
 
 class td_cache_stats_t(ctypes.Structure):
@@ -35,6 +36,17 @@ class td_cache_stats_t(ctypes.Structure):
 class td_kernel_stat_t(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64), ("ms", ctypes.c_double),
                 ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+class td_request(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("x0", ctypes.c_int64), ("y0", ctypes.c_int64), ("w", ctypes.c_int32),
+                ("h", ctypes.c_int32), ("level", ctypes.c_int32), ("dev_out", ctypes.c_void_p),
+                ("out_len", ctypes.c_size_t)]
+
+
+class td_server_stats_t(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "admitted", "completed", "rounds", "batched_windows",
+                                               "in_flight", "queued", "mem_in_flight", "canvas_bytes")]
 
 
 class TDError(RuntimeError):
@@ -66,6 +78,12 @@ def _load():
         "td_kappa": ([i64, i64, i64, i64, i32, i32, i32, ctypes.POINTER(i64)], ctypes.c_int),
         "td_cone_windows": ([i64, i64, i64, i64, i32, i32, i32, i32, i32, ctypes.POINTER(u64)], ctypes.c_int),
         "td_kernel_stats": ([vp, ctypes.POINTER(td_kernel_stat_t), i32, ctypes.POINTER(i32), i32], ctypes.c_int),
+        "td_server_create": ([vp, sz, i32, ctypes.POINTER(vp)], ctypes.c_int),
+        "td_server_destroy": ([vp], None),
+        "td_server_submit": ([vp, ctypes.POINTER(td_request), ctypes.POINTER(u64)], ctypes.c_int),
+        "td_server_progress": ([vp, i32, ctypes.POINTER(i32)], ctypes.c_int),
+        "td_server_poll": ([vp, u64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+        "td_server_stats": ([vp, ctypes.POINTER(td_server_stats_t)], ctypes.c_int),
         "td_last_error": ([vp], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -204,6 +222,45 @@ def td_kernel_stats(ctx, reset=False):
                                    "bytes": arr[i].bytes} for i in range(min(n.value, 32))}
 
 
+def td_server_create(ctx, hbm_budget, max_inflight):
+    p = ctypes.c_void_p()
+    _check(ctx, lib.td_server_create(ctx, hbm_budget, max_inflight, ctypes.byref(p)))
+    return p
+
+
+def td_server_destroy(srv):
+    lib.td_server_destroy(srv)
+
+
+def td_server_submit(ctx, srv, seed, x0, y0, w, h, level, dev_out):
+    """Queue a latent query whose result goes to dev_out (float32 torch tensor [C][h][w])."""
+    assert dev_out.is_contiguous() and dev_out.element_size() == 4
+    r = td_request(seed & (2 ** 64 - 1), x0, y0, w, h, level, dev_out.data_ptr(), dev_out.numel())
+    t = ctypes.c_uint64()
+    _check(ctx, lib.td_server_submit(srv, ctypes.byref(r), ctypes.byref(t)))
+    return t.value
+
+
+def td_server_progress(ctx, srv, rounds=1):
+    n = ctypes.c_int32()
+    _check(ctx, lib.td_server_progress(srv, rounds, ctypes.byref(n)))
+    return n.value
+
+
+def td_server_poll(ctx, srv, ticket):
+    """(done, latency_ms); a finished ticket is released."""
+    d = ctypes.c_int32()
+    lat = ctypes.c_double()
+    _check(ctx, lib.td_server_poll(srv, ticket, ctypes.byref(d), ctypes.byref(lat)))
+    return bool(d.value), lat.value
+
+
+def td_server_stats(ctx, srv):
+    st = td_server_stats_t()
+    _check(ctx, lib.td_server_stats(srv, ctypes.byref(st)))
+    return {k: getattr(st, k) for k, _ in td_server_stats_t._fields_}
+
+
 def td_last_error(ctx):
     return lib.td_last_error(ctx).decode()
 
@@ -269,3 +326,34 @@ class Context:
 
     def lap_decode(self, latent_dev, lx0, ly0, X0, Y0, W, H, out_dev, stream=None):
         return td_lap_decode(self.ctx, latent_dev, lx0, ly0, X0, Y0, W, H, out_dev, stream)
+
+
+class Server:
+    """Continuous-batching request loop over a Context (see td_server_* in td.h)."""
+
+    def __init__(self, ctx, hbm_budget, max_inflight):
+        self.c = ctx
+        self.srv = td_server_create(ctx.ctx, hbm_budget, max_inflight)
+
+    def submit(self, seed, x0, y0, w, h, level, dev_out):
+        return td_server_submit(self.c.ctx, self.srv, seed, x0, y0, w, h, level, dev_out)
+
+    def progress(self, rounds=1):
+        return td_server_progress(self.c.ctx, self.srv, rounds)
+
+    def poll(self, ticket):
+        return td_server_poll(self.c.ctx, self.srv, ticket)
+
+    def stats(self):
+        return td_server_stats(self.c.ctx, self.srv)
+
+    def close(self):
+        if self.srv:
+            td_server_destroy(self.srv)
+            self.srv = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

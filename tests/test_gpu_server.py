@@ -1,0 +1,74 @@
+"""Continuous-batching server: every query's result in a concurrent mix
+equals the same query made alone (bit for bit), and the rounds really mix
+windows of several queries."""
+import numpy as np
+import pytest
+
+from gpu_common import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+QUERIES = [  # (seed, x0, y0, w, h, level): uneven sizes, overlaps, repeats, two seeds
+    (3, 0, 0, 64, 64, 0), (3, 40, -20, 96, 48, 0), (3, 0, 0, 64, 64, 0), (7, -1000003, 999983, 33, 70, 0),
+    (3, 500, 500, 128, 17, 0), (3, 30, 10, 20, 20, 2), (7, -1000003, 999990, 64, 64, 0), (3, -64, 0, 64, 64, 0),
+    (3, 1000, -3000, 160, 96, 0), (7, 5, 5, 9, 9, 0), (3, 47, -13, 31, 77, 1), (3, 600, 450, 64, 64, 0),
+]
+
+
+def run_alone(td, torch, wpath, q):
+    with td.Context(0) as c:
+        c.load_weights(wpath)
+        C = c.info("channels")
+        out = torch.empty((C, q[4], q[3]), device="cuda")
+        c.sample_region_async(*q, out)
+        torch.cuda.synchronize()
+        return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("config,inflight,budget", [("c1", 6, 64 << 30), ("c1", 2, 200 << 20),
+                                                    ("c1t2", 12, 64 << 30), ("lg", 4, 64 << 30)])
+def test_mix_equals_alone(weights, config, inflight, budget):
+    require_gpu()
+    import torch
+    from paper_2512_08309_amd import td
+    wpath = weights(config)
+    with td.Context(0) as c:
+        c.load_weights(wpath)
+        T = c.info("levels")
+    queries = [q[:5] + (min(q[5], T - 1),) for q in QUERIES]
+    alone = [run_alone(td, torch, wpath, q) for q in queries]
+    with td.Context(0) as c:
+        c.load_weights(wpath)
+        C = c.info("channels")
+        with td.Server(c, budget, inflight) as srv:
+            outs, tickets = [], []
+            # submit in two waves: the second arrives while the first is in flight
+            for i, q in enumerate(queries):
+                outs.append(torch.full((C, q[4], q[3]), float("nan"), device="cuda"))
+                tickets.append(srv.submit(*q, outs[-1]))
+                if i == 5:
+                    srv.progress(3)
+            done = {}
+            for _ in range(100000):
+                n = srv.progress(1)
+                for t in tickets:
+                    if t not in done:
+                        ok, lat = srv.poll(t)
+                        if ok:
+                            done[t] = lat
+                if len(done) == len(tickets):
+                    break
+            torch.cuda.synchronize()
+            st = srv.stats()
+        assert len(done) == len(queries) and n == 0
+        assert st["completed"] == len(queries) and st["rounds"] > 0
+        for q, o, a in zip(queries, outs, alone):
+            assert np.array_equal(o.cpu().numpy(), a), q
+        cs = c.cache_stats()
+        # shared windows are evaluated once: fewer evaluations than the sum of cold cones
+        from oracle import windows as wn
+        H, S, T = c.info("window"), c.info("stride"), c.info("levels")
+        cold = sum(wn.cone_window_count(q[1:5], q[5], T, H, S) for q in queries)
+        assert cs["misses"] < cold
+        print(config, "inflight", inflight, "rounds", st["rounds"], "windows", st["batched_windows"],
+              "cold-sum", cold, "mean batch %.1f" % (st["batched_windows"] / st["rounds"]))
