@@ -46,6 +46,8 @@ def parse():
                    help="cold steps timed again per reduced-precision mode (0 = skip)")
     p.add_argument("--lowp-modes", default="1,2", help="precision modes to time: 1 bf16, 2 bf16 + fp8 weights")
     p.add_argument("--truncated", default="c2t2", help="truncated-T config timed cold ('' = skip)")
+    p.add_argument("--serve-queries", type=int, default=256, help="queries of the serving stream (0 = skip)")
+    p.add_argument("--serve-rate", type=float, default=256.0, help="Poisson arrival rate, queries/s")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="run one plain elementwise copy (read N MiB, write N MiB) before the steps, as the "
                         "reference dispatch that scales hardware byte counters")
@@ -95,6 +97,64 @@ def latency_stream(td, torch, weights_path, pairs, seed=11):
                         "in [-1e6,1e6) seed %d, each followed by its right neighbour; end-to-end through "
                         "td_sample_region_async incl. planning" % (pairs, seed),
             "first": pct(first), "neighbour": pct(second)}
+
+
+def serving_stream(td, torch, weights_path, n, rate, seed=17, budget=64 << 30, inflight=64, precision=1):
+    """Poisson stream of region queries through the continuous-batching server:
+    sides uniform in [64, 512] latent px, coordinates uniform in [-1e6, 1e6),
+    30% revisits of an earlier region (shifted by up to half its size)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    qs = []
+    for i in range(n):
+        if qs and rng.random() < 0.3:
+            b = qs[rng.integers(len(qs))]
+            dx, dy = (int(v) for v in rng.integers(-(b[2] // 2), b[2] // 2 + 1, size=2))
+            qs.append((b[0] + dx, b[1] + dy, b[2], b[3]))
+        else:
+            w, h = (int(v) for v in rng.integers(64, 513, size=2))
+            x, y = (int(v) for v in rng.integers(-10 ** 6, 10 ** 6, size=2))
+            qs.append((x, y, w, h))
+    with td.Context(0) as c:
+        c.load_weights(weights_path)
+        c.set_option("precision", precision)
+        C = c.info("channels")
+        warm = torch.empty((C, 64, 64), device="cuda")
+        c.sample_region_async(seed, 0, 0, 64, 64, 0, warm)     # kernels, workspaces
+        torch.cuda.synchronize()
+        c.cache_clear()
+        outs, tick, lat = {}, {}, []
+        with td.Server(c, budget, inflight) as srv:
+            t0 = time.perf_counter()
+            i = 0
+            while len(lat) < n:
+                now = time.perf_counter() - t0
+                while i < n and arrivals[i] <= now:
+                    x, y, w, h = qs[i]
+                    outs[i] = torch.empty((C, h, w), device="cuda")
+                    tick[i] = srv.submit(seed, x, y, w, h, 0, outs[i])
+                    i += 1
+                if srv.progress(1) == 0 and i < n:
+                    time.sleep(max(0.0, min(1e-3, arrivals[i] - (time.perf_counter() - t0))))
+                for j in list(tick):
+                    ok, ms = srv.poll(tick[j])
+                    if ok:
+                        lat.append(ms)
+                        del tick[j]
+                        del outs[j]
+            wall = time.perf_counter() - t0
+            st = srv.stats()
+        cs = c.cache_stats()
+    lat = np.array(lat)
+    return {"workload": "fine 1-channel model (2-level UNet 16/32, windows 32/16, K=8), %s denoiser; %d queries, "
+                        "Poisson %.0f q/s, sides U[64,512], coords U[-1e6,1e6), 30%% revisits; HBM admission "
+                        "budget %d GB, <= %d in flight; no coarse conditioning model"
+                        % ("BF16" if precision == 1 else "FP32", n, rate, budget >> 30, inflight),
+            "queries_per_s": n / wall, "window_denoises_per_s": st["batched_windows"] / wall,
+            "latency_p50_ms": float(np.percentile(lat, 50)), "latency_p99_ms": float(np.percentile(lat, 99)),
+            "rounds": st["rounds"], "mean_batch": st["batched_windows"] / max(st["rounds"], 1),
+            "cache_hits": cs["hits"], "windows_evaluated": cs["misses"], "wall_s": wall}
 
 
 def main():
@@ -234,6 +294,10 @@ def main():
     if a.latency_pairs > 0:
         print("[bench] latency stream", file=sys.stderr, flush=True)
         lat = latency_stream(td, torch, cached_weights("c1", wdir, 0), a.latency_pairs)
+    serve = None
+    if a.serve_queries > 0:
+        print("[bench] serving stream", file=sys.stderr, flush=True)
+        serve = serving_stream(td, torch, cached_weights("c1", wdir, 0), a.serve_queries, a.serve_rate)
     cpu = None
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
@@ -278,6 +342,7 @@ def main():
         "latency": lat,
         "reduced_precision": lowp,
         "truncated_T": trunc,
+        "serving": serve,
         "cpu_baseline": cpu,
         "output_finite": finite,
     }
