@@ -10,10 +10,11 @@
 // (pixel, 8-channel) segment per load.
 //
 // Tile 128 x 128 per 256-thread workgroup (4 waves, 2 x 2, 64 x 64 each),
-// K advances BK per stage through double-buffered LDS.  LDS rows hold BK
-// BF16 values of one pixel (A) or one output channel (B); the 16-byte
-// segments of a row are XOR-swizzled by the row index so that the MFMA
-// operand reads (16 consecutive rows, same segment) are bank-conflict free.
+// K advances BK = 32 per stage through double-buffered LDS (32 KB, so four
+// workgroups share a CU).  LDS rows hold BK BF16 values of one pixel (A) or
+// one output channel (B); the 16-byte segments of a row are XOR-swizzled by
+// the row index so that the MFMA operand reads (16 consecutive rows, same
+// segment) are bank-conflict free.
 // A K-group g of an MFMA lane pairs the same 8 K indices for A and B, so
 // the product is the plain dot product whatever order the hardware sums
 // the 32 terms in; that order is fixed, keeping results batch-invariant.
@@ -22,9 +23,9 @@
 // (applied in the epilogue); they are widened to BF16 while staging, which
 // is exact.
 //
-// FAST (C_in a multiple of BK = 64): a stage never straddles a tap, so the
-// shifted pixel address is computed once per tap.  Otherwise (small C_in)
-// BK = 32 and every segment resolves its own (tap, channel).
+// FAST (C_in a multiple of BK): a stage never straddles a tap, so the
+// shifted pixel address is computed once per tap.  Otherwise every segment
+// resolves its own (tap, channel).
 #include <type_traits>
 
 #include "td_internal.h"
@@ -47,15 +48,14 @@ __device__ __forceinline__ u2v fp8x4_to_bf16x4(unsigned w) {
   return (u2v){__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b)};
 }
 
-template <int BK>
-__device__ __forceinline__ int swz(int row, int seg) {
-  return BK == 64 ? (seg ^ (row & 7)) : (seg ^ ((row >> 1) & 3));
-}
+// 4 segments of 16 bytes per 64-byte row; rows 2r and 2r+1 share a 128-byte
+// bank line, so the swizzle changes every second row.
+__device__ __forceinline__ int swz(int row, int seg) { return seg ^ ((row >> 1) & 3); }
 
 template <int TAPS, bool FAST, bool W8, int BN, int WM, int WN>
-__global__ __launch_bounds__(256, 2) void conv_bf16_kernel(ConvLpArgs a, int n_tiles_n) {
+__global__ __launch_bounds__(256, 4) void conv_bf16_kernel(ConvLpArgs a, int n_tiles_n) {
   constexpr int BM = 128;
-  constexpr int BK = FAST ? 64 : 32;
+  constexpr int BK = 32;
   constexpr int SEGS = BK / 8;             // 16-byte segments per row
   constexpr int AL = BM * SEGS / 256;      // A segment loads per thread
   constexpr int BL = (BN * SEGS + 255) / 256;
@@ -77,44 +77,53 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_kernel(ConvLpArgs a, int n_t
   const __bf16* wts = reinterpret_cast<const __bf16*>(a.wt);
   const unsigned char* wts8 = reinterpret_cast<const unsigned char*>(a.wt);
 
-  // this thread's A pixel (fixed) and segments s = tid/128 + 2j
-  const int am = tid & (BM - 1), s0 = tid >> 7;
-  const int mrow = m0 + am;
-  const bool mval = mrow < M;
-  const int mm = mval ? mrow : 0;
-  const int ab = mm >> lhw, ay = (mm >> lw) & (H - 1), ax = mm & (W - 1);
+  // Staging map: consecutive lanes take consecutive 16-byte segments of one
+  // LDS row, so a wave's load instruction reads SEGS-lane runs of contiguous
+  // bytes (64-byte row halves of a 128-byte line) instead of one segment from 64
+  // different lines.  Thread tid owns segment sg of rows r0 + RSTEP * j.
+  constexpr int RSTEP = 256 / SEGS;
+  const int sg = tid % SEGS, r0 = tid / SEGS;
+  int mpix[AL];
+  bool mval[AL];
+#pragma unroll
+  for (int j = 0; j < AL; ++j) {
+    const int m = m0 + r0 + RSTEP * j;
+    mval[j] = m < M;
+    mpix[j] = mval[j] ? m : 0;
+  }
 
   u4v ra[AL];
   typedef typename std::conditional<W8, u2v, u4v>::type wreg;
   wreg rb[BL];
   const u4v zero = {0u, 0u, 0u, 0u};
-  const __bf16* pix = act;   // shifted pixel base (FAST)
-  bool pok = false;
+  const __bf16* pix[AL];   // shifted pixel + segment base (FAST)
+  bool pok[AL];
   auto set_tap = [&](int tap) {
     int dy = 0, dx = 0;
     if (TAPS == 9) { dy = tap / 3 - 1; dx = tap % 3 - 1; }
-    const int yy = ay + dy, xx = ax + dx;
-    pok = mval && yy >= 0 && yy < H && xx >= 0 && xx < W;
-    const int yc = pok ? yy : 0, xc = pok ? xx : 0;
-    pix = act + ((((size_t)ab << lhw) + ((size_t)yc << lw) + xc) * cin);
+#pragma unroll
+    for (int j = 0; j < AL; ++j) {
+      const int yy = ((mpix[j] >> lw) & (H - 1)) + dy, xx = (mpix[j] & (W - 1)) + dx;
+      pok[j] = mval[j] && yy >= 0 && yy < H && xx >= 0 && xx < W;
+      const int p = pok[j] ? mpix[j] + dy * W + dx : 0;
+      pix[j] = act + ((size_t)p * cin + 8 * sg);
+    }
   };
   auto load_stage = [&](int k0, int ci0) {
 #pragma unroll
     for (int j = 0; j < AL; ++j) {
-      const int s = s0 + 2 * j;
       if (FAST) {
-        u4v v = *reinterpret_cast<const u4v*>(pix + ci0 + 8 * s);
-        ra[j] = pok ? v : zero;
+        u4v v = *reinterpret_cast<const u4v*>(pix[j] + ci0);
+        ra[j] = pok[j] ? v : zero;
       } else {
-        const int k = k0 + 8 * s;
+        const int k = k0 + 8 * sg;
         const int t = k / cin, ci = k - t * cin;
         int dy = 0, dx = 0;
         if (TAPS == 9) { dy = t / 3 - 1; dx = t % 3 - 1; }
-        const int yy = ay + dy, xx = ax + dx;
-        const bool ok = mval && k < K && yy >= 0 && yy < H && xx >= 0 && xx < W;
-        const int yc = ok ? yy : 0, xc = ok ? xx : 0;
-        u4v v = *reinterpret_cast<const u4v*>(
-            act + ((((size_t)ab << lhw) + ((size_t)yc << lw) + xc) * cin + (ok ? ci : 0)));
+        const int yy = ((mpix[j] >> lw) & (H - 1)) + dy, xx = (mpix[j] & (W - 1)) + dx;
+        const bool ok = mval[j] && k < K && yy >= 0 && yy < H && xx >= 0 && xx < W;
+        const int p = ok ? mpix[j] + dy * W + dx : 0;
+        u4v v = *reinterpret_cast<const u4v*>(act + ((size_t)p * cin + (ok ? ci : 0)));
         ra[j] = ok ? v : zero;
       }
     }
@@ -122,28 +131,28 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_kernel(ConvLpArgs a, int n_t
     for (int j = 0; j < BL; ++j) {
       const int e = tid + 256 * j;
       if (e < BN * SEGS) {
-        const int n = e % BN, s = e / BN;
-        if (W8) rb[j] = *reinterpret_cast<const wreg*>(wts8 + (size_t)(n0 + n) * Kp + k0 + 8 * s);
-        else rb[j] = *reinterpret_cast<const wreg*>(wts + (size_t)(n0 + n) * Kp + k0 + 8 * s);
+        const int n = e / SEGS;
+        if (W8) rb[j] = *reinterpret_cast<const wreg*>(wts8 + (size_t)(n0 + n) * Kp + k0 + 8 * sg);
+        else rb[j] = *reinterpret_cast<const wreg*>(wts + (size_t)(n0 + n) * Kp + k0 + 8 * sg);
       }
     }
   };
   auto store_stage = [&](int buf) {
 #pragma unroll
     for (int j = 0; j < AL; ++j) {
-      const int s = s0 + 2 * j;
-      As[buf][am * SEGS + swz<BK>(am, s)] = ra[j];
+      const int row = r0 + RSTEP * j;
+      As[buf][row * SEGS + swz(row, sg)] = ra[j];
     }
 #pragma unroll
     for (int j = 0; j < BL; ++j) {
       const int e = tid + 256 * j;
       if (e < BN * SEGS) {
-        const int n = e % BN, s = e / BN;
+        const int n = e / SEGS;
         if constexpr (W8) {
           u2v lo = fp8x4_to_bf16x4(rb[j].x), hi = fp8x4_to_bf16x4(rb[j].y);
-          Bs[buf][n * SEGS + swz<BK>(n, s)] = (u4v){lo.x, lo.y, hi.x, hi.y};
+          Bs[buf][n * SEGS + swz(n, sg)] = (u4v){lo.x, lo.y, hi.x, hi.y};
         } else {
-          Bs[buf][n * SEGS + swz<BK>(n, s)] = rb[j];
+          Bs[buf][n * SEGS + swz(n, sg)] = rb[j];
         }
       }
     }
@@ -184,13 +193,13 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_kernel(ConvLpArgs a, int n_t
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
         const int row = wm * (BM / WM) + 16 * i + r16;
-        u4v u = As[buf][row * SEGS + swz<BK>(row, seg)];
+        u4v u = As[buf][row * SEGS + swz(row, seg)];
         av[kk][i] = __builtin_bit_cast(bf8v, u);
       }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const int col = wn * (BN / WN) + 16 * j + r16;
-        u4v w = Bs[buf][col * SEGS + swz<BK>(col, seg)];
+        u4v w = Bs[buf][col * SEGS + swz(col, seg)];
         bv[kk][j] = __builtin_bit_cast(bf8v, w);
       }
     }
@@ -253,8 +262,8 @@ void launch_conv_lp(hipStream_t st, const ConvLpArgs& a) {
            "bf16 conv: needs C_in % 8 == 0 and C_out in {16, 32, 128k}");
   TD_CHECK(a.taps == 9 || a.taps == 1, -5, "bf16 conv: taps must be 9 or 1");
   if (!a.nb) return;
-  const bool fast = a.cin % 64 == 0;
-  const int BK = fast ? 64 : 32;
+  const bool fast = a.cin % 32 == 0;
+  const int BK = 32;
   TD_CHECK(a.kp % BK == 0 && a.kp >= a.taps * a.cin, -5, "bf16 conv: bad padded K");
   const double Md = (double)(a.nb << (a.lh + a.lw));
   prof_begin(st);

@@ -119,10 +119,7 @@ struct ConvLpArgs {
 };
 void launch_conv_lp(hipStream_t st, const ConvLpArgs& a);
 // K padding a weight matrix for launch_conv_lp needs.
-inline int conv_lp_kp(int taps, int cin) {
-  int bk = cin % 64 == 0 ? 64 : 32;
-  return (taps * cin + bk - 1) / bk * bk;
-}
+inline int conv_lp_kp(int taps, int cin) { return (taps * cin + 31) / 32 * 32; }
 
 // GroupNorm apply (+ SiLU) of the virtual conv input, written as BF16 NHWC:
 // act 0 = convert only, 1 = affine, 2 = affine + SiLU.
