@@ -18,6 +18,15 @@ TEST INFRASTRUCTURE (oracle).
   (iy ascending, then ix ascending).
 * Levels are blend levels: T = K unless the header truncates T (Phi then
   runs several window-local Euler steps, oracle.schedule.level_steps).
+* J_T uses the noise counter word the header names ("noise_step", default
+  0), so that the stages of a hierarchy draw independent noise.
+* Hierarchy (Sec. 5.1; DAGs of infinite tensors, infinite-tensor appendix):
+  a model whose header has "cond" = {channels, factor f} is the child of a
+  parent model (Model.parent).  Window i of the child receives, besides
+  J_{t+1}[R_i], the parent's final latent J_0 nearest-upsampled by f:
+  child pixel (X, Y) reads parent pixel (floor(X/f), floor(Y/f)).  The
+  parent is sampled (same seed) on the region that covers every window of
+  the child's cone.
 
 Outputs are float64 arrays [h, w, C] (row y, column x, channel).
 
@@ -38,7 +47,7 @@ from .windows import cone, kappa_list, weight_map
 class Model:
     """A weight file opened by the oracle: header, float64 tensors, denoiser."""
 
-    def __init__(self, path_or_header, tensors=None):
+    def __init__(self, path_or_header, tensors=None, parent=None):
         if isinstance(path_or_header, str):
             self.header, self.tensors = read_tdw(path_or_header)
         else:
@@ -46,6 +55,11 @@ class Model:
         h = self.header
         self.C = h["denoiser"]["in_channels"]
         self.steps = h["sampler"]["steps"]
+        self.noise_step = h["sampler"].get("noise_step", 0)
+        self.cond = h.get("cond")
+        self.parent = parent
+        if self.cond and parent is not None and parent.C != self.cond["channels"]:
+            raise ValueError("parent channels do not match the conditioning channels")
         self.points = blend_points(h["sampler"])
         self.K = len(self.points) - 1          # blend levels T
         win = h["window"]
@@ -63,7 +77,31 @@ def _crop(canvas, canvas_region, sub):
     return canvas[y0 - cy:y0 - cy + h, x0 - cx:x0 - cx + w]
 
 
-def level_step(model, j_next, region_next, region, windows, t):
+def conditioning(model, seed, region):
+    """Conditioning source of a child model for windows inside `region`:
+    the parent's J_0 on the parent-resolution cover of the region."""
+    if model.parent is None:
+        raise ValueError("a conditioned model needs its parent model")
+    f = model.cond["factor"]
+    x0, y0, w, h = region
+    cx0, cy0 = x0 // f, y0 // f
+    cw, ch = (x0 + w - 1) // f - cx0 + 1, (y0 + h - 1) // f - cy0 + 1
+    return f, (cx0, cy0), sample(model.parent, seed, cx0, cy0, cw, ch, 0)
+
+
+def cond_windows(src, windows, model):
+    """[n, H, H, C_y]: the nearest-upsampled conditioning of each window."""
+    f, (cx0, cy0), J = src
+    out = []
+    for ix, iy in windows:
+        ox, oy = ix * model.s + model.o, iy * model.s + model.o
+        rows = np.arange(oy, oy + model.H, dtype=np.int64) // f - cy0
+        cols = np.arange(ox, ox + model.H, dtype=np.int64) // f - cx0
+        out.append(J[rows[:, None], cols[None, :]])
+    return np.stack(out)
+
+
+def level_step(model, j_next, region_next, region, windows, t, cond_src=None):
     """J_t on `region` from J_{t+1} on `region_next` using the given windows."""
     H = model.H
     x0, y0, w, h = region
@@ -72,10 +110,15 @@ def level_step(model, j_next, region_next, region, windows, t):
     if windows:
         xs = np.stack([_crop(j_next, region_next, (ix * model.s + model.o, iy * model.s + model.o, H, H))
                        for ix, iy in windows])
+        cond = None
+        if model.cond:
+            if cond_src is None:
+                raise ValueError("conditioned model stepped without its conditioning")
+            cond = cond_windows(cond_src, windows, model)
         phi = xs
         for k in level_steps(model.points, t):
             sig, sig_next = model.sched[k], model.sched[k + 1]
-            D = model.denoiser(phi, sig, windows)
+            D = model.denoiser(phi, sig, windows, cond)
             phi = phi + euler_factor(sig, sig_next) * (phi - D)
         model.phi_calls += len(windows)
         for n, (ix, iy) in enumerate(windows):
@@ -99,18 +142,22 @@ def sample(model, seed, x0, y0, w, h, level):
         raise ValueError("level out of range")
     region = (x0, y0, w, h)
     if level == K:
-        return model.sched[0] * noise_region(seed, x0, y0, w, h, model.C).astype(np.float64)
+        return model.sched[0] * noise_region(seed, x0, y0, w, h, model.C, model.noise_step).astype(np.float64)
     regions, kappas = cone(region, level, K, model.H, model.s, model.o)
     top = level
     while top < K and kappas[top] is not None:
         top += 1
     if top == K:
         rK = regions[K]
-        j = model.sched[0] * noise_region(seed, rK[0], rK[1], rK[2], rK[3], model.C).astype(np.float64)
+        j = model.sched[0] * noise_region(seed, rK[0], rK[1], rK[2], rK[3], model.C,
+                                          model.noise_step).astype(np.float64)
     else:
         j = np.zeros((regions[top][3], regions[top][2], model.C))
+    # every window of the cone lies inside the top region
+    src = conditioning(model, seed, regions[top]) if (model.cond and top > level) else None
     for t in range(top - 1, level - 1, -1):
-        j = level_step(model, j, regions[t + 1], regions[t], kappa_list(regions[t], model.H, model.s, model.o), t)
+        j = level_step(model, j, regions[t + 1], regions[t], kappa_list(regions[t], model.H, model.s, model.o), t,
+                       src)
     return j
 
 
@@ -123,9 +170,12 @@ def sample_levels(model, seed, x0, y0, w, h, level=0):
     if any(kappas[t] is None for t in range(level, K)):
         raise ValueError("sample_levels needs a layout without gaps")
     rK = regions[K]
-    j = model.sched[0] * noise_region(seed, rK[0], rK[1], rK[2], rK[3], model.C).astype(np.float64)
+    j = model.sched[0] * noise_region(seed, rK[0], rK[1], rK[2], rK[3], model.C,
+                                      model.noise_step).astype(np.float64)
     out = {K: _crop(j, rK, region).copy()}
+    src = conditioning(model, seed, rK) if model.cond else None
     for t in range(K - 1, level - 1, -1):
-        j = level_step(model, j, regions[t + 1], regions[t], kappa_list(regions[t], model.H, model.s, model.o), t)
+        j = level_step(model, j, regions[t + 1], regions[t], kappa_list(regions[t], model.H, model.s, model.o), t,
+                       src)
         out[t] = _crop(j, regions[t], region).copy()
     return out

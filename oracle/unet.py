@@ -25,6 +25,11 @@ layout is read as follows (activations NHWC, float64):
 * emb = SiLU(Lin2(SiLU(Lin1(pe(c_noise))))), pe = [cos(c w_j), sin(c w_j)],
   w_j = P^(-j/(c0/2)), j < c0/2, P = pe_max_period (positional embedding
   in place of Fourier features, as in sCM).
+* Conditioning (hierarchy, Sec. 5.1; DAGs of infinite tensors in the
+  infinite-tensor appendix): a conditioned network's input conv reads
+  concat(c_in x, y), the window's conditioning channels y appended after
+  the scaled input and not scaled themselves.  The linear-Gaussian stand-in
+  adds y (channel c mod C_y) to its prior mean.
 
 Pins (tests/test_oracle_unet.py): conv against a direct seven-loop sum and
 against scipy.signal.correlate; GroupNorm output moments; attention against
@@ -169,12 +174,15 @@ class UNetDenoiser:
         self.sigma_data = header["sampler"]["sigma_data"]
         self.batch = batch
 
-    def __call__(self, x, sigma, windows):
+    def __call__(self, x, sigma, windows, cond=None):
         c_skip, c_out, c_in, c_noise = precond(sigma, self.sigma_data)
         out = np.empty_like(x)
         for b0 in range(0, x.shape[0], self.batch):
             xb = x[b0:b0 + self.batch]
-            out[b0:b0 + self.batch] = c_skip * xb + c_out * self.net.forward(c_in * xb, c_noise)
+            inp = c_in * xb
+            if cond is not None:
+                inp = np.concatenate([inp, cond[b0:b0 + self.batch]], axis=-1)
+            out[b0:b0 + self.batch] = c_skip * xb + c_out * self.net.forward(inp, c_noise)
         return out
 
 
@@ -191,11 +199,13 @@ class LinearGaussianDenoiser:
     def __init__(self, header):
         self.s = header["denoiser"]["prior_std"]
 
-    def __call__(self, x, sigma, windows):
+    def __call__(self, x, sigma, windows, cond=None):
         C = x.shape[-1]
         a = self.s ** 2 / (self.s ** 2 + sigma ** 2)
         mu = np.array([[prior_mean(ix, iy, c) for c in range(C)] for ix, iy in windows],
                       dtype=np.float64)[:, None, None, :]
+        if cond is not None:
+            mu = mu + cond[..., [c % cond.shape[-1] for c in range(C)]]
         return mu + a * (x - mu)
 
 

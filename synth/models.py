@@ -13,6 +13,11 @@ workloads the method is measured on:
             windows 32 at stride 16, K = 8.
 * ``c1t2``, ``lgt2``, ``c2t1``/``c2t2``/``c2t5``: the same models with
             truncated T (blends only at the listed schedule indices).
+* ``cc``  : coarse model of the hierarchy (1 channel, 2-level UNet 64/128,
+            windows 32/16, K = 8 with one blend at the end, noise counter
+            word 2); ``c1h`` is ``c1`` conditioned on it (its final latent,
+            nearest-upsampled 8x, concatenated to the input).
+* ``lgc``, ``lgh``: the linear-Gaussian pair with the same wiring.
 
 Initialisation: every tensor is Gaussian from numpy's PCG64 seeded with the
 given seed, drawn in file order.  Conv / linear weights ~ N(0, 1/fan_in);
@@ -55,6 +60,28 @@ for _k in (4, 2):
     CONFIGS["c2k%d" % _k]["sampler"]["steps"] = _k
 CONFIGS["c1k2"] = copy.deepcopy(CONFIGS["c1"])
 CONFIGS["c1k2"]["sampler"]["steps"] = 2
+# hierarchy: a coarse model at 1/8 resolution (its own noise stream, one
+# blend at the end) whose final latent conditions the 1-channel fine model
+CONFIGS["cc"] = {
+    "denoiser": {"kind": "unet", "in_channels": 1, "channels": [64, 128], "num_res_blocks": 2,
+                 "attn_levels": [], "mid_attn": False, "num_heads": 1, "gn_groups": 32,
+                 "gn_eps": 1e-5, "emb_mult": 4, "pe_max_period": 10000.0},
+    "sampler": dict(SAMPLER_EDM, steps=8, blend=[0, 8], noise_step=2),
+    "window": {"size": 32, "stride": 16, "offset": 0, "eps": 0.01},
+}
+CONFIGS["c1h"] = copy.deepcopy(CONFIGS["c1"])
+CONFIGS["c1h"]["cond"] = {"channels": 1, "factor": 8}
+CONFIGS["lgc"] = {
+    "denoiser": {"kind": "linear_gaussian", "in_channels": 1, "prior_std": 0.5},
+    "sampler": dict(SAMPLER_EDM, steps=8, blend=[0, 8], noise_step=2),
+    "window": {"size": 32, "stride": 16, "offset": 0, "eps": 0.01},
+}
+CONFIGS["lgh"] = {
+    "denoiser": {"kind": "linear_gaussian", "in_channels": 1, "prior_std": 0.5},
+    "sampler": dict(SAMPLER_EDM, steps=8),
+    "window": {"size": 32, "stride": 16, "offset": 0, "eps": 0.01},
+    "cond": {"channels": 1, "factor": 8},
+}
 # truncated T (blend only after the listed schedule indices)
 for _name, _base, _blend in [("c1t2", "c1", [0, 4, 8]), ("lgt2", "lg", [0, 3, 8]), ("c2t2", "c2", [0, 10, 20]),
                              ("c2t5", "c2", [0, 4, 8, 12, 16, 20]), ("c2t1", "c2", [0, 20])]:
@@ -79,17 +106,19 @@ def _attn(prefix, c):
             (prefix + "proj.weight", (c, c, 1, 1), c), (prefix + "proj.bias", (c,), "bias")]
 
 
-def unet_tensor_specs(arch):
-    """Ordered (name, shape, init) for a UNet architecture; init is fan_in or a tag."""
+def unet_tensor_specs(arch, cond_channels=0):
+    """Ordered (name, shape, init) for a UNet architecture; init is fan_in or a tag.
+    A conditioned network's input conv also reads the conditioning channels."""
     ch = arch["channels"]
     nl = len(ch)
     nres = arch["num_res_blocks"]
     cin_img = arch["in_channels"]
+    cin_x = cin_img + cond_channels
     emb = arch["emb_mult"] * ch[0]
     attn = set(arch["attn_levels"])
     t = [("emb.lin1.weight", (emb, ch[0]), ch[0]), ("emb.lin1.bias", (emb,), "bias"),
          ("emb.lin2.weight", (emb, emb), emb), ("emb.lin2.bias", (emb,), "bias"),
-         ("conv_in.weight", (ch[0], cin_img, 3, 3), cin_img * 9), ("conv_in.bias", (ch[0],), "bias")]
+         ("conv_in.weight", (ch[0], cin_x, 3, 3), cin_x * 9), ("conv_in.bias", (ch[0],), "bias")]
     skips = []
     c = ch[0]
     for l in range(nl):
@@ -145,14 +174,16 @@ def param_count(config):
     cfg = CONFIGS[config]
     if cfg["denoiser"]["kind"] != "unet":
         return 0
-    return int(sum(np.prod(s) for _, s, _ in unet_tensor_specs(cfg["denoiser"])))
+    cc = cfg.get("cond", {}).get("channels", 0)
+    return int(sum(np.prod(s) for _, s, _ in unet_tensor_specs(cfg["denoiser"], cc)))
 
 
 def make_weights(config, path, seed=0):
     """Write the seeded random-init weight file for a configuration."""
     hdr = header_for(config)
     if hdr["denoiser"]["kind"] == "unet":
-        tensors = init_tensors(unet_tensor_specs(hdr["denoiser"]), seed)
+        cc = hdr.get("cond", {}).get("channels", 0)
+        tensors = init_tensors(unet_tensor_specs(hdr["denoiser"], cc), seed)
     else:
         tensors = []
     hdr["init_seed"] = seed
