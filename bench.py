@@ -99,10 +99,13 @@ def latency_stream(td, torch, weights_path, pairs, seed=11):
             "first": pct(first), "neighbour": pct(second)}
 
 
-def serving_stream(td, torch, weights_path, n, rate, seed=17, budget=64 << 30, inflight=64, precision=1):
+def serving_stream(td, torch, weights_path, parent_path, n, rate, seed=17, budget=64 << 30, inflight=64,
+                   precision=1):
     """Poisson stream of region queries through the continuous-batching server:
     sides uniform in [64, 512] latent px, coordinates uniform in [-1e6, 1e6),
-    30% revisits of an earlier region (shifted by up to half its size)."""
+    30% revisits of an earlier region (shifted by up to half its size).  The
+    fine model is conditioned on a coarse model at 1/8 resolution when
+    parent_path is given."""
     import numpy as np
     rng = np.random.default_rng(seed)
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n))
@@ -116,9 +119,13 @@ def serving_stream(td, torch, weights_path, n, rate, seed=17, budget=64 << 30, i
             w, h = (int(v) for v in rng.integers(64, 513, size=2))
             x, y = (int(v) for v in rng.integers(-10 ** 6, 10 ** 6, size=2))
             qs.append((x, y, w, h))
-    with td.Context(0) as c:
+    with td.Context(0) as c, td.Context(0) as parent:
         c.load_weights(weights_path)
         c.set_option("precision", precision)
+        if parent_path:
+            parent.load_weights(parent_path)
+            parent.set_option("precision", precision)
+            c.set_conditioning(parent)
         C = c.info("channels")
         warm = torch.empty((C, 64, 64), device="cuda")
         c.sample_region_async(seed, 0, 0, 64, 64, 0, warm)     # kernels, workspaces
@@ -146,12 +153,16 @@ def serving_stream(td, torch, weights_path, n, rate, seed=17, budget=64 << 30, i
             wall = time.perf_counter() - t0
             st = srv.stats()
         cs = c.cache_stats()
+        ps = parent.cache_stats() if parent_path else None
     lat = np.array(lat)
-    return {"workload": "fine 1-channel model (2-level UNet 16/32, windows 32/16, K=8), %s denoiser; %d queries, "
-                        "Poisson %.0f q/s, sides U[64,512], coords U[-1e6,1e6), 30%% revisits; HBM admission "
-                        "budget %d GB, <= %d in flight; no coarse conditioning model"
-                        % ("BF16" if precision == 1 else "FP32", n, rate, budget >> 30, inflight),
+    hier = ("conditioned on a coarse 2-level UNet (64/128, windows 32/16 at 1/8 resolution, K=8, one blend)"
+            if parent_path else "no coarse conditioning model")
+    return {"workload": "fine 1-channel model (2-level UNet 16/32, windows 32/16, K=8) %s, %s denoisers; "
+                        "%d queries, Poisson %.0f q/s, sides U[64,512], coords U[-1e6,1e6), 30%% revisits; HBM "
+                        "admission budget %d GB, <= %d in flight"
+                        % (hier, "BF16" if precision == 1 else "FP32", n, rate, budget >> 30, inflight),
             "queries_per_s": n / wall, "window_denoises_per_s": st["batched_windows"] / wall,
+            "coarse_window_denoises_per_s": (ps["denoiser_evals"] / wall) if ps else None,
             "latency_p50_ms": float(np.percentile(lat, 50)), "latency_p99_ms": float(np.percentile(lat, 99)),
             "rounds": st["rounds"], "mean_batch": st["batched_windows"] / max(st["rounds"], 1),
             "cache_hits": cs["hits"], "windows_evaluated": cs["misses"], "wall_s": wall}
@@ -297,7 +308,8 @@ def main():
     serve = None
     if a.serve_queries > 0:
         print("[bench] serving stream", file=sys.stderr, flush=True)
-        serve = serving_stream(td, torch, cached_weights("c1", wdir, 0), a.serve_queries, a.serve_rate)
+        serve = serving_stream(td, torch, cached_weights("c1h", wdir, 0), cached_weights("cc", wdir, 0),
+                               a.serve_queries, a.serve_rate)
     cpu = None
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)

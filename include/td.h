@@ -78,6 +78,22 @@ void td_destroy(td_ctx *ctx);
  * model-specific).  TD_E_IO if unreadable, TD_E_FORMAT if malformed. */
 td_status td_load_weights(td_ctx *ctx, const char *path);
 
+/* Hierarchy (Sec. 5.1; DAGs of infinite tensors, infinite-tensor appendix):
+ * make `parent`'s final latent J_0 the conditioning of `child`.  A model
+ * whose header has "cond" = {channels C_y, factor f} reads, for each window,
+ * concat(c_in x, y) where y is the parent's J_0 (same seed) nearest-
+ * upsampled by f: child pixel (X, Y) takes parent pixel (floor(X/f),
+ * floor(Y/f)).  A query of the child first samples the parent (through the
+ * parent's own cache, on the parent's stream) on the parent-resolution cover
+ * of the child's new windows; a parent may itself be conditioned (chains).
+ * Both contexts must be on one device; the parent is not owned and must
+ * stay alive while linked (td_destroy of either unlinks).  NULL unlinks.
+ * Clears the child's cache; a later td_load_weights or "precision" change
+ * of the parent clears it again at the child's next query.  TD_E_INVAL for
+ * a cycle or another device; a child query without a linked parent whose
+ * channels equal C_y gives TD_E_STATE. */
+td_status td_set_conditioning(td_ctx *child, td_ctx *parent);
+
 /* J_level[R] for seed `seed` (Alg. 1 applied recursively from J_T = sigma_0 G).
  * level in [0, T] (T = blend levels, "levels" in td_get_info; T = sampler
  * steps K unless the weight file truncates T, Sec. 3.4, in which case Phi
@@ -132,17 +148,21 @@ td_status td_cache_peek(td_ctx *ctx, uint64_t seed, int32_t level, int64_t ix,
 td_status td_set_option(td_ctx *ctx, const char *key, int64_t value);
 
 /* Model facts: "channels", "steps" (K), "levels" (T), "window", "stride", "offset",
- * "factor" (decode), "params", "batch", "precision".  TD_E_INVAL for
- * unknown keys. */
+ * "factor" (decode), "params", "batch", "precision", "cond_channels" and
+ * "cond_factor" (0 for an unconditioned model), "noise_step" (counter word
+ * of the model's J_T noise).  TD_E_INVAL for unknown keys. */
 td_status td_get_info(td_ctx *ctx, const char *key, int64_t *value);
 
 /* Denoiser D(x; sigma_k) of the loaded model on `n` windows (EDM
  * preconditioning, the definition of Phi's network call): x_dev and
  * out_dev are device arrays [n][H][H][C] float32 (H = window size), k in
- * [0, K-1] selects sigma_k of the schedule.  Synchronous.  For checking
- * the network apart from the sampler. */
-td_status td_denoise_windows(td_ctx *ctx, const float *x_dev, int32_t n,
-                             int32_t k, float *out_dev);
+ * [0, K-1] selects sigma_k of the schedule.  cond_dev: the windows'
+ * conditioning [n][H][H][C_y] float32 for a conditioned model, NULL
+ * otherwise (TD_E_INVAL if that does not match the model).  Synchronous.
+ * For checking the network apart from the sampler. */
+td_status td_denoise_windows(td_ctx *ctx, const float *x_dev,
+                             const float *cond_dev, int32_t n, int32_t k,
+                             float *out_dev);
 
 /* Laplacian decode (Sec. 5.2, with the signed-sqrt inverse of the
  * signed-sqrt appendix) of a latent held in device memory, [lh][lw][C]

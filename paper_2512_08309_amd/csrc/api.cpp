@@ -139,28 +139,25 @@ class Arena {
     cap_ = off_ = 0;
   }
   void reset() { off_ = 0; }
-  // Make room for `bytes` of reservations in the current query (only
-  // before the first reservation of a query).
+  // Make room for `bytes` more of reservations.  Called where no reservation
+  // is outstanding (each was copied and its kernels enqueued), so growing
+  // only has to wait for the device: then the old buffers are no longer read
+  // and the new ones start empty.
   void ensure(size_t bytes) {
-    if (bytes <= cap_) return;
-    TD_CHECK(off_ == 0, -2, "metadata arena resized within a query");
+    if (off_ + bytes <= cap_) return;
     TD_HIP(hipDeviceSynchronize());
+    const size_t want = std::max<size_t>(std::max(bytes, 2 * cap_), 1 << 20);
     release();
-    cap_ = std::max<size_t>(bytes, 1 << 20);
-    TD_HIP(hipHostMalloc((void**)&h_, cap_, hipHostMallocDefault));
-    TD_HIP(hipMalloc((void**)&d_, cap_));
+    TD_HIP(hipHostMalloc((void**)&h_, want, hipHostMallocDefault));
+    TD_HIP(hipMalloc((void**)&d_, want));
+    cap_ = want;
   }
-  // Reserve n bytes; returns the host and device addresses.  Growing
-  // synchronises the device (only when an earlier query needed less).
+  // Reserve n bytes; returns the host and device addresses.
   std::pair<char*, char*> reserve(size_t n) {
     n = (n + 255) / 256 * 256;
     if (off_ + n > cap_) {
       TD_CHECK(off_ == 0, -2, "metadata arena overflow within a query");
-      TD_HIP(hipDeviceSynchronize());
-      release();
-      cap_ = std::max<size_t>(n, 1 << 20);
-      TD_HIP(hipHostMalloc((void**)&h_, cap_, hipHostMallocDefault));
-      TD_HIP(hipMalloc((void**)&d_, cap_));
+      ensure(n);
     }
     auto r = std::make_pair(h_ + off_, d_ + off_);
     off_ += n;
@@ -207,6 +204,15 @@ struct td_ctx {
   float* outbuf = nullptr;
   size_t outbuf_cap = 0;
   std::unique_ptr<td::Profiler> prof;
+  // hierarchy: the parent whose final latent conditions this model, the
+  // children it conditions, and a generation that changes with the values
+  // this context produces (weights, precision)
+  td_ctx* parent = nullptr;
+  std::vector<td_ctx*> children;
+  uint64_t gen = 1, parent_gen = 0;
+  float* cond = nullptr;      // parent latent of the current query, [h][w][Cc]
+  size_t cond_cap = 0;
+  hipEvent_t xev = nullptr;   // orders this stream and the parent's
 };
 
 namespace td {
@@ -224,6 +230,43 @@ void grow(float*& p, size_t& cap, size_t n) {
 }
 
 void need_model(td_ctx* c) { TD_CHECK(c->model, TD_E_STATE, "no weights loaded"); }
+
+// Drops every cached contribution (none may be pinned by a query in flight).
+void drop_cache(td_ctx* c) {
+  for (auto& kv : c->map) c->pool.give(kv.second.slot);
+  c->map.clear();
+  c->lru.clear();
+  c->stats.bytes_used = 0;
+}
+
+Region region_union(const Region& a, const Region& b) {
+  if (a.w <= 0) return b;
+  const int64_t x0 = std::min(a.x0, b.x0), y0 = std::min(a.y0, b.y0);
+  const int64_t x1 = std::max(a.x0 + a.w, b.x0 + b.w), y1 = std::max(a.y0 + a.h, b.y0 + b.h);
+  return Region{x0, y0, x1 - x0, y1 - y0};
+}
+
+// A conditioned model needs its parent; its cache is only valid for the
+// parent's current generation.  `may_clear`: no query holds pins.
+void check_parent(td_ctx* c, bool may_clear) {
+  const ModelDesc& d = c->model->d;
+  if (!d.Cc) return;
+  td_ctx* p = c->parent;
+  TD_CHECK(p && p->model, TD_E_STATE, "conditioned model: link a parent with td_set_conditioning");
+  TD_CHECK(p->model->d.C == d.Cc, TD_E_STATE, "parent channels differ from the conditioning channels");
+  if (c->parent_gen != p->gen) {
+    TD_CHECK(may_clear || c->map.empty(), TD_E_STATE, "the parent model changed while queries are in flight");
+    drop_cache(c);
+    c->parent_gen = p->gen;
+  }
+}
+
+// Parent-resolution cover of a child region.
+Region parent_region(const ModelDesc& d, const Region& r) {
+  const int64_t f = d.cond_factor;
+  const int64_t x0 = floordiv64(r.x0, f), y0 = floordiv64(r.y0, f);
+  return Region{x0, y0, floordiv64(r.x0 + r.w - 1, f) - x0 + 1, floordiv64(r.y0 + r.h - 1, f) - y0 + 1};
+}
 
 void touch(td_ctx* c, Entry& e, const Key& k) {
   c->lru.erase(e.lru);
@@ -295,13 +338,55 @@ void check_region(int64_t x0, int64_t y0, int64_t w, int64_t h) {
   TD_CHECK(x0 > -lim && y0 > -lim && x0 + w < lim && y0 + h < lim, TD_E_INVAL, "region coordinates out of range");
 }
 
+void sample_latent(td_ctx* c, Arena& arena, uint64_t seed, Region r, int level, int layout, float* dev_out);
+
+// The parent's J_0 on the parent-resolution cover of `hull` (child pixels),
+// written to dst ([h][w][Cc], child-owned) and ordered before the child's
+// later work; rc receives the parent region.  The parent runs on its own
+// stream (and cache) after everything already enqueued on the child's.
+void sample_parent(td_ctx* c, Arena& arena, uint64_t seed, const Region& hull, float* dst, Region* rc) {
+  td_ctx* p = c->parent;
+  *rc = parent_region(c->model->d, hull);
+  check_region(rc->x0, rc->y0, rc->w, rc->h);
+  TD_CHECK(p->device == c->device, TD_E_STATE, "parent and child must share a device");
+  check_parent(p, true);
+  TD_HIP(hipEventRecord(c->xev, c->stream));
+  TD_HIP(hipStreamWaitEvent(p->stream, c->xev, 0));
+  sample_latent(p, arena, seed, *rc, 0, 0, dst);
+  TD_HIP(hipEventRecord(c->xev, p->stream));
+  TD_HIP(hipStreamWaitEvent(c->stream, c->xev, 0));
+}
+
+// Conditioning windows of a batch: window j (index (ix, iy)) reads the
+// parent canvas whose origin in child pixels is (fx, fy).
+void cond_batch(td_ctx* c, Arena& arena, const CondSrc* hsrc, int nb) {
+  const ModelDesc& d = c->model->d;
+  auto cs = arena.reserve((size_t)nb * sizeof(CondSrc));
+  std::memcpy(cs.first, hsrc, (size_t)nb * sizeof(CondSrc));
+  TD_HIP(hipMemcpyAsync(cs.second, cs.first, (size_t)nb * sizeof(CondSrc), hipMemcpyHostToDevice, c->stream));
+  launch_cond_gather(c->stream, (const CondSrc*)cs.second, nb, d.H, d.Cc, d.cond_factor, c->model->cond_buffer());
+}
+
+CondSrc cond_src(const ModelDesc& d, const float* base, int64_t pitch, int64_t fx, int64_t fy, int64_t ix,
+                 int64_t iy) {
+  CondSrc q{};
+  q.base = base;
+  q.pitch = (int)pitch;
+  const int64_t ox = ix * d.S + d.O - fx, oy = iy * d.S + d.O - fy;
+  TD_CHECK(ox >= 0 && oy >= 0 && ox < (1LL << 30) && oy < (1LL << 30), TD_E_DEVICE,
+           "internal: window outside its conditioning canvas");
+  q.offx = (int)ox;
+  q.offy = (int)oy;
+  return q;
+}
+
 // J_level on region r written to dev_out (layout 0: [h][w][C], 1: [C][h][w]).
-void sample_latent(td_ctx* c, uint64_t seed, Region r, int level, int layout, float* dev_out) {
+void sample_latent(td_ctx* c, Arena& arena, uint64_t seed, Region r, int level, int layout, float* dev_out) {
   const ModelDesc& d = c->model->d;
   hipStream_t st = c->stream;
   c->stats.queries++;
   if (level == d.T) {
-    launch_noise(st, seed, r.x0, r.y0, (int)r.w, (int)r.h, d.C, 0, (float)d.sched[0], layout, dev_out);
+    launch_noise(st, seed, r.x0, r.y0, (int)r.w, (int)r.h, d.C, d.noise_step, (float)d.sched[0], layout, dev_out);
     return;
   }
   // ---- plan
@@ -338,15 +423,27 @@ void sample_latent(td_ctx* c, uint64_t seed, Region r, int level, int layout, fl
     if (lv.k.empty || lv.fresh.empty()) break;
     R = lv.in_region;
   }
+  // ---- conditioning: the parent's latent under every new window
+  Region rc{};
+  if (d.Cc) {
+    Region hull{0, 0, 0, 0};
+    for (const Level& lv : levels)
+      if (!lv.fresh.empty()) hull = region_union(hull, lv.in_region);
+    if (hull.w > 0) {
+      const Region pr = parent_region(d, hull);
+      grow(c->cond, c->cond_cap, (size_t)pr.w * pr.h * d.Cc);
+      sample_parent(c, arena, seed, hull, c->cond, &rc);
+    }
+  }
   // ---- run, deepest level first
   const int maxb = auto_batch(c);
   size_t meta = 65536;
   for (const Level& lv : levels) {
     meta += (size_t)lv.k.count() * sizeof(float*) + 256;
     size_t nbat = (lv.fresh.size() + maxb - 1) / maxb;
-    meta += lv.fresh.size() * (4 * sizeof(int) + sizeof(float*)) + nbat * 3 * 256;
+    meta += lv.fresh.size() * (4 * sizeof(int) + sizeof(float*) + sizeof(CondSrc)) + nbat * 4 * 256;
   }
-  c->arena.ensure(meta);
+  arena.ensure(meta);
   c->model->ensure_workspace(std::min<int>(maxb, 1 << 20));
   for (int i = (int)levels.size() - 1; i >= 0; --i) {
     Level& lv = levels[i];
@@ -356,11 +453,12 @@ void sample_latent(td_ctx* c, uint64_t seed, Region r, int level, int layout, fl
     grow(c->canvas, c->canvas_cap, cn);
     const int tn = lv.t + 1;
     if (tn == d.T) {
-      launch_noise(st, seed, cr.x0, cr.y0, (int)cr.w, (int)cr.h, d.C, 0, (float)d.sched[0], 0, c->canvas);
+      launch_noise(st, seed, cr.x0, cr.y0, (int)cr.w, (int)cr.h, d.C, d.noise_step, (float)d.sched[0], 0,
+                   c->canvas);
     } else {
       const Level& up = levels[i + 1];
       if (up.k.empty) launch_fill(st, c->canvas, cn, 0.f);
-      else blend_into(c, c->arena, seed, up, cr, 0, c->canvas);
+      else blend_into(c, arena, seed, up, cr, 0, c->canvas);
       unpin_level(c, seed, up);
     }
     // new windows -> slots, then batched denoiser rounds
@@ -377,9 +475,9 @@ void sample_latent(td_ctx* c, uint64_t seed, Region r, int level, int layout, fl
     if (lv.t < 64) c->stats.windows_evaluated[lv.t] += nf;
     for (size_t b0 = 0; b0 < nf; b0 += (size_t)maxb) {
       int nb = (int)std::min<size_t>(maxb, nf - b0);
-      auto o = c->arena.reserve((size_t)nb * 2 * sizeof(int));
-      auto w = c->arena.reserve((size_t)nb * 2 * sizeof(int));
-      auto s = c->arena.reserve((size_t)nb * sizeof(float*));
+      auto o = arena.reserve((size_t)nb * 2 * sizeof(int));
+      auto w = arena.reserve((size_t)nb * 2 * sizeof(int));
+      auto s = arena.reserve((size_t)nb * sizeof(float*));
       int* ho = (int*)o.first;
       int* hw = (int*)w.first;
       float** hs = (float**)s.first;
@@ -402,6 +500,14 @@ void sample_latent(td_ctx* c, uint64_t seed, Region r, int level, int layout, fl
       wb.d_slots = (float* const*)s.second;
       wb.n = nb;
       wb.mode = 0;
+      if (d.Cc) {
+        std::vector<CondSrc> cs(nb);
+        for (int j = 0; j < nb; ++j)
+          cs[j] = cond_src(d, c->cond, rc.w, rc.x0 * d.cond_factor, rc.y0 * d.cond_factor, lv.fresh[b0 + j].first,
+                           lv.fresh[b0 + j].second);
+        cond_batch(c, arena, cs.data(), nb);
+        wb.cond = c->model->cond_buffer();
+      }
       c->model->run_level(st, wb, lv.t);
       c->stats.batches++;
     }
@@ -412,7 +518,7 @@ void sample_latent(td_ctx* c, uint64_t seed, Region r, int level, int layout, fl
   if (top.k.empty) {
     launch_fill(st, dev_out, (size_t)r.w * r.h * d.C, 0.f);
   } else {
-    blend_into(c, c->arena, seed, top, r, layout, dev_out);
+    blend_into(c, arena, seed, top, r, layout, dev_out);
     unpin_level(c, seed, top);
   }
   evict_to_budget(c);
@@ -462,18 +568,19 @@ void sample_any(td_ctx* c, uint64_t seed, int64_t x0, int64_t y0, int32_t w, int
     c->pending = false;
   }
   c->arena.reset();
+  check_parent(c, true);
   if (level == TD_LEVEL_HEIGHT) {
     TD_CHECK(out_len >= (size_t)w * h, TD_E_INVAL, "output buffer too small");
     Region full{x0, y0, w, h};
     Region lat = decode_apron(d, full);
     size_t n = (size_t)lat.w * lat.h * d.C;
     grow(c->tmp, c->tmp_cap, n);
-    sample_latent(c, seed, lat, 0, 0, c->tmp);
+    sample_latent(c, c->arena, seed, lat, 0, 0, c->tmp);
     decode_into(c, c->tmp, lat, full, dev_out, c->stream);
   } else {
     TD_CHECK(level >= 0 && level <= d.T, TD_E_INVAL, "level out of range");
     TD_CHECK(out_len >= (size_t)w * h * d.C, TD_E_INVAL, "output buffer too small");
-    sample_latent(c, seed, Region{x0, y0, w, h}, level, 1, dev_out);
+    sample_latent(c, c->arena, seed, Region{x0, y0, w, h}, level, 1, dev_out);
   }
   c->stats.bytes_budget = c->budget;
   TD_HIP(hipEventRecord(c->done, c->stream));
@@ -529,6 +636,7 @@ td_status td_create(int hip_device, td_ctx** out) {
     TD_HIP(hipSetDevice(hip_device));
     TD_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     TD_HIP(hipEventCreateWithFlags(&c->done, hipEventDisableTiming));
+    TD_HIP(hipEventCreateWithFlags(&c->xev, hipEventDisableTiming));
   });
   if (s != TD_OK) {
     td_destroy(c);
@@ -542,15 +650,22 @@ void td_destroy(td_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (td_ctx* ch : c->children) ch->parent = nullptr;
+  if (c->parent) {
+    auto& v = c->parent->children;
+    v.erase(std::remove(v.begin(), v.end(), c), v.end());
+    (void)hipStreamSynchronize(c->parent->stream);   // it may still write our buffers
+  }
   c->map.clear();
   c->lru.clear();
   c->pool.release();
   c->model.reset();
   c->arena.release();
   c->prof.reset();
-  for (float* p : {c->canvas, c->tmp, c->dec, c->outbuf})
+  for (float* p : {c->canvas, c->tmp, c->dec, c->outbuf, c->cond})
     if (p) (void)hipFree(p);
   if (c->done) (void)hipEventDestroy(c->done);
+  if (c->xev) (void)hipEventDestroy(c->xev);
   if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -571,6 +686,29 @@ td_status td_load_weights(td_ctx* c, const char* path) {
     c->model = std::move(m);
     c->stats = td_cache_stats_t{};
     c->stats.bytes_budget = c->budget;
+    c->gen++;
+    c->parent_gen = 0;
+  });
+}
+
+td_status td_set_conditioning(td_ctx* child, td_ctx* parent) {
+  if (!child) return TD_E_INVAL;
+  return guarded(child, [&] {
+    TD_CHECK(parent != child, TD_E_INVAL, "a model cannot condition itself");
+    for (td_ctx* a = parent; a; a = a->parent)
+      TD_CHECK(a != child, TD_E_INVAL, "conditioning would form a cycle");
+    TD_CHECK(!parent || parent->device == child->device, TD_E_INVAL, "parent and child must share a device");
+    TD_HIP(hipSetDevice(child->device));
+    TD_HIP(hipStreamSynchronize(child->stream));
+    child->pending = false;
+    if (child->parent) {
+      auto& v = child->parent->children;
+      v.erase(std::remove(v.begin(), v.end(), child), v.end());
+    }
+    child->parent = parent;
+    if (parent) parent->children.push_back(child);
+    drop_cache(child);
+    child->parent_gen = 0;
   });
 }
 
@@ -675,10 +813,10 @@ td_status td_set_option(td_ctx* c, const char* key, int64_t value) {
       need_model(c);
       TD_HIP(hipStreamSynchronize(c->stream));
       c->model->set_precision((int)value);
-      // cached contributions were computed at the previous precision
-      for (auto& kv : c->map) c->pool.give(kv.second.slot);
-      c->map.clear();
-      c->lru.clear();
+      // cached contributions were computed at the previous precision, and
+      // so were the latents of any child this model conditions
+      drop_cache(c);
+      c->gen++;
     } else if (k == "timing") {
       if (value && !c->prof) c->prof.reset(new Profiler());
       if (!value && c->prof) {
@@ -712,16 +850,21 @@ td_status td_get_info(td_ctx* c, const char* key, int64_t* value) {
     else if (k == "params") *value = (int64_t)d.params;
     else if (k == "batch") *value = auto_batch(c);
     else if (k == "precision") *value = c->model->precision();
+    else if (k == "cond_channels") *value = d.Cc;
+    else if (k == "cond_factor") *value = d.cond_factor;
+    else if (k == "noise_step") *value = d.noise_step;
     else throw Error{TD_E_INVAL, "unknown info key: " + k};
   });
 }
 
-td_status td_denoise_windows(td_ctx* c, const float* x_dev, int32_t n, int32_t k, float* out_dev) {
+td_status td_denoise_windows(td_ctx* c, const float* x_dev, const float* cond_dev, int32_t n, int32_t k,
+                             float* out_dev) {
   if (!c) return TD_E_INVAL;
   return guarded(c, [&] {
     need_model(c);
     const ModelDesc& d = c->model->d;
     TD_CHECK(x_dev && out_dev && n >= 0, TD_E_INVAL, "bad arguments");
+    TD_CHECK(!d.Cc == !cond_dev, TD_E_INVAL, "conditioning windows are required by (and only by) a conditioned model");
     TD_CHECK(k >= 0 && k < d.K, TD_E_INVAL, "sigma index out of range");
     TD_HIP(hipSetDevice(c->device));
     if (c->pending) {
@@ -749,6 +892,7 @@ td_status td_denoise_windows(td_ctx* c, const float* x_dev, int32_t n, int32_t k
       wb.n = nb;
       wb.mode = 1;
       wb.dout = out_dev + (size_t)b0 * d.H * d.H * d.C;
+      if (cond_dev) wb.cond = cond_dev + (size_t)b0 * d.H * d.H * d.Cc;
       c->model->run_batch(c->stream, wb, k);
     }
     TD_HIP(hipStreamSynchronize(c->stream));
@@ -882,6 +1026,9 @@ struct SrvQuery {
   int cur = -1;
   hipEvent_t ev = nullptr;
   size_t mem = 0;
+  // conditioned model: the parent latent under this query's new windows
+  float* cond = nullptr;
+  Region cond_r{};
 };
 
 constexpr int kRing = 8;
@@ -951,12 +1098,17 @@ size_t query_bytes(td_ctx* c, const td_request& r) {
     R = Region{k.ix0 * d.S + d.O, k.iy0 * d.S + d.O, (k.ix1 - k.ix0) * d.S + d.H, (k.iy1 - k.iy0) * d.S + d.H};
     bytes += (size_t)R.w * R.h * d.C * sizeof(float);
   }
+  if (d.Cc) {   // the parent latent under the cone
+    const Region pr = parent_region(d, R);
+    bytes += (size_t)pr.w * pr.h * d.Cc * sizeof(float);
+  }
   return bytes;
 }
 
-void plan_query(td_server* s, SrvQuery& Q) {
+void plan_query(td_server* s, SrvQuery& Q, Arena& arena) {
   td_ctx* c = s->c;
   const ModelDesc& d = c->model->d;
+  check_parent(c, s->active.empty());
   Region R{Q.r.x0, Q.r.y0, Q.r.w, Q.r.h};
   for (int t = Q.r.level; t < d.T; ++t) {
     SrvLevel S;
@@ -1010,6 +1162,16 @@ void plan_query(td_server* s, SrvQuery& Q) {
     R = B.L.in_region;
   }
   Q.cur = (int)Q.lv.size() - 1;
+  if (d.Cc) {
+    Region hull{0, 0, 0, 0};
+    for (const SrvLevel& S : Q.lv)
+      if (!S.own.empty()) hull = region_union(hull, S.L.in_region);
+    if (hull.w > 0) {
+      const Region pr = parent_region(d, hull);
+      Q.cond = take_canvas(s, (size_t)pr.w * pr.h * d.Cc);
+      sample_parent(c, arena, Q.r.seed, hull, Q.cond, &Q.cond_r);
+    }
+  }
 }
 
 bool all_enqueued(td_server* s, uint64_t seed, const Level& L) {
@@ -1055,6 +1217,11 @@ void advance(td_server* s, SrvQuery& Q, Arena& arena) {
       S.canvas = nullptr;
       Q.cur--;
       continue;
+    }
+    // every own window enqueued: its conditioning has been gathered
+    if (Q.cond) {
+      give_canvas(s, Q.cond);
+      Q.cond = nullptr;
     }
     // every level evaluated: the result is the blend of the query level
     const Level& top = Q.lv[0].L;
@@ -1126,6 +1293,14 @@ bool run_round_batch(td_server* s, Arena& arena) {
   TD_HIP(hipMemcpyAsync(wix.second, wix.first, (size_t)nb * 2 * sizeof(int), hipMemcpyHostToDevice, st));
   TD_HIP(hipMemcpyAsync(slo.second, slo.first, (size_t)nb * sizeof(float*), hipMemcpyHostToDevice, st));
   launch_gather(st, (const float* const*)src.second, (const int*)pit.second, nb, d.H, d.C, s->batch_in);
+  std::vector<CondSrc> cs(d.Cc ? nb : 0);
+  for (int j = 0; j < (int)cs.size(); ++j) {
+    const SrvTask& T = s->tasks[ids[j]];
+    const SrvQuery& O = s->q[T.q];
+    cs[j] = cond_src(d, O.cond, O.cond_r.w, O.cond_r.x0 * d.cond_factor, O.cond_r.y0 * d.cond_factor, T.key.ix,
+                     T.key.iy);
+  }
+  if (d.Cc) cond_batch(c, arena, cs.data(), nb);
   WindowBatch wb;
   wb.canvas = s->batch_in;
   wb.canvas_w = d.H;
@@ -1134,6 +1309,7 @@ bool run_round_batch(td_server* s, Arena& arena) {
   wb.d_slots = (float* const*)slo.second;
   wb.n = nb;
   wb.mode = 0;
+  if (d.Cc) wb.cond = c->model->cond_buffer();
   c->model->run_level(st, wb, best);
   c->stats.batches++;
   s->stats.batched_windows += nb;
@@ -1148,7 +1324,7 @@ bool run_round_batch(td_server* s, Arena& arena) {
   return true;
 }
 
-void admit(td_server* s) {
+void admit(td_server* s, Arena& arena) {
   while (!s->queued.empty() && (int)s->active.size() < s->max_inflight) {
     SrvQuery& Q = s->q[s->queued.front()];
     size_t need = query_bytes(s->c, Q.r);
@@ -1156,7 +1332,7 @@ void admit(td_server* s) {
     s->queued.pop_front();
     Q.mem = need;
     s->mem_used += need;
-    plan_query(s, Q);
+    plan_query(s, Q, arena);
     Q.state = 1;
     s->active.push_back(Q.ticket);
     s->stats.admitted++;
@@ -1169,13 +1345,13 @@ void server_round(td_server* s) {
   if (s->ring_used[slot]) TD_HIP(hipEventSynchronize(s->ring_ev[slot]));
   Arena& arena = s->ring[slot];
   arena.reset();
-  admit(s);
+  admit(s, arena);
   size_t need = 65536;   // metadata of this round: pointer grids + one batch
   for (uint64_t t : s->active) {
     const SrvQuery& Q = s->q[t];
     for (const SrvLevel& S : Q.lv) need += (size_t)S.L.k.count() * sizeof(float*) + 256;
   }
-  need += (size_t)s->maxb * 48 + 5 * 256;
+  need += (size_t)s->maxb * (48 + sizeof(CondSrc)) + 6 * 256;
   arena.ensure(need);
   for (uint64_t t : s->active) advance(s, s->q[t], arena);
   if (run_round_batch(s, arena)) s->stats.rounds++;

@@ -97,7 +97,8 @@ __device__ __forceinline__ int floor_mod(int a, int m) {
 
 __global__ __launch_bounds__(256) void lg_step_kernel(int H, int C, const float* __restrict__ canvas,
                                                       int canvas_w, const int* __restrict__ origins,
-                                                      const int* __restrict__ widx, float a_post,
+                                                      const int* __restrict__ widx,
+                                                      const float* __restrict__ cond, int cc, float a_post,
                                                       float c_euler, const float* __restrict__ w1d,
                                                       float* const* __restrict__ slots, int mode,
                                                       float* __restrict__ dout) {
@@ -111,6 +112,7 @@ __global__ __launch_bounds__(256) void lg_step_kernel(int H, int C, const float*
   float x = canvas[((size_t)(oy + v) * canvas_w + ox + u) * C + c];
   int ix = widx[2 * b], iy = widx[2 * b + 1];
   float mu = 0.1f * (float)(floor_mod(ix, 7) - 3) - 0.05f * (float)(floor_mod(iy, 5) - 2) + 0.01f * (float)c;
+  if (cc) mu += cond[((size_t)b * H * H + pix) * cc + c % cc];
   float d = mu + a_post * (x - mu);
   if (mode == 1) {
     dout[(size_t)b * H * H * C + idx] = d;
@@ -134,7 +136,31 @@ __global__ __launch_bounds__(256) void gather_kernel(const float* const* __restr
   out[(size_t)b * per + e] = src[b][((size_t)v * pitch[b] + u) * C + c];
 }
 
+// Conditioning windows: nearest upsampling of a parent-resolution canvas.
+__global__ __launch_bounds__(256) void cond_gather_kernel(const CondSrc* __restrict__ src, int H, int cc,
+                                                          int factor, float* __restrict__ out) {
+  const int b = blockIdx.y;
+  const int per = H * H * cc;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= per) return;
+  const int c = e % cc, p = e / cc;
+  const int v = p / H, u = p - v * H;
+  const CondSrc s = src[b];
+  const int py = (s.offy + v) / factor, px = (s.offx + u) / factor;
+  out[(size_t)b * per + e] = s.base[((size_t)py * s.pitch + px) * cc + c];
+}
+
 }  // namespace
+
+void launch_cond_gather(hipStream_t st, const CondSrc* src, int nb, int H, int cc, int factor, float* out) {
+  if (!nb) return;
+  TD_CHECK(cc >= 1 && factor >= 1, -5, "conditioning gather: bad channels or factor");
+  const int per = H * H * cc;
+  prof_begin(st);
+  hipLaunchKernelGGL(cond_gather_kernel, dim3((per + 255) / 256, nb), dim3(256), 0, st, src, H, cc, factor, out);
+  TD_LAUNCHED();
+  prof_end(st, K_GATHER, 0.0, 8.0 * per * nb);
+}
 
 void launch_gather(hipStream_t st, const float* const* src, const int* pitch, int nb, int H, int C, float* out) {
   if (!nb) return;
@@ -166,15 +192,17 @@ void launch_blend(hipStream_t st, const WinGeom& g, int rx0, int ry0, int w, int
 }
 
 void launch_lg_step(hipStream_t st, const WinGeom& g, const float* canvas, int canvas_w,
-                    const int* origins, const int* widx, int nwin, double prior_std, double sigma,
+                    const int* origins, const int* widx, const float* cond, int cc, int nwin,
+                    double prior_std, double sigma,
                     float c_euler, const float* w1d, float* const* slots, int mode, float* dout) {
   if (!nwin) return;
+  TD_CHECK(cc == 0 || cond, -5, "conditioned denoiser run without conditioning");
   int per = g.size * g.size * g.channels;
   double s2 = prior_std * prior_std;
   float a_post = (float)(s2 / (s2 + sigma * sigma));
   prof_begin(st);
   hipLaunchKernelGGL(lg_step_kernel, dim3((per + 255) / 256, nwin), dim3(256), 0, st, g.size, g.channels,
-                     canvas, canvas_w, origins, widx, a_post, c_euler, w1d, slots, mode, dout);
+                     canvas, canvas_w, origins, widx, cond, cc, a_post, c_euler, w1d, slots, mode, dout);
   TD_LAUNCHED();
   prof_end(st, K_LG, 6.0 * per * nwin, 8.0 * per * nwin);
 }

@@ -13,30 +13,36 @@ namespace {
 __device__ __forceinline__ float silu_f(float v) { return __fdividef(v, 1.0f + __expf(-v)); }
 
 // ---------------------------------------------------------------- conv_in
-// One workgroup per (window, 16x16 output tile).  LDS: (16+2)^2 x cimg
-// scaled inputs (zero outside the window: the network pads with zeros),
-// and the 9 x cimg x c0 weights.
-template <int CI>
+// One workgroup per (window, 16x16 output tile).  LDS: (16+2)^2 x (CI + CC)
+// inputs (c_in-scaled latent channels, then the conditioning channels; zero
+// outside the window: the network pads with zeros), and the 9 x (CI + CC)
+// x c0 weights.
+template <int CI, int CC>
 __global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ canvas, int canvas_w,
-                                                      const int* __restrict__ origins, int H, int c0,
+                                                      const int* __restrict__ origins,
+                                                      const float* __restrict__ cond, int H, int c0,
                                                       float c_in, const float* __restrict__ wt,
                                                       const float* __restrict__ bias, float* __restrict__ out) {
+  constexpr int CT = CI + CC;
   extern __shared__ float sm[];
-  float* halo = sm;                 // [18*18][CI]
-  float* wl = sm + 18 * 18 * CI;    // [9][CI][c0]
+  float* halo = sm;                 // [18*18][CT]
+  float* wl = sm + 18 * 18 * CT;    // [9][CT][c0]
   const int b = blockIdx.y;
   const int tiles_x = H / 16;
   const int tx0 = (blockIdx.x % tiles_x) * 16, ty0 = (blockIdx.x / tiles_x) * 16;
   const int ox = origins[2 * b], oy = origins[2 * b + 1];
-  for (int e = threadIdx.x; e < 18 * 18 * CI; e += 256) {
-    int c = e % CI, p = e / CI;
+  for (int e = threadIdx.x; e < 18 * 18 * CT; e += 256) {
+    int c = e % CT, p = e / CT;
     int hy = p / 18, hx = p % 18;
     int y = ty0 + hy - 1, x = tx0 + hx - 1;
     float v = 0.f;
-    if (y >= 0 && y < H && x >= 0 && x < H) v = c_in * canvas[((size_t)(oy + y) * canvas_w + ox + x) * CI + c];
+    if (y >= 0 && y < H && x >= 0 && x < H) {
+      if (c < CI) v = c_in * canvas[((size_t)(oy + y) * canvas_w + ox + x) * CI + c];
+      else v = cond[(((size_t)b * H + y) * H + x) * CC + (c - CI)];
+    }
     halo[e] = v;
   }
-  for (int e = threadIdx.x; e < 9 * CI * c0; e += 256) wl[e] = wt[e];
+  for (int e = threadIdx.x; e < 9 * CT * c0; e += 256) wl[e] = wt[e];
   __syncthreads();
   for (int e = threadIdx.x; e < 256 * c0; e += 256) {
     int co = e % c0, p = e / c0;
@@ -45,9 +51,9 @@ __global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ 
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
       int dy = t / 3, dx = t % 3;
-      const float* hp = halo + ((py + dy) * 18 + px + dx) * CI;
+      const float* hp = halo + ((py + dy) * 18 + px + dx) * CT;
 #pragma unroll
-      for (int c = 0; c < CI; ++c) acc += hp[c] * wl[(t * CI + c) * c0 + co];
+      for (int c = 0; c < CT; ++c) acc += hp[c] * wl[(t * CT + c) * c0 + co];
     }
     out[(((size_t)b * H + ty0 + py) * H + tx0 + px) * c0 + co] = acc;
   }
@@ -220,24 +226,29 @@ __global__ __launch_bounds__(256) void attention_kernel(const float* __restrict_
 }  // namespace
 
 void launch_conv_in(hipStream_t st, const float* canvas, int canvas_w, const int* origins, int nwin, int H,
-                    int cimg, int c0, float c_in, const float* wt, const float* bias, float* out) {
+                    int cimg, const float* cond, int ccond, int c0, float c_in, const float* wt, const float* bias,
+                    float* out) {
   if (!nwin) return;
   TD_CHECK(H % 16 == 0, -5, "conv_in: window size must be a multiple of 16");
+  TD_CHECK(ccond == 0 || cond, -5, "conv_in: conditioning channels without conditioning input");
+  const int ct = cimg + ccond;
   dim3 grid((H / 16) * (H / 16), nwin);
-  size_t shm = (18 * 18 * cimg + 9 * cimg * c0) * sizeof(float);
+  size_t shm = (18 * 18 * ct + 9 * ct * c0) * sizeof(float);
   TD_CHECK(shm <= 64 * 1024, -5, "conv_in: too many channels");
   prof_begin(st);
-  if (cimg == 4)
-    hipLaunchKernelGGL(conv_in_kernel<4>, grid, dim3(256), shm, st, canvas, canvas_w, origins, H, c0, c_in, wt,
-                       bias, out);
-  else if (cimg == 1)
-    hipLaunchKernelGGL(conv_in_kernel<1>, grid, dim3(256), shm, st, canvas, canvas_w, origins, H, c0, c_in, wt,
-                       bias, out);
-  else
-    TD_CHECK(false, -5, "conv_in: latent channels must be 1 or 4");
+#define TD_CONV_IN(CI, CC)                                                                                   \
+  hipLaunchKernelGGL((conv_in_kernel<CI, CC>), grid, dim3(256), shm, st, canvas, canvas_w, origins, cond, H, \
+                     c0, c_in, wt, bias, out)
+  if (cimg == 4 && ccond == 0) TD_CONV_IN(4, 0);
+  else if (cimg == 1 && ccond == 0) TD_CONV_IN(1, 0);
+  else if (cimg == 1 && ccond == 1) TD_CONV_IN(1, 1);
+  else if (cimg == 4 && ccond == 1) TD_CONV_IN(4, 1);
+  else if (cimg == 4 && ccond == 4) TD_CONV_IN(4, 4);
+  else TD_CHECK(false, -5, "conv_in: supported (latent, conditioning) channels are (1|4, 0), (1|4, 1), (4, 4)");
+#undef TD_CONV_IN
   TD_LAUNCHED();
   const double px = (double)nwin * H * H;
-  prof_end(st, K_CONV_IN, 2.0 * px * c0 * 9 * cimg, 4.0 * px * (cimg + c0));
+  prof_end(st, K_CONV_IN, 2.0 * px * c0 * 9 * ct, 4.0 * px * (ct + c0));
 }
 
 void launch_conv_out(hipStream_t st, const OutArgs& a) {

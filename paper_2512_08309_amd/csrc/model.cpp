@@ -170,6 +170,20 @@ void Model::load(const std::string& path, hipStream_t st) {
   d.smin = sp.at("sigma_min").num();
   d.rho = sp.at("rho").num();
   d.sigma_data = sp.at("sigma_data").num();
+  d.noise_step = 0;
+  if (sp.has("noise_step")) {
+    const int64_t ns = sp.at("noise_step").integer();
+    TD_CHECK(ns >= 0 && ns <= 0xffffffffLL, -5, "weight header: noise_step must be a 32-bit counter word");
+    d.noise_step = (uint32_t)ns;
+  }
+  d.Cc = d.cond_factor = 0;
+  if (h.has("cond")) {
+    const Json& cj = h.at("cond");
+    d.Cc = (int)cj.at("channels").integer();
+    d.cond_factor = (int)cj.at("factor").integer();
+    TD_CHECK(d.Cc >= 1 && d.Cc <= 4 && d.cond_factor >= 1 && d.cond_factor <= 64, -5,
+             "weight header: conditioning needs 1..4 channels and a factor in 1..64");
+  }
   const Json& wn = h.at("window");
   d.H = (int)wn.at("size").integer();
   d.S = (int)wn.at("stride").integer();
@@ -307,7 +321,7 @@ void Model::build_unet(const std::map<std::string, std::vector<float>>& host,
   const int nl = (int)d.ch.size();
   const int c0 = d.ch[0];
   const int emb = d.emb_mult * c0;
-  conv_in_w_ = conv_layout("conv_in.weight", c0, d.C, 3);
+  conv_in_w_ = conv_layout("conv_in.weight", c0, d.C + d.Cc, 3);
   conv_in_b_ = vec("conv_in.bias", c0);
 
   // per-level embedding: pe -> lin1 -> SiLU -> lin2 -> SiLU, for every sigma_k
@@ -411,7 +425,8 @@ void Model::build_unet(const std::map<std::string, std::vector<float>>& host,
 }
 
 size_t Model::workspace_bytes_per_window() const {
-  const size_t state = d.T < d.K ? (size_t)d.H * d.H * d.C * sizeof(float) + 2 * sizeof(int) : 0;
+  const size_t state = (d.T < d.K ? (size_t)d.H * d.H * d.C * sizeof(float) + 2 * sizeof(int) : 0) +
+                       (size_t)d.H * d.H * d.Cc * sizeof(float);
   if (d.kind != "unet") return state;
   size_t f = 0;
   const int nl = (int)d.ch.size();
@@ -447,6 +462,7 @@ void Model::ensure_workspace(int max_batch) {
   };
   state_ = nullptr;
   state_origins_ = nullptr;
+  cond_ = d.Cc ? take((size_t)max_batch * d.H * d.H * d.Cc) : nullptr;
   if (d.T < d.K) {
     state_ = take((size_t)max_batch * d.H * d.H * d.C);
     state_origins_ = (int*)take((size_t)max_batch * 2);
@@ -706,9 +722,10 @@ void Model::run_batch(hipStream_t st, const WindowBatch& wb, int k) {
   const float c_skip = (float)(sd * sd / s2), c_out = (float)(sigma * sd / std::sqrt(s2));
   const float c_in = (float)(1.0 / std::sqrt(s2)), c_euler = (float)((sigma_next - sigma) / sigma);
   WinGeom g{d.H, d.S, d.C};
+  TD_CHECK(d.Cc == 0 || wb.cond, -6, "conditioned model run without its conditioning windows");
   if (d.kind == "linear_gaussian") {
-    launch_lg_step(st, g, wb.canvas, wb.canvas_w, wb.d_origins, wb.d_widx, wb.n, d.prior_std, sigma,
-                   c_euler, w1d_, wb.d_slots, wb.mode, wb.dout);
+    launch_lg_step(st, g, wb.canvas, wb.canvas_w, wb.d_origins, wb.d_widx, wb.cond, d.Cc, wb.n, d.prior_std,
+                   sigma, c_euler, w1d_, wb.d_slots, wb.mode, wb.dout);
     return;
   }
   TD_CHECK(wb.n <= ws_batch_, -1, "batch larger than workspace");
@@ -717,8 +734,8 @@ void Model::run_batch(hipStream_t st, const WindowBatch& wb, int k) {
   //  element before writing it, so dout may alias the canvas)
   const int nb = wb.n;
   LevelBufs& L0 = lb_[0];
-  launch_conv_in(st, wb.canvas, wb.canvas_w, wb.d_origins, nb, d.H, d.C, d.ch[0], c_in, conv_in_w_, conv_in_b_,
-                 L0.X);
+  launch_conv_in(st, wb.canvas, wb.canvas_w, wb.d_origins, nb, d.H, d.C, wb.cond, d.Cc, d.ch[0], c_in, conv_in_w_,
+                 conv_in_b_, L0.X);
   const float* h = L0.X;
   int hc = d.ch[0];
   for (int l = 0; l < nl; ++l) {

@@ -23,6 +23,10 @@ struct ModelDesc {
   double pe_max_period = 10000.0;
   // analytic denoiser
   double prior_std = 0.5;
+  // hierarchy: conditioning channels read from a parent model's final
+  // latent, nearest-upsampled by cond_factor (0 channels: unconditioned)
+  int Cc = 0, cond_factor = 0;
+  uint32_t noise_step = 0;    // counter word of this model's J_T noise
   // sampler
   int K = 0;
   double smax = 80, smin = 0.002, rho = 7, sigma_data = 0.5;
@@ -76,6 +80,7 @@ struct WindowBatch {
   const int* d_widx = nullptr;      // [n][2] device (window indices, analytic kind)
   float* const* d_slots = nullptr;  // [n] device pointers, mode 0
   float* dout = nullptr;            // mode 1: [n][H][H][C]
+  const float* cond = nullptr;      // [n][H][H][Cc] conditioning windows (Cc > 0)
   int n = 0;
   int mode = 0;                     // 0: contributions W (x) Phi, 1: raw D, 2: Phi to dout
 };
@@ -95,6 +100,8 @@ class Model {
   size_t workspace_bytes_per_window() const;
   void ensure_workspace(int max_batch);
   int max_batch() const { return ws_batch_; }
+  // [max_batch][H][H][Cc] conditioning windows of one batch (Cc > 0)
+  float* cond_buffer() const { return cond_; }
   const float* w1d() const { return w1d_; }
   const float* decode_taps() const { return taps_; }
   const float* decode_atoms() const { return atoms_; }
@@ -127,6 +134,7 @@ class Model {
   std::vector<LevelBufs> lb_;
   float *gn_scale_ = nullptr, *gn_shift_ = nullptr;
   double* gn_part_ = nullptr;
+  float* cond_ = nullptr;         // conditioning windows of a batch
   float* state_ = nullptr;        // window states between the steps of one Phi
   int* state_origins_ = nullptr;  // (0, b*H) for b < ws_batch_
 

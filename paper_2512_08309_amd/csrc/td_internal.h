@@ -77,9 +77,24 @@ void launch_fill(hipStream_t st, float* p, size_t n, float v);
 // pitch[b] is its canvas row length in pixels.
 void launch_gather(hipStream_t st, const float* const* src, const int* pitch, int nb, int H, int C, float* out);
 
+// Conditioning windows of a child model (hierarchy): window b reads a
+// parent-resolution canvas base ([rows][pitch][cc]) nearest-upsampled by
+// `factor`; its pixel (u, v) takes parent pixel ((offx + u) / factor,
+// (offy + v) / factor) with offx, offy >= 0 the window origin relative to
+// factor * (canvas origin).  out: [nb][H][H][cc].
+struct CondSrc {
+  const float* base;
+  int pitch;
+  int offx, offy;
+  int pad;
+};
+void launch_cond_gather(hipStream_t st, const CondSrc* src, int nb, int H, int cc, int factor, float* out);
+
 // Analytic linear-Gaussian denoiser + Euler step + weighting (see kernels).
+// cond (nullable): [nwin][H][H][cc] conditioning added to the prior mean.
 void launch_lg_step(hipStream_t st, const WinGeom& g, const float* canvas,
                     int canvas_w, const int* origins, const int* widx,
+                    const float* cond, int cc,
                     int nwin, double prior_std, double sigma, float c_euler,
                     const float* w1d, float* const* slots, int mode,
                     float* dout);
@@ -154,10 +169,13 @@ void launch_gn(hipStream_t st, const GnArgs& a);
 void launch_avgpool(hipStream_t st, const float* in, float* out, int nb, int h,
                     int w, int C);
 
-// conv_in: gathers each window from the canvas, scales by c_in and applies
-// the 3x3 input conv.  origins: [nwin][2] canvas-relative (x, y).
+// conv_in: gathers each window from the canvas, scales by c_in, appends the
+// window's conditioning channels (cond [nwin][H][H][ccond], unscaled; none
+// when ccond = 0) and applies the 3x3 input conv (weights [9][cimg +
+// ccond][c0]).  origins: [nwin][2] canvas-relative (x, y).
 void launch_conv_in(hipStream_t st, const float* canvas, int canvas_w,
-                    const int* origins, int nwin, int H, int cimg, int c0,
+                    const int* origins, int nwin, int H, int cimg,
+                    const float* cond, int ccond, int c0,
                     float c_in, const float* wt, const float* bias,
                     float* out);
 

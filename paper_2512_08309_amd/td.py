@@ -19,7 +19,8 @@ STATUS_NAMES = {0: "TD_OK", -1: "TD_E_INVAL", -2: "TD_E_NOMEM", -3: "TD_E_DEVICE
                 -5: "TD_E_FORMAT", -6: "TD_E_STATE"}
 
 # Every symbol include/td.h declares.
-EXPORTS = ["td_create", "td_destroy", "td_load_weights", "td_sample_region", "td_sample_region_async",
+EXPORTS = ["td_create", "td_destroy", "td_load_weights", "td_set_conditioning", "td_sample_region",
+           "td_sample_region_async",
            "td_cache_set_budget", "td_cache_clear", "td_cache_stats", "td_cache_peek", "td_set_option",
            "td_get_info", "td_denoise_windows", "td_lap_decode", "td_kappa", "td_cone_windows", "td_kernel_stats",
            "td_server_create", "td_server_destroy", "td_server_submit", "td_server_progress", "td_server_poll",
@@ -65,6 +66,7 @@ def _load():
         "td_create": ([ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
         "td_destroy": ([vp], None),
         "td_load_weights": ([vp, ctypes.c_char_p], ctypes.c_int),
+        "td_set_conditioning": ([vp, vp], ctypes.c_int),
         "td_sample_region": ([vp, u64, i64, i64, i32, i32, i32, fp, sz], ctypes.c_int),
         "td_sample_region_async": ([vp, u64, i64, i64, i32, i32, i32, vp, sz, vp], ctypes.c_int),
         "td_cache_set_budget": ([vp, sz], ctypes.c_int),
@@ -73,7 +75,7 @@ def _load():
         "td_cache_peek": ([vp, u64, i32, i64, i64, fp, sz], ctypes.c_int),
         "td_set_option": ([vp, ctypes.c_char_p, i64], ctypes.c_int),
         "td_get_info": ([vp, ctypes.c_char_p, ctypes.POINTER(i64)], ctypes.c_int),
-        "td_denoise_windows": ([vp, vp, i32, i32, vp], ctypes.c_int),
+        "td_denoise_windows": ([vp, vp, vp, i32, i32, vp], ctypes.c_int),
         "td_lap_decode": ([vp, vp, i64, i64, i32, i32, i64, i64, i32, i32, vp, vp], ctypes.c_int),
         "td_kappa": ([i64, i64, i64, i64, i32, i32, i32, ctypes.POINTER(i64)], ctypes.c_int),
         "td_cone_windows": ([i64, i64, i64, i64, i32, i32, i32, i32, i32, ctypes.POINTER(u64)], ctypes.c_int),
@@ -180,10 +182,20 @@ def td_set_option(ctx, key, value):
     _check(ctx, lib.td_set_option(ctx, key.encode(), value))
 
 
-def td_denoise_windows(ctx, x_dev, k, out_dev):
-    """x_dev, out_dev: contiguous float32 torch tensors [n][H][H][C] on the device."""
+def td_set_conditioning(child, parent):
+    """Make parent's final latent condition child (parent None unlinks)."""
+    _check(child, lib.td_set_conditioning(child, parent))
+
+
+def td_denoise_windows(ctx, x_dev, k, out_dev, cond_dev=None):
+    """x_dev, out_dev: contiguous float32 torch tensors [n][H][H][C] on the
+    device; cond_dev: [n][H][H][C_y] for a conditioned model, else None."""
     assert x_dev.is_contiguous() and out_dev.is_contiguous() and x_dev.shape == out_dev.shape
-    _check(ctx, lib.td_denoise_windows(ctx, ctypes.c_void_p(x_dev.data_ptr()), x_dev.shape[0], k,
+    cp = None
+    if cond_dev is not None:
+        assert cond_dev.is_contiguous() and cond_dev.shape[:3] == x_dev.shape[:3]
+        cp = ctypes.c_void_p(cond_dev.data_ptr())
+    _check(ctx, lib.td_denoise_windows(ctx, ctypes.c_void_p(x_dev.data_ptr()), cp, x_dev.shape[0], k,
                                        ctypes.c_void_p(out_dev.data_ptr())))
     return out_dev
 
@@ -294,6 +306,12 @@ class Context:
         td_load_weights(self.ctx, path)
         return self
 
+    def set_conditioning(self, parent):
+        """parent: the Context whose final latent conditions this one (None unlinks)."""
+        td_set_conditioning(self.ctx, parent.ctx if parent is not None else None)
+        self._parent = parent      # keep the parent alive while linked
+        return self
+
     def info(self, key):
         return td_get_info(self.ctx, key)
 
@@ -318,8 +336,8 @@ class Context:
     def set_option(self, key, value):
         td_set_option(self.ctx, key, value)
 
-    def denoise_windows(self, x_dev, k, out_dev):
-        return td_denoise_windows(self.ctx, x_dev, k, out_dev)
+    def denoise_windows(self, x_dev, k, out_dev, cond_dev=None):
+        return td_denoise_windows(self.ctx, x_dev, k, out_dev, cond_dev)
 
     def kernel_stats(self, reset=False):
         return td_kernel_stats(self.ctx, reset)

@@ -60,6 +60,8 @@ def test_argument_errors_without_device():
     assert td.td_last_error(None) == ""
     assert td.lib.td_sample_region(None, 0, 0, 0, 1, 1, 0, None, 0) == td.TD_E_INVAL
     assert td.lib.td_cache_clear(None) == td.TD_E_INVAL
+    assert td.lib.td_set_conditioning(None, None) == td.TD_E_INVAL
+    assert td.lib.td_denoise_windows(None, None, None, 0, 0, None) == td.TD_E_INVAL
 
 
 def test_create_fails_cleanly_without_gpu():

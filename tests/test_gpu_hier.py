@@ -1,0 +1,141 @@
+"""GPU parity of the hierarchy (a parent model's final latent conditions a
+child model), through the C-ABI, against the FP64 oracle.
+
+Bars: linear-Gaussian pair rel L2 <= 1e-6; conditioned UNet denoiser
+<= 1e-5; UNet pair (coarse 64/128 parent, 1-channel fine child) sampler
+<= 1e-4; crops, batch sizes and cache budgets bit-exact; a parent that
+changes (new weights) invalidates the child's cached windows.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import planar, rel_l2, require_gpu
+from oracle.sampler import Model, sample
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pair(weights):
+    require_gpu()
+    from paper_2512_08309_amd import td
+    made = []
+
+    def get(child, parent, parent_seed=0):
+        p = td.Context(0).load_weights(weights(parent, seed=parent_seed))
+        c = td.Context(0).load_weights(weights(child)).set_conditioning(p)
+        made.extend([c, p])
+        return c, p
+    yield get
+    for c in made:
+        c.close()
+
+
+def oracle_pair(weights, child, parent, parent_seed=0):
+    return Model(weights(child), parent=Model(weights(parent, seed=parent_seed)))
+
+
+@pytest.mark.parametrize("seed,region,level", [(0, (-37, -21, 23, 17), 0), (4, (1000003, -999985, 40, 9), 0),
+                                               (2, (-5, 9, 31, 33), 3)])
+def test_linear_gaussian_pair_matches_oracle(pair, weights, seed, region, level):
+    c, _ = pair("lgh", "lgc")
+    assert c.info("cond_channels") == 1 and c.info("cond_factor") == 8
+    got = c.sample_region(seed, *region, level)
+    ref = planar(sample(oracle_pair(weights, "lgh", "lgc"), seed, *region, level))
+    assert rel_l2(got, ref) <= 1e-6
+
+
+def test_parent_noise_uses_its_counter_word(pair):
+    from oracle import noise as onoise
+    _, p = pair("lgh", "lgc")
+    assert p.info("noise_step") == 2
+    got = p.sample_region(9, -3, 4, 10, 6, p.info("levels"))
+    want = planar(np.float32(80.0) * onoise.noise_region(9, -3, 4, 10, 6, 1, step=2))
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("k", [0, 6])
+def test_conditioned_unet_denoiser_matches_oracle(pair, weights, k):
+    import torch
+    from oracle.tdw import read_tdw
+    from oracle.unet import UNetDenoiser
+    c, _ = pair("c1h", "cc")
+    hdr, t = read_tdw(weights("c1h"))
+    sig = Model(weights("c1h")).sched[k]
+    rng = np.random.default_rng(30 + k)
+    x = (sig * rng.standard_normal((5, 32, 32, 1))).astype(np.float32)
+    y = rng.standard_normal((5, 32, 32, 1)).astype(np.float32)
+    out = torch.empty((5, 32, 32, 1), device="cuda")
+    c.denoise_windows(torch.from_numpy(x).cuda(), k, out, torch.from_numpy(y).cuda())
+    ref = UNetDenoiser(hdr, t)(x.astype(np.float64), sig, None, cond=y.astype(np.float64))
+    assert rel_l2(out.cpu().numpy(), ref) <= 1e-5
+
+
+def test_unet_pair_sampler_matches_oracle(pair, weights):
+    c, _ = pair("c1h", "cc")
+    got = c.sample_region(3, -20, 11, 48, 40, 0)
+    ref = planar(sample(oracle_pair(weights, "c1h", "cc"), 3, -20, 11, 48, 40, 0))
+    assert rel_l2(got, ref) <= 1e-4
+
+
+def test_unet_pair_seed_consistency_bit_exact(pair):
+    c, p = pair("c1h", "cc")
+    c.cache_clear()
+    p.cache_clear()
+    big = c.sample_region(6, -40, -8, 96, 80, 0)
+    c.cache_clear()
+    p.cache_clear()
+    c.set_option("batch", 7)
+    p.set_option("batch", 3)
+    p.cache_set_budget(0)          # the parent keeps nothing between its levels
+    try:
+        small = c.sample_region(6, -7, 21, 29, 30, 0)
+    finally:
+        c.set_option("batch", 4096)
+        p.set_option("batch", 4096)
+        p.cache_set_budget(8 << 30)
+    assert np.array_equal(small, big[:, 29:59, 33:62])
+
+
+def test_parent_change_invalidates_child_cache(pair, weights):
+    c, p = pair("c1h", "cc")
+    a = c.sample_region(1, 0, 0, 24, 24, 0)
+    p.load_weights(weights("cc", seed=1))
+    b = c.sample_region(1, 0, 0, 24, 24, 0)
+    assert np.abs(a - b).max() > 1e-3
+    c2, _ = pair("c1h", "cc", parent_seed=1)
+    assert np.array_equal(b, c2.sample_region(1, 0, 0, 24, 24, 0))
+    p.load_weights(weights("cc"))
+    assert np.array_equal(a, c.sample_region(1, 0, 0, 24, 24, 0))
+
+
+def test_conditioning_errors(weights):
+    require_gpu()
+    import torch
+    from paper_2512_08309_amd import td
+    with td.Context(0) as child, td.Context(0) as other, td.Context(0) as p4:
+        child.load_weights(weights("lgh"))
+        with pytest.raises(td.TDError) as e:
+            child.sample_region(0, 0, 0, 8, 8, 0)            # no parent linked
+        assert e.value.status == td.TD_E_STATE
+        p4.load_weights(weights("lg"))                        # 4 channels, conditioning has 1
+        child.set_conditioning(p4)
+        with pytest.raises(td.TDError) as e:
+            child.sample_region(0, 0, 0, 8, 8, 0)
+        assert e.value.status == td.TD_E_STATE
+        with pytest.raises(td.TDError) as e:
+            child.set_conditioning(child)
+        assert e.value.status == td.TD_E_INVAL
+        other.load_weights(weights("lgc"))
+        other.set_conditioning(child)
+        with pytest.raises(td.TDError) as e:
+            child.set_conditioning(other)                     # child -> other -> child
+        assert e.value.status == td.TD_E_INVAL
+        other.set_conditioning(None)
+        child.set_conditioning(other)
+        assert child.sample_region(0, 0, 0, 8, 8, 0).shape == (1, 8, 8)
+        x = torch.zeros((1, 32, 32, 1), device="cuda")
+        with pytest.raises(td.TDError):
+            child.denoise_windows(x, 0, torch.empty_like(x))   # conditioning missing
+        with pytest.raises(td.TDError):
+            other.denoise_windows(x, 0, torch.empty_like(x), x)  # unconditioned model given conditioning

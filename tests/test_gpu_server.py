@@ -1,6 +1,7 @@
 """Continuous-batching server: every query's result in a concurrent mix
 equals the same query made alone (bit for bit), and the rounds really mix
-windows of several queries."""
+windows of several queries.  Also with a conditioned (child) model, whose
+queries first sample the parent model."""
 import numpy as np
 import pytest
 
@@ -15,9 +16,15 @@ QUERIES = [  # (seed, x0, y0, w, h, level): uneven sizes, overlaps, repeats, two
 ]
 
 
-def run_alone(td, torch, wpath, q):
-    with td.Context(0) as c:
-        c.load_weights(wpath)
+def context(td, wpath, ppath):
+    c = td.Context(0).load_weights(wpath)
+    if ppath:
+        c.set_conditioning(td.Context(0).load_weights(ppath))
+    return c
+
+
+def run_alone(td, torch, wpath, ppath, q):
+    with context(td, wpath, ppath) as c:
         C = c.info("channels")
         out = torch.empty((C, q[4], q[3]), device="cuda")
         c.sample_region_async(*q, out)
@@ -25,20 +32,21 @@ def run_alone(td, torch, wpath, q):
         return out.cpu().numpy()
 
 
-@pytest.mark.parametrize("config,inflight,budget", [("c1", 6, 64 << 30), ("c1", 2, 200 << 20),
-                                                    ("c1t2", 12, 64 << 30), ("lg", 4, 64 << 30)])
-def test_mix_equals_alone(weights, config, inflight, budget):
+@pytest.mark.parametrize("config,inflight,budget,parent", [("c1", 6, 64 << 30, None), ("c1", 2, 200 << 20, None),
+                                                           ("c1t2", 12, 64 << 30, None), ("lg", 4, 64 << 30, None),
+                                                           ("c1h", 6, 64 << 30, "cc"), ("lgh", 3, 64 << 30, "lgc")])
+def test_mix_equals_alone(weights, config, inflight, budget, parent):
     require_gpu()
     import torch
     from paper_2512_08309_amd import td
     wpath = weights(config)
+    ppath = weights(parent) if parent else None
     with td.Context(0) as c:
         c.load_weights(wpath)
         T = c.info("levels")
     queries = [q[:5] + (min(q[5], T - 1),) for q in QUERIES]
-    alone = [run_alone(td, torch, wpath, q) for q in queries]
-    with td.Context(0) as c:
-        c.load_weights(wpath)
+    alone = [run_alone(td, torch, wpath, ppath, q) for q in queries]
+    with context(td, wpath, ppath) as c:
         C = c.info("channels")
         with td.Server(c, budget, inflight) as srv:
             outs, tickets = [], []
