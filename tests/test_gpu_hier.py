@@ -35,6 +35,16 @@ def oracle_pair(weights, child, parent, parent_seed=0):
     return Model(weights(child), parent=Model(weights(parent, seed=parent_seed)))
 
 
+_UNET_PAIR_REF = {}
+
+
+def unet_pair_reference(weights):
+    """FP64 oracle of the UNet pair on the region the FP32 and BF16 checks share."""
+    if "ref" not in _UNET_PAIR_REF:
+        _UNET_PAIR_REF["ref"] = planar(sample(oracle_pair(weights, "c1h", "cc"), 3, -20, 11, 48, 40, 0))
+    return _UNET_PAIR_REF["ref"]
+
+
 @pytest.mark.parametrize("seed,region,level", [(0, (-37, -21, 23, 17), 0), (4, (1000003, -999985, 40, 9), 0),
                                                (2, (-5, 9, 31, 33), 3)])
 def test_linear_gaussian_pair_matches_oracle(pair, weights, seed, region, level):
@@ -74,8 +84,7 @@ def test_conditioned_unet_denoiser_matches_oracle(pair, weights, k):
 def test_unet_pair_sampler_matches_oracle(pair, weights):
     c, _ = pair("c1h", "cc")
     got = c.sample_region(3, -20, 11, 48, 40, 0)
-    ref = planar(sample(oracle_pair(weights, "c1h", "cc"), 3, -20, 11, 48, 40, 0))
-    assert rel_l2(got, ref) <= 1e-4
+    assert rel_l2(got, unet_pair_reference(weights)) <= 1e-4
 
 
 def test_unet_pair_seed_consistency_bit_exact(pair):
@@ -139,3 +148,17 @@ def test_conditioning_errors(weights):
             child.denoise_windows(x, 0, torch.empty_like(x))   # conditioning missing
         with pytest.raises(td.TDError):
             other.denoise_windows(x, 0, torch.empty_like(x), x)  # unconditioned model given conditioning
+
+
+def test_bf16_pair_close_to_oracle(weights):
+    """Both stages with BF16 convolutions (the serving configuration)."""
+    require_gpu()
+    from paper_2512_08309_amd import td
+    with td.Context(0) as p, td.Context(0) as c:
+        p.load_weights(weights("cc")).set_option("precision", 1)
+        c.load_weights(weights("c1h")).set_option("precision", 1)
+        c.set_conditioning(p)
+        got = c.sample_region(3, -20, 11, 48, 40, 0)
+    err = rel_l2(got, unet_pair_reference(weights))
+    print("bf16 pair rel L2 %.3e" % err)
+    assert err <= 2e-2

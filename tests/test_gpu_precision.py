@@ -44,7 +44,8 @@ HEIGHT_BARS = {1: 2e-2, 2: 8e-2}
 
 
 @pytest.mark.parametrize("prec", [1, 2])
-@pytest.mark.parametrize("config,k,n", [("c1", 0, 8), ("c1", 5, 8), ("c2", 0, 2), ("c2", 15, 2)])
+@pytest.mark.parametrize("config,k,n", [("c1", 0, 8), ("c1", 5, 8), ("c2", 0, 2), ("c2", 15, 2), ("cc", 0, 4),
+                                        ("cc", 6, 4)])
 def test_lowp_denoiser_close_to_oracle(lp_ctx, weights, config, k, n, prec):
     import torch
     from oracle.tdw import read_tdw
