@@ -20,6 +20,11 @@ TEST INFRASTRUCTURE (oracle).
   runs several window-local Euler steps, oracle.schedule.level_steps).
 * J_T uses the noise counter word the header names ("noise_step", default
   0), so that the stages of a hierarchy draw independent noise.
+* Consistency sampling (oracle.schedule): Phi of step k is D(x; s_k) plus
+  s_{k+1} G(step = k + 1) on the window's pixels.  With a judge (Model.judge
+  = (teacher, threshold)), a window whose denoised estimate differs from the
+  teacher's one-step estimate D_teacher(x; s_k) by more than the threshold
+  in RMS over the window takes the teacher's estimate instead.
 * Hierarchy (Sec. 5.1; DAGs of infinite tensors, infinite-tensor appendix):
   a model whose header has "cond" = {channels, factor f} is the child of a
   parent model (Model.parent).  Window i of the child receives, besides
@@ -38,7 +43,7 @@ query-order independence.
 import numpy as np
 
 from .noise import noise_region
-from .schedule import blend_points, euler_factor, level_steps, sigmas
+from .schedule import blend_points, euler_factor, level_steps, sampler_sigmas
 from .tdw import read_tdw
 from .unet import make_denoiser
 from .windows import cone, kappa_list, weight_map
@@ -65,7 +70,10 @@ class Model:
         win = h["window"]
         self.H, self.s, self.o, self.eps = win["size"], win["stride"], win["offset"], win["eps"]
         sp = h["sampler"]
-        self.sched = sigmas(self.steps, sp["sigma_max"], sp["sigma_min"], sp["rho"])
+        self.consistency = sp.get("kind", "edm") == "consistency"
+        self.sched = sampler_sigmas(sp)
+        self.judge = None          # (teacher Model, RMS threshold) for consistency sampling
+        self.fallbacks = 0
         self.W = weight_map(self.H, self.eps)
         self.denoiser = make_denoiser(h, self.tensors)
         self.phi_calls = 0
@@ -101,7 +109,18 @@ def cond_windows(src, windows, model):
     return np.stack(out)
 
 
-def level_step(model, j_next, region_next, region, windows, t, cond_src=None):
+def judged(model, D, x, sigma, windows, cond):
+    """The student's estimate per window, or the teacher's where their RMS
+    difference over the window exceeds the threshold."""
+    teacher, thr = model.judge
+    DT = teacher.denoiser(x, sigma, windows, cond if teacher.cond else None)
+    r = np.sqrt(((D - DT) ** 2).mean(axis=(1, 2, 3)))
+    use = r > thr
+    model.fallbacks += int(use.sum())
+    return np.where(use[:, None, None, None], DT, D)
+
+
+def level_step(model, j_next, region_next, region, windows, t, cond_src=None, seed=None):
     """J_t on `region` from J_{t+1} on `region_next` using the given windows."""
     H = model.H
     x0, y0, w, h = region
@@ -119,7 +138,16 @@ def level_step(model, j_next, region_next, region, windows, t, cond_src=None):
         for k in level_steps(model.points, t):
             sig, sig_next = model.sched[k], model.sched[k + 1]
             D = model.denoiser(phi, sig, windows, cond)
-            phi = phi + euler_factor(sig, sig_next) * (phi - D)
+            if not model.consistency:
+                phi = phi + euler_factor(sig, sig_next) * (phi - D)
+                continue
+            if model.judge is not None:
+                D = judged(model, D, phi, sig, windows, cond)
+            phi = D
+            if sig_next > 0:
+                phi = phi + sig_next * np.stack([
+                    noise_region(seed, ix * model.s + model.o, iy * model.s + model.o, H, H, model.C, k + 1)
+                    for ix, iy in windows]).astype(np.float64)
         model.phi_calls += len(windows)
         for n, (ix, iy) in enumerate(windows):
             ox, oy = ix * model.s + model.o, iy * model.s + model.o
@@ -157,7 +185,7 @@ def sample(model, seed, x0, y0, w, h, level):
     src = conditioning(model, seed, regions[top]) if (model.cond and top > level) else None
     for t in range(top - 1, level - 1, -1):
         j = level_step(model, j, regions[t + 1], regions[t], kappa_list(regions[t], model.H, model.s, model.o), t,
-                       src)
+                       src, seed)
     return j
 
 
@@ -176,6 +204,6 @@ def sample_levels(model, seed, x0, y0, w, h, level=0):
     src = conditioning(model, seed, rK) if model.cond else None
     for t in range(K - 1, level - 1, -1):
         j = level_step(model, j, regions[t + 1], regions[t], kappa_list(regions[t], model.H, model.s, model.o), t,
-                       src)
+                       src, seed)
         out[t] = _crop(j, regions[t], region).copy()
     return out

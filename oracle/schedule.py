@@ -17,6 +17,14 @@ The reading used here is the EDM sampler of Karras et al. (2022):
   the header's "blend" list; level t then holds the state at
   sigma_{b_{T-t}} and its Phi runs the Euler steps b_{T-t-1} .. b_{T-t}-1
   on the window alone.
+* Few-step consistency sampling (Sec. 3.4 lets Phi be a few-step
+  consistency model; the paper's core model takes two steps with the
+  intermediate sigma 0.35, implementation-details table): the header gives
+  "kind": "consistency" and the noise levels "sigmas" [s_0 > ... > s_{K-1}],
+  with s_K = 0.  Step k maps x to D(x; s_k) + s_{k+1} G(seed, ., ., c,
+  step = k + 1): the denoised estimate re-noised to the next level with
+  fresh coordinate-hashed noise (multistep consistency sampling, Song et al.
+  2023).  Every step is blended (T = K).
 
 Pins: the schedule's end points and monotonicity; the linear-Gaussian
 closed form of the whole sampler (tests/test_oracle_sampler.py) fixes the
@@ -24,6 +32,18 @@ level indexing, the Euler factor and the preconditioning-free path, for
 every blend schedule.
 """
 import math
+
+
+def sampler_sigmas(sampler):
+    """[sigma_0, ..., sigma_{K-1}, 0] of either sampler kind."""
+    if sampler.get("kind", "edm") == "consistency":
+        s = [float(v) for v in sampler["sigmas"]]
+        if not s or any(v <= 0 for v in s) or any(a <= b for a, b in zip(s, s[1:])):
+            raise ValueError("consistency sigmas must be positive and decreasing")
+        if len(s) != sampler["steps"] or "blend" in sampler:
+            raise ValueError("consistency sampling blends every one of its steps")
+        return s + [0.0]
+    return sigmas(sampler["steps"], sampler["sigma_max"], sampler["sigma_min"], sampler["rho"])
 
 
 def sigmas(steps, sigma_max, sigma_min, rho):

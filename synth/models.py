@@ -18,6 +18,9 @@ workloads the method is measured on:
             word 2); ``c1h`` is ``c1`` conditioned on it (its final latent,
             nearest-upsampled 8x, concatenated to the input).
 * ``lgc``, ``lgh``: the linear-Gaussian pair with the same wiring.
+* ``s2``  : the half-width student of ``c2`` (64/128/128/256), two-step
+            consistency sampling at sigma 80 and 0.35; ``lgs`` is an analytic
+            two-step model (prior std 0.7) whose teacher stand-in is ``lg``.
 
 Initialisation: every tensor is Gaussian from numpy's PCG64 seeded with the
 given seed, drawn in file order.  Conv / linear weights ~ N(0, 1/fan_in);
@@ -81,6 +84,20 @@ CONFIGS["lgh"] = {
     "sampler": dict(SAMPLER_EDM, steps=8),
     "window": {"size": 32, "stride": 16, "offset": 0, "eps": 0.01},
     "cond": {"channels": 1, "factor": 8},
+}
+# few-step students (consistency sampling: two steps, intermediate sigma 0.35)
+CONSISTENCY_2 = {"kind": "consistency", "steps": 2, "sigmas": [80.0, 0.35], "sigma_data": 0.5}
+CONFIGS["s2"] = {
+    "denoiser": {"kind": "unet", "in_channels": 4, "channels": [64, 128, 128, 256], "num_res_blocks": 2,
+                 "attn_levels": [3], "mid_attn": True, "num_heads": 8, "gn_groups": 32, "gn_eps": 1e-5,
+                 "emb_mult": 4, "pe_max_period": 10000.0},
+    "sampler": dict(CONSISTENCY_2),
+    "window": {"size": 64, "stride": 32, "offset": 0, "eps": 0.01},
+}
+CONFIGS["lgs"] = {
+    "denoiser": {"kind": "linear_gaussian", "in_channels": 4, "prior_std": 0.7},
+    "sampler": dict(CONSISTENCY_2),
+    "window": {"size": 32, "stride": 16, "offset": 0, "eps": 0.01},
 }
 # truncated T (blend only after the listed schedule indices)
 for _name, _base, _blend in [("c1t2", "c1", [0, 4, 8]), ("lgt2", "lg", [0, 3, 8]), ("c2t2", "c2", [0, 10, 20]),
