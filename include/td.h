@@ -58,6 +58,8 @@ typedef struct {
   uint64_t queries;       /* td_sample_region* calls served                */
   uint64_t denoiser_evals;/* network evaluations (windows x Euler steps)   */
   uint64_t windows_evaluated[64];
+  uint64_t judge_fallbacks;/* consistency windows that took the teacher's  */
+                           /* estimate (td_set_judge)                      */
 } td_cache_stats_t;
 
 /* Elevation query level: decoded height in metres on full-resolution pixels
@@ -93,6 +95,23 @@ td_status td_load_weights(td_ctx *ctx, const char *path);
  * a cycle or another device; a child query without a linked parent whose
  * channels equal C_y gives TD_E_STATE. */
 td_status td_set_conditioning(td_ctx *child, td_ctx *parent);
+
+/* Few-step consistency sampling with a fallback (Sec. 3.4 lets Phi be a
+ * few-step consistency model; the paper's distilled core model takes two
+ * steps): for a model whose sampler kind is "consistency", every window of
+ * every step is also denoised by `teacher` at the same noise level (one
+ * teacher network evaluation), and a window whose estimate differs from the
+ * teacher's by more than `threshold` in RMS over the window (all pixels and
+ * channels, FP32) takes the teacher's estimate; td_cache_stats counts those
+ * windows in judge_fallbacks.  The teacher needs the student's channels and
+ * window layout; its network runs on the student's stream in the teacher's
+ * workspace, ordered after the teacher's own work (do not query the teacher
+ * from another thread meanwhile).  NULL teacher turns the judge off.
+ * Clears the student's cache; reloading the teacher clears it again at the
+ * student's next query.  TD_E_INVAL if the student is not a consistency
+ * model, threshold < 0 or the devices differ; TD_E_STATE at query time if
+ * the teacher's layout does not match. */
+td_status td_set_judge(td_ctx *student, td_ctx *teacher, float threshold);
 
 /* J_level[R] for seed `seed` (Alg. 1 applied recursively from J_T = sigma_0 G).
  * level in [0, T] (T = blend levels, "levels" in td_get_info; T = sampler

@@ -74,6 +74,7 @@ class Model:
         self.sched = sampler_sigmas(sp)
         self.judge = None          # (teacher Model, RMS threshold) for consistency sampling
         self.fallbacks = 0
+        self.residuals = []        # the judge's RMS differences, in evaluation order
         self.W = weight_map(self.H, self.eps)
         self.denoiser = make_denoiser(h, self.tensors)
         self.phi_calls = 0
@@ -115,6 +116,7 @@ def judged(model, D, x, sigma, windows, cond):
     teacher, thr = model.judge
     DT = teacher.denoiser(x, sigma, windows, cond if teacher.cond else None)
     r = np.sqrt(((D - DT) ** 2).mean(axis=(1, 2, 3)))
+    model.residuals.extend(float(v) for v in r)
     use = r > thr
     model.fallbacks += int(use.sum())
     return np.where(use[:, None, None, None], DT, D)

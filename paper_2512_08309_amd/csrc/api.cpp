@@ -213,6 +213,13 @@ struct td_ctx {
   float* cond = nullptr;      // parent latent of the current query, [h][w][Cc]
   size_t cond_cap = 0;
   hipEvent_t xev = nullptr;   // orders this stream and the parent's
+  // consistency sampling: the teacher whose one-step estimate judges ours
+  td_ctx* judge = nullptr;
+  std::vector<td_ctx*> judged_by;
+  uint64_t judge_gen = 0;
+  float judge_thr = 0.f;
+  unsigned long long* d_fallbacks = nullptr;   // device counter
+  uint64_t fallbacks_base = 0;
 };
 
 namespace td {
@@ -231,6 +238,16 @@ void grow(float*& p, size_t& cap, size_t n) {
 
 void need_model(td_ctx* c) { TD_CHECK(c->model, TD_E_STATE, "no weights loaded"); }
 
+// Windows that took the judge's estimate since the context was made.
+uint64_t read_fallbacks(td_ctx* c) {
+  if (!c->d_fallbacks) return 0;
+  unsigned long long v = 0;
+  TD_HIP(hipSetDevice(c->device));
+  TD_HIP(hipStreamSynchronize(c->stream));
+  TD_HIP(hipMemcpy(&v, c->d_fallbacks, sizeof(v), hipMemcpyDeviceToHost));
+  return (uint64_t)v;
+}
+
 // Drops every cached contribution (none may be pinned by a query in flight).
 void drop_cache(td_ctx* c) {
   for (auto& kv : c->map) c->pool.give(kv.second.slot);
@@ -246,9 +263,47 @@ Region region_union(const Region& a, const Region& b) {
   return Region{x0, y0, x1 - x0, y1 - y0};
 }
 
+void check_judge(td_ctx* c, bool may_clear) {
+  td_ctx* j = c->judge;
+  if (!j) {
+    c->model->set_judge(nullptr, 0.f, nullptr);
+    return;
+  }
+  const ModelDesc& d = c->model->d;
+  TD_CHECK(d.consistency, TD_E_STATE, "a judge applies to consistency sampling only");
+  TD_CHECK(j->model, TD_E_STATE, "the judge context has no weights");
+  const ModelDesc& t = j->model->d;
+  TD_CHECK(t.C == d.C && t.H == d.H && t.S == d.S && t.O == d.O, TD_E_STATE,
+           "judge and student must share channels and window layout");
+  TD_CHECK(!t.Cc || (t.Cc == d.Cc && t.cond_factor == d.cond_factor), TD_E_STATE,
+           "a conditioned judge needs the student's conditioning");
+  if (c->judge_gen != j->gen) {
+    TD_CHECK(may_clear || c->map.empty(), TD_E_STATE, "the judge model changed while queries are in flight");
+    drop_cache(c);
+    c->judge_gen = j->gen;
+  }
+  c->model->set_judge(j->model.get(), c->judge_thr, c->d_fallbacks);
+}
+
+// Orders the judge's stream around work on c's stream that uses the judge's
+// model (before: after the judge's own work; after: the judge waits).
+void judge_fence(td_ctx* c, bool before) {
+  td_ctx* j = c->judge;
+  if (!j) return;
+  if (before) {
+    TD_HIP(hipEventRecord(j->xev, j->stream));
+    TD_HIP(hipStreamWaitEvent(c->stream, j->xev, 0));
+  } else {
+    TD_HIP(hipEventRecord(j->xev, c->stream));
+    TD_HIP(hipStreamWaitEvent(j->stream, j->xev, 0));
+  }
+}
+
 // A conditioned model needs its parent; its cache is only valid for the
-// parent's current generation.  `may_clear`: no query holds pins.
+// parent's current generation.  `may_clear`: no query holds pins.  Also
+// refreshes the consistency judge.
 void check_parent(td_ctx* c, bool may_clear) {
+  check_judge(c, may_clear);
   const ModelDesc& d = c->model->d;
   if (!d.Cc) return;
   td_ctx* p = c->parent;
@@ -321,6 +376,14 @@ void blend_into(td_ctx* c, Arena& arena, uint64_t seed, const Level& lv, const R
   WinGeom g{d.H, d.S, d.C};
   launch_blend(c->stream, g, (int)(r.x0 - bx), (int)(r.y0 - by), (int)r.w, (int)r.h, (int)lv.k.nx(),
                (int)lv.k.ny(), grid, c->model->w1d(), layout, out);
+  if (d.consistency) {
+    // level t came from step K-t-1: its state is re-noised to sigma_{K-t}
+    // with fresh noise on counter word K-t (zero at the final level)
+    const int kn = d.K - lv.t;
+    if (d.sched[kn] > 0)
+      launch_noise(c->stream, seed, r.x0, r.y0, (int)r.w, (int)r.h, d.C, (uint32_t)kn, (float)d.sched[kn], layout,
+                   out, 1);
+  }
 }
 
 int auto_batch(td_ctx* c) {
@@ -569,6 +632,7 @@ void sample_any(td_ctx* c, uint64_t seed, int64_t x0, int64_t y0, int32_t w, int
   }
   c->arena.reset();
   check_parent(c, true);
+  judge_fence(c, true);
   if (level == TD_LEVEL_HEIGHT) {
     TD_CHECK(out_len >= (size_t)w * h, TD_E_INVAL, "output buffer too small");
     Region full{x0, y0, w, h};
@@ -583,6 +647,7 @@ void sample_any(td_ctx* c, uint64_t seed, int64_t x0, int64_t y0, int32_t w, int
     sample_latent(c, c->arena, seed, Region{x0, y0, w, h}, level, 1, dev_out);
   }
   c->stats.bytes_budget = c->budget;
+  judge_fence(c, false);
   TD_HIP(hipEventRecord(c->done, c->stream));
   c->pending = true;
 }
@@ -651,6 +716,16 @@ void td_destroy(td_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (td_ctx* ch : c->children) ch->parent = nullptr;
+  for (td_ctx* st : c->judged_by) {
+    st->judge = nullptr;
+    if (st->model) st->model->set_judge(nullptr, 0.f, nullptr);
+  }
+  if (c->judge) {
+    auto& v = c->judge->judged_by;
+    v.erase(std::remove(v.begin(), v.end(), c), v.end());
+    (void)hipStreamSynchronize(c->judge->stream);
+  }
+  if (c->d_fallbacks) (void)hipFree(c->d_fallbacks);
   if (c->parent) {
     auto& v = c->parent->children;
     v.erase(std::remove(v.begin(), v.end(), c), v.end());
@@ -709,6 +784,44 @@ td_status td_set_conditioning(td_ctx* child, td_ctx* parent) {
     if (parent) parent->children.push_back(child);
     drop_cache(child);
     child->parent_gen = 0;
+  });
+}
+
+td_status td_set_judge(td_ctx* student, td_ctx* teacher, float threshold) {
+  if (!student) return TD_E_INVAL;
+  return guarded(student, [&] {
+    need_model(student);
+    TD_CHECK(student->model->d.consistency, TD_E_INVAL, "a judge applies to consistency sampling only");
+    TD_CHECK(teacher != student, TD_E_INVAL, "a model cannot judge itself");
+    TD_CHECK(!teacher || teacher->device == student->device, TD_E_INVAL, "judge and student must share a device");
+    TD_CHECK(threshold >= 0.f, TD_E_INVAL, "threshold must be >= 0");
+    if (teacher) {
+      TD_CHECK(teacher->model, TD_E_STATE, "the judge context has no weights");
+      const ModelDesc& d = student->model->d;
+      const ModelDesc& t = teacher->model->d;
+      TD_CHECK(t.C == d.C && t.H == d.H && t.S == d.S && t.O == d.O, TD_E_INVAL,
+               "judge and student must share channels and window layout");
+    }
+    TD_HIP(hipSetDevice(student->device));
+    TD_HIP(hipStreamSynchronize(student->stream));
+    student->pending = false;
+    if (student->judge) {
+      auto& v = student->judge->judged_by;
+      v.erase(std::remove(v.begin(), v.end(), student), v.end());
+    }
+    student->judge = teacher;
+    student->judge_thr = threshold;
+    student->judge_gen = 0;
+    if (teacher) {
+      teacher->judged_by.push_back(student);
+      if (!student->d_fallbacks) {
+        TD_HIP(hipMalloc(&student->d_fallbacks, sizeof(unsigned long long)));
+        TD_HIP(hipMemset(student->d_fallbacks, 0, sizeof(unsigned long long)));
+        student->fallbacks_base = 0;
+      }
+    }
+    drop_cache(student);
+    check_judge(student, true);
   });
 }
 
@@ -773,15 +886,18 @@ td_status td_cache_clear(td_ctx* c) {
     c->lru.clear();
     c->stats = td_cache_stats_t{};
     c->stats.bytes_budget = c->budget;
+    c->fallbacks_base = read_fallbacks(c);
   });
 }
 
 td_status td_cache_stats(td_ctx* c, td_cache_stats_t* out) {
   if (!c || !out) return TD_E_INVAL;
-  c->stats.bytes_used = c->model ? c->map.size() * c->pool.slot_bytes() : 0;
-  c->stats.bytes_budget = c->budget;
-  *out = c->stats;
-  return TD_OK;
+  return guarded(c, [&] {
+    c->stats.bytes_used = c->model ? c->map.size() * c->pool.slot_bytes() : 0;
+    c->stats.bytes_budget = c->budget;
+    c->stats.judge_fallbacks = read_fallbacks(c) - c->fallbacks_base;
+    *out = c->stats;
+  });
 }
 
 td_status td_cache_peek(td_ctx* c, uint64_t seed, int32_t level, int64_t ix, int64_t iy, float* out,
@@ -1353,9 +1469,11 @@ void server_round(td_server* s) {
   }
   need += (size_t)s->maxb * (48 + sizeof(CondSrc)) + 6 * 256;
   arena.ensure(need);
+  judge_fence(c, true);
   for (uint64_t t : s->active) advance(s, s->q[t], arena);
   if (run_round_batch(s, arena)) s->stats.rounds++;
   for (uint64_t t : s->active) advance(s, s->q[t], arena);
+  judge_fence(c, false);
   TD_HIP(hipEventRecord(s->ring_ev[slot], c->stream));
   s->ring_used[slot] = true;
   s->round++;

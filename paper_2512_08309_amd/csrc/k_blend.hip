@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) void lg_step_kernel(int H, int C, const float*
                                                       int canvas_w, const int* __restrict__ origins,
                                                       const int* __restrict__ widx,
                                                       const float* __restrict__ cond, int cc, float a_post,
-                                                      float c_euler, const float* __restrict__ w1d,
+                                                      float c_euler, int direct, const float* __restrict__ w1d,
                                                       float* const* __restrict__ slots, int mode,
                                                       float* __restrict__ dout) {
   int b = blockIdx.y;
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void lg_step_kernel(int H, int C, const float*
     dout[(size_t)b * H * H * C + idx] = d;
     return;
   }
-  float phi = x + c_euler * (x - d);
+  float phi = direct ? d : x + c_euler * (x - d);
   if (mode == 2) dout[(size_t)b * H * H * C + idx] = phi;
   else slots[b][idx] = (w1d[u] * w1d[v]) * phi;
 }
@@ -150,7 +150,51 @@ __global__ __launch_bounds__(256) void cond_gather_kernel(const CondSrc* __restr
   out[(size_t)b * per + e] = s.base[((size_t)py * s.pitch + px) * cc + c];
 }
 
+// Judge: one workgroup per window.  Fixed-order reduction (thread-strided
+// partial sums, then a fixed tree), so the decision does not depend on the
+// batch a window is in.
+__global__ __launch_bounds__(256) void judge_kernel(const float* __restrict__ ds, const float* __restrict__ dt,
+                                                    int H, int C, float thr, const float* __restrict__ w1d,
+                                                    float* const* __restrict__ slots,
+                                                    unsigned long long* __restrict__ counter) {
+  __shared__ float red[256];
+  const int b = blockIdx.x;
+  const int n = H * H * C;
+  const float* s = ds + (size_t)b * n;
+  const float* t = dt + (size_t)b * n;
+  float acc = 0.f;
+  for (int e = threadIdx.x; e < n; e += 256) {
+    const float q = s[e] - t[e];
+    acc += q * q;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const bool use_t = __builtin_sqrtf(red[0] / (float)n) > thr;
+  if (use_t && threadIdx.x == 0 && counter) atomicAdd(counter, 1ull);
+  const float* src = use_t ? t : s;
+  float* o = slots[b];
+  for (int e = threadIdx.x; e < n; e += 256) {
+    const int p = e / C;
+    const int v = p / H, u = p - v * H;
+    o[e] = (w1d[u] * w1d[v]) * src[e];
+  }
+}
+
 }  // namespace
+
+void launch_judge(hipStream_t st, const float* ds, const float* dt, int nwin, int H, int C, float thr,
+                  const float* w1d, float* const* slots, unsigned long long* counter) {
+  if (!nwin) return;
+  prof_begin(st);
+  hipLaunchKernelGGL(judge_kernel, dim3(nwin), dim3(256), 0, st, ds, dt, H, C, thr, w1d, slots, counter);
+  TD_LAUNCHED();
+  const double n = (double)nwin * H * H * C;
+  prof_end(st, K_BLEND, 3.0 * n, 12.0 * n);
+}
 
 void launch_cond_gather(hipStream_t st, const CondSrc* src, int nb, int H, int cc, int factor, float* out) {
   if (!nb) return;
@@ -194,7 +238,7 @@ void launch_blend(hipStream_t st, const WinGeom& g, int rx0, int ry0, int w, int
 void launch_lg_step(hipStream_t st, const WinGeom& g, const float* canvas, int canvas_w,
                     const int* origins, const int* widx, const float* cond, int cc, int nwin,
                     double prior_std, double sigma,
-                    float c_euler, const float* w1d, float* const* slots, int mode, float* dout) {
+                    float c_euler, int direct, const float* w1d, float* const* slots, int mode, float* dout) {
   if (!nwin) return;
   TD_CHECK(cc == 0 || cond, -5, "conditioned denoiser run without conditioning");
   int per = g.size * g.size * g.channels;
@@ -202,7 +246,7 @@ void launch_lg_step(hipStream_t st, const WinGeom& g, const float* canvas, int c
   float a_post = (float)(s2 / (s2 + sigma * sigma));
   prof_begin(st);
   hipLaunchKernelGGL(lg_step_kernel, dim3((per + 255) / 256, nwin), dim3(256), 0, st, g.size, g.channels,
-                     canvas, canvas_w, origins, widx, cond, cc, a_post, c_euler, w1d, slots, mode, dout);
+                     canvas, canvas_w, origins, widx, cond, cc, a_post, c_euler, direct, w1d, slots, mode, dout);
   TD_LAUNCHED();
   prof_end(st, K_LG, 6.0 * per * nwin, 8.0 * per * nwin);
 }

@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void conv_out_kernel(OutArgs a) {
     if (a.mode == 1) {
       a.dout[(((size_t)b * H + v) * H + u) * CO + o] = d;
     } else {
-      float phi = x + a.c_euler * (x - d);
+      float phi = a.direct ? d : x + a.c_euler * (x - d);
       if (a.mode == 2) a.dout[(((size_t)b * H + v) * H + u) * CO + o] = phi;
       else a.slots[b][((size_t)v * H + u) * CO + o] = wuv * phi;
     }

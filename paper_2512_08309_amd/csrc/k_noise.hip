@@ -104,7 +104,7 @@ __device__ __forceinline__ void box_muller(uint32_t ra, uint32_t rb, float* ev, 
 
 __global__ __launch_bounds__(256) void noise_kernel(uint32_t k0, uint32_t k1, int64_t x0, int64_t y0,
                                                     int w, int h, int C, uint32_t step, float scale,
-                                                    int layout, float* __restrict__ out) {
+                                                    int layout, int accumulate, float* __restrict__ out) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)w * h) return;
   int ry = (int)(idx / w), rx = (int)(idx - (int64_t)ry * w);
@@ -117,7 +117,12 @@ __global__ __launch_bounds__(256) void noise_kernel(uint32_t k0, uint32_t k1, in
     box_muller(c[0], c[1], &z[0], &z[1]);
     box_muller(c[2], c[3], &z[2], &z[3]);
     int nc = C - cq < 4 ? C - cq : 4;
-    if (layout == 0) {
+    if (accumulate) {
+      for (int j = 0; j < nc; ++j) {
+        float* o = layout == 0 ? out + idx * C + cq + j : out + (int64_t)(cq + j) * w * h + idx;
+        *o = *o + z[j] * scale;
+      }
+    } else if (layout == 0) {
       float* o = out + idx * C + cq;
       if (nc == 4 && (C & 3) == 0) {
         *reinterpret_cast<float4*>(o) = make_float4(z[0] * scale, z[1] * scale, z[2] * scale, z[3] * scale);
@@ -138,15 +143,15 @@ __global__ void fill_kernel(float* p, size_t n, float v) {
 }  // namespace
 
 void launch_noise(hipStream_t st, uint64_t seed, int64_t x0, int64_t y0, int w, int h, int C,
-                  uint32_t step, float scale, int layout, float* out) {
+                  uint32_t step, float scale, int layout, float* out, int accumulate) {
   int64_t n = (int64_t)w * h;
   if (n == 0) return;
   int blocks = (int)((n + 255) / 256);
   prof_begin(st);
   hipLaunchKernelGGL(noise_kernel, dim3(blocks), dim3(256), 0, st, (uint32_t)(seed & 0xFFFFFFFFu),
-                     (uint32_t)(seed >> 32), x0, y0, w, h, C, step, scale, layout, out);
+                     (uint32_t)(seed >> 32), x0, y0, w, h, C, step, scale, layout, accumulate, out);
   TD_LAUNCHED();
-  prof_end(st, K_NOISE, 0.0, 4.0 * n * C);
+  prof_end(st, K_NOISE, 0.0, (accumulate ? 8.0 : 4.0) * n * C);
 }
 
 void launch_fill(hipStream_t st, float* p, size_t n, float v) {

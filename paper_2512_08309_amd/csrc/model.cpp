@@ -166,9 +166,27 @@ void Model::load(const std::string& path, hipStream_t st) {
   d.C = (int)dn.at("in_channels").integer();
   const Json& sp = h.at("sampler");
   d.K = (int)sp.at("steps").integer();
-  d.smax = sp.at("sigma_max").num();
-  d.smin = sp.at("sigma_min").num();
-  d.rho = sp.at("rho").num();
+  d.consistency = sp.has("kind") && sp.at("kind").str() == "consistency";
+  if (sp.has("kind"))
+    TD_CHECK(d.consistency || sp.at("kind").str() == "edm", -5, "weight header: unknown sampler kind");
+  if (d.consistency) {
+    const auto& sg = sp.at("sigmas").arr();
+    TD_CHECK((int)sg.size() == d.K && d.K >= 1, -5, "weight header: consistency sigmas must number steps");
+    d.sched.clear();
+    for (const Json& v : sg) d.sched.push_back(v.num());
+    for (int k = 0; k < d.K; ++k)
+      TD_CHECK(d.sched[k] > 0 && (k == 0 || d.sched[k] < d.sched[k - 1]), -5,
+               "weight header: consistency sigmas must be positive and decreasing");
+    d.sched.push_back(0.0);
+    d.smax = d.sched[0];
+    d.smin = d.sched[d.K - 1];
+    d.rho = 1;
+    TD_CHECK(!sp.has("blend"), -5, "weight header: consistency sampling blends every step");
+  } else {
+    d.smax = sp.at("sigma_max").num();
+    d.smin = sp.at("sigma_min").num();
+    d.rho = sp.at("rho").num();
+  }
   d.sigma_data = sp.at("sigma_data").num();
   d.noise_step = 0;
   if (sp.has("noise_step")) {
@@ -199,7 +217,9 @@ void Model::load(const std::string& path, hipStream_t st) {
            "weight header: bad sampler/window constants");
   TD_CHECK(d.factor == 8 && d.blur_radius >= 0 && d.blur_radius <= 64, -5, "weight header: unsupported decode");
   TD_CHECK(d.smax > d.smin && d.smin > 0 && d.rho > 0 && d.sigma_data > 0, -5, "weight header: bad schedule");
-  d.sched = edm_sigmas(d.K, d.smax, d.smin, d.rho);
+  if (!d.consistency) d.sched = edm_sigmas(d.K, d.smax, d.smin, d.rho);
+  // a re-noised level adds noise to every pixel, which needs every pixel covered
+  TD_CHECK(!d.consistency || d.S <= d.H, -5, "weight header: consistency sampling needs stride <= window size");
   d.points.clear();
   if (sp.has("blend")) {
     for (const Json& b : sp.at("blend").arr()) d.points.push_back((int)b.integer());
@@ -336,6 +356,10 @@ void Model::build_unet(const std::map<std::string, std::vector<float>>& host,
   const float* l1b = vec("emb.lin1.bias", emb);
   const float* l2w = upload(get("emb.lin2.weight", {emb, emb}));
   const float* l2b = vec("emb.lin2.bias", emb);
+  emb_l1w_ = l1w;
+  emb_l1b_ = l1b;
+  emb_l2w_ = l2w;
+  emb_l2b_ = l2b;
   launch_gemv(st, l1w, l1b, nullptr, pe, e1, d.K, c0, emb, 1);
   launch_gemv(st, l2w, l2b, nullptr, e1, e2, d.K, emb, emb, 1);
 
@@ -408,25 +432,65 @@ void Model::build_unet(const std::map<std::string, std::vector<float>>& host,
   out_w_ = conv_layout("out.conv.weight", d.C, c, 3);
   out_b_ = vec("out.conv.bias", d.C);
 
-  // bias_eff[block][k][cout] = conv1.bias + Lin_emb(emb_k)
+  // bias_eff[block][k][cout] = conv1.bias + Lin_emb(emb_k), with kExtraSigmas
+  // more rows per block for noise levels off the schedule (sigma_slot)
   size_t total = 0;
-  for (auto& o : order) total += (size_t)d.K * o.second;
+  for (auto& o : order) total += (size_t)(d.K + kExtraSigmas) * o.second;
   bias_eff_ = dalloc(total);
   size_t off = 0;
   for (auto& o : order) {
     ResBlockW& w = rb_[o.first];
     w.bias_off = off;
-    const float* ew = upload(get(o.first + "emb.weight", {o.second, emb}));
-    const float* eb = vec(o.first + "emb.bias", o.second);
-    const float* b1 = vec(o.first + "conv1.bias", o.second);
-    launch_gemv(st, ew, eb, b1, e2, bias_eff_ + off, d.K, emb, o.second, 0);
-    off += (size_t)d.K * o.second;
+    w.emb_w = upload(get(o.first + "emb.weight", {o.second, emb}));
+    w.emb_b = vec(o.first + "emb.bias", o.second);
+    w.b1 = vec(o.first + "conv1.bias", o.second);
+    launch_gemv(st, w.emb_w, w.emb_b, w.b1, e2, bias_eff_ + off, d.K, emb, o.second, 0);
+    off += (size_t)(d.K + kExtraSigmas) * o.second;
   }
+  emb_scratch_ = dalloc((size_t)c0 + 2 * emb + 1);
+}
+
+int Model::sigma_slot(hipStream_t st, double sigma) {
+  for (int k = 0; k < d.K; ++k)
+    if (d.sched[k] == sigma) return k;
+  for (size_t j = 0; j < extra_sigma_.size(); ++j)
+    if (extra_sigma_[j] == sigma) return d.K + (int)j;
+  TD_CHECK(sigma > 0, -1, "noise level must be positive");
+  TD_CHECK(extra_sigma_.size() < (size_t)kExtraSigmas, -1, "too many noise levels off the schedule");
+  const int k = d.K + (int)extra_sigma_.size();
+  if (d.kind == "unet") {
+    const int c0 = d.ch[0], emb = d.emb_mult * c0;
+    float* pe = emb_scratch_;
+    float* e1 = pe + c0;
+    float* e2 = e1 + emb;
+    float* cn = e2 + emb;
+    const float h = (float)(0.25 * std::log(sigma));
+    TD_HIP(hipMemcpyAsync(cn, &h, sizeof(float), hipMemcpyHostToDevice, st));
+    launch_pos_emb(st, cn, 1, c0, (float)d.pe_max_period, pe);
+    launch_gemv(st, emb_l1w_, emb_l1b_, nullptr, pe, e1, 1, c0, emb, 1);
+    launch_gemv(st, emb_l2w_, emb_l2b_, nullptr, e1, e2, 1, emb, emb, 1);
+    for (auto& kv : rb_) {
+      const ResBlockW& w = kv.second;
+      launch_gemv(st, w.emb_w, w.emb_b, w.b1, e2, bias_eff_ + w.bias_off + (size_t)k * w.cout, 1, emb, w.cout, 0);
+    }
+    TD_HIP(hipStreamSynchronize(st));   // the host value above must stay alive until copied
+  }
+  extra_sigma_.push_back(sigma);
+  return k;
+}
+
+double Model::sigma_of(int k) const { return k < d.K ? d.sched[k] : extra_sigma_.at(k - d.K); }
+
+void Model::set_judge(Model* teacher, float threshold, unsigned long long* counter) {
+  judge_ = teacher;
+  judge_thr_ = threshold;
+  judge_count_ = counter;
 }
 
 size_t Model::workspace_bytes_per_window() const {
   const size_t state = (d.T < d.K ? (size_t)d.H * d.H * d.C * sizeof(float) + 2 * sizeof(int) : 0) +
-                       (size_t)d.H * d.H * d.Cc * sizeof(float);
+                       (size_t)d.H * d.H * d.Cc * sizeof(float) +
+                       (d.consistency ? 2 * (size_t)d.H * d.H * d.C * sizeof(float) : 0);
   if (d.kind != "unet") return state;
   size_t f = 0;
   const int nl = (int)d.ch.size();
@@ -463,6 +527,8 @@ void Model::ensure_workspace(int max_batch) {
   state_ = nullptr;
   state_origins_ = nullptr;
   cond_ = d.Cc ? take((size_t)max_batch * d.H * d.H * d.Cc) : nullptr;
+  judge_s_ = d.consistency ? take((size_t)max_batch * d.H * d.H * d.C) : nullptr;
+  judge_t_ = d.consistency ? take((size_t)max_batch * d.H * d.H * d.C) : nullptr;
   if (d.T < d.K) {
     state_ = take((size_t)max_batch * d.H * d.H * d.C);
     state_origins_ = (int*)take((size_t)max_batch * 2);
@@ -715,17 +781,39 @@ void Model::run_level(hipStream_t st, const WindowBatch& wb, int t) {
 }
 
 void Model::run_batch(hipStream_t st, const WindowBatch& wb, int k) {
-  TD_CHECK(k >= 0 && k < d.K, -1, "sigma index out of range");
-  const double sigma = d.sched[k], sigma_next = d.sched[k + 1];
+  TD_CHECK(k >= 0 && k < d.K + (int)extra_sigma_.size(), -1, "sigma index out of range");
+  TD_CHECK(k < d.K || wb.mode == 1, -1, "off-schedule noise levels give raw estimates only");
+  if (judge_ && d.consistency && wb.mode == 0) {
+    // student and teacher estimates side by side, then the per-window choice
+    TD_CHECK(wb.n <= ws_batch_, -1, "batch larger than workspace");
+    WindowBatch s = wb;
+    s.mode = 1;
+    s.dout = judge_s_;
+    run_net(st, s, k);
+    WindowBatch t = wb;
+    t.mode = 1;
+    t.dout = judge_t_;
+    if (judge_->d.Cc != d.Cc) t.cond = nullptr;
+    judge_->ensure_workspace(std::max(judge_->max_batch(), wb.n));
+    judge_->run_batch(st, t, judge_->sigma_slot(st, d.sched[k]));
+    launch_judge(st, judge_s_, judge_t_, wb.n, d.H, d.C, judge_thr_, w1d_, wb.d_slots, judge_count_);
+    return;
+  }
+  run_net(st, wb, k);
+}
+
+void Model::run_net(hipStream_t st, const WindowBatch& wb, int k) {
+  const double sigma = sigma_of(k), sigma_next = k < d.K ? d.sched[k + 1] : 0.0;
   const double sd = d.sigma_data;
   const double s2 = sigma * sigma + sd * sd;
   const float c_skip = (float)(sd * sd / s2), c_out = (float)(sigma * sd / std::sqrt(s2));
   const float c_in = (float)(1.0 / std::sqrt(s2)), c_euler = (float)((sigma_next - sigma) / sigma);
+  const int direct = d.consistency ? 1 : 0;   // Phi = D (re-noising happens at the blend)
   WinGeom g{d.H, d.S, d.C};
   TD_CHECK(d.Cc == 0 || wb.cond, -6, "conditioned model run without its conditioning windows");
   if (d.kind == "linear_gaussian") {
     launch_lg_step(st, g, wb.canvas, wb.canvas_w, wb.d_origins, wb.d_widx, wb.cond, d.Cc, wb.n, d.prior_std,
-                   sigma, c_euler, w1d_, wb.d_slots, wb.mode, wb.dout);
+                   sigma, c_euler, direct, w1d_, wb.d_slots, wb.mode, wb.dout);
     return;
   }
   TD_CHECK(wb.n <= ws_batch_, -1, "batch larger than workspace");
@@ -810,6 +898,7 @@ void Model::run_batch(hipStream_t st, const WindowBatch& wb, int k) {
   oa.c_skip = c_skip;
   oa.c_out = c_out;
   oa.c_euler = c_euler;
+  oa.direct = direct;
   oa.w1d = w1d_;
   oa.slots = wb.d_slots;
   oa.mode = wb.mode;

@@ -27,7 +27,9 @@ struct ModelDesc {
   // latent, nearest-upsampled by cond_factor (0 channels: unconditioned)
   int Cc = 0, cond_factor = 0;
   uint32_t noise_step = 0;    // counter word of this model's J_T noise
-  // sampler
+  // sampler: EDM Euler, or few-step consistency sampling (Phi = D, the
+  // next level re-noised with G on counter word k + 1 at the blend)
+  bool consistency = false;
   int K = 0;
   double smax = 80, smin = 0.002, rho = 7, sigma_data = 0.5;
   std::vector<double> sched;  // sigma_0..sigma_{K-1}, 0
@@ -52,7 +54,8 @@ struct ResBlockW {
   bool has_skip = false;
   const float *gn1_g = nullptr, *gn1_b = nullptr, *w1 = nullptr, *gn2_g = nullptr, *gn2_b = nullptr;
   const float *w2 = nullptr, *b2 = nullptr, *wskip = nullptr, *bskip = nullptr;
-  size_t bias_off = 0;     // offset of this block's [K][cout] table in bias_eff
+  size_t bias_off = 0;     // offset of this block's [K + extra][cout] table in bias_eff
+  const float *emb_w = nullptr, *emb_b = nullptr, *b1 = nullptr;   // Lin_emb and conv1 bias
   // reduced precision: [cout][kp] BF16 weights (K = tap * cin + c_in)
   const uint16_t *w1_lp = nullptr, *w2_lp = nullptr, *wskip_lp = nullptr;
   int kp1 = 0, kp2 = 0, kps = 0;
@@ -91,8 +94,17 @@ class Model {
   ~Model();
   void load(const std::string& path, hipStream_t st);
   // One denoiser round of a batch (n <= max_batch) at schedule index k
-  // (sigma = sched[k]), Euler target sched[k+1].
+  // (sigma = sched[k]), Euler target sched[k+1]; k >= K selects a noise
+  // level added by sigma_slot (raw estimates, mode 1, only).
   void run_batch(hipStream_t st, const WindowBatch& b, int k);
+  // Index of noise level sigma: its schedule index, or a row of embedding
+  // biases computed on first use (at most kExtraSigmas such levels).
+  int sigma_slot(hipStream_t st, double sigma);
+  double sigma_of(int k) const;
+  // Consistency sampling with a teacher judge: a window whose estimate
+  // differs from the teacher's by more than `threshold` RMS takes the
+  // teacher's; `counter` (device) counts such windows.  teacher null: off.
+  void set_judge(Model* teacher, float threshold, unsigned long long* counter);
   // Phi of blend level t: the Euler steps points[T-t-1] .. points[T-t]-1 on
   // every window of the batch, the last one writing b.mode's output.
   void run_level(hipStream_t st, const WindowBatch& b, int t);
@@ -135,6 +147,15 @@ class Model {
   float *gn_scale_ = nullptr, *gn_shift_ = nullptr;
   double* gn_part_ = nullptr;
   float* cond_ = nullptr;         // conditioning windows of a batch
+  static constexpr int kExtraSigmas = 8;
+  std::vector<double> extra_sigma_;
+  const float *emb_l1w_ = nullptr, *emb_l1b_ = nullptr, *emb_l2w_ = nullptr, *emb_l2b_ = nullptr;
+  float* emb_scratch_ = nullptr;
+  Model* judge_ = nullptr;
+  float judge_thr_ = 0.f;
+  unsigned long long* judge_count_ = nullptr;
+  float *judge_s_ = nullptr, *judge_t_ = nullptr;   // student / teacher estimates of a batch
+  void run_net(hipStream_t st, const WindowBatch& b, int k);
   float* state_ = nullptr;        // window states between the steps of one Phi
   int* state_origins_ = nullptr;  // (0, b*H) for b < ws_batch_
 

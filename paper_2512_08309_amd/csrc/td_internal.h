@@ -57,10 +57,11 @@ struct WinGeom {
 };
 
 // Counter-hash Gaussian noise scaled by `scale` on a region.  layout 0:
-// [h][w][C] with row pitch w*C; layout 1: planar [C][h][w].
+// [h][w][C] with row pitch w*C; layout 1: planar [C][h][w].  accumulate:
+// out += scale * G instead of out = scale * G.
 void launch_noise(hipStream_t st, uint64_t seed, int64_t x0, int64_t y0,
                   int w, int h, int C, uint32_t step, float scale, int layout,
-                  float* out);
+                  float* out, int accumulate = 0);
 
 // Blend of cached window contributions:
 //   out(p) = sum_i V_i(p - o_i) / sum_i W(p - o_i)   (0 where no window covers p)
@@ -92,12 +93,20 @@ void launch_cond_gather(hipStream_t st, const CondSrc* src, int nb, int H, int c
 
 // Analytic linear-Gaussian denoiser + Euler step + weighting (see kernels).
 // cond (nullable): [nwin][H][H][cc] conditioning added to the prior mean.
+// direct: Phi = D (consistency sampling) instead of the Euler step.
 void launch_lg_step(hipStream_t st, const WinGeom& g, const float* canvas,
                     int canvas_w, const int* origins, const int* widx,
                     const float* cond, int cc,
                     int nwin, double prior_std, double sigma, float c_euler,
-                    const float* w1d, float* const* slots, int mode,
+                    int direct, const float* w1d, float* const* slots, int mode,
                     float* dout);
+
+// Teacher judge of consistency sampling: per window b, r = RMS over the
+// window of (ds - dt) ([nwin][H][H][C] each); the window's contribution
+// W (x) (r > thr ? dt : ds) goes to slots[b]; counter (device, nullable)
+// is incremented per window that took dt.
+void launch_judge(hipStream_t st, const float* ds, const float* dt, int nwin, int H, int C, float thr,
+                  const float* w1d, float* const* slots, unsigned long long* counter);
 
 struct ConvArgs {
   const float* src0;
@@ -194,6 +203,7 @@ struct OutArgs {
   int canvas_w;
   const int* origins;
   float c_skip, c_out, c_euler;
+  int direct;            // 1: Phi = D (consistency sampling)
   const float* w1d;
   float* const* slots;
   int mode;

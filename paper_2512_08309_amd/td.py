@@ -19,7 +19,7 @@ STATUS_NAMES = {0: "TD_OK", -1: "TD_E_INVAL", -2: "TD_E_NOMEM", -3: "TD_E_DEVICE
                 -5: "TD_E_FORMAT", -6: "TD_E_STATE"}
 
 # Every symbol include/td.h declares.
-EXPORTS = ["td_create", "td_destroy", "td_load_weights", "td_set_conditioning", "td_sample_region",
+EXPORTS = ["td_create", "td_destroy", "td_load_weights", "td_set_conditioning", "td_set_judge", "td_sample_region",
            "td_sample_region_async",
            "td_cache_set_budget", "td_cache_clear", "td_cache_stats", "td_cache_peek", "td_set_option",
            "td_get_info", "td_denoise_windows", "td_lap_decode", "td_kappa", "td_cone_windows", "td_kernel_stats",
@@ -31,7 +31,7 @@ class td_cache_stats_t(ctypes.Structure):
     _fields_ = [("hits", ctypes.c_uint64), ("misses", ctypes.c_uint64), ("evictions", ctypes.c_uint64),
                 ("bytes_used", ctypes.c_uint64), ("bytes_budget", ctypes.c_uint64), ("batches", ctypes.c_uint64),
                 ("queries", ctypes.c_uint64), ("denoiser_evals", ctypes.c_uint64),
-                ("windows_evaluated", ctypes.c_uint64 * 64)]
+                ("windows_evaluated", ctypes.c_uint64 * 64), ("judge_fallbacks", ctypes.c_uint64)]
 
 
 class td_kernel_stat_t(ctypes.Structure):
@@ -67,6 +67,7 @@ def _load():
         "td_destroy": ([vp], None),
         "td_load_weights": ([vp, ctypes.c_char_p], ctypes.c_int),
         "td_set_conditioning": ([vp, vp], ctypes.c_int),
+        "td_set_judge": ([vp, vp, ctypes.c_float], ctypes.c_int),
         "td_sample_region": ([vp, u64, i64, i64, i32, i32, i32, fp, sz], ctypes.c_int),
         "td_sample_region_async": ([vp, u64, i64, i64, i32, i32, i32, vp, sz, vp], ctypes.c_int),
         "td_cache_set_budget": ([vp, sz], ctypes.c_int),
@@ -187,6 +188,11 @@ def td_set_conditioning(child, parent):
     _check(child, lib.td_set_conditioning(child, parent))
 
 
+def td_set_judge(student, teacher, threshold):
+    """Teacher fallback for consistency sampling (teacher None turns it off)."""
+    _check(student, lib.td_set_judge(student, teacher, threshold))
+
+
 def td_denoise_windows(ctx, x_dev, k, out_dev, cond_dev=None):
     """x_dev, out_dev: contiguous float32 torch tensors [n][H][H][C] on the
     device; cond_dev: [n][H][H][C_y] for a conditioned model, else None."""
@@ -304,6 +310,12 @@ class Context:
 
     def load_weights(self, path):
         td_load_weights(self.ctx, path)
+        return self
+
+    def set_judge(self, teacher, threshold):
+        """teacher: Context whose one-step estimate judges this consistency model (None: off)."""
+        td_set_judge(self.ctx, teacher.ctx if teacher is not None else None, threshold)
+        self._judge = teacher
         return self
 
     def set_conditioning(self, parent):

@@ -34,7 +34,8 @@ def run_alone(td, torch, wpath, ppath, q):
 
 @pytest.mark.parametrize("config,inflight,budget,parent", [("c1", 6, 64 << 30, None), ("c1", 2, 200 << 20, None),
                                                            ("c1t2", 12, 64 << 30, None), ("lg", 4, 64 << 30, None),
-                                                           ("c1h", 6, 64 << 30, "cc"), ("lgh", 3, 64 << 30, "lgc")])
+                                                           ("c1h", 6, 64 << 30, "cc"), ("lgh", 3, 64 << 30, "lgc"),
+                                                           ("lgs", 5, 64 << 30, None)])
 def test_mix_equals_alone(weights, config, inflight, budget, parent):
     require_gpu()
     import torch

@@ -1,0 +1,156 @@
+"""GPU parity of two-step consistency sampling (the student's sampler) and
+of the teacher fallback judge, through the C-ABI, against the FP64 oracle.
+
+Bars: analytic model rel L2 <= 1e-6; the half-width UNet student <= 1e-4;
+judge decisions equal the oracle's (thresholds are placed in gaps of the
+oracle's residuals, so FP32 vs FP64 rounding cannot flip one); crops
+bit-exact.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_common import planar, rel_l2, require_gpu
+from oracle.sampler import Model, sample
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctxs(weights):
+    require_gpu()
+    from paper_2512_08309_amd import td
+    made = {}
+
+    def get(config):
+        if config not in made:
+            made[config] = td.Context(0).load_weights(weights(config))
+        return made[config]
+    yield get
+    for c in made.values():
+        c.close()
+
+
+@pytest.mark.parametrize("seed,region,level", [(0, (0, 0, 23, 17), 0), (3, (-37, 1000003, 40, 8), 0),
+                                               (5, (3, -4, 31, 29), 1)])
+def test_consistency_linear_gaussian_matches_oracle(ctxs, weights, seed, region, level):
+    c = ctxs("lgs")
+    c.set_judge(None, 0.0)
+    assert c.info("steps") == 2 and c.info("levels") == 2
+    got = c.sample_region(seed, *region, level)
+    assert rel_l2(got, planar(sample(Model(weights("lgs")), seed, *region, level))) <= 1e-6
+
+
+def gap_threshold(residuals):
+    """A threshold in the widest relative gap of the residuals."""
+    r = sorted(residuals)
+    best, thr = 0.0, r[0] * 0.5
+    for a, b in zip(r, r[1:]):
+        if a > 0 and b / a > 1 + best:
+            best, thr = b / a - 1, math.sqrt(a * b)
+    assert best > 1e-3, "no usable gap"
+    return thr
+
+
+def judged_reference(weights, student, teacher, seed, region):
+    """Oracle run with a threshold that no residual of that same run comes
+    within 0.1% of (later steps' residuals depend on earlier decisions, so
+    the threshold is re-placed until it is stable)."""
+    m = Model(weights(student))
+    m.judge = (Model(weights(teacher)), math.inf)
+    sample(m, seed, *region, 0)
+    thr = gap_threshold(m.residuals)
+    for _ in range(4):
+        m = Model(weights(student))
+        m.judge = (Model(weights(teacher)), thr)
+        ref = planar(sample(m, seed, *region, 0))
+        if min(abs(math.log(r / thr)) for r in m.residuals if r > 0) > 1e-3:
+            return m, thr, ref
+        thr = gap_threshold(m.residuals)
+    raise AssertionError("no stable threshold")
+
+
+@pytest.mark.parametrize("mode", ["all", "none", "mixed"])
+def test_linear_gaussian_judge_matches_oracle(ctxs, weights, mode):
+    c, t = ctxs("lgs"), ctxs("lg")
+    region = (-9, 40, 47, 33)
+    if mode == "mixed":
+        m, thr, ref = judged_reference(weights, "lgs", "lg", 2, region)
+    else:
+        thr = {"all": 0.0, "none": 1e30}[mode]
+        m = Model(weights("lgs"))
+        m.judge = (Model(weights("lg")), thr)
+        ref = planar(sample(m, 2, *region, 0))
+    c.set_judge(t, thr)
+    c.cache_clear()                 # counters from zero
+    try:
+        got = c.sample_region(2, *region, 0)
+        st = c.cache_stats()
+    finally:
+        c.set_judge(None, 0.0)
+    assert rel_l2(got, ref) <= 1e-6
+    assert st["judge_fallbacks"] == m.fallbacks and st["misses"] == m.phi_calls
+    if mode == "mixed":
+        assert 0 < m.fallbacks < m.phi_calls
+
+
+def test_unet_student_matches_oracle(ctxs, weights):
+    c = ctxs("s2")
+    got = c.sample_region(4, -20, 33, 40, 24, 0)
+    assert rel_l2(got, planar(sample(Model(weights("s2")), 4, -20, 33, 40, 24, 0))) <= 1e-4
+
+
+def test_unet_student_with_teacher_judge_matches_oracle(ctxs, weights):
+    c, t = ctxs("s2"), ctxs("c2")
+    m2, thr, ref = judged_reference(weights, "s2", "c2", 1, (7, 7, 16, 16))
+    c.set_judge(t, thr)
+    c.cache_clear()
+    try:
+        got = c.sample_region(1, 7, 7, 16, 16, 0)
+        st = c.cache_stats()
+    finally:
+        c.set_judge(None, 0.0)
+    assert rel_l2(got, ref) <= 1e-4
+    assert st["judge_fallbacks"] == m2.fallbacks
+
+
+def test_student_seed_consistency_bit_exact(ctxs):
+    c = ctxs("s2")
+    c.cache_clear()
+    big = c.sample_region(8, -50, -30, 120, 90, 0)
+    c.cache_clear()
+    c.set_option("batch", 3)
+    try:
+        small = c.sample_region(8, -21, 1, 45, 38, 0)
+    finally:
+        c.set_option("batch", 4096)
+    assert np.array_equal(small, big[:, 31:69, 29:74])
+
+
+def test_judge_errors(ctxs, weights):
+    from paper_2512_08309_amd import td
+    c1 = ctxs("c1")
+    with pytest.raises(td.TDError) as e:
+        c1.set_judge(ctxs("c2"), 0.05)                   # not a consistency model
+    assert e.value.status == td.TD_E_INVAL
+    s = ctxs("lgs")
+    with pytest.raises(td.TDError):
+        s.set_judge(s, 0.05)
+    with pytest.raises(td.TDError) as e:
+        s.set_judge(ctxs("c1"), 0.05)                    # 1 channel vs 4
+    assert e.value.status == td.TD_E_INVAL
+    s.cache_clear()
+    assert s.sample_region(0, 0, 0, 8, 8, 0).shape == (4, 8, 8)   # the failed call left no judge
+    assert s.cache_stats()["judge_fallbacks"] == 0
+    # a teacher reloaded with another layout is refused at query time
+    with td.Context(0) as t:
+        t.load_weights(weights("lg"))
+        s.set_judge(t, 0.05)
+        try:
+            t.load_weights(weights("c1"))
+            with pytest.raises(td.TDError) as e:
+                s.sample_region(0, 0, 0, 8, 8, 0)
+            assert e.value.status == td.TD_E_STATE
+        finally:
+            s.set_judge(None, 0.0)
