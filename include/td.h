@@ -183,6 +183,22 @@ td_status td_denoise_windows(td_ctx *ctx, const float *x_dev,
                              const float *cond_dev, int32_t n, int32_t k,
                              float *out_dev);
 
+/* The model's own sampler steps k0 .. k1-1 (0 <= k0 < k1 <= K, EDM Euler)
+ * on `n` windows independently, without blending: x_dev [n][H][H][C] holds
+ * the windows at sigma_k0, out_dev receives them at sigma_k1 (k1 = K: the
+ * sample).  With k0 = 0 and x = sigma_0 G this is the plain sampler on a
+ * single window (the teacher output of distillation).  out_dev may equal
+ * x_dev.  Synchronous.  TD_E_INVAL for consistency or conditioned models. */
+td_status td_denoise_steps(td_ctx *ctx, const float *x_dev, int32_t n, int32_t k0, int32_t k1, float *out_dev);
+
+/* scale * G(seed, x, y, c, step) on [x0, x0+w) x [y0, y0+h), written to
+ * dev_out as [h][w][channels] float32 on `hip_stream` (NULL: default
+ * stream): the seed noise of the seeds paragraph of the formal appendix
+ * with any counter word `step` (0 is J_T's; the student's re-noising uses
+ * 1).  Asynchronous. */
+td_status td_noise_region(uint64_t seed, int64_t x0, int64_t y0, int32_t w, int32_t h, int32_t channels,
+                          uint32_t step, float scale, float *dev_out, void *hip_stream);
+
 /* Laplacian decode (Sec. 5.2, with the signed-sqrt inverse of the
  * signed-sqrt appendix) of a latent held in device memory, [lh][lw][C]
  * float32 with latent origin (lx0, ly0), onto the full-resolution region
@@ -278,6 +294,53 @@ td_status td_server_stats(td_server *srv, td_server_stats_t *out);
 /* Description of the last error on ctx (owned by ctx, valid until the next
  * call); "" if none.  Safe on NULL. */
 const char *td_last_error(const td_ctx *ctx);
+
+/* ---------------------------------------------------------------- training
+ * Hand-written forward and backward of a window UNet denoiser, for
+ * distilling a few-step student (Sec. 5.1: the core model is distilled into
+ * a two-step consistency model; the student here is distilled on (noise
+ * window, teacher output) pairs).  The network is the sampler's (EDM
+ * preconditioning around the UNet of the weight file's header); parameters
+ * are one flat float32 device buffer laid out as the file's data section
+ * (tensor i at float offset offset_i / 4, conv weights [co][ci][kh][kw]),
+ * so a file's data can be loaded, trained and written back as it is.
+ * Gradients use the same layout.  FP32 throughout; all reductions run in a
+ * fixed order (deterministic gradients).  One trainer is not thread-safe;
+ * calls are asynchronous on the HIP stream `stream` (NULL: the device's
+ * default stream). */
+typedef struct td_trainer td_trainer;
+
+/* Trainer for the UNet of weight file `path` (its architecture and tensor
+ * table; the values are not read).  TD_E_FORMAT for analytic or
+ * conditioned models. */
+td_status td_train_create(int hip_device, const char *path, td_trainer **out);
+void td_train_destroy(td_trainer *tr);
+const char *td_train_last_error(const td_trainer *tr);
+
+/* Length in floats of the flat parameter buffer (the data section). */
+td_status td_train_param_count(td_trainer *tr, size_t *n);
+
+/* D = D_theta(x; sigma) for n windows x [n][H][H][C] float32 (device), out
+ * D the same shape.  Keeps the activations the next td_train_backward
+ * needs (one pending backward per trainer). */
+td_status td_train_forward(td_trainer *tr, const float *params, const float *x, int32_t n, double sigma, float *D,
+                           void *stream);
+
+/* Adds dL/dparams to grads (same layout as params) for the dL/dD of the
+ * last forward, which must have used the same params pointer
+ * (TD_E_STATE otherwise). */
+td_status td_train_backward(td_trainer *tr, const float *params, const float *dD, float *grads, void *stream);
+
+/* Weighted mean squared error over n floats: dD = weight 2 (D - y) / n;
+ * *loss (nullable; synchronises) = weight mean((D - y)^2). */
+td_status td_train_mse(td_trainer *tr, const float *D, const float *y, size_t n, float weight, float *dD,
+                       double *loss, void *stream);
+
+/* AdamW step `step` (>= 1) on n floats: bias-corrected moments m, v
+ * (device, zero-initialised by the caller), decoupled weight decay
+ * params -= lr (m_hat / (sqrt(v_hat) + eps) + weight_decay params). */
+td_status td_train_adamw(td_trainer *tr, float *params, const float *grads, float *m, float *v, size_t n, float lr,
+                         float beta1, float beta2, float eps, float weight_decay, int32_t step, void *stream);
 
 #ifdef __cplusplus
 }

@@ -1015,6 +1015,61 @@ td_status td_denoise_windows(td_ctx* c, const float* x_dev, const float* cond_de
   });
 }
 
+td_status td_denoise_steps(td_ctx* c, const float* x_dev, int32_t n, int32_t k0, int32_t k1, float* out_dev) {
+  if (!c) return TD_E_INVAL;
+  return guarded(c, [&] {
+    need_model(c);
+    const ModelDesc& d = c->model->d;
+    TD_CHECK(x_dev && out_dev && n >= 0, TD_E_INVAL, "bad arguments");
+    TD_CHECK(!d.consistency, TD_E_INVAL, "window-local steps need an Euler (EDM) sampler");
+    TD_CHECK(!d.Cc, TD_E_INVAL, "window-local steps of a conditioned model are not supported");
+    TD_CHECK(0 <= k0 && k0 < k1 && k1 <= d.K, TD_E_INVAL, "steps must satisfy 0 <= k0 < k1 <= K");
+    TD_HIP(hipSetDevice(c->device));
+    if (c->pending) {
+      TD_HIP(hipEventSynchronize(c->done));
+      c->pending = false;
+    }
+    c->arena.reset();
+    const int maxb = auto_batch(c);
+    c->model->ensure_workspace(maxb);
+    const size_t per = (size_t)d.H * d.H * d.C;
+    c->arena.ensure((size_t)(n / maxb + 1) * (256 + (size_t)std::min(n, maxb) * 2 * sizeof(int)));
+    for (int b0 = 0; b0 < n; b0 += maxb) {
+      const int nb = std::min(maxb, n - b0);
+      auto o = c->arena.reserve((size_t)nb * 2 * sizeof(int));
+      int* ho = (int*)o.first;
+      for (int j = 0; j < nb; ++j) {
+        ho[2 * j] = 0;
+        ho[2 * j + 1] = j * d.H;
+      }
+      TD_HIP(hipMemcpyAsync(o.second, o.first, (size_t)nb * 2 * sizeof(int), hipMemcpyHostToDevice, c->stream));
+      for (int k = k0; k < k1; ++k) {
+        WindowBatch wb;
+        wb.canvas = (k == k0 ? x_dev : out_dev) + (size_t)b0 * per;   // Phi may overwrite its own input
+        wb.canvas_w = d.H;
+        wb.d_origins = (const int*)o.second;
+        wb.d_widx = (const int*)o.second;
+        wb.n = nb;
+        wb.mode = 2;
+        wb.dout = out_dev + (size_t)b0 * per;
+        c->model->run_batch(c->stream, wb, k);
+      }
+    }
+    TD_HIP(hipStreamSynchronize(c->stream));
+  });
+}
+
+td_status td_noise_region(uint64_t seed, int64_t x0, int64_t y0, int32_t w, int32_t h, int32_t channels,
+                          uint32_t step, float scale, float* dev_out, void* hip_stream) {
+  if (!dev_out || w < 1 || h < 1 || channels < 1 || (int64_t)w * h > (1LL << 30)) return TD_E_INVAL;
+  try {
+    launch_noise((hipStream_t)hip_stream, seed, x0, y0, w, h, channels, step, scale, 0, dev_out);
+  } catch (const Error& e) {
+    return (td_status)e.status;
+  }
+  return TD_OK;
+}
+
 td_status td_lap_decode(td_ctx* c, const float* latent_dev, int64_t lx0, int64_t ly0, int32_t lw, int32_t lh,
                         int64_t X0, int64_t Y0, int32_t W, int32_t H, float* out_dev, void* hip_stream) {
   if (!c) return TD_E_INVAL;

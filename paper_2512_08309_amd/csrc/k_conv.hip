@@ -260,15 +260,14 @@ void launch_conv(hipStream_t st, const ConvArgs& a) {
   TD_CHECK(!a.up0 || (a.lh >= 1 && a.lw >= 1), -5, "conv: upsampled source needs h, w >= 2");
   TD_CHECK(a.lh + a.lw <= 20, -5, "conv: image too large");
   if (a.nb == 0) return;
-  TD_CHECK(a.cout % 128 == 0 || a.cout == 64 || a.cout == 32 || a.cout == 16, -5,
-           "conv: unsupported output channel count");
+  TD_CHECK(a.cout % 16 == 0 && a.cout > 0, -5, "conv: output channels must be a multiple of 16");
   const double M = (double)a.nb * (1 << (a.lh + a.lw));
   const double in_bytes = 4.0 * (a.up0 ? M / 4 * a.c0 + M * a.c1 : M * cin);
   const double bytes = in_bytes + 4.0 * a.taps * cin * a.cout + 4.0 * M * a.cout * (a.res ? 2 : 1);
   prof_begin(st);
   if (a.cout % 128 == 0) launch_cfg<128, 2, 2>(st, a);
-  else if (a.cout == 64) launch_cfg<64, 2, 2>(st, a);
-  else if (a.cout == 32) launch_cfg<32, 4, 1>(st, a);
+  else if (a.cout % 64 == 0) launch_cfg<64, 2, 2>(st, a);
+  else if (a.cout % 32 == 0) launch_cfg<32, 4, 1>(st, a);
   else launch_cfg<16, 4, 1>(st, a);
   prof_end(st, a.taps == 9 ? K_CONV3 : K_CONV1, 2.0 * M * a.cout * a.taps * cin, bytes);
 }

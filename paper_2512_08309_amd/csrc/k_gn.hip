@@ -99,6 +99,10 @@ __global__ __launch_bounds__(256) void gn_finalize_kernel(GnArgs a, int nchunk) 
     double var = tq / n - mean * mean;
     if (var < 0) var = 0;
     double rstd = 1.0 / sqrt(var + (double)a.eps);
+    if (a.mean && c % cgp == 0) {
+      a.mean[(size_t)b * a.groups + g] = (float)mean;
+      a.rstd[(size_t)b * a.groups + g] = (float)rstd;
+    }
     double sc = (double)a.gamma[c] * rstd;
     a.scale[(size_t)b * cin + c] = (float)sc;
     a.shift[(size_t)b * cin + c] = (float)((double)a.beta[c] - mean * sc);

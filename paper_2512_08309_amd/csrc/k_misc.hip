@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void conv_out_kernel(OutArgs a) {
   const int u = tx0 + px, v = ty0 + py;
   const int ox = a.origins[2 * b], oy = a.origins[2 * b + 1];
   const float* xin = a.canvas + ((size_t)(oy + v) * a.canvas_w + ox + u) * CO;
-  const float wuv = a.w1d[u] * a.w1d[v];
+  const float wuv = a.mode == 0 ? a.w1d[u] * a.w1d[v] : 0.f;   // window weight: contributions only
 #pragma unroll
   for (int o = 0; o < CO; ++o) {
     float x = xin[o];
@@ -254,6 +254,7 @@ void launch_conv_in(hipStream_t st, const float* canvas, int canvas_w, const int
 void launch_conv_out(hipStream_t st, const OutArgs& a) {
   if (!a.nb) return;
   TD_CHECK(a.H % 16 == 0, -5, "conv_out: window size must be a multiple of 16");
+  TD_CHECK(a.mode == 0 ? (a.w1d && a.slots) : a.dout != nullptr, -5, "conv_out: output buffers missing for the mode");
   dim3 grid((a.H / 16) * (a.H / 16), a.nb);
   prof_begin(st);
   if (a.cimg == 4 && a.c0 % 32 == 0)

@@ -39,7 +39,7 @@ struct Error {
 // bytes of the launch).  When no profiler is installed the hooks are no-ops.
 enum KClass {
   K_CONV3 = 0, K_CONV1, K_GN, K_CONV_IN, K_CONV_OUT, K_ATTN, K_POOL, K_NOISE, K_BLEND, K_DECODE, K_LG, K_EMB,
-  K_CONV3_LP, K_CONV1_LP, K_APPLY, K_GATHER, K_NCLASS
+  K_CONV3_LP, K_CONV1_LP, K_APPLY, K_GATHER, K_WGRAD, K_NCLASS
 };
 const char* kclass_name(int k);
 struct Profiler;
@@ -171,6 +171,8 @@ struct GnArgs {
   double* partial;       // workspace [nb][nchunk][groups][2]
   float* scale;          // [nb][cin]
   float* shift;
+  float* mean = nullptr; // optional [nb][groups] statistics (training)
+  float* rstd = nullptr;
 };
 size_t gn_partial_doubles(int nb, int lh, int lw, int cin, int groups);
 void launch_gn(hipStream_t st, const GnArgs& a);

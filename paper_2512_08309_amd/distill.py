@@ -1,0 +1,111 @@
+"""Distil a two-step student from the plain sampler (the learned part).
+
+Teacher: a UNet weight file with the EDM Euler sampler (e.g. the 20-step
+4-channel model).  For seed i the pair is (x_i, y_i) with x_i = sigma_0 G(i)
+on the window at the origin (the seed noise, counter word 0) and y_i the
+teacher's plain sampler run on that window alone (td_denoise_steps, all K
+steps).  The student (a consistency-sampled weight file with noise levels
+[s_0, s_1]) is trained so that both of its steps land on y:
+
+    L = 1/2 mean((D_S(x; s_0) - y)^2) + 1/2 mean((D_S(y + s_1 e; s_1) - y)^2)
+
+with e = G(i) on counter word 1 (the noise its second step re-draws when
+sampling).  Forward and backward are the library's hand-written kernels
+(td_train_*); AdamW updates FP32 master weights.  Usage:
+
+    python -m paper_2512_08309_amd.distill TEACHER.tdw STUDENT_INIT.tdw OUT.tdw \\
+        [--pairs 50000] [--steps 800] [--batch 64] [--lr 2e-4]
+"""
+import argparse
+import json
+import time
+
+import numpy as np
+
+
+def make_pairs(td, torch, teacher_path, n, seed0=1, chunk=1024, precision=0):
+    """(x, y, e) device tensors [n][H][H][C]: teacher inputs, outputs, re-noise."""
+    with td.Context(0) as t:
+        t.load_weights(teacher_path)
+        t.set_option("precision", precision)
+        H, C, K = t.info("window"), t.info("channels"), t.info("steps")
+        sigma0 = 80.0
+        x = torch.empty((n, H, H, C), device="cuda")
+        y = torch.empty_like(x)
+        e = torch.empty_like(x)
+        for i in range(n):
+            td.td_noise_region(seed0 + i, 0, 0, x[i], step=0, scale=sigma0)
+            td.td_noise_region(seed0 + i, 0, 0, e[i], step=1, scale=1.0)
+        torch.cuda.synchronize()
+        for i0 in range(0, n, chunk):
+            i1 = min(n, i0 + chunk)
+            t.denoise_steps(x[i0:i1], 0, K, y[i0:i1])
+        torch.cuda.synchronize()
+    return x, y, e
+
+
+def train(td, torch, student_path, x, y, e, steps, batch=64, lr=2e-4, seed=0, log_every=50, sigmas=(80.0, 0.35)):
+    """AdamW on the student's flat parameters; returns (params, loss history)."""
+    tr = td.Trainer(student_path)
+    P = tr.load_params(student_path)
+    G, m, v = torch.zeros_like(P), torch.zeros_like(P), torch.zeros_like(P)
+    n = x.shape[0]
+    rng = np.random.default_rng(seed)
+    D = torch.empty((batch,) + tuple(x.shape[1:]), device="cuda")
+    dD = torch.empty_like(D)
+    hist = []
+    perm = rng.permutation(n)
+    pos = 0
+    for step in range(1, steps + 1):
+        if pos + batch > n:
+            perm, pos = rng.permutation(n), 0
+        idx = torch.from_numpy(perm[pos:pos + batch]).cuda()
+        pos += batch
+        xb, yb = x.index_select(0, idx), y.index_select(0, idx)
+        x2 = yb + sigmas[1] * e.index_select(0, idx)
+        G.zero_()
+        tr.forward(P, xb, sigmas[0], D)
+        l1 = tr.mse(D, yb, dD, weight=0.5, want_loss=(step % log_every == 0 or step == 1))
+        tr.backward(P, dD, G)
+        tr.forward(P, x2, sigmas[1], D)
+        l2 = tr.mse(D, yb, dD, weight=0.5, want_loss=(step % log_every == 0 or step == 1))
+        tr.backward(P, dD, G)
+        tr.adamw(P, G, m, v, lr=lr, step=step)
+        if l1 is not None:
+            hist.append((step, l1 + l2))
+    torch.cuda.synchronize()
+    tr.close()
+    return P, hist
+
+
+def save(td, student_path, P, out_path):
+    head, data = td.read_tdw_data(student_path)
+    data = data.copy()
+    data[:P.numel()] = P.cpu().numpy()
+    td.write_tdw_data(out_path, head, data)
+
+
+def main():
+    import torch
+    from paper_2512_08309_amd import td
+    ap = argparse.ArgumentParser()
+    ap.add_argument("teacher")
+    ap.add_argument("student_init")
+    ap.add_argument("out")
+    ap.add_argument("--pairs", type=int, default=50000)
+    ap.add_argument("--steps", type=int, default=800)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--lr", type=float, default=2e-4)
+    ap.add_argument("--teacher-precision", type=int, default=0)
+    a = ap.parse_args()
+    t0 = time.perf_counter()
+    x, y, e = make_pairs(td, torch, a.teacher, a.pairs, precision=a.teacher_precision)
+    t1 = time.perf_counter()
+    P, hist = train(td, torch, a.student_init, x, y, e, a.steps, a.batch, a.lr)
+    t2 = time.perf_counter()
+    save(td, a.student_init, P, a.out)
+    print(json.dumps({"pairs": a.pairs, "pair_s": t1 - t0, "steps": a.steps, "train_s": t2 - t1, "loss": hist}))
+
+
+if __name__ == "__main__":
+    main()

@@ -22,9 +22,10 @@ STATUS_NAMES = {0: "TD_OK", -1: "TD_E_INVAL", -2: "TD_E_NOMEM", -3: "TD_E_DEVICE
 EXPORTS = ["td_create", "td_destroy", "td_load_weights", "td_set_conditioning", "td_set_judge", "td_sample_region",
            "td_sample_region_async",
            "td_cache_set_budget", "td_cache_clear", "td_cache_stats", "td_cache_peek", "td_set_option",
-           "td_get_info", "td_denoise_windows", "td_lap_decode", "td_kappa", "td_cone_windows", "td_kernel_stats",
+           "td_get_info", "td_denoise_windows", "td_denoise_steps", "td_noise_region", "td_lap_decode", "td_kappa", "td_cone_windows", "td_kernel_stats",
            "td_server_create", "td_server_destroy", "td_server_submit", "td_server_progress", "td_server_poll",
-           "td_server_stats", "td_last_error"]
+           "td_server_stats", "td_last_error", "td_train_create", "td_train_destroy", "td_train_last_error",
+           "td_train_param_count", "td_train_forward", "td_train_backward", "td_train_mse", "td_train_adamw"]
 
 
 class td_cache_stats_t(ctypes.Structure):
@@ -77,6 +78,8 @@ def _load():
         "td_set_option": ([vp, ctypes.c_char_p, i64], ctypes.c_int),
         "td_get_info": ([vp, ctypes.c_char_p, ctypes.POINTER(i64)], ctypes.c_int),
         "td_denoise_windows": ([vp, vp, vp, i32, i32, vp], ctypes.c_int),
+        "td_denoise_steps": ([vp, vp, i32, i32, i32, vp], ctypes.c_int),
+        "td_noise_region": ([u64, i64, i64, i32, i32, i32, ctypes.c_uint32, ctypes.c_float, vp, vp], ctypes.c_int),
         "td_lap_decode": ([vp, vp, i64, i64, i32, i32, i64, i64, i32, i32, vp, vp], ctypes.c_int),
         "td_kappa": ([i64, i64, i64, i64, i32, i32, i32, ctypes.POINTER(i64)], ctypes.c_int),
         "td_cone_windows": ([i64, i64, i64, i64, i32, i32, i32, i32, i32, ctypes.POINTER(u64)], ctypes.c_int),
@@ -88,6 +91,15 @@ def _load():
         "td_server_poll": ([vp, u64, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "td_server_stats": ([vp, ctypes.POINTER(td_server_stats_t)], ctypes.c_int),
         "td_last_error": ([vp], ctypes.c_char_p),
+        "td_train_create": ([ctypes.c_int, ctypes.c_char_p, ctypes.POINTER(vp)], ctypes.c_int),
+        "td_train_destroy": ([vp], None),
+        "td_train_last_error": ([vp], ctypes.c_char_p),
+        "td_train_param_count": ([vp, ctypes.POINTER(sz)], ctypes.c_int),
+        "td_train_forward": ([vp, vp, vp, i32, ctypes.c_double, vp, vp], ctypes.c_int),
+        "td_train_backward": ([vp, vp, vp, vp, vp], ctypes.c_int),
+        "td_train_mse": ([vp, vp, vp, sz, ctypes.c_float, vp, ctypes.POINTER(ctypes.c_double), vp], ctypes.c_int),
+        "td_train_adamw": ([vp, vp, vp, vp, vp, sz, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                            ctypes.c_float, i32, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -186,6 +198,24 @@ def td_set_option(ctx, key, value):
 def td_set_conditioning(child, parent):
     """Make parent's final latent condition child (parent None unlinks)."""
     _check(child, lib.td_set_conditioning(child, parent))
+
+
+def td_denoise_steps(ctx, x_dev, k0, k1, out_dev):
+    """Sampler steps k0..k1-1 on independent windows [n][H][H][C] (device tensors)."""
+    assert x_dev.is_contiguous() and out_dev.is_contiguous() and x_dev.shape == out_dev.shape
+    _check(ctx, lib.td_denoise_steps(ctx, ctypes.c_void_p(x_dev.data_ptr()), x_dev.shape[0], k0, k1,
+                                     ctypes.c_void_p(out_dev.data_ptr())))
+    return out_dev
+
+
+def td_noise_region(seed, x0, y0, out_dev, step=0, scale=1.0, stream=None):
+    """scale * G(seed, ., ., c, step) into a contiguous device tensor [h][w][C]."""
+    h, w, C = out_dev.shape
+    status = lib.td_noise_region(seed & (2 ** 64 - 1), x0, y0, w, h, C, step, scale,
+                                 ctypes.c_void_p(out_dev.data_ptr()), _stream(stream))
+    if status != TD_OK:
+        raise TDError(status, "td_noise_region")
+    return out_dev
 
 
 def td_set_judge(student, teacher, threshold):
@@ -351,6 +381,9 @@ class Context:
     def denoise_windows(self, x_dev, k, out_dev, cond_dev=None):
         return td_denoise_windows(self.ctx, x_dev, k, out_dev, cond_dev)
 
+    def denoise_steps(self, x_dev, k0, k1, out_dev):
+        return td_denoise_steps(self.ctx, x_dev, k0, k1, out_dev)
+
     def kernel_stats(self, reset=False):
         return td_kernel_stats(self.ctx, reset)
 
@@ -387,3 +420,119 @@ class Server:
 
     def __exit__(self, *exc):
         self.close()
+
+
+# ---------------------------------------------------------------- training
+
+def read_tdw_data(path):
+    """(header bytes up to the data start, float32 data section) of a .tdw file."""
+    import numpy as np
+    with open(path, "rb") as f:
+        raw = f.read()
+    if raw[:4] != b"TDW1":
+        raise ValueError("not a TDW1 file")
+    n = int.from_bytes(raw[4:8], "little")
+    start = (8 + n + 63) // 64 * 64
+    return raw[:start], np.frombuffer(raw[start:], dtype="<f4").copy()
+
+
+def write_tdw_data(path, head, data):
+    """Write a .tdw file with the header block of another and new data."""
+    import numpy as np
+    with open(path, "wb") as f:
+        f.write(head)
+        f.write(np.ascontiguousarray(data, dtype="<f4").tobytes())
+
+
+def _torch_stream(stream):
+    """The given stream, else torch's current stream (the one the tensors are ordered on)."""
+    if stream is not None:
+        return _stream(stream)
+    import torch
+    return _stream(torch.cuda.current_stream())
+
+
+class Trainer:
+    """Hand-written forward/backward of a weight file's UNet (td_train_* in td.h).
+    Tensors are contiguous float32 torch tensors on the device; calls run on
+    torch's current stream unless a stream is given."""
+
+    def __init__(self, path, device=0):
+        h = ctypes.c_void_p()
+        status = lib.td_train_create(device, path.encode(), ctypes.byref(h))
+        if status != TD_OK:
+            raise TDError(status, "td_train_create failed for %s" % path)
+        self.tr = h
+        n = ctypes.c_size_t()
+        self._check(lib.td_train_param_count(self.tr, ctypes.byref(n)))
+        self.n_params = n.value
+
+    def _check(self, status):
+        if status != TD_OK:
+            msg = lib.td_train_last_error(self.tr)
+            raise TDError(status, msg.decode() if msg else "")
+
+    def load_params(self, path):
+        import torch
+        _, data = read_tdw_data(path)
+        assert data.size >= self.n_params
+        return torch.from_numpy(data[:self.n_params].copy()).cuda()
+
+    def forward(self, params, x, sigma, out, stream=None):
+        assert params.is_contiguous() and x.is_contiguous() and out.is_contiguous()
+        self._check(lib.td_train_forward(self.tr, ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                         x.shape[0], float(sigma), ctypes.c_void_p(out.data_ptr()), _torch_stream(stream)))
+        return out
+
+    def backward(self, params, dD, grads, stream=None):
+        self._check(lib.td_train_backward(self.tr, ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(dD.data_ptr()),
+                                          ctypes.c_void_p(grads.data_ptr()), _torch_stream(stream)))
+        return grads
+
+    def mse(self, D, y, dD, weight=1.0, want_loss=True, stream=None):
+        loss = ctypes.c_double()
+        self._check(lib.td_train_mse(self.tr, ctypes.c_void_p(D.data_ptr()), ctypes.c_void_p(y.data_ptr()), D.numel(),
+                                     float(weight), ctypes.c_void_p(dD.data_ptr()),
+                                     ctypes.byref(loss) if want_loss else None, _torch_stream(stream)))
+        return loss.value if want_loss else None
+
+    def adamw(self, params, grads, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.01, stream=None):
+        self._check(lib.td_train_adamw(self.tr, ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(grads.data_ptr()),
+                                       ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(v.data_ptr()), params.numel(),
+                                       lr, beta1, beta2, eps, weight_decay, step, _torch_stream(stream)))
+
+    def close(self):
+        if self.tr:
+            lib.td_train_destroy(self.tr)
+            self.tr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def student_function():
+    """torch.autograd.Function over the trainer's hand-written kernels:
+    D = f.apply(params, x, sigma, trainer); gradients flow to params only.
+    One forward may be pending per trainer (its backward uses the saved tape)."""
+    import torch
+
+    class StudentD(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, params, x, sigma, trainer):
+            out = torch.empty_like(x)
+            trainer.forward(params, x.contiguous(), sigma, out)
+            ctx.trainer = trainer
+            ctx.save_for_backward(params)
+            return out
+
+        @staticmethod
+        def backward(ctx, dD):
+            (params,) = ctx.saved_tensors
+            grads = torch.zeros_like(params)
+            ctx.trainer.backward(params, dD.contiguous(), grads)
+            return grads, None, None, None
+
+    return StudentD

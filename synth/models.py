@@ -20,7 +20,9 @@ workloads the method is measured on:
 * ``lgc``, ``lgh``: the linear-Gaussian pair with the same wiring.
 * ``s2``  : the half-width student of ``c2`` (64/128/128/256), two-step
             consistency sampling at sigma 80 and 0.35; ``lgs`` is an analytic
-            two-step model (prior std 0.7) whose teacher stand-in is ``lg``.
+            two-step model (prior std 0.7) whose teacher stand-in is ``lg``;
+            ``st`` is a small network of the student's shape (32/32, windows
+            16) for gradient checks.
 
 Initialisation: every tensor is Gaussian from numpy's PCG64 seeded with the
 given seed, drawn in file order.  Conv / linear weights ~ N(0, 1/fan_in);
@@ -93,6 +95,13 @@ CONFIGS["s2"] = {
                  "emb_mult": 4, "pe_max_period": 10000.0},
     "sampler": dict(CONSISTENCY_2),
     "window": {"size": 64, "stride": 32, "offset": 0, "eps": 0.01},
+}
+CONFIGS["st"] = {   # a small student-shaped network for gradient checks
+    "denoiser": {"kind": "unet", "in_channels": 4, "channels": [32, 32], "num_res_blocks": 1,
+                 "attn_levels": [1], "mid_attn": True, "num_heads": 2, "gn_groups": 8, "gn_eps": 1e-5,
+                 "emb_mult": 4, "pe_max_period": 10000.0},
+    "sampler": dict(CONSISTENCY_2),
+    "window": {"size": 16, "stride": 8, "offset": 0, "eps": 0.01},
 }
 CONFIGS["lgs"] = {
     "denoiser": {"kind": "linear_gaussian", "in_channels": 4, "prior_std": 0.7},

@@ -154,3 +154,35 @@ def test_judge_errors(ctxs, weights):
             assert e.value.status == td.TD_E_STATE
         finally:
             s.set_judge(None, 0.0)
+
+
+def test_window_local_steps_match_oracle(ctxs, weights):
+    """td_denoise_steps: the plain sampler on independent windows (the teacher
+    output of distillation)."""
+    import torch
+    from oracle.schedule import euler_factor
+    from oracle.tdw import read_tdw
+    from oracle.unet import UNetDenoiser
+    c = ctxs("c1k2")
+    hdr, t = read_tdw(weights("c1k2"))
+    m = Model(weights("c1k2"))
+    x = (80.0 * np.random.default_rng(12).standard_normal((3, 32, 32, 1))).astype(np.float32)
+    out = torch.empty((3, 32, 32, 1), device="cuda")
+    c.denoise_steps(torch.from_numpy(x).cuda(), 0, 2, out)
+    ref = x.astype(np.float64)
+    den = UNetDenoiser(hdr, t)
+    for k in range(2):
+        ref = ref + euler_factor(m.sched[k], m.sched[k + 1]) * (ref - den(ref, m.sched[k], None))
+    assert rel_l2(out.cpu().numpy(), ref) <= 1e-5
+
+
+def test_noise_region_any_counter_word():
+    require_gpu()
+    import torch
+    from oracle import noise as onoise
+    from paper_2512_08309_amd import td
+    out = torch.empty((9, 13, 4), device="cuda")
+    td.td_noise_region(77, -5, 1000, out, step=1, scale=0.35)
+    torch.cuda.synchronize()
+    want = np.float32(0.35) * onoise.noise_region(77, -5, 1000, 13, 9, 4, step=1)
+    assert np.array_equal(out.cpu().numpy(), want)

@@ -1,0 +1,173 @@
+"""Student training kernels (hand-written backward of the window UNet)
+against finite differences of the FP64 oracle's loss, through the C-ABI.
+
+The loss is L = mean((D_theta(x; sigma) - y)^2) with D the EDM-
+preconditioned UNet.  Gradients of sampled parameters of every tensor kind
+(convs, 1x1 skip, GroupNorm affine, attention qkv / proj, noise-embedding
+MLP and per-block embedding projections, input and output convs) are
+checked against central differences of the oracle's L in FP64.  Also:
+gradients are bit-deterministic, the torch.autograd.Function gives the same
+gradient, AdamW follows its formula, and training lowers the loss.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(weights, config, nwin, sigma, seed=0):
+    require_gpu()
+    import torch
+    from oracle.tdw import read_tdw
+    from paper_2512_08309_amd import td
+    path = weights(config)
+    tr = td.Trainer(path)
+    P = tr.load_params(path)
+    hdr, t = read_tdw(path)
+    H, C = hdr["window"]["size"], hdr["denoiser"]["in_channels"]
+    rng = np.random.default_rng(seed)
+    x = (sigma * rng.standard_normal((nwin, H, H, C)) / np.sqrt(1 + sigma ** 2) * 2).astype(np.float32)
+    y = rng.standard_normal((nwin, H, H, C)).astype(np.float32)
+    return td, torch, tr, P, hdr, t, x, y
+
+
+def _gpu_grad(torch, tr, P, x, y, sigma):
+    xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    D = torch.empty_like(xd)
+    dD = torch.empty_like(xd)
+    tr.forward(P, xd, sigma, D)
+    loss = tr.mse(D, yd, dD)
+    G = torch.zeros_like(P)
+    tr.backward(P, dD, G)
+    torch.cuda.synchronize()
+    return loss, G.cpu().numpy()
+
+
+def _oracle_loss(hdr, t, x, y, sigma):
+    from oracle.unet import UNetDenoiser
+    D = UNetDenoiser(hdr, t)(x.astype(np.float64), sigma, None)
+    return float(((D - y.astype(np.float64)) ** 2).mean())
+
+
+def _fd_check(hdr, t, x, y, sigma, G, per_tensor, rng, h=1e-4, names=None):
+    offs = {e["name"]: e["offset"] // 4 for e in hdr["tensors"]}
+    got, want = [], []
+    for name in (names or sorted(t)):
+        arr = t[name]
+        for idx in rng.choice(arr.size, size=min(per_tensor, arr.size), replace=False):
+            flat = arr.reshape(-1)
+            keep = flat[idx]
+            flat[idx] = keep + h
+            lp = _oracle_loss(hdr, t, x, y, sigma)
+            flat[idx] = keep - h
+            lm = _oracle_loss(hdr, t, x, y, sigma)
+            flat[idx] = keep
+            want.append((lp - lm) / (2 * h))
+            got.append(float(G[offs[name] + idx]))
+    got, want = np.array(got), np.array(want)
+    scale = np.abs(want).max()
+    bad = np.abs(got - want) > 3e-3 * np.abs(want) + 1e-3 * scale
+    assert not bad.any(), list(zip(got[bad], want[bad]))
+    return np.linalg.norm(got - want) / np.linalg.norm(want)
+
+
+@pytest.mark.parametrize("sigma", [0.35, 80.0])
+def test_small_network_gradients_match_finite_differences(weights, sigma):
+    td, torch, tr, P, hdr, t, x, y = _setup(weights, "st", 2, sigma)
+    loss, G = _gpu_grad(torch, tr, P, x, y, sigma)
+    assert loss == pytest.approx(_oracle_loss(hdr, t, x, y, sigma), rel=1e-5)
+    rel = _fd_check(hdr, t, x, y, sigma, G, 3, np.random.default_rng(1))
+    print("st sigma %.2f: gradient rel error vs finite differences %.2e" % (sigma, rel))
+    assert rel < 1e-3
+    tr.close()
+
+
+def test_student_gradients_match_finite_differences(weights):
+    sigma = 0.35
+    td, torch, tr, P, hdr, t, x, y = _setup(weights, "s2", 1, sigma, seed=3)
+    loss, G = _gpu_grad(torch, tr, P, x, y, sigma)
+    assert loss == pytest.approx(_oracle_loss(hdr, t, x, y, sigma), rel=1e-5)
+    names = ["conv_in.weight", "enc.0.0.conv1.weight", "enc.1.0.skip.weight", "enc.3.1.attn.qkv.weight",
+             "mid.attn.proj.weight", "dec.1.0.gn1.weight", "dec.1.0.conv1.weight", "dec.0.1.emb.weight",
+             "emb.lin1.weight", "out.conv.weight", "out.gn.bias"]
+    rel = _fd_check(hdr, t, x, y, sigma, G, 1, np.random.default_rng(2), names=names)
+    print("s2: gradient rel error vs finite differences %.2e" % rel)
+    assert rel < 1e-3
+    tr.close()
+
+
+def test_gradients_deterministic_and_autograd_function(weights):
+    td, torch, tr, P, hdr, t, x, y = _setup(weights, "st", 3, 1.3)
+    _, G1 = _gpu_grad(torch, tr, P, x, y, 1.3)
+    _, G2 = _gpu_grad(torch, tr, P, x, y, 1.3)
+    assert np.array_equal(G1, G2)
+    Fn = td.student_function()
+    Pg = P.clone().requires_grad_(True)
+    xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    D = Fn.apply(Pg, xd, 1.3, tr)
+    ((D - yd) ** 2).mean().backward()
+    g = Pg.grad.cpu().numpy()
+    assert np.linalg.norm(g - G1) <= 1e-5 * np.linalg.norm(G1)
+    tr.close()
+
+
+def test_adamw_step_follows_formula(weights):
+    require_gpu()
+    import torch
+    from paper_2512_08309_amd import td
+    tr = td.Trainer(weights("st"))
+    rng = np.random.default_rng(4)
+    w, g, m, v = (rng.standard_normal(1000).astype(np.float32) for _ in range(4))
+    v = np.abs(v)
+    dw, dg, dm, dv = (torch.from_numpy(a.copy()).cuda() for a in (w, g, m, v))
+    tr.adamw(dw, dg, dm, dv, lr=2e-4, step=3)
+    torch.cuda.synchronize()
+    b1, b2, eps, wd = 0.9, 0.999, 1e-8, 0.01
+    m2 = b1 * m + (1 - b1) * g
+    v2 = b2 * v + (1 - b2) * g * g
+    w2 = w - 2e-4 * ((m2 / (1 - b1 ** 3)) / (np.sqrt(v2 / (1 - b2 ** 3)) + eps) + wd * w)
+    assert np.allclose(dw.cpu().numpy(), w2, rtol=1e-5, atol=1e-7)
+    # FP32 with fused multiply-adds vs numpy's separate roundings: a few ulps
+    assert np.allclose(dm.cpu().numpy(), m2, rtol=1e-6, atol=1e-7)
+    assert np.allclose(dv.cpu().numpy(), v2, rtol=1e-6, atol=1e-7)
+    tr.close()
+
+
+def test_training_lowers_the_loss(weights):
+    td, torch, tr, P, hdr, t, x, y = _setup(weights, "st", 8, 2.0)
+    xd, yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    D, dD = torch.empty_like(xd), torch.empty_like(xd)
+    G, m, v = torch.zeros_like(P), torch.zeros_like(P), torch.zeros_like(P)
+    losses = []
+    for step in range(1, 31):
+        tr.forward(P, xd, 2.0, D)
+        losses.append(tr.mse(D, yd, dD))
+        G.zero_()
+        tr.backward(P, dD, G)
+        tr.adamw(P, G, m, v, lr=1e-3, step=step)
+    torch.cuda.synchronize()
+    print("loss %.4f -> %.4f" % (losses[0], losses[-1]))
+    assert losses[-1] < 0.8 * losses[0]
+    tr.close()
+
+
+def test_distillation_pipeline(weights, tmp_path):
+    """Pairs from the plain sampler (teacher with K = 2 here, to keep the test
+    short), a few AdamW steps on the two-step objective, and the trained
+    student file loads and samples through the lazy sampler."""
+    require_gpu()
+    import torch
+    from paper_2512_08309_amd import distill, td
+    x, y, e = distill.make_pairs(td, torch, weights("c2k2"), 64)
+    assert torch.isfinite(y).all() and float(y.std()) > 0
+    P, hist = distill.train(td, torch, weights("s2"), x, y, e, steps=12, batch=16, lr=1e-3, log_every=4)
+    print("distillation loss", hist)
+    assert hist[-1][1] < hist[0][1]
+    out = str(tmp_path / "student.tdw")
+    distill.save(td, weights("s2"), P, out)
+    with td.Context(0) as c:
+        c.load_weights(out)
+        z = c.sample_region(5, 0, 0, 40, 24, 0)
+    assert z.shape == (4, 24, 40) and np.isfinite(z).all()
