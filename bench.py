@@ -48,6 +48,9 @@ def parse():
     p.add_argument("--truncated", default="c2t2", help="truncated-T config timed cold ('' = skip)")
     p.add_argument("--serve-queries", type=int, default=256, help="queries of the serving stream (0 = skip)")
     p.add_argument("--serve-rate", type=float, default=256.0, help="Poisson arrival rate, queries/s")
+    p.add_argument("--student-steps", type=int, default=300,
+                   help="AdamW steps of the in-bench student distillation (0 = skip the student leg)")
+    p.add_argument("--student-pairs", type=int, default=4096, help="teacher pairs of the in-bench distillation")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="run one plain elementwise copy (read N MiB, write N MiB) before the steps, as the "
                         "reference dispatch that scales hardware byte counters")
@@ -168,6 +171,59 @@ def serving_stream(td, torch, weights_path, parent_path, n, rate, seed=17, budge
             "cache_hits": cs["hits"], "windows_evaluated": cs["misses"], "wall_s": wall}
 
 
+def student_leg(td, torch, teacher, teacher_path, student_init, a, region, level, out, ref32, stream, wps32, dt32):
+    """Distil the half-width two-step student from the 20-step teacher (a short
+    run: a.student_pairs pairs, a.student_steps AdamW steps at batch 64, lr
+    2e-4), then time the same cold query with it: alone, judged by the FP32
+    teacher (fallback above 0.05 RMS), and with BF16 convolutions."""
+    import tempfile
+    from paper_2512_08309_amd import distill
+    t0 = time.perf_counter()
+    x, y, e = distill.make_pairs(td, torch, teacher_path, a.student_pairs, precision=1)
+    xh, yh, eh = distill.make_pairs(td, torch, teacher_path, 256, seed0=1 + a.student_pairs, precision=1)
+    t1 = time.perf_counter()
+    P, hist = distill.train(td, torch, student_init, x, y, e, a.student_steps, batch=64, lr=2e-4, log_every=100)
+    t2 = time.perf_counter()
+    held = distill.evaluate(td, torch, student_init, P, xh, yh, eh)
+    del x, y, e
+    res = {"student": "half-width UNet 64/128/128/256 (14.0 M parameters, 8.67 GFLOP per window), two-step "
+                      "consistency sampling at sigma 80 and 0.35, T = 2",
+           "distillation": {"pairs": a.student_pairs, "steps": a.student_steps, "batch": 64, "lr": 2e-4,
+                            "teacher": "20-step plain sampler of the bench model, BF16 convolutions",
+                            "pair_s": round(t1 - t0, 1), "train_s": round(t2 - t1, 1),
+                            "ms_per_train_step": round(1e3 * (t2 - t1) / a.student_steps, 1),
+                            "loss_first_last": [hist[0][1], hist[-1][1]],
+                            "heldout_window_rel_rmse_vs_teacher": held}}
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "student.tdw")
+        distill.save(td, student_init, P, path)
+        with td.Context(0) as s:
+            s.load_weights(path)
+            for name, judge, prec in (("student_fp32", None, 0), ("student_judged_fp32", teacher, 0),
+                                      ("student_bf16", None, 1)):
+                s.set_option("precision", prec)
+                s.set_judge(judge, 0.05)
+                s.sample_region_async(a.seed, *region, level, out, stream)      # first use
+                torch.cuda.synchronize()
+                s.cache_clear()
+                t0 = time.perf_counter()
+                s.sample_region_async(a.seed, *region, level, out, stream)
+                torch.cuda.synchronize()
+                dts = time.perf_counter() - t0
+                st = s.cache_stats()
+                rel = float(torch.linalg.vector_norm((out - ref32).double()) /
+                            torch.linalg.vector_norm(ref32.double()))
+                res[name] = {"ms_per_step": 1e3 * dts, "query_speedup_vs_fp32_plain": dt32 / dts,
+                             "window_denoises_per_s": st["denoiser_evals"] / dts, "windows": st["misses"],
+                             "judge_fallbacks": st["judge_fallbacks"],
+                             "rel_rmse_heightfield_vs_fp32_plain": rel}
+                print("[bench] %s done" % name, file=sys.stderr, flush=True)
+            s.set_judge(None, 0.0)
+    res["note"] = ("random-init teacher and a short distillation: the student does not reach the 2e-2 heightfield "
+                   "RMSE; its speed is measured at the error it has")
+    return res
+
+
 def main():
     a = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -228,10 +284,10 @@ def main():
     ks = ctx.kernel_stats()
     ctx.set_option("timing", 0)
     finite = bool(torch.isfinite(out).all().item())
+    ref32 = out.clone()
 
     lowp = None
     if a.bf16_steps > 0:
-        ref32 = out.clone()
         lowp = {}
         names = {1: "bf16", 2: "bf16_fp8w"}
         descr = {1: "BF16 convolution operands (activations and weights), FP32 accumulation",
@@ -262,6 +318,11 @@ def main():
                 if c16["ms"] else None,
                 "kernels_ms": {k: round(v["ms"], 1) for k, v in sorted(ks16.items(), key=lambda kv: -kv[1]["ms"])}}
         ctx.set_option("precision", 0)
+    student = None
+    if a.student_steps > 0 and a.config == "c2":
+        print("[bench] student distillation", file=sys.stderr, flush=True)
+        student = student_leg(td, torch, ctx, wpath, cached_weights("s2", wdir, 0), a, region, level, out, ref32,
+                              stream, windows / dt, dt)
     ctx.close()
 
     conv = ks.get("conv3x3_mfma_f32", {"launches": 0, "ms": 0.0, "flops": 0.0})
@@ -355,6 +416,7 @@ def main():
         "reduced_precision": lowp,
         "truncated_T": trunc,
         "serving": serve,
+        "student": student,
         "cpu_baseline": cpu,
         "output_finite": finite,
     }

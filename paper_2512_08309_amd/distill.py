@@ -18,6 +18,7 @@ sampling).  Forward and backward are the library's hand-written kernels
 """
 import argparse
 import json
+import sys
 import time
 
 import numpy as np
@@ -40,6 +41,7 @@ def make_pairs(td, torch, teacher_path, n, seed0=1, chunk=1024, precision=0):
         for i0 in range(0, n, chunk):
             i1 = min(n, i0 + chunk)
             t.denoise_steps(x[i0:i1], 0, K, y[i0:i1])
+            print("[distill] teacher pairs %d / %d" % (i1, n), file=sys.stderr, flush=True)
         torch.cuda.synchronize()
     return x, y, e
 
@@ -73,9 +75,32 @@ def train(td, torch, student_path, x, y, e, steps, batch=64, lr=2e-4, seed=0, lo
         tr.adamw(P, G, m, v, lr=lr, step=step)
         if l1 is not None:
             hist.append((step, l1 + l2))
+            print("[distill] step %d loss %.5f" % (step, l1 + l2), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     tr.close()
     return P, hist
+
+
+def student_windows(td, torch, student_path, P, x, e, sigmas=(80.0, 0.35), chunk=256):
+    """The student's two-step sample of independent windows: D(x; s0), re-noised
+    with s1 e, then D(.; s1) (consistency sampling without blending)."""
+    tr = td.Trainer(student_path)
+    out = torch.empty_like(x)
+    for i0 in range(0, x.shape[0], chunk):
+        xb = x[i0:i0 + chunk].contiguous()
+        d1 = torch.empty_like(xb)
+        tr.forward(P, xb, sigmas[0], d1)
+        x2 = (d1 + sigmas[1] * e[i0:i0 + chunk]).contiguous()
+        tr.forward(P, x2, sigmas[1], out[i0:i0 + chunk])
+    torch.cuda.synchronize()
+    tr.close()
+    return out
+
+
+def evaluate(td, torch, student_path, P, x, y, e):
+    """Relative RMSE of the student's two-step windows against the teacher's."""
+    s = student_windows(td, torch, student_path, P, x, e)
+    return float(torch.linalg.norm((s - y).flatten()) / torch.linalg.norm(y.flatten()))
 
 
 def save(td, student_path, P, out_path):
@@ -97,14 +122,22 @@ def main():
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--lr", type=float, default=2e-4)
     ap.add_argument("--teacher-precision", type=int, default=0)
+    ap.add_argument("--holdout", type=int, default=512, help="held-out pairs (seeds after the training seeds)")
     a = ap.parse_args()
     t0 = time.perf_counter()
-    x, y, e = make_pairs(td, torch, a.teacher, a.pairs, precision=a.teacher_precision)
+    x, y, e = make_pairs(td, torch, a.teacher, a.pairs + a.holdout, precision=a.teacher_precision)
     t1 = time.perf_counter()
-    P, hist = train(td, torch, a.student_init, x, y, e, a.steps, a.batch, a.lr)
+    xt, yt, et = x[:a.pairs], y[:a.pairs], e[:a.pairs]
+    xh, yh, eh = x[a.pairs:], y[a.pairs:], e[a.pairs:]
+    P0 = td.Trainer(a.student_init).load_params(a.student_init)
+    before = evaluate(td, torch, a.student_init, P0, xh, yh, eh)
+    P, hist = train(td, torch, a.student_init, xt, yt, et, a.steps, a.batch, a.lr)
     t2 = time.perf_counter()
+    after = evaluate(td, torch, a.student_init, P, xh, yh, eh)
     save(td, a.student_init, P, a.out)
-    print(json.dumps({"pairs": a.pairs, "pair_s": t1 - t0, "steps": a.steps, "train_s": t2 - t1, "loss": hist}))
+    print(json.dumps({"pairs": a.pairs, "holdout": a.holdout, "pair_s": t1 - t0, "steps": a.steps,
+                      "batch": a.batch, "lr": a.lr, "train_s": t2 - t1, "ms_per_step": 1e3 * (t2 - t1) / a.steps,
+                      "holdout_rel_rmse_before": before, "holdout_rel_rmse_after": after, "loss": hist}))
 
 
 if __name__ == "__main__":
