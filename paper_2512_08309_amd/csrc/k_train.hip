@@ -150,17 +150,23 @@ __global__ void sum_rows_kernel(const float* __restrict__ in, int rows, int C, i
   out[c] = accumulate ? out[c] + s : s;
 }
 
-// part[chunk][c] = sum of rows chunk*per .. of in[M][C]
-__global__ void colsum_part_kernel(const float* __restrict__ in, size_t M, int C, int per,
-                                   float* __restrict__ part) {
+// part[chunk][c] = sum of rows chunk*per .. of in[M][C].  A workgroup takes
+// 64 columns; its 4 waves take rows r0 + w, r0 + w + 4, ... (a wave reads 64
+// consecutive floats of a row), then the 4 partial sums are added in order.
+__global__ __launch_bounds__(256) void colsum_part_kernel(const float* __restrict__ in, size_t M, int C, int per,
+                                                          float* __restrict__ part) {
+  __shared__ float red[4][64];
   const int chunk = blockIdx.y;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= C) return;
+  const int cl = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + cl;
   const size_t r0 = (size_t)chunk * per;
   const size_t r1 = r0 + per < M ? r0 + per : M;
   float s = 0.f;
-  for (size_t r = r0; r < r1; ++r) s += in[r * C + c];
-  part[(size_t)chunk * C + c] = s;
+  if (c < C)
+    for (size_t r = r0 + w; r < r1; r += 4) s += in[r * C + c];
+  red[w][cl] = s;
+  __syncthreads();
+  if (w == 0 && c < C) part[(size_t)chunk * C + c] = ((red[0][cl] + red[1][cl]) + red[2][cl]) + red[3][cl];
 }
 
 // Weight gradient of a 3x3 (taps 9, zero padding) or 1x1 conv over the
@@ -502,7 +508,7 @@ void tr_sum_rows(hipStream_t st, const float* in, int rows, int C, int accumulat
 void tr_colsum(hipStream_t st, const float* in, size_t M, int C, float* part, int nchunk, int accumulate,
                float* out) {
   const int per = (int)((M + nchunk - 1) / nchunk);
-  hipLaunchKernelGGL(colsum_part_kernel, dim3(blocks(C), nchunk), dim3(256), 0, st, in, M, C, per, part);
+  hipLaunchKernelGGL(colsum_part_kernel, dim3((C + 63) / 64, nchunk), dim3(256), 0, st, in, M, C, per, part);
   TD_LAUNCHED();
   tr_sum_rows(st, part, nchunk, C, accumulate, out);
 }

@@ -326,7 +326,7 @@ float* Trainer::gradbuf(const float* act, size_t n, hipStream_t st) {
 }
 
 void Trainer::bias_grad(hipStream_t st, const float* dY, size_t M, int C_, float* out) {
-  const int nchunk = (int)std::min<size_t>(256, (M + 1023) / 1024);
+  const int nchunk = (int)std::min<size_t>(1024, (M + 255) / 256);
   float* part = ba_.take((size_t)nchunk * C_);
   tr_colsum(st, dY, M, C_, part, nchunk, 1, out);
 }
@@ -406,7 +406,7 @@ void Trainer::res_bwd(hipStream_t st, Node& n, float* G, float* de2) {
   gn_param_grads(st, dgp, dbp, n.cout, G, p + "gn2");
   // noise-level bias (conv1.bias + Lin_emb(e2))
   float* db = ba_.take(n.cout);
-  const int nchunk = (int)std::min<size_t>(256, (px + 1023) / 1024);
+  const int nchunk = (int)std::min<size_t>(1024, (px + 255) / 256);
   float* cp = ba_.take((size_t)nchunk * n.cout);
   tr_colsum(st, dh1, px, n.cout, cp, nchunk, 0, db);
   tr_emb_bias_bwd(st, db, e2_, prm(p + "emb.weight"), n.cout, emb, grd(G, p + "emb.weight"), grd(G, p + "emb.bias"),
