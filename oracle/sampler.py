@@ -24,7 +24,9 @@ TEST INFRASTRUCTURE (oracle).
   s_{k+1} G(step = k + 1) on the window's pixels.  With a judge (Model.judge
   = (teacher, threshold)), a window whose denoised estimate differs from the
   teacher's one-step estimate D_teacher(x; s_k) by more than the threshold
-  in RMS over the window takes the teacher's estimate instead.
+  in RMS over the window takes, instead of its estimate, the teacher's plain
+  sampler run on that window from s_k to 0: Euler steps through s_k, then
+  the teacher's schedule values below s_k, then 0.
 * Hierarchy (Sec. 5.1; DAGs of infinite tensors, infinite-tensor appendix):
   a model whose header has "cond" = {channels, factor f} is the child of a
   parent model (Model.parent).  Window i of the child receives, besides
@@ -110,16 +112,33 @@ def cond_windows(src, windows, model):
     return np.stack(out)
 
 
+def teacher_trajectory(teacher, x, sigma, windows, cond):
+    """The teacher's plain (Euler) sampler on windows x at noise level sigma,
+    down to 0 through its own schedule values below sigma."""
+    seq = [sigma] + [v for v in teacher.sched[:-1] if v < sigma] + [0.0]
+    for a, b in zip(seq, seq[1:]):
+        D = teacher.denoiser(x, a, windows, cond if teacher.cond else None)
+        x = x + euler_factor(a, b) * (x - D)
+    return x
+
+
 def judged(model, D, x, sigma, windows, cond):
-    """The student's estimate per window, or the teacher's where their RMS
-    difference over the window exceeds the threshold."""
+    """The student's estimate per window, or the teacher's plain sampler where
+    the student differs from the teacher's one-step estimate by more than the
+    threshold (RMS over the window)."""
     teacher, thr = model.judge
     DT = teacher.denoiser(x, sigma, windows, cond if teacher.cond else None)
     r = np.sqrt(((D - DT) ** 2).mean(axis=(1, 2, 3)))
     model.residuals.extend(float(v) for v in r)
     use = r > thr
     model.fallbacks += int(use.sum())
-    return np.where(use[:, None, None, None], DT, D)
+    if not use.any():
+        return D
+    out = D.copy()
+    idx = np.nonzero(use)[0]
+    out[idx] = teacher_trajectory(teacher, x[idx], sigma, [windows[i] for i in idx],
+                                  None if cond is None else cond[idx])
+    return out
 
 
 def level_step(model, j_next, region_next, region, windows, t, cond_src=None, seed=None):
