@@ -48,6 +48,8 @@ def parse():
     p.add_argument("--truncated", default="c2t2", help="truncated-T config timed cold ('' = skip)")
     p.add_argument("--serve-queries", type=int, default=256, help="queries of the serving stream (0 = skip)")
     p.add_argument("--serve-rate", type=float, default=256.0, help="Poisson arrival rate, queries/s")
+    p.add_argument("--serve-rate-sustained", type=float, default=32.0,
+                   help="a second, lower arrival rate the server keeps up with (0 = skip)")
     p.add_argument("--student-steps", type=int, default=300,
                    help="AdamW steps of the in-bench student distillation (0 = skip the student leg)")
     p.add_argument("--student-pairs", type=int, default=4096, help="teacher pairs of the in-bench distillation")
@@ -371,6 +373,12 @@ def main():
         print("[bench] serving stream", file=sys.stderr, flush=True)
         serve = serving_stream(td, torch, cached_weights("c1h", wdir, 0), cached_weights("cc", wdir, 0),
                                a.serve_queries, a.serve_rate)
+        if a.serve_rate_sustained > 0:
+            print("[bench] serving stream (sustained rate)", file=sys.stderr, flush=True)
+            serve = {"offered_%g_qps" % a.serve_rate: serve,
+                     "offered_%g_qps" % a.serve_rate_sustained:
+                         serving_stream(td, torch, cached_weights("c1h", wdir, 0), cached_weights("cc", wdir, 0),
+                                        a.serve_queries, a.serve_rate_sustained)}
     cpu = None
     if not a.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)

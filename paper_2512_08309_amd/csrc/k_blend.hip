@@ -152,10 +152,10 @@ __global__ __launch_bounds__(256) void cond_gather_kernel(const CondSrc* __restr
 
 // Judge: one workgroup per window.  Fixed-order reduction (thread-strided
 // partial sums, then a fixed tree), so the decision does not depend on the
-// batch a window is in.
+// batch a window is in.  flags[b] = 1 where the RMS of ds - dt over the
+// window exceeds thr.
 __global__ __launch_bounds__(256) void judge_kernel(const float* __restrict__ ds, const float* __restrict__ dt,
-                                                    int H, int C, float thr, const float* __restrict__ w1d,
-                                                    float* const* __restrict__ slots,
+                                                    int H, int C, float thr, int* __restrict__ flags,
                                                     unsigned long long* __restrict__ counter) {
   __shared__ float red[256];
   const int b = blockIdx.x;
@@ -173,27 +173,76 @@ __global__ __launch_bounds__(256) void judge_kernel(const float* __restrict__ ds
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  const bool use_t = __builtin_sqrtf(red[0] / (float)n) > thr;
-  if (use_t && threadIdx.x == 0 && counter) atomicAdd(counter, 1ull);
-  const float* src = use_t ? t : s;
-  float* o = slots[b];
-  for (int e = threadIdx.x; e < n; e += 256) {
-    const int p = e / C;
-    const int v = p / H, u = p - v * H;
-    o[e] = (w1d[u] * w1d[v]) * src[e];
+  if (threadIdx.x == 0) {
+    const bool fall = __builtin_sqrtf(red[0] / (float)n) > thr;
+    flags[b] = fall ? 1 : 0;
+    if (fall && counter) atomicAdd(counter, 1ull);
   }
+}
+
+// The flagged windows idx[j] (j < nf) of a canvas batch, packed: out[j] =
+// window j's input, widx_out[j] = its window index.
+__global__ __launch_bounds__(256) void compact_kernel(const float* __restrict__ canvas, int canvas_w,
+                                                      const int* __restrict__ origins, const int* __restrict__ widx,
+                                                      const int* __restrict__ idx, int H, int C,
+                                                      float* __restrict__ out, int* __restrict__ widx_out) {
+  const int j = blockIdx.y;
+  const int b = idx[j];
+  const int per = H * H * C;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e == 0) {
+    widx_out[2 * j] = widx[2 * b];
+    widx_out[2 * j + 1] = widx[2 * b + 1];
+  }
+  if (e >= per) return;
+  const int c = e % C, p = e / C;
+  const int v = p / H, u = p - v * H;
+  const int ox = origins[2 * b], oy = origins[2 * b + 1];
+  out[(size_t)j * per + e] = canvas[((size_t)(oy + v) * canvas_w + ox + u) * C + c];
+}
+
+// slots[b] = W (x) (pos[b] < 0 ? ds[b] : fb[pos[b]])
+__global__ __launch_bounds__(256) void select_kernel(const float* __restrict__ ds, const float* __restrict__ fb,
+                                                     const int* __restrict__ pos, int H, int C,
+                                                     const float* __restrict__ w1d, float* const* __restrict__ slots) {
+  const int b = blockIdx.y;
+  const int per = H * H * C;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= per) return;
+  const int p = e / C;
+  const int v = p / H, u = p - v * H;
+  const int k = pos[b];
+  const float x = k < 0 ? ds[(size_t)b * per + e] : fb[(size_t)k * per + e];
+  slots[b][e] = (w1d[u] * w1d[v]) * x;
 }
 
 }  // namespace
 
-void launch_judge(hipStream_t st, const float* ds, const float* dt, int nwin, int H, int C, float thr,
-                  const float* w1d, float* const* slots, unsigned long long* counter) {
+void launch_judge(hipStream_t st, const float* ds, const float* dt, int nwin, int H, int C, float thr, int* flags,
+                  unsigned long long* counter) {
   if (!nwin) return;
   prof_begin(st);
-  hipLaunchKernelGGL(judge_kernel, dim3(nwin), dim3(256), 0, st, ds, dt, H, C, thr, w1d, slots, counter);
+  hipLaunchKernelGGL(judge_kernel, dim3(nwin), dim3(256), 0, st, ds, dt, H, C, thr, flags, counter);
   TD_LAUNCHED();
   const double n = (double)nwin * H * H * C;
-  prof_end(st, K_BLEND, 3.0 * n, 12.0 * n);
+  prof_end(st, K_BLEND, 3.0 * n, 8.0 * n);
+}
+
+void launch_compact(hipStream_t st, const float* canvas, int canvas_w, const int* origins, const int* widx,
+                    const int* idx, int nf, int H, int C, float* out, int* widx_out) {
+  if (!nf) return;
+  const int per = H * H * C;
+  hipLaunchKernelGGL(compact_kernel, dim3((per + 255) / 256, nf), dim3(256), 0, st, canvas, canvas_w, origins, widx,
+                     idx, H, C, out, widx_out);
+  TD_LAUNCHED();
+}
+
+void launch_select(hipStream_t st, const float* ds, const float* fb, const int* pos, int nwin, int H, int C,
+                   const float* w1d, float* const* slots) {
+  if (!nwin) return;
+  const int per = H * H * C;
+  hipLaunchKernelGGL(select_kernel, dim3((per + 255) / 256, nwin), dim3(256), 0, st, ds, fb, pos, H, C, w1d, slots);
+  TD_LAUNCHED();
 }
 
 void launch_cond_gather(hipStream_t st, const CondSrc* src, int nb, int H, int cc, int factor, float* out) {

@@ -490,7 +490,7 @@ void Model::set_judge(Model* teacher, float threshold, unsigned long long* count
 size_t Model::workspace_bytes_per_window() const {
   const size_t state = (d.T < d.K ? (size_t)d.H * d.H * d.C * sizeof(float) + 2 * sizeof(int) : 0) +
                        (size_t)d.H * d.H * d.Cc * sizeof(float) +
-                       (d.consistency ? 2 * (size_t)d.H * d.H * d.C * sizeof(float) : 0);
+                       (d.consistency ? 2 * (size_t)d.H * d.H * d.C * sizeof(float) + 7 * sizeof(int) + 5 * 256 : 0);
   if (d.kind != "unet") return state;
   size_t f = 0;
   const int nl = (int)d.ch.size();
@@ -527,8 +527,23 @@ void Model::ensure_workspace(int max_batch) {
   state_ = nullptr;
   state_origins_ = nullptr;
   cond_ = d.Cc ? take((size_t)max_batch * d.H * d.H * d.Cc) : nullptr;
-  judge_s_ = d.consistency ? take((size_t)max_batch * d.H * d.H * d.C) : nullptr;
-  judge_t_ = d.consistency ? take((size_t)max_batch * d.H * d.H * d.C) : nullptr;
+  judge_s_ = judge_t_ = nullptr;
+  judge_flags_ = judge_idx_ = judge_pos_ = judge_widx_ = judge_origins_ = nullptr;
+  if (d.consistency) {
+    judge_s_ = take((size_t)max_batch * d.H * d.H * d.C);
+    judge_t_ = take((size_t)max_batch * d.H * d.H * d.C);
+    judge_flags_ = (int*)take((size_t)max_batch);
+    judge_idx_ = (int*)take((size_t)max_batch);
+    judge_pos_ = (int*)take((size_t)max_batch);
+    judge_widx_ = (int*)take((size_t)max_batch * 2);
+    judge_origins_ = (int*)take((size_t)max_batch * 2);
+    std::vector<int> o(2 * (size_t)max_batch);
+    for (int b = 0; b < max_batch; ++b) {
+      o[2 * b] = 0;
+      o[2 * b + 1] = b * d.H;
+    }
+    TD_HIP(hipMemcpy(judge_origins_, o.data(), o.size() * sizeof(int), hipMemcpyHostToDevice));
+  }
   if (d.T < d.K) {
     state_ = take((size_t)max_batch * d.H * d.H * d.C);
     state_origins_ = (int*)take((size_t)max_batch * 2);
@@ -796,14 +811,46 @@ void Model::run_batch(hipStream_t st, const WindowBatch& wb, int k) {
     if (judge_->d.Cc != d.Cc) t.cond = nullptr;
     judge_->ensure_workspace(std::max(judge_->max_batch(), wb.n));
     judge_->run_batch(st, t, judge_->sigma_slot(st, d.sched[k]));
-    launch_judge(st, judge_s_, judge_t_, wb.n, d.H, d.C, judge_thr_, w1d_, wb.d_slots, judge_count_);
+    launch_judge(st, judge_s_, judge_t_, wb.n, d.H, d.C, judge_thr_, judge_flags_, judge_count_);
+    // the flagged windows take the teacher's plain sampler from sigma_k to 0
+    std::vector<int> flags(wb.n), idx, pos(wb.n, -1);
+    TD_HIP(hipMemcpyAsync(flags.data(), judge_flags_, (size_t)wb.n * sizeof(int), hipMemcpyDeviceToHost, st));
+    TD_HIP(hipStreamSynchronize(st));
+    for (int b = 0; b < wb.n; ++b)
+      if (flags[b]) {
+        pos[b] = (int)idx.size();
+        idx.push_back(b);
+      }
+    TD_HIP(hipMemcpy(judge_pos_, pos.data(), pos.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (!idx.empty()) {
+      const int nf = (int)idx.size();
+      TD_HIP(hipMemcpy(judge_idx_, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice));
+      launch_compact(st, wb.canvas, wb.canvas_w, wb.d_origins, wb.d_widx, judge_idx_, nf, d.H, d.C, judge_t_,
+                     judge_widx_);
+      std::vector<double> seq{d.sched[k]};
+      for (int j = 0; j < judge_->d.K; ++j)
+        if (judge_->d.sched[j] < d.sched[k]) seq.push_back(judge_->d.sched[j]);
+      seq.push_back(0.0);
+      WindowBatch f;
+      f.canvas = judge_t_;
+      f.canvas_w = d.H;
+      f.d_origins = judge_origins_;
+      f.d_widx = judge_widx_;
+      f.n = nf;
+      f.mode = 2;
+      f.dout = judge_t_;   // each step reads a window element before writing it
+      for (size_t j = 0; j + 1 < seq.size(); ++j)
+        judge_->run_net(st, f, judge_->sigma_slot(st, seq[j]), seq[j + 1]);
+    }
+    launch_select(st, judge_s_, judge_t_, judge_pos_, wb.n, d.H, d.C, w1d_, wb.d_slots);
     return;
   }
   run_net(st, wb, k);
 }
 
-void Model::run_net(hipStream_t st, const WindowBatch& wb, int k) {
-  const double sigma = sigma_of(k), sigma_next = k < d.K ? d.sched[k + 1] : 0.0;
+void Model::run_net(hipStream_t st, const WindowBatch& wb, int k, double sigma_next_override) {
+  const double sigma = sigma_of(k);
+  const double sigma_next = sigma_next_override >= 0 ? sigma_next_override : (k < d.K ? d.sched[k + 1] : 0.0);
   const double sd = d.sigma_data;
   const double s2 = sigma * sigma + sd * sd;
   const float c_skip = (float)(sd * sd / s2), c_out = (float)(sigma * sd / std::sqrt(s2));

@@ -155,7 +155,10 @@ class Model {
   float judge_thr_ = 0.f;
   unsigned long long* judge_count_ = nullptr;
   float *judge_s_ = nullptr, *judge_t_ = nullptr;   // student / teacher estimates of a batch
-  void run_net(hipStream_t st, const WindowBatch& b, int k);
+  int *judge_flags_ = nullptr, *judge_idx_ = nullptr, *judge_pos_ = nullptr, *judge_widx_ = nullptr,
+      *judge_origins_ = nullptr;
+  // sigma_next_override >= 0: the Euler step goes to that level (mode 2)
+  void run_net(hipStream_t st, const WindowBatch& b, int k, double sigma_next_override = -1.0);
   float* state_ = nullptr;        // window states between the steps of one Phi
   int* state_origins_ = nullptr;  // (0, b*H) for b < ws_batch_
 
