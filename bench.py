@@ -361,7 +361,9 @@ def main():
         trunc["timed"] = {"config": a.truncated, "T": tctx.info("levels"), "ms_per_step": 1e3 * dtt,
                           "windows": stt["misses"], "denoiser_evals": stt["denoiser_evals"],
                           "denoiser_evals_per_s": stt["denoiser_evals"] / dtt,
-                          "speedup_vs_T20_step": (1e3 * dt / a.steps) / (1e3 * dtt)}
+                          "speedup_vs_T20_step": (1e3 * dt / a.steps) / (1e3 * dtt),
+                          "rel_rmse_heightfield_vs_T20": float(torch.linalg.vector_norm((out - ref32).double()) /
+                                                               torch.linalg.vector_norm(ref32.double()))}
         tctx.close()
 
     lat = None
