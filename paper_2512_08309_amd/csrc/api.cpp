@@ -404,10 +404,13 @@ void check_region(int64_t x0, int64_t y0, int64_t w, int64_t h) {
 void sample_latent(td_ctx* c, Arena& arena, uint64_t seed, Region r, int level, int layout, float* dev_out);
 
 // The parent's J_0 on the parent-resolution cover of `hull` (child pixels),
-// written to dst ([h][w][Cc], child-owned) and ordered before the child's
-// later work; rc receives the parent region.  The parent runs on its own
-// stream (and cache) after everything already enqueued on the child's.
-void sample_parent(td_ctx* c, Arena& arena, uint64_t seed, const Region& hull, float* dst, Region* rc) {
+// written to dst ([h][w][Cc], child-owned); rc receives the parent region.
+// The parent runs on its own stream (and cache) after everything already
+// enqueued on the child's.  Without `done` the child's later work waits for
+// it; with `done` the completion is recorded there and the caller makes the
+// child wait before it reads dst.
+void sample_parent(td_ctx* c, Arena& arena, uint64_t seed, const Region& hull, float* dst, Region* rc,
+                   hipEvent_t done = nullptr) {
   td_ctx* p = c->parent;
   *rc = parent_region(c->model->d, hull);
   check_region(rc->x0, rc->y0, rc->w, rc->h);
@@ -416,8 +419,12 @@ void sample_parent(td_ctx* c, Arena& arena, uint64_t seed, const Region& hull, f
   TD_HIP(hipEventRecord(c->xev, c->stream));
   TD_HIP(hipStreamWaitEvent(p->stream, c->xev, 0));
   sample_latent(p, arena, seed, *rc, 0, 0, dst);
-  TD_HIP(hipEventRecord(c->xev, p->stream));
-  TD_HIP(hipStreamWaitEvent(c->stream, c->xev, 0));
+  if (done) {
+    TD_HIP(hipEventRecord(done, p->stream));
+  } else {
+    TD_HIP(hipEventRecord(c->xev, p->stream));
+    TD_HIP(hipStreamWaitEvent(c->stream, c->xev, 0));
+  }
 }
 
 // Conditioning windows of a batch: window j (index (ix, iy)) reads the
@@ -1197,9 +1204,13 @@ struct SrvQuery {
   int cur = -1;
   hipEvent_t ev = nullptr;
   size_t mem = 0;
-  // conditioned model: the parent latent under this query's new windows
+  // conditioned model: the parent latent under this query's new windows,
+  // written on the parent's stream; cond_ev marks its completion, which the
+  // child's stream waits for before its first batch with this query's windows
   float* cond = nullptr;
   Region cond_r{};
+  hipEvent_t cond_ev = nullptr;
+  bool cond_pending = false;
 };
 
 constexpr int kRing = 8;
@@ -1224,6 +1235,9 @@ struct td_server {
   td::Arena ring[td::kRing];
   hipEvent_t ring_ev[td::kRing] = {};
   bool ring_used[td::kRing] = {};
+  hipEvent_t ring_pev[td::kRing] = {};   // the parent's work that used the slot's arena
+  bool ring_pused[td::kRing] = {};
+  bool parent_round = false;             // parent work issued in the current round
   uint64_t round = 0;
   float* batch_in = nullptr;
   size_t batch_cap = 0;
@@ -1340,7 +1354,10 @@ void plan_query(td_server* s, SrvQuery& Q, Arena& arena) {
     if (hull.w > 0) {
       const Region pr = parent_region(d, hull);
       Q.cond = take_canvas(s, (size_t)pr.w * pr.h * d.Cc);
-      sample_parent(c, arena, Q.r.seed, hull, Q.cond, &Q.cond_r);
+      if (!Q.cond_ev) TD_HIP(hipEventCreateWithFlags(&Q.cond_ev, hipEventDisableTiming));
+      sample_parent(c, arena, Q.r.seed, hull, Q.cond, &Q.cond_r, Q.cond_ev);
+      Q.cond_pending = true;
+      s->parent_round = true;
     }
   }
 }
@@ -1467,7 +1484,11 @@ bool run_round_batch(td_server* s, Arena& arena) {
   std::vector<CondSrc> cs(d.Cc ? nb : 0);
   for (int j = 0; j < (int)cs.size(); ++j) {
     const SrvTask& T = s->tasks[ids[j]];
-    const SrvQuery& O = s->q[T.q];
+    SrvQuery& O = s->q[T.q];
+    if (O.cond_pending) {   // the parent latent this window reads must be written
+      TD_HIP(hipStreamWaitEvent(st, O.cond_ev, 0));
+      O.cond_pending = false;
+    }
     cs[j] = cond_src(d, O.cond, O.cond_r.w, O.cond_r.x0 * d.cond_factor, O.cond_r.y0 * d.cond_factor, T.key.ix,
                      T.key.iy);
   }
@@ -1514,6 +1535,9 @@ void server_round(td_server* s) {
   td_ctx* c = s->c;
   const int slot = (int)(s->round % kRing);
   if (s->ring_used[slot]) TD_HIP(hipEventSynchronize(s->ring_ev[slot]));
+  if (s->ring_pused[slot]) TD_HIP(hipEventSynchronize(s->ring_pev[slot]));
+  s->ring_pused[slot] = false;
+  s->parent_round = false;
   Arena& arena = s->ring[slot];
   arena.reset();
   admit(s, arena);
@@ -1531,6 +1555,10 @@ void server_round(td_server* s) {
   judge_fence(c, false);
   TD_HIP(hipEventRecord(s->ring_ev[slot], c->stream));
   s->ring_used[slot] = true;
+  if (s->parent_round) {
+    TD_HIP(hipEventRecord(s->ring_pev[slot], c->parent->stream));
+    s->ring_pused[slot] = true;
+  }
   s->round++;
   // completions
   std::vector<uint64_t> still;
@@ -1571,7 +1599,10 @@ td_status td_server_create(td_ctx* c, size_t hbm_budget, int32_t max_inflight, t
     s->max_inflight = max_inflight;
     s->maxb = std::min(auto_batch(c), 4096);
     c->model->ensure_workspace(s->maxb);
-    for (int i = 0; i < kRing; ++i) TD_HIP(hipEventCreateWithFlags(&s->ring_ev[i], hipEventDisableTiming));
+    for (int i = 0; i < kRing; ++i) {
+      TD_HIP(hipEventCreateWithFlags(&s->ring_ev[i], hipEventDisableTiming));
+      TD_HIP(hipEventCreateWithFlags(&s->ring_pev[i], hipEventDisableTiming));
+    }
   });
   if (st != TD_OK) {
     td_server_destroy(s);
@@ -1586,6 +1617,7 @@ void td_server_destroy(td_server* s) {
   td_ctx* c = s->c;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  if (c->parent) (void)hipStreamSynchronize(c->parent->stream);   // parent latents still being written
   // release what unfinished queries hold: pins and not-yet-evaluated slots
   for (auto& kv : s->pending) {
     auto m = c->map.find(kv.first);
@@ -1601,11 +1633,14 @@ void td_server_destroy(td_server* s) {
       for (int i = std::max(Q.cur, 0); i < (int)Q.lv.size(); ++i) unpin_level(c, Q.r.seed, Q.lv[i].L);
     }
     if (Q.ev) (void)hipEventDestroy(Q.ev);
+    if (Q.cond_ev) (void)hipEventDestroy(Q.cond_ev);
   }
   for (float* p : s->all_canvas) (void)hipFree(p);
   if (s->batch_in) (void)hipFree(s->batch_in);
-  for (int i = 0; i < kRing; ++i)
+  for (int i = 0; i < kRing; ++i) {
     if (s->ring_ev[i]) (void)hipEventDestroy(s->ring_ev[i]);
+    if (s->ring_pev[i]) (void)hipEventDestroy(s->ring_pev[i]);
+  }
   delete s;
 }
 
@@ -1650,6 +1685,7 @@ td_status td_server_poll(td_server* s, uint64_t ticket, int32_t* done, double* l
   if (Q.state == 3) {
     if (latency_ms) *latency_ms = Q.t_done - Q.t_sub;
     if (Q.ev) (void)hipEventDestroy(Q.ev);
+    if (Q.cond_ev) (void)hipEventDestroy(Q.cond_ev);
     s->q.erase(it);
   }
   return TD_OK;
