@@ -53,6 +53,8 @@ def parse():
     p.add_argument("--student-steps", type=int, default=300,
                    help="AdamW steps of the in-bench student distillation (0 = skip the student leg)")
     p.add_argument("--student-pairs", type=int, default=4096, help="teacher pairs of the in-bench distillation")
+    p.add_argument("--micro-only", action="store_true",
+                   help="only the decode / noise micro-benchmarks (8192^2 heightfield, 8192^2 x 4 noise)")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="run one plain elementwise copy (read N MiB, write N MiB) before the steps, as the "
                         "reference dispatch that scales hardware byte counters")
@@ -173,6 +175,37 @@ def serving_stream(td, torch, weights_path, parent_path, n, rate, seed=17, budge
             "cache_hits": cs["hits"], "windows_evaluated": cs["misses"], "wall_s": wall}
 
 
+def micro_bench(td, torch, ctx, reps=5):
+    """HBM-bound kernels on their own: the Laplacian decode of a 1058^2 x 4 fBm
+    terrain latent (seed 21) to an 8192^2 heightfield, and the seed noise G on
+    8192^2 x 4 values (counter word 0); achieved GB/s of the bytes each must write."""
+    from synth.fbm import terrain_latent
+    lx, ly = 13 - 17, -1000001 - 17
+    lat = torch.from_numpy(terrain_latent(21, lx, ly, 1058, 1058)).cuda().contiguous()
+    out = torch.empty((8192, 8192), device="cuda")
+    noise = torch.empty((8192, 8192, 4), device="cuda")
+    ctx.lap_decode(lat, lx, ly, 8 * 13, 8 * -1000001, 8192, 8192, out)     # first use: scratch
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    e0.record()
+    for _ in range(reps):
+        ctx.lap_decode(lat, lx, ly, 8 * 13, 8 * -1000001, 8192, 8192, out, stream)
+    e1.record()
+    torch.cuda.synchronize()
+    dec_ms = e0.elapsed_time(e1) / reps
+    e0.record()
+    for _ in range(reps):
+        td.td_noise_region(7, 0, 0, noise, step=0, scale=80.0)
+    e1.record()
+    torch.cuda.synchronize()
+    noise_ms = e0.elapsed_time(e1) / reps
+    return {"decode_8192": {"ms": dec_ms, "GB_per_s_written": 8192 * 8192 * 4 / (dec_ms * 1e-3) / 1e9,
+                            "note": "all four decode kernels; 268 MB of heightfield written"},
+            "noise_8192x4": {"ms": noise_ms, "GB_per_s_written": noise.numel() * 4 / (noise_ms * 1e-3) / 1e9,
+                             "note": "Philox + bit-exact IEEE Box-Muller per pair: ALU-bound"}}
+
+
 def student_leg(td, torch, teacher, teacher_path, student_init, a, region, level, out, ref32, stream, wps32, dt32):
     """Distil the half-width two-step student from the 20-step teacher (a short
     run: a.student_pairs pairs, a.student_steps AdamW steps at batch 64, lr
@@ -243,6 +276,10 @@ def main():
     wdir = os.path.join(ROOT, ".td_weights")
     wpath = cached_weights(a.config, wdir, 0)
     ctx = td.Context(0).load_weights(wpath)
+    if a.micro_only:
+        print(json.dumps({"micro": micro_bench(td, torch, ctx)}))
+        ctx.close()
+        return
     if a.batch:
         ctx.set_option("batch", a.batch)
     K, C = ctx.info("steps"), ctx.info("channels")
@@ -287,6 +324,7 @@ def main():
     ctx.set_option("timing", 0)
     finite = bool(torch.isfinite(out).all().item())
     ref32 = out.clone()
+    micro = micro_bench(td, torch, ctx)
 
     lowp = None
     if a.bf16_steps > 0:
@@ -427,6 +465,7 @@ def main():
         "truncated_T": trunc,
         "serving": serve,
         "student": student,
+        "micro": micro,
         "cpu_baseline": cpu,
         "output_finite": finite,
     }

@@ -12,9 +12,9 @@
 //
 // Stages: (1) down8(P) per latent block as a 3x3 stencil on the latent;
 // (2) vertical then (3) horizontal 31-tap blur at latent
-// resolution; (4) the full-resolution pass, one thread per output pixel,
-// which is the HBM-bound one (4 B written per pixel, the latent read once
-// through the caches).
+// resolution; (4) the full-resolution pass, 8 x 1024-pixel tiles with their
+// inputs staged in LDS, which is the HBM-bound one (4 B written per pixel,
+// the latent read once).
 #include "td_internal.h"
 
 namespace td {
@@ -36,30 +36,6 @@ inline Span span_of(const DecodeArgs& a) {
   s.yl = floordiv(2 * a.Y0 - 7, 16);
   s.yh = floordiv(2 * (a.Y0 + a.H - 1) - 7, 16) + 1;
   return s;
-}
-
-// bilinear sample of L (= sigma_low * channel 0) at full-res pixel with
-// coordinates relative to 8*lx0, 8*ly0 (both >= 8 by the apron).
-__device__ __forceinline__ float up8_latent(const float* lat, int lw, int C, float sl, int Xr, int Yr) {
-  int ix = (2 * Xr - 7) >> 4, iy = (2 * Yr - 7) >> 4;
-  float fx = (float)((2 * Xr - 7) - 16 * ix) * 0.0625f;
-  float fy = (float)((2 * Yr - 7) - 16 * iy) * 0.0625f;
-  const float* r0 = lat + ((size_t)iy * lw + ix) * C;
-  const float* r1 = r0 + (size_t)lw * C;
-  float a0 = (1.f - fy) * r0[0] + fy * r1[0];
-  float a1 = (1.f - fy) * r0[C] + fy * r1[C];
-  return sl * ((1.f - fx) * a0 + fx * a1);
-}
-
-__device__ __forceinline__ float residual_at(const float* lat, int lw, int C, float sr, const float* atoms,
-                                             int Xr, int Yr) {
-  if (C < 2) return 0.f;
-  const float* p = lat + ((size_t)(Yr >> 3) * lw + (Xr >> 3)) * C;
-  int a = (Yr & 7) * 8 + (Xr & 7);
-  float h = 0.f;
-  int nk = C - 1 < 3 ? C - 1 : 3;
-  for (int k = 0; k < nk; ++k) h += p[1 + k] * atoms[k * 64 + a];
-  return sr * h;
 }
 
 // (1) D(bx, by) = mean of P over latent block (bx, by).  Bilinear
@@ -110,39 +86,70 @@ __global__ __launch_bounds__(256) void blur_h_kernel(const float* __restrict__ i
 }
 
 // (4) full resolution: z = up8(L_hat) + Hres, elevation = sign(z) z^2.
-// Each thread writes 4 consecutive pixels of a row (one 16-byte store when
-// the row is 16-byte aligned).
-__device__ __forceinline__ float decode_px(const float* __restrict__ lat, int lw, int C, float sr,
-                                           const float* __restrict__ atoms, const float* __restrict__ lhat,
-                                           int nlx, int hx0, int hy0, int Xr, int Yr) {
-  int ix = ((2 * Xr - 7) >> 4) - hx0, iy = ((2 * Yr - 7) >> 4) - hy0;
-  float fx = (float)((2 * Xr - 7) - 16 * ((2 * Xr - 7) >> 4)) * 0.0625f;
-  float fy = (float)((2 * Yr - 7) - 16 * ((2 * Yr - 7) >> 4)) * 0.0625f;
-  const float* r0 = lhat + (size_t)iy * nlx + ix;
-  float a0 = (1.f - fy) * r0[0] + fy * r0[nlx];
-  float a1 = (1.f - fy) * r0[1] + fy * r0[nlx + 1];
-  float z = (1.f - fx) * a0 + fx * a1 + residual_at(lat, lw, C, sr, atoms, Xr, Yr);
-  return (z < 0.f ? -z : z) * z;
-}
-
-__global__ __launch_bounds__(256) void decode_out_kernel(const float* __restrict__ lat, int lw, int C, float sr,
+// A workgroup writes a tile of 8 rows x 1024 columns; the L_hat rows and
+// columns, the residual latents of the (at most 2 x 130) blocks it covers
+// and the atom table are staged in LDS once, so each output pixel costs LDS
+// reads and its share of one 16-byte store.
+constexpr int kTileW = 1024, kTileH = 8;
+__global__ __launch_bounds__(256) void decode_out_kernel(const float* __restrict__ lat, int lw, int lh, int C, float sr,
                                                          const float* __restrict__ atoms,
-                                                         const float* __restrict__ lhat, int nlx, int hx0,
+                                                         const float* __restrict__ lhat, int nlx, int nly, int hx0,
                                                          int hy0, int xo, int yo, int W, int H,
                                                          float* __restrict__ out) {
-  int X = 4 * (blockIdx.x * 256 + threadIdx.x);
-  int Y = blockIdx.y;
+  __shared__ float sl[3][kTileW / 8 + 4];        // L_hat rows iy0..iy0+2, columns ix0..
+  __shared__ float sres[2][kTileW / 8 + 2][3];   // residual latents of blocks by0.., bx0..
+  __shared__ float sat[3 * 64];
+  const int tid = threadIdx.x;
+  const int X0 = blockIdx.x * kTileW, Y0 = blockIdx.y * kTileH;
+  const int Xa = xo + X0, Ya = yo + Y0;                   // relative full-res coordinates (>= 8)
+  const int ix0 = ((2 * Xa - 7) >> 4) - hx0, iy0 = ((2 * Ya - 7) >> 4) - hy0;
+  const int bx0 = Xa >> 3, by0 = Ya >> 3;
+  const int nk = C - 1 < 3 ? C - 1 : 3;
+  for (int e = tid; e < 3 * (kTileW / 8 + 4); e += 256) {
+    const int r = e / (kTileW / 8 + 4), c = e % (kTileW / 8 + 4);
+    const int gy = iy0 + r, gx = ix0 + c;
+    sl[r][c] = (gy < nly && gx < nlx) ? lhat[(size_t)gy * nlx + gx] : 0.f;
+  }
+  for (int e = tid; e < 2 * (kTileW / 8 + 2) * 3; e += 256) {
+    const int k = e % 3, c = (e / 3) % (kTileW / 8 + 2), r = e / (3 * (kTileW / 8 + 2));
+    const int gy = by0 + r, gx = bx0 + c;
+    float v = 0.f;
+    if (k < nk && gx < lw && gy < lh) v = lat[((size_t)gy * lw + gx) * C + 1 + k];
+    sres[r][c][k] = v;
+  }
+  for (int e = tid; e < 3 * 64; e += 256) sat[e] = e < nk * 64 ? atoms[e] : 0.f;
+  __syncthreads();
+  const int X = X0 + 4 * tid;
   if (X >= W) return;
-  int Yr = yo + Y;
-  float v[4];
+  for (int yy = 0; yy < kTileH; ++yy) {
+    const int Y = Y0 + yy;
+    if (Y >= H) break;
+    const int Yr = yo + Y;
+    const int ty = (2 * Yr - 7) >> 4;
+    const int ry = ty - hy0 - iy0;
+    const float fy = (float)((2 * Yr - 7) - 16 * ty) * 0.0625f;
+    const int rb = (Yr >> 3) - by0;
+    float v[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
-    v[q] = (X + q < W) ? decode_px(lat, lw, C, sr, atoms, lhat, nlx, hx0, hy0, xo + X + q, Yr) : 0.f;
-  float* o = out + (size_t)Y * W + X;
-  if (X + 3 < W && (((uintptr_t)o) & 15) == 0) {
-    *reinterpret_cast<float4*>(o) = make_float4(v[0], v[1], v[2], v[3]);
-  } else {
-    for (int q = 0; q < 4 && X + q < W; ++q) o[q] = v[q];
+    for (int q = 0; q < 4; ++q) {
+      const int Xr = xo + X + q;
+      const int tx = (2 * Xr - 7) >> 4;
+      const int cx = tx - hx0 - ix0;
+      const float fx = (float)((2 * Xr - 7) - 16 * tx) * 0.0625f;
+      const float a0 = (1.f - fy) * sl[ry][cx] + fy * sl[ry + 1][cx];
+      const float a1 = (1.f - fy) * sl[ry][cx + 1] + fy * sl[ry + 1][cx + 1];
+      const int a = (Yr & 7) * 8 + (Xr & 7);
+      const float* rr = sres[rb][(Xr >> 3) - bx0];
+      const float h = sr * ((rr[0] * sat[a] + rr[1] * sat[64 + a]) + rr[2] * sat[128 + a]);
+      const float z = (1.f - fx) * a0 + fx * a1 + (C < 2 ? 0.f : h);
+      v[q] = (z < 0.f ? -z : z) * z;
+    }
+    float* o = out + (size_t)Y * W + X;
+    if (X + 3 < W && (((uintptr_t)o) & 15) == 0) {
+      *reinterpret_cast<float4*>(o) = make_float4(v[0], v[1], v[2], v[3]);
+    } else {
+      for (int q = 0; q < 4 && X + q < W; ++q) o[q] = v[q];
+    }
   }
 }
 
@@ -175,9 +182,9 @@ void launch_decode(hipStream_t st, const DecodeArgs& a) {
                      a.work0);
   TD_LAUNCHED();
   const int xo = (int)(a.X0 - 8 * a.lx0), yo = (int)(a.Y0 - 8 * a.ly0);
-  hipLaunchKernelGGL(decode_out_kernel, dim3((a.W + 1023) / 1024, a.H), dim3(256), 0, st, a.latent, a.lw, a.C,
-                     a.sigma_res, a.atoms, a.work0, nx, (int)(s.xl - a.lx0), (int)(s.yl - a.ly0), xo, yo, a.W,
-                     a.H, a.out);
+  hipLaunchKernelGGL(decode_out_kernel, dim3((a.W + kTileW - 1) / kTileW, (a.H + kTileH - 1) / kTileH), dim3(256), 0,
+                     st, a.latent, a.lw, a.lh, a.C, a.sigma_res, a.atoms, a.work0, nx, ny, (int)(s.xl - a.lx0),
+                     (int)(s.yl - a.ly0), xo, yo, a.W, a.H, a.out);
   TD_LAUNCHED();
   prof_end(st, K_DECODE, 20.0 * a.W * a.H, 4.0 * (double)a.W * a.H + 4.0 * (double)nxD * nyD * a.C);
 }
