@@ -317,6 +317,13 @@ td_status td_train_create(int hip_device, const char *path, td_trainer **out);
 void td_train_destroy(td_trainer *tr);
 const char *td_train_last_error(const td_trainer *tr);
 
+/* 0 (default): FP32 convolutions.  1: BF16 operands (activations and
+ * weights, converted from the FP32 masters at every forward) for the
+ * forward and data-gradient convolutions, FP32 accumulation; weight
+ * gradients, GroupNorm, attention and the optimizer stay FP32.
+ * TD_E_INVAL for other values. */
+td_status td_train_set_precision(td_trainer *tr, int32_t precision);
+
 /* Length in floats of the flat parameter buffer (the data section). */
 td_status td_train_param_count(td_trainer *tr, size_t *n);
 

@@ -258,8 +258,8 @@ void launch_lp_w(hipStream_t st, const ConvLpArgs& a, bool fast) {
 }  // namespace
 
 void launch_conv_lp(hipStream_t st, const ConvLpArgs& a) {
-  TD_CHECK(a.cin % 8 == 0 && (a.cout % 128 == 0 || a.cout == 64 || a.cout == 32 || a.cout == 16), -5,
-           "bf16 conv: needs C_in % 8 == 0 and C_out in {16, 32, 64, 128k}");
+  TD_CHECK(a.cin % 8 == 0 && a.cout % 16 == 0 && a.cout > 0, -5,
+           "bf16 conv: needs C_in % 8 == 0 and C_out % 16 == 0");
   TD_CHECK(a.taps == 9 || a.taps == 1, -5, "bf16 conv: taps must be 9 or 1");
   if (!a.nb) return;
   const bool fast = a.cin % 32 == 0;
@@ -269,8 +269,8 @@ void launch_conv_lp(hipStream_t st, const ConvLpArgs& a) {
   prof_begin(st);
   TD_CHECK(!a.w8 || a.wscale, -5, "fp8 weights need per-channel scales");
   if (a.cout % 128 == 0) launch_lp_w<128, 2, 2>(st, a, fast);
-  else if (a.cout == 64) launch_lp_w<64, 2, 2>(st, a, fast);
-  else if (a.cout == 32) launch_lp_w<32, 4, 1>(st, a, fast);
+  else if (a.cout % 64 == 0) launch_lp_w<64, 2, 2>(st, a, fast);
+  else if (a.cout % 32 == 0) launch_lp_w<32, 4, 1>(st, a, fast);
   else launch_lp_w<16, 4, 1>(st, a, fast);
   prof_end(st, a.taps == 9 ? K_CONV3_LP : K_CONV1_LP, 2.0 * Md * a.cout * a.taps * a.cin,
            2.0 * Md * a.cin + 2.0 * a.kp * a.cout + 4.0 * Md * a.cout * (a.res ? 2 : 1));

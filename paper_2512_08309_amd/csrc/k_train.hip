@@ -31,6 +31,24 @@ __global__ void relayout_kernel(const float* __restrict__ w, int co, int ci, int
   if (flip) flip[((size_t)(kk - 1 - t) * co_pad + o) * ci + i] = v;
 }
 
+// BF16 weights for the reduced-precision convolution, [rows][kp] with
+// K = tap * cols + col, zero-padded to kp.  flip = 0: the forward conv
+// (rows = co, cols = ci, value w[o][i][t]); flip = 1: the data-gradient conv
+// (rows = ci, cols = co, value w[o][i][kk-1-t]).
+__global__ void lp_weights_kernel(const float* __restrict__ w, int co, int ci, int kk, int kp, int flip,
+                                  __bf16* __restrict__ out) {
+  const int rows = flip ? ci : co, cols = flip ? co : ci;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * kp) return;
+  const int r = e / kp, k = e % kp;
+  float v = 0.f;
+  if (k < kk * cols) {
+    const int t = k / cols, c = k % cols;
+    v = flip ? w[((size_t)c * ci + r) * kk + (kk - 1 - t)] : w[((size_t)r * ci + c) * kk + t];
+  }
+  out[e] = (__bf16)v;
+}
+
 // out[b][y][x][c] = concat(up0 ? s0[b][y/2][x/2] : s0[b][y][x], s1[b][y][x])
 __global__ void dense_in_kernel(const float* __restrict__ s0, int c0, int up0, const float* __restrict__ s1,
                                 int c1, int lh, int lw, size_t n, float* __restrict__ out) {
@@ -474,6 +492,13 @@ inline unsigned blocks(size_t n) { return (unsigned)((n + 255) / 256); }
 void tr_relayout(hipStream_t st, const float* w, int co, int ci, int kk, int co_pad, float* fwd, float* flip) {
   const int n = co_pad * ci * kk;
   hipLaunchKernelGGL(relayout_kernel, dim3(blocks(n)), dim3(256), 0, st, w, co, ci, kk, co_pad, fwd, flip);
+  TD_LAUNCHED();
+}
+
+void tr_lp_weights(hipStream_t st, const float* w, int co, int ci, int kk, int kp, int flip, uint16_t* out) {
+  const int n = (flip ? ci : co) * kp;
+  hipLaunchKernelGGL(lp_weights_kernel, dim3(blocks(n)), dim3(256), 0, st, w, co, ci, kk, kp, flip,
+                     reinterpret_cast<__bf16*>(out));
   TD_LAUNCHED();
 }
 

@@ -55,6 +55,7 @@ void tr_split_bwd(hipStream_t st, const float* dd, int c0, int up0, int c1, int 
                   float* ds0, float* ds1);
 void tr_adamw(hipStream_t st, float* w, const float* g, float* m, float* v, size_t n, float lr, float b1, float b2,
               float eps, float wd, int step);
+void tr_lp_weights(hipStream_t st, const float* w, int co, int ci, int kk, int kp, int flip, uint16_t* out);
 
 namespace {
 
@@ -117,6 +118,12 @@ class Trainer {
   }
   void load(const std::string& path);
   size_t param_floats() const { return nparam_; }
+  // 0: FP32 convolutions; 1: BF16 operands of the forward and data-gradient
+  // convolutions (FP32 accumulation, FP32 master weights and weight gradients)
+  void set_precision(int p) {
+    TD_CHECK(p == 0 || p == 1, -1, "training precision must be 0 or 1");
+    prec_ = p;
+  }
   void forward(hipStream_t st, const float* P, const float* x, int nb, double sigma, float* D);
   void backward(hipStream_t st, const float* P, const float* dD, float* G);
 
@@ -161,6 +168,13 @@ class Trainer {
   std::unordered_map<const float*, float*> grad_;
   // per-forward weight layouts: forward [tap][ci][co] and flipped [tap][co_pad][ci]
   std::map<std::string, std::pair<float*, float*>> wl_;
+  // BF16 copies (precision 1): forward [co][kp] and data-gradient [ci][kp']
+  struct LpW {
+    uint16_t *fwd = nullptr, *flip = nullptr;
+    int kp = 0, kpf = 0;
+  };
+  std::map<const float*, LpW> lp_;   // keyed by the forward layout's pointer
+  int prec_ = 0;
   float* gn_scale_ = nullptr;
   float* gn_shift_ = nullptr;
   double* gn_part_ = nullptr;
@@ -187,7 +201,38 @@ class Trainer {
       e.second = fa_.take((size_t)co_pad * ci * kk);
     }
     tr_relayout(st, prm(name), co, ci, kk, co_pad, e.first, e.second);
+    if (!prec_) return;
+    // the BF16 kernel takes inputs in multiples of 8 channels and outputs in
+    // multiples of 16; other shapes (the 4-channel input and output convs) stay FP32
+    LpW l;
+    if (co % 16 == 0 && ci % 8 == 0) {
+      l.kp = conv_lp_kp(kk, ci);
+      l.fwd = (uint16_t*)fa_.take(((size_t)co * l.kp + 1) / 2);
+      tr_lp_weights(st, prm(name), co, ci, kk, l.kp, 0, l.fwd);
+    }
+    if (ci % 16 == 0 && co % 8 == 0) {
+      l.kpf = conv_lp_kp(kk, co);
+      l.flip = (uint16_t*)fa_.take(((size_t)ci * l.kpf + 1) / 2);
+      tr_lp_weights(st, prm(name), co, ci, kk, l.kpf, 1, l.flip);
+    }
+    lp_[e.first] = l;
+    lp_[e.second] = l;
   }
+  // BF16 copy of a dense FP32 activation (precision 1)
+  const uint16_t* to_bf16(ChunkArena& ar, const float* x, int C_, int lh) {
+    uint16_t* o = (uint16_t*)ar.take((((size_t)nb_ << (2 * lh)) * C_ + 1) / 2);
+    ApplyArgs a{};
+    a.src0 = x;
+    a.c0 = C_;
+    a.act = 0;
+    a.nb = nb_;
+    a.lh = lh;
+    a.lw = lh;
+    a.out = o;
+    launch_apply(st_, a);
+    return o;
+  }
+  hipStream_t st_ = nullptr;
   // GroupNorm statistics of the virtual input concat(up0 ? up(s0) : s0, s1)
   void gn_stats(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int lh, float* mean,
                 float* rstd, const std::string& pre);
@@ -284,6 +329,25 @@ void Trainer::gn_stats(hipStream_t st, const float* s0, int c0, int up0, const f
 float* Trainer::conv(hipStream_t st, const float* A, int cin, int lh, int cout, int taps, const float* wfwd,
                      const float* bias, const float* res) {
   float* out = fa_.take(((size_t)nb_ << (2 * lh)) * cout);
+  auto lp = lp_.find(wfwd);
+  if (prec_ && lp != lp_.end() && lp->second.fwd) {
+    st_ = st;
+    ConvLpArgs c{};
+    c.act = to_bf16(ba_, A, cin, lh);
+    c.cin = cin;
+    c.nb = nb_;
+    c.lh = lh;
+    c.lw = lh;
+    c.cout = cout;
+    c.taps = taps;
+    c.kp = lp->second.kp;
+    c.wt = lp->second.fwd;
+    c.bias = bias;
+    c.res = res;
+    c.out = out;
+    launch_conv_lp(st, c);
+    return out;
+  }
   ConvArgs c{};
   c.src0 = A;
   c.c0 = cin;
@@ -302,6 +366,23 @@ float* Trainer::conv(hipStream_t st, const float* A, int cin, int lh, int cout, 
 
 float* Trainer::dgrad(hipStream_t st, const float* dY, int co, int lh, int ci, int taps, const float* flip) {
   float* out = ba_.take(((size_t)nb_ << (2 * lh)) * ci);
+  auto lp = lp_.find(flip);
+  if (prec_ && lp != lp_.end() && lp->second.flip) {
+    st_ = st;
+    ConvLpArgs c{};
+    c.act = to_bf16(ba_, dY, co, lh);
+    c.cin = co;
+    c.nb = nb_;
+    c.lh = lh;
+    c.lw = lh;
+    c.cout = ci;
+    c.taps = taps;
+    c.kp = lp->second.kpf;
+    c.wt = lp->second.flip;
+    c.out = out;
+    launch_conv_lp(st, c);
+    return out;
+  }
   ConvArgs c{};
   c.src0 = dY;
   c.c0 = co;
@@ -477,7 +558,9 @@ void Trainer::forward(hipStream_t st, const float* P, const float* x, int nb, do
   sigma_ = sigma;
   x_ = x;
   fa_.reset();
+  ba_.reset();
   wl_.clear();
+  lp_.clear();
   gn_cap_ = 0;
   tape_.clear();
   const int nl = (int)ch.size(), c0 = ch[0], lH = ilog2i(H);
@@ -774,6 +857,11 @@ void td_train_destroy(td_trainer* t) {
 }
 
 const char* td_train_last_error(const td_trainer* t) { return t ? t->err.c_str() : ""; }
+
+td_status td_train_set_precision(td_trainer* t, int32_t precision) {
+  if (!t) return TD_E_INVAL;
+  return tguard(t, [&] { t->tr.set_precision(precision); });
+}
 
 td_status td_train_param_count(td_trainer* t, size_t* n) {
   if (!t || !n) return TD_E_INVAL;

@@ -11,7 +11,8 @@ steps).  The student (a consistency-sampled weight file with noise levels
 
 with e = G(i) on counter word 1 (the noise its second step re-draws when
 sampling).  Forward and backward are the library's hand-written kernels
-(td_train_*); AdamW updates FP32 master weights.  Usage:
+(td_train_*): BF16 convolution operands by default, FP32 master weights,
+weight gradients and AdamW.  Usage:
 
     python -m paper_2512_08309_amd.distill TEACHER.tdw STUDENT_INIT.tdw OUT.tdw \\
         [--pairs 50000] [--steps 800] [--batch 64] [--lr 2e-4]
@@ -46,9 +47,11 @@ def make_pairs(td, torch, teacher_path, n, seed0=1, chunk=1024, precision=0):
     return x, y, e
 
 
-def train(td, torch, student_path, x, y, e, steps, batch=64, lr=2e-4, seed=0, log_every=50, sigmas=(80.0, 0.35)):
-    """AdamW on the student's flat parameters; returns (params, loss history)."""
-    tr = td.Trainer(student_path)
+def train(td, torch, student_path, x, y, e, steps, batch=64, lr=2e-4, seed=0, log_every=50, sigmas=(80.0, 0.35),
+          precision=1):
+    """AdamW on the student's flat FP32 master parameters (BF16 convolution
+    operands with precision 1); returns (params, loss history)."""
+    tr = td.Trainer(student_path).set_precision(precision)
     P = tr.load_params(student_path)
     G, m, v = torch.zeros_like(P), torch.zeros_like(P), torch.zeros_like(P)
     n = x.shape[0]
@@ -123,6 +126,7 @@ def main():
     ap.add_argument("--lr", type=float, default=2e-4)
     ap.add_argument("--teacher-precision", type=int, default=0)
     ap.add_argument("--holdout", type=int, default=512, help="held-out pairs (seeds after the training seeds)")
+    ap.add_argument("--precision", type=int, default=1, help="1: BF16 convolution operands, 0: FP32")
     a = ap.parse_args()
     t0 = time.perf_counter()
     x, y, e = make_pairs(td, torch, a.teacher, a.pairs + a.holdout, precision=a.teacher_precision)
@@ -131,7 +135,7 @@ def main():
     xh, yh, eh = x[a.pairs:], y[a.pairs:], e[a.pairs:]
     P0 = td.Trainer(a.student_init).load_params(a.student_init)
     before = evaluate(td, torch, a.student_init, P0, xh, yh, eh)
-    P, hist = train(td, torch, a.student_init, xt, yt, et, a.steps, a.batch, a.lr)
+    P, hist = train(td, torch, a.student_init, xt, yt, et, a.steps, a.batch, a.lr, precision=a.precision)
     t2 = time.perf_counter()
     after = evaluate(td, torch, a.student_init, P, xh, yh, eh)
     save(td, a.student_init, P, a.out)

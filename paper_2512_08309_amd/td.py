@@ -25,7 +25,7 @@ EXPORTS = ["td_create", "td_destroy", "td_load_weights", "td_set_conditioning", 
            "td_get_info", "td_denoise_windows", "td_denoise_steps", "td_noise_region", "td_lap_decode", "td_kappa", "td_cone_windows", "td_kernel_stats",
            "td_server_create", "td_server_destroy", "td_server_submit", "td_server_progress", "td_server_poll",
            "td_server_stats", "td_last_error", "td_train_create", "td_train_destroy", "td_train_last_error",
-           "td_train_param_count", "td_train_forward", "td_train_backward", "td_train_mse", "td_train_adamw"]
+           "td_train_param_count", "td_train_set_precision", "td_train_forward", "td_train_backward", "td_train_mse", "td_train_adamw"]
 
 
 class td_cache_stats_t(ctypes.Structure):
@@ -95,6 +95,7 @@ def _load():
         "td_train_destroy": ([vp], None),
         "td_train_last_error": ([vp], ctypes.c_char_p),
         "td_train_param_count": ([vp, ctypes.POINTER(sz)], ctypes.c_int),
+        "td_train_set_precision": ([vp, i32], ctypes.c_int),
         "td_train_forward": ([vp, vp, vp, i32, ctypes.c_double, vp, vp], ctypes.c_int),
         "td_train_backward": ([vp, vp, vp, vp, vp], ctypes.c_int),
         "td_train_mse": ([vp, vp, vp, sz, ctypes.c_float, vp, ctypes.POINTER(ctypes.c_double), vp], ctypes.c_int),
@@ -471,6 +472,11 @@ class Trainer:
         if status != TD_OK:
             msg = lib.td_train_last_error(self.tr)
             raise TDError(status, msg.decode() if msg else "")
+
+    def set_precision(self, precision):
+        """0: FP32 convolutions; 1: BF16 operands with FP32 accumulation and FP32 master weights."""
+        self._check(lib.td_train_set_precision(self.tr, precision))
+        return self
 
     def load_params(self, path):
         import torch
