@@ -118,7 +118,9 @@ __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
 }
 
 // One thread per (pixel, 8 channels): reads the virtual conv input in FP32,
-// applies the GroupNorm affine (and SiLU), writes 16 bytes of BF16.
+// applies the GroupNorm affine (and SiLU), writes 16 bytes of BF16 or 32
+// bytes of FP32.
+template <bool F32>
 __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
   const int cin = a.c0 + a.c1, q8 = cin / 8;
   const int lhw = a.lh + a.lw;
@@ -151,8 +153,14 @@ __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
       if (a.act == 2) v[j] = silu_f(v[j]);
     }
   }
-  uint4 o = {pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]), pack_bf16(v[4], v[5]), pack_bf16(v[6], v[7])};
-  *reinterpret_cast<uint4*>(a.out + p * cin + c) = o;
+  if constexpr (F32) {
+    float4* o = reinterpret_cast<float4*>(a.out32 + p * cin + c);
+    o[0] = make_float4(v[0], v[1], v[2], v[3]);
+    o[1] = make_float4(v[4], v[5], v[6], v[7]);
+  } else {
+    uint4 o = {pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]), pack_bf16(v[4], v[5]), pack_bf16(v[6], v[7])};
+    *reinterpret_cast<uint4*>(a.out + p * cin + c) = o;
+  }
 }
 
 }  // namespace
@@ -163,10 +171,14 @@ void launch_apply(hipStream_t st, const ApplyArgs& a) {
   const size_t n = ((size_t)a.nb << (a.lh + a.lw)) * (cin / 8);
   if (!n) return;
   prof_begin(st);
-  hipLaunchKernelGGL(apply_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+  TD_CHECK((a.out != nullptr) != (a.out32 != nullptr), -5, "apply: exactly one of the BF16 and FP32 outputs");
+  if (a.out32)
+    hipLaunchKernelGGL(apply_kernel<true>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(apply_kernel<false>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
   TD_LAUNCHED();
   const double el = 8.0 * n;
-  prof_end(st, K_APPLY, 4.0 * el, el * (2.0 + (a.up0 ? 4.0 * a.c1 / cin + 1.0 * a.c0 / cin : 4.0)));
+  prof_end(st, a.out32 ? K_APPLY32 : K_APPLY, 4.0 * el, el * ((a.out32 ? 4.0 : 2.0) + (a.up0 ? 4.0 * a.c1 / cin + 1.0 * a.c0 / cin : 4.0)));
 }
 
 size_t gn_partial_doubles(int nb, int lh, int lw, int cin, int groups) {

@@ -505,6 +505,8 @@ size_t Model::workspace_bytes_per_window() const {
   size_t lp = 0;
   if (prec_)
     for (int l = 0; l < nl; ++l) lp += 2 * (size_t)(d.H >> l) * (d.H >> l) * cin_max(l);   // A, A0 (BF16)
+  else
+    for (int l = 0; l < nl; ++l) f += (size_t)(d.H >> l) * (d.H >> l) * cin_max(l);       // F (FP32)
   return state + f * sizeof(float) + lp * sizeof(uint16_t) + (size_t)16 * d.groups * 2 * sizeof(double) + 64 * 256;
 }
 
@@ -573,11 +575,13 @@ void Model::ensure_workspace(int max_batch) {
     } else {
       b.Q = b.O = nullptr;
     }
+    b.A = b.A0 = nullptr;
+    b.F = nullptr;
     if (prec_) {
       b.A = (uint16_t*)take((r2 * cin_max(l) + 1) / 2);
       b.A0 = (uint16_t*)take((r2 * cin_max(l) + 1) / 2);
     } else {
-      b.A = b.A0 = nullptr;
+      b.F = take(r2 * cin_max(l));
     }
   }
   if (d.kind == "unet") {
@@ -636,7 +640,7 @@ void Model::conv_lp(hipStream_t st, const uint16_t* act, int cin, int nb, int lr
 }
 
 void Model::apply(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int act, int nb, int lr,
-                  uint16_t* out) {
+                  uint16_t* out, float* out32) {
   ApplyArgs a{};
   a.src0 = s0;
   a.src1 = s1;
@@ -650,7 +654,26 @@ void Model::apply(hipStream_t st, const float* s0, int c0, int up0, const float*
   a.lh = lr;
   a.lw = lr;
   a.out = out;
+  a.out32 = out32;
   launch_apply(st, a);
+}
+
+// 3x3 convolution of an already activated dense FP32 input
+void Model::conv3_f32(hipStream_t st, const float* in, int cin, int nb, int lr, int cout, const float* wt,
+                      const float* bias, const float* res, float* out) {
+  ConvArgs a{};
+  a.src0 = in;
+  a.c0 = cin;
+  a.nb = nb;
+  a.lh = lr;
+  a.lw = lr;
+  a.cout = cout;
+  a.taps = 9;
+  a.wt = wt;
+  a.bias = bias;
+  a.res = res;
+  a.out = out;
+  launch_conv(st, a);
 }
 
 void Model::resblock(hipStream_t st, const ResBlockW& w, int k, const float* s0, int c0, int up0, const float* s1,
@@ -676,31 +699,23 @@ void Model::resblock(hipStream_t st, const ResBlockW& w, int k, const float* s0,
     conv_lp(st, B.A, w.cout, nb, lr, w.cout, 9, w.w2_lp, w.w2_8, w.s2_8, w.kp2, w.b2, res, out);
     return;
   }
+  // FP32: GroupNorm + SiLU are applied once per input element into F, not
+  // once per tap inside the 3x3 conv's staging
   gn(st, s0, c0, up0, s1, c1, nb, lr, lr, w.gn1_g, w.gn1_b);
-  ConvArgs a{};
-  a.src0 = s0;
-  a.src1 = s1;
-  a.c0 = c0;
-  a.c1 = c1;
-  a.up0 = up0;
-  a.gn_scale = gn_scale_;
-  a.gn_shift = gn_shift_;
-  a.act = 2;
-  a.nb = nb;
-  a.lh = lr;
-  a.lw = lr;
-  a.cout = w.cout;
-  a.taps = 9;
-  a.wt = w.w1;
-  a.bias = bias_eff_ + w.bias_off + (size_t)k * w.cout;
-  a.res = nullptr;
-  a.out = B.T;
-  launch_conv(st, a);
+  apply(st, s0, c0, up0, s1, c1, 2, nb, lr, nullptr, B.F);
+  conv3_f32(st, B.F, w.cin, nb, lr, w.cout, w.w1, bias_eff_ + w.bias_off + (size_t)k * w.cout, nullptr, B.T);
   const float* res = s0;
   if (w.has_skip) {
-    ConvArgs s = a;
-    s.gn_scale = s.gn_shift = nullptr;
-    s.act = 0;
+    ConvArgs s{};
+    s.src0 = s0;
+    s.src1 = s1;
+    s.c0 = c0;
+    s.c1 = c1;
+    s.up0 = up0;
+    s.nb = nb;
+    s.lh = lr;
+    s.lw = lr;
+    s.cout = w.cout;
     s.taps = 1;
     s.wt = w.wskip;
     s.bias = w.bskip;
@@ -711,22 +726,8 @@ void Model::resblock(hipStream_t st, const ResBlockW& w, int k, const float* s0,
     TD_CHECK(c1 == 0 && !up0, -5, "identity skip needs a plain input");
   }
   gn(st, B.T, w.cout, 0, nullptr, 0, nb, lr, lr, w.gn2_g, w.gn2_b);
-  ConvArgs b2{};
-  b2.src0 = B.T;
-  b2.c0 = w.cout;
-  b2.gn_scale = gn_scale_;
-  b2.gn_shift = gn_shift_;
-  b2.act = 2;
-  b2.nb = nb;
-  b2.lh = lr;
-  b2.lw = lr;
-  b2.cout = w.cout;
-  b2.taps = 9;
-  b2.wt = w.w2;
-  b2.bias = w.b2;
-  b2.res = res;
-  b2.out = out;
-  launch_conv(st, b2);
+  apply(st, B.T, w.cout, 0, nullptr, 0, 2, nb, lr, nullptr, B.F);
+  conv3_f32(st, B.F, w.cout, nb, lr, w.cout, w.w2, w.b2, res, out);
 }
 
 void Model::attention(hipStream_t st, const AttnW& w, const float* in, int nb, int lvl, float* out) {

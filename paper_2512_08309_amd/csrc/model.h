@@ -142,6 +142,7 @@ class Model {
     float *T, *R, *X, *Y, *P, *Q, *O;
     std::vector<float*> S;
     uint16_t *A, *A0;      // BF16 operand buffers (reduced precision)
+    float* F;              // activated FP32 input of a 3x3 conv (FP32)
   };
   std::vector<LevelBufs> lb_;
   float *gn_scale_ = nullptr, *gn_shift_ = nullptr;
@@ -171,7 +172,9 @@ class Model {
                const uint16_t* wt, const uint8_t* w8, const float* w8s, int kp, const float* bias,
                const float* res, float* out);
   void apply(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int act, int nb,
-             int lr, uint16_t* out);
+             int lr, uint16_t* out, float* out32 = nullptr);
+  void conv3_f32(hipStream_t st, const float* in, int cin, int nb, int lr, int cout, const float* wt,
+                 const float* bias, const float* res, float* out);
   void build_unet(const std::map<std::string, std::vector<float>>& host,
                   const std::map<std::string, std::vector<int>>& shapes, hipStream_t st);
   void gn(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int nb, int lh, int lw,

@@ -39,7 +39,7 @@ struct Error {
 // bytes of the launch).  When no profiler is installed the hooks are no-ops.
 enum KClass {
   K_CONV3 = 0, K_CONV1, K_GN, K_CONV_IN, K_CONV_OUT, K_ATTN, K_POOL, K_NOISE, K_BLEND, K_DECODE, K_LG, K_EMB,
-  K_CONV3_LP, K_CONV1_LP, K_APPLY, K_GATHER, K_WGRAD, K_NCLASS
+  K_CONV3_LP, K_CONV1_LP, K_APPLY, K_GATHER, K_WGRAD, K_APPLY32, K_NCLASS
 };
 const char* kclass_name(int k);
 struct Profiler;
@@ -151,8 +151,9 @@ void launch_conv_lp(hipStream_t st, const ConvLpArgs& a);
 // K padding a weight matrix for launch_conv_lp needs.
 inline int conv_lp_kp(int taps, int cin) { return (taps * cin + 31) / 32 * 32; }
 
-// GroupNorm apply (+ SiLU) of the virtual conv input, written as BF16 NHWC:
-// act 0 = convert only, 1 = affine, 2 = affine + SiLU.
+// GroupNorm apply (+ SiLU) of the virtual conv input, written NHWC as BF16
+// (out) or FP32 (out32, when set): act 0 = copy / convert only, 1 = affine,
+// 2 = affine + SiLU.
 struct ApplyArgs {
   const float* src0;
   const float* src1;
@@ -161,7 +162,8 @@ struct ApplyArgs {
   const float* shift;
   int act;
   int nb, lh, lw;
-  uint16_t* out;         // [nb][h][w][c0 + c1]
+  uint16_t* out;         // [nb][h][w][c0 + c1] BF16
+  float* out32;          // [nb][h][w][c0 + c1] FP32 (instead of out)
 };
 void launch_apply(hipStream_t st, const ApplyArgs& a);
 
