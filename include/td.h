@@ -22,7 +22,8 @@
  *    device cache and its workspaces, all freed by td_destroy.
  *  - Device pointers are HIP device addresses on the context's device;
  *    streams are hipStream_t passed as void* (NULL = the context's own
- *    stream).
+ *    stream where a call has a context, else the device's default stream;
+ *    TD_STREAM_DEFAULT always names the device's default stream).
  */
 #ifndef TD_H
 #define TD_H
@@ -33,6 +34,11 @@
 #ifdef __cplusplus
 extern "C" {
 #endif
+
+/* Stream argument naming the device's default (null) stream; the value of
+ * HIP's hipStreamLegacy handle.  Work enqueued with it is ordered with
+ * everything the caller put on the default stream. */
+#define TD_STREAM_DEFAULT ((void *)1)
 
 typedef struct td_ctx td_ctx;
 
@@ -304,8 +310,9 @@ const char *td_last_error(const td_ctx *ctx);
  * are one flat float32 device buffer laid out as the file's data section
  * (tensor i at float offset offset_i / 4, conv weights [co][ci][kh][kw]),
  * so a file's data can be loaded, trained and written back as it is.
- * Gradients use the same layout.  FP32 throughout; all reductions run in a
- * fixed order (deterministic gradients).  One trainer is not thread-safe;
+ * Gradients use the same layout.  FP32 by default (BF16 convolution
+ * operands with td_train_set_precision); all reductions run in a fixed
+ * order (deterministic gradients).  One trainer is not thread-safe;
  * calls are asynchronous on the HIP stream `stream` (NULL: the device's
  * default stream). */
 typedef struct td_trainer td_trainer;

@@ -838,8 +838,8 @@ td_status td_sample_region_async(td_ctx* c, uint64_t seed, int64_t x0, int64_t y
   return guarded(c, [&] {
     TD_CHECK(dev_out, TD_E_INVAL, "null output");
     TD_HIP(hipSetDevice(c->device));
-    hipStream_t user = (hipStream_t)hip_stream;
-    if (user && user != c->stream) {
+    hipStream_t user = hip_stream == TD_STREAM_DEFAULT ? nullptr : (hipStream_t)hip_stream;
+    if (hip_stream && user != c->stream) {
       // order after the caller's stream, run on ours, then make theirs wait
       hipEvent_t ev;
       TD_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
@@ -1070,7 +1070,7 @@ td_status td_noise_region(uint64_t seed, int64_t x0, int64_t y0, int32_t w, int3
                           uint32_t step, float scale, float* dev_out, void* hip_stream) {
   if (!dev_out || w < 1 || h < 1 || channels < 1 || (int64_t)w * h > (1LL << 30)) return TD_E_INVAL;
   try {
-    launch_noise((hipStream_t)hip_stream, seed, x0, y0, w, h, channels, step, scale, 0, dev_out);
+    launch_noise(hip_stream == TD_STREAM_DEFAULT ? nullptr : (hipStream_t)hip_stream, seed, x0, y0, w, h, channels, step, scale, 0, dev_out);
   } catch (const Error& e) {
     return (td_status)e.status;
   }
@@ -1085,7 +1085,7 @@ td_status td_lap_decode(td_ctx* c, const float* latent_dev, int64_t lx0, int64_t
     TD_CHECK(latent_dev && out_dev && lw > 0 && lh > 0, TD_E_INVAL, "bad arguments");
     check_region(X0, Y0, W, H);
     TD_HIP(hipSetDevice(c->device));
-    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : c->stream;
+    hipStream_t st = !hip_stream ? c->stream : hip_stream == TD_STREAM_DEFAULT ? nullptr : (hipStream_t)hip_stream;
     if (c->pending) {
       TD_HIP(hipEventSynchronize(c->done));
       c->pending = false;

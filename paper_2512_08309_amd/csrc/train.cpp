@@ -821,7 +821,7 @@ td_status tguard(td_trainer* t, F&& f) {
 
 // NULL is the device's default stream, as in HIP (so that callers whose work
 // is on the default stream, torch's included, are ordered with ours).
-hipStream_t tstream(td_trainer*, void* s) { return (hipStream_t)s; }
+hipStream_t tstream(td_trainer*, void* s) { return s == TD_STREAM_DEFAULT ? nullptr : (hipStream_t)s; }
 
 }  // namespace
 

@@ -122,10 +122,18 @@ def _fptr(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
 
 
+TD_STREAM_DEFAULT = 1   # the device's default (null) stream
+
+
 def _stream(stream):
+    """None: the call's own default (the context's stream, or the device's
+    default stream for calls without a context).  A torch stream object is
+    that stream; torch's default stream (handle 0) maps to TD_STREAM_DEFAULT,
+    not to NULL, so the work stays ordered with torch's."""
     if stream is None:
         return None
-    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+    h = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    return ctypes.c_void_p(h if h else TD_STREAM_DEFAULT)
 
 
 # ---------------------------------------------------------------- raw calls

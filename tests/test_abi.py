@@ -71,3 +71,18 @@ def test_create_fails_cleanly_without_gpu():
     td = _td()
     with pytest.raises(td.TDError):
         td.td_create(0)
+
+
+def test_stream_argument_mapping():
+    """None stays NULL (the call's own default); torch's default stream
+    (handle 0) becomes TD_STREAM_DEFAULT, not NULL; other handles pass."""
+    from paper_2512_08309_amd import td
+
+    class S:
+        def __init__(self, h):
+            self.cuda_stream = h
+
+    assert td._stream(None) is None
+    assert td._stream(S(0)).value == td.TD_STREAM_DEFAULT == 1
+    assert td._stream(S(0x7f00aa00)).value == 0x7f00aa00
+    assert td._stream(0x1234).value == 0x1234

@@ -60,3 +60,33 @@ def test_height_query_matches_oracle(weights):
         ref = laplace.decode(lat, (lx0, ly0), region, DEC)
         assert got.shape == (40, 48)
         assert rel_l2(got, ref) <= 1e-4
+
+
+def test_calls_on_torch_default_stream_are_ordered_with_torch(ctx):
+    """A call given torch's current stream (the default stream, handle 0) is
+    ordered with torch's work on it: the decode reads a latent torch writes
+    just before it behind a spin, and a region query's result is not
+    overwritten by a fill torch queued before it."""
+    import torch
+    from paper_2512_08309_amd import td
+    region = (0, 0, 256, 192)
+    lx0, ly0, lw, lh = laplace.required_latent(region, DEC)
+    src = torch.from_numpy(terrain_latent(21, lx0, ly0, lw, lh, 4)).cuda()
+    ref = torch.empty((192, 256), device="cuda")
+    ctx.lap_decode(src, lx0, ly0, *region, ref)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    assert s.cuda_stream == 0
+    lat = torch.zeros_like(src)
+    out = torch.zeros_like(ref)
+    torch.cuda._sleep(20_000_000)
+    lat.copy_(src)
+    ctx.lap_decode(lat, lx0, ly0, *region, out, s)
+    assert float((out - ref).abs().max()) == 0.0
+
+    want = torch.from_numpy(ctx.sample_region(5, 3, 4, 40, 24, 0)).cuda()
+    got = torch.empty_like(want)
+    torch.cuda._sleep(20_000_000)
+    got.fill_(-1.0)
+    ctx.sample_region_async(5, 3, 4, 40, 24, 0, got, s)
+    assert float((got - want).abs().max()) == 0.0
