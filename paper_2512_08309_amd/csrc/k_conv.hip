@@ -20,6 +20,11 @@
 // results are batch-invariant, which the bit-exact seed consistency of the
 // sampler relies on.
 //
+// Convolutions whose input is already activated and dense (one source, no
+// upsampling) take a specialisation with fewer live registers that reads
+// the LDS operands of k-step kk + 1 while the MFMAs of kk run; the MFMA
+// sequence per accumulator is unchanged, so results are identical.
+//
 // Workgroups are remapped so that each XCD (blockIdx % 8) walks a
 // contiguous range of tiles: neighbouring N tiles of one M tile share the
 // activation rows in that XCD's L2.
@@ -34,7 +39,10 @@ __device__ __forceinline__ float silu_f(float v) {
   return v * __builtin_amdgcn_rcpf(1.0f + __expf(-v));
 }
 
-template <int TAPS, int BN, int WM, int WN>
+// DENSE: one source, no upsampling, no activation (the input is already
+// activated); fewer live registers, which leaves room to double-buffer the
+// LDS operand reads of consecutive k-steps.
+template <int TAPS, int BN, int WM, int WN, bool DENSE>
 __global__ __launch_bounds__(256, 4) void conv_kernel(ConvArgs a, int n_tiles_n) {
   constexpr int BM = 128, BK = 16, KS = BK / 4;
   constexpr int TM = BM / WM / 16, TN = BN / WN / 16;
@@ -55,7 +63,7 @@ __global__ __launch_bounds__(256, 4) void conv_kernel(ConvArgs a, int n_tiles_n)
   const int lw = a.lw, lh = a.lh;
   const int W = 1 << lw, H = 1 << lh, lhw = lw + lh;
   const int M = a.nb << lhw;
-  const int c0 = a.c0, c1 = a.c1, cin = c0 + c1;
+  const int c0 = a.c0, c1 = DENSE ? 0 : a.c1, cin = c0 + c1;
 
   // Per-thread A staging slots: 2 float4 (pixel aml, channel quad akq).
   int ab[2], ay[2], ax[2], akq[2], aml[2];
@@ -89,11 +97,11 @@ __global__ __launch_bounds__(256, 4) void conv_kernel(ConvArgs a, int n_tiles_n)
       const bool ok = aval[i] && yy >= 0 && yy < H && xx >= 0 && xx < W;
       const int yc = ok ? yy : 0, xc = ok ? xx : 0;
       pok[i] = ok;
-      if (a.up0)
+      if (!DENSE && a.up0)
         p0[i] = a.src0 + ((((size_t)ab[i] << (lhw - 2)) + ((size_t)(yc >> 1) << (lw - 1)) + (xc >> 1)) * c0 + 4 * akq[i]);
       else
         p0[i] = a.src0 + ((((size_t)ab[i] << lhw) + ((size_t)yc << lw) + xc) * c0 + 4 * akq[i]);
-      p1[i] = c1 ? a.src1 + ((((size_t)ab[i] << lhw) + ((size_t)yc << lw) + xc) * c1 + 4 * akq[i]) : a.src0;
+      p1[i] = (!DENSE && c1) ? a.src1 + ((((size_t)ab[i] << lhw) + ((size_t)yc << lw) + xc) * c1 + 4 * akq[i]) : a.src0;
     }
   };
 
@@ -101,7 +109,7 @@ __global__ __launch_bounds__(256, 4) void conv_kernel(ConvArgs a, int n_tiles_n)
   auto load_chunk = [&](int tap, int ci0) {
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      const float* p = ci0 < c0 ? p0[i] + ci0 : p1[i] + (ci0 - c0);
+      const float* p = (DENSE || ci0 < c0) ? p0[i] + ci0 : p1[i] + (ci0 - c0);
       ra[i] = *reinterpret_cast<const f4v*>(p);
 
     }
@@ -119,7 +127,7 @@ __global__ __launch_bounds__(256, 4) void conv_kernel(ConvArgs a, int n_tiles_n)
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       f4v v = ra[i];
-      if (a.act) {
+      if (!DENSE && a.act) {
         const size_t so = (size_t)ab[i] * cin + ci0 + 4 * akq[i];
         v = v * *reinterpret_cast<const f4v*>(a.gn_scale + so) + *reinterpret_cast<const f4v*>(a.gn_shift + so);
         if (a.act == 2) {
@@ -172,35 +180,59 @@ __global__ __launch_bounds__(256, 4) void conv_kernel(ConvArgs a, int n_tiles_n)
       }
       load_chunk(tap_n, ci_n);
     }
-    // All LDS operand reads of the stage first, then the MFMA chain.
     const float* Ab = As[buf];
     const float* Bb = Bs[buf];
-    float av[KS][TM], bv[KS][TN];
+    if constexpr (DENSE && TM == 4 && TN == 4) {
+      // operands of k-step kk + 1 are read while the MFMAs of kk run
+      f4v ac = *reinterpret_cast<const f4v*>(&Ab[kl * AS + arow]);
+      f4v bc = *reinterpret_cast<const f4v*>(&Bb[kl * BS + brow]);
 #pragma unroll
-    for (int kk = 0; kk < KS; ++kk) {
-      const int krow = kk * 4 + kl;
-      if constexpr (TM == 4) {
-        f4v t = *reinterpret_cast<const f4v*>(&Ab[krow * AS + arow]);
-        av[kk][0] = t.x; av[kk][1] = t.y; av[kk][2] = t.z; av[kk][3] = t.w;
-      } else {
+      for (int kk = 0; kk < KS; ++kk) {
+        f4v an = ac, bn = bc;
+        if (kk + 1 < KS) {
+          an = *reinterpret_cast<const f4v*>(&Ab[((kk + 1) * 4 + kl) * AS + arow]);
+          bn = *reinterpret_cast<const f4v*>(&Bb[((kk + 1) * 4 + kl) * BS + brow]);
+        }
+        __builtin_amdgcn_sched_barrier(0);   // keep those reads ahead of this k-step's MFMAs
+        const float av4[4] = {ac.x, ac.y, ac.z, ac.w}, bv4[4] = {bc.x, bc.y, bc.z, bc.w};
 #pragma unroll
-        for (int r = 0; r < TM; ++r) av[kk][r] = Ab[krow * AS + arow + r];
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av4[i], bv4[j], acc[i][j], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+        ac = an;
+        bc = bn;
       }
-      if constexpr (TN == 4) {
-        f4v t = *reinterpret_cast<const f4v*>(&Bb[krow * BS + brow]);
-        bv[kk][0] = t.x; bv[kk][1] = t.y; bv[kk][2] = t.z; bv[kk][3] = t.w;
-      } else {
+    } else {
+      // All LDS operand reads of the stage first, then the MFMA chain.
+      float av[KS][TM], bv[KS][TN];
 #pragma unroll
-        for (int r = 0; r < TN; ++r) bv[kk][r] = Bb[krow * BS + brow + r];
+      for (int kk = 0; kk < KS; ++kk) {
+        const int krow = kk * 4 + kl;
+        if constexpr (TM == 4) {
+          f4v t = *reinterpret_cast<const f4v*>(&Ab[krow * AS + arow]);
+          av[kk][0] = t.x; av[kk][1] = t.y; av[kk][2] = t.z; av[kk][3] = t.w;
+        } else {
+#pragma unroll
+          for (int r = 0; r < TM; ++r) av[kk][r] = Ab[krow * AS + arow + r];
+        }
+        if constexpr (TN == 4) {
+          f4v t = *reinterpret_cast<const f4v*>(&Bb[krow * BS + brow]);
+          bv[kk][0] = t.x; bv[kk][1] = t.y; bv[kk][2] = t.z; bv[kk][3] = t.w;
+        } else {
+#pragma unroll
+          for (int r = 0; r < TN; ++r) bv[kk][r] = Bb[krow * BS + brow + r];
+        }
       }
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk)
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk][i], bv[kk][j], acc[i][j], 0, 0, 0);
     }
-#pragma unroll
-    for (int kk = 0; kk < KS; ++kk)
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kk][i], bv[kk][j], acc[i][j], 0, 0, 0);
     if (more) store_chunk(buf ^ 1, ci_n);
     __syncthreads();
   }
@@ -244,10 +276,15 @@ void launch_cfg(hipStream_t st, const ConvArgs& a) {
   int M = a.nb << (a.lh + a.lw);
   int mt = (M + 127) / 128;
   int nt = a.cout / BN;
-  if (a.taps == 9)
-    hipLaunchKernelGGL((conv_kernel<9, BN, WM, WN>), dim3(mt * nt), dim3(256), 0, st, a, nt);
+  const bool dense = !a.src1 && !a.c1 && !a.up0 && !a.act;
+  if (a.taps == 9 && dense)
+    hipLaunchKernelGGL((conv_kernel<9, BN, WM, WN, true>), dim3(mt * nt), dim3(256), 0, st, a, nt);
+  else if (a.taps == 9)
+    hipLaunchKernelGGL((conv_kernel<9, BN, WM, WN, false>), dim3(mt * nt), dim3(256), 0, st, a, nt);
+  else if (dense)
+    hipLaunchKernelGGL((conv_kernel<1, BN, WM, WN, true>), dim3(mt * nt), dim3(256), 0, st, a, nt);
   else
-    hipLaunchKernelGGL((conv_kernel<1, BN, WM, WN>), dim3(mt * nt), dim3(256), 0, st, a, nt);
+    hipLaunchKernelGGL((conv_kernel<1, BN, WM, WN, false>), dim3(mt * nt), dim3(256), 0, st, a, nt);
   TD_LAUNCHED();
 }
 
