@@ -203,6 +203,8 @@ struct td_ctx {
   size_t dec_cap = 0;
   float* outbuf = nullptr;
   size_t outbuf_cap = 0;
+  float* gath = nullptr;      // batched window inputs of sample_latent_multi
+  size_t gath_cap = 0;
   std::unique_ptr<td::Profiler> prof;
   // hierarchy: the parent whose final latent conditions this model, the
   // children it conditions, and a generation that changes with the values
@@ -427,6 +429,35 @@ void sample_parent(td_ctx* c, Arena& arena, uint64_t seed, const Region& hull, f
   }
 }
 
+// One region of a multi-region query: J_0 of (seed, r) into dst, [h][w][C].
+struct RegionJob {
+  uint64_t seed;
+  Region r;
+  float* dst;
+};
+
+void sample_latent_multi(td_ctx* c, Arena& arena, const std::vector<RegionJob>& jobs);
+
+// The parent latents of several child queries (seed, hull of new windows,
+// destination), sampled together on the parent's stream after everything
+// already enqueued on the child's; rcs receives the parent regions.
+void sample_parents(td_ctx* c, Arena& arena, const std::vector<RegionJob>& hulls, std::vector<Region>* rcs) {
+  td_ctx* p = c->parent;
+  TD_CHECK(p->device == c->device, TD_E_STATE, "parent and child must share a device");
+  check_parent(p, true);
+  std::vector<RegionJob> jobs;
+  rcs->clear();
+  for (const RegionJob& h : hulls) {
+    const Region rc = parent_region(c->model->d, h.r);
+    check_region(rc.x0, rc.y0, rc.w, rc.h);
+    rcs->push_back(rc);
+    jobs.push_back(RegionJob{h.seed, rc, h.dst});
+  }
+  TD_HIP(hipEventRecord(c->xev, c->stream));
+  TD_HIP(hipStreamWaitEvent(p->stream, c->xev, 0));
+  sample_latent_multi(p, arena, jobs);
+}
+
 // Conditioning windows of a batch: window j (index (ix, iy)) reads the
 // parent canvas whose origin in child pixels is (fx, fy).
 void cond_batch(td_ctx* c, Arena& arena, const CondSrc* hsrc, int nb) {
@@ -590,6 +621,168 @@ void sample_latent(td_ctx* c, Arena& arena, uint64_t seed, Region r, int level, 
   } else {
     blend_into(c, arena, seed, top, r, layout, dev_out);
     unpin_level(c, seed, top);
+  }
+  evict_to_budget(c);
+}
+
+// J_0 of several regions (unconditioned models): each region's cone is
+// planned as in sample_latent, but a window shared by several cones is
+// evaluated once (the first region claims it; the others find it in the
+// cache map and only pin it), and every level's new windows of all regions
+// are gathered from their regions' canvases into shared batches.  Window
+// values do not depend on the batch they run in, so each result equals the
+// region's own sample_latent.
+void sample_latent_multi(td_ctx* c, Arena& arena, const std::vector<RegionJob>& jobs) {
+  const ModelDesc& d = c->model->d;
+  TD_CHECK(d.Cc == 0, TD_E_STATE, "internal: batched regions of a conditioned model");
+  hipStream_t st = c->stream;
+  const int nr = (int)jobs.size();
+  if (!nr) return;
+  // ---- plan: levels[i][t] for region i; fresh windows enter the map now
+  std::vector<std::vector<Level>> levels(nr);
+  std::vector<std::vector<std::vector<uint32_t>>> slots(nr);
+  int tmax = -1;
+  size_t meta = 65536, nfresh = 0;
+  for (int i = 0; i < nr; ++i) {
+    c->stats.queries++;
+    Region R = jobs[i].r;
+    for (int t = 0; t < d.T; ++t) {
+      Level lv;
+      lv.t = t;
+      lv.region = R;
+      lv.k = kappa(R, d.H, d.S, d.O);
+      std::vector<uint32_t> sl;
+      if (!lv.k.empty) {
+        TD_CHECK(lv.k.count() <= (1LL << 26), TD_E_INVAL, "query too large");
+        int64_t mnx = INT64_MAX, mxx = INT64_MIN, mny = INT64_MAX, mxy = INT64_MIN;
+        for (int64_t iy = lv.k.iy0; iy <= lv.k.iy1; ++iy)
+          for (int64_t ix = lv.k.ix0; ix <= lv.k.ix1; ++ix) {
+            Key key{jobs[i].seed, t, ix, iy};
+            auto m = c->map.find(key);
+            if (m != c->map.end()) {
+              m->second.pins++;
+              touch(c, m->second, key);
+              c->stats.hits++;
+              continue;
+            }
+            const uint32_t slot = c->pool.take();
+            c->lru.push_front(key);
+            c->map[key] = Entry{slot, 1, c->lru.begin()};
+            sl.push_back(slot);
+            lv.fresh.push_back({ix, iy});
+            mnx = std::min(mnx, ix);
+            mxx = std::max(mxx, ix);
+            mny = std::min(mny, iy);
+            mxy = std::max(mxy, iy);
+          }
+        if (!lv.fresh.empty())
+          lv.in_region = Region{mnx * d.S + d.O, mny * d.S + d.O, (mxx - mnx) * d.S + d.H, (mxy - mny) * d.S + d.H};
+        meta += (size_t)lv.k.count() * sizeof(float*) + 256;
+      }
+      nfresh += lv.fresh.size();
+      const bool stop = lv.k.empty || lv.fresh.empty();
+      if (!stop) tmax = std::max(tmax, t);
+      levels[i].push_back(std::move(lv));
+      slots[i].push_back(std::move(sl));
+      if (stop) break;
+      R = levels[i].back().in_region;
+    }
+  }
+  const int maxb = auto_batch(c);
+  meta += nfresh * (3 * sizeof(int) + 2 * sizeof(float*)) + (nfresh / maxb + 2 * (tmax + 2)) * 5 * 256;
+  arena.ensure(meta);
+  c->model->ensure_workspace(std::min<int>(maxb, 1 << 20));
+  const size_t per = (size_t)d.H * d.H * d.C;
+  // ---- run, deepest level first
+  for (int t = tmax; t >= 0; --t) {
+    // canvases of this level, one per region with new windows here
+    std::vector<size_t> off(nr, 0);
+    size_t total = 0;
+    for (int i = 0; i < nr; ++i)
+      if (t < (int)levels[i].size() && !levels[i][t].fresh.empty()) {
+        off[i] = total;
+        const Region& cr = levels[i][t].in_region;
+        total += (size_t)cr.w * cr.h * d.C;
+      }
+    if (!total) continue;
+    grow(c->canvas, c->canvas_cap, total);
+    std::vector<std::pair<int, size_t>> work;   // (region, index into its fresh list)
+    for (int i = 0; i < nr; ++i) {
+      if (t >= (int)levels[i].size() || levels[i][t].fresh.empty()) continue;
+      Level& lv = levels[i][t];
+      const Region& cr = lv.in_region;
+      float* canvas = c->canvas + off[i];
+      if (t + 1 == d.T) {
+        launch_noise(st, jobs[i].seed, cr.x0, cr.y0, (int)cr.w, (int)cr.h, d.C, d.noise_step, (float)d.sched[0], 0,
+                     canvas);
+      } else {
+        const Level& up = levels[i][t + 1];
+        if (up.k.empty) launch_fill(st, canvas, (size_t)cr.w * cr.h * d.C, 0.f);
+        else blend_into(c, arena, jobs[i].seed, up, cr, 0, canvas);
+        unpin_level(c, jobs[i].seed, up);
+      }
+      for (size_t j = 0; j < lv.fresh.size(); ++j) work.push_back({i, j});
+      c->stats.misses += lv.fresh.size();
+      c->stats.denoiser_evals += (uint64_t)lv.fresh.size() * c->model->level_steps(t);
+      if (t < 64) c->stats.windows_evaluated[t] += lv.fresh.size();
+    }
+    grow(c->gath, c->gath_cap, (size_t)std::min<size_t>(work.size(), (size_t)maxb) * per);
+    for (size_t b0 = 0; b0 < work.size(); b0 += (size_t)maxb) {
+      const int nb = (int)std::min<size_t>(maxb, work.size() - b0);
+      auto src = arena.reserve((size_t)nb * sizeof(float*));
+      auto pit = arena.reserve((size_t)nb * sizeof(int));
+      auto org = arena.reserve((size_t)nb * 2 * sizeof(int));
+      auto wix = arena.reserve((size_t)nb * 2 * sizeof(int));
+      auto slo = arena.reserve((size_t)nb * sizeof(float*));
+      const float** hs = (const float**)src.first;
+      int* hp = (int*)pit.first;
+      int* ho = (int*)org.first;
+      int* hw = (int*)wix.first;
+      float** hsl = (float**)slo.first;
+      for (int j = 0; j < nb; ++j) {
+        const int i = work[b0 + j].first;
+        const size_t f = work[b0 + j].second;
+        const Level& lv = levels[i][t];
+        const Region& cr = lv.in_region;
+        const auto ij = lv.fresh[f];
+        const int64_t ox = ij.first * d.S + d.O - cr.x0, oy = ij.second * d.S + d.O - cr.y0;
+        hs[j] = c->canvas + off[i] + ((size_t)oy * cr.w + ox) * d.C;
+        hp[j] = (int)cr.w;
+        ho[2 * j] = 0;
+        ho[2 * j + 1] = j * d.H;
+        hw[2 * j] = (int)ij.first;
+        hw[2 * j + 1] = (int)ij.second;
+        hsl[j] = c->pool.ptr(slots[i][t][f]);
+      }
+      TD_HIP(hipMemcpyAsync(src.second, src.first, (size_t)nb * sizeof(float*), hipMemcpyHostToDevice, st));
+      TD_HIP(hipMemcpyAsync(pit.second, pit.first, (size_t)nb * sizeof(int), hipMemcpyHostToDevice, st));
+      TD_HIP(hipMemcpyAsync(org.second, org.first, (size_t)nb * 2 * sizeof(int), hipMemcpyHostToDevice, st));
+      TD_HIP(hipMemcpyAsync(wix.second, wix.first, (size_t)nb * 2 * sizeof(int), hipMemcpyHostToDevice, st));
+      TD_HIP(hipMemcpyAsync(slo.second, slo.first, (size_t)nb * sizeof(float*), hipMemcpyHostToDevice, st));
+      launch_gather(st, (const float* const*)src.second, (const int*)pit.second, nb, d.H, d.C, c->gath);
+      WindowBatch wb;
+      wb.canvas = c->gath;
+      wb.canvas_w = d.H;
+      wb.d_origins = (const int*)org.second;
+      wb.d_widx = (const int*)wix.second;
+      wb.d_slots = (float* const*)slo.second;
+      wb.n = nb;
+      wb.mode = 0;
+      c->model->run_level(st, wb, t);
+      c->stats.batches++;
+    }
+    evict_to_budget(c);
+  }
+  // ---- outputs
+  for (int i = 0; i < nr; ++i) {
+    const Level& top = levels[i][0];
+    const Region& r = jobs[i].r;
+    if (top.k.empty) {
+      launch_fill(st, jobs[i].dst, (size_t)r.w * r.h * d.C, 0.f);
+    } else {
+      blend_into(c, arena, jobs[i].seed, top, r, 0, jobs[i].dst);
+      unpin_level(c, jobs[i].seed, top);
+    }
   }
   evict_to_budget(c);
 }
@@ -1238,6 +1431,9 @@ struct td_server {
   hipEvent_t ring_pev[td::kRing] = {};   // the parent's work that used the slot's arena
   bool ring_pused[td::kRing] = {};
   bool parent_round = false;             // parent work issued in the current round
+  // queries admitted in this round whose parent latent is still to be
+  // sampled (one batched parent call per round)
+  std::vector<uint64_t> parent_wait;
   uint64_t round = 0;
   float* batch_in = nullptr;
   size_t batch_cap = 0;
@@ -1355,9 +1551,14 @@ void plan_query(td_server* s, SrvQuery& Q, Arena& arena) {
       const Region pr = parent_region(d, hull);
       Q.cond = take_canvas(s, (size_t)pr.w * pr.h * d.Cc);
       if (!Q.cond_ev) TD_HIP(hipEventCreateWithFlags(&Q.cond_ev, hipEventDisableTiming));
-      sample_parent(c, arena, Q.r.seed, hull, Q.cond, &Q.cond_r, Q.cond_ev);
-      Q.cond_pending = true;
-      s->parent_round = true;
+      if (c->parent->model->d.Cc == 0) {   // batched with the round's other admissions
+        Q.cond_r = hull;                   // (child pixels until the parent call)
+        s->parent_wait.push_back(Q.ticket);
+      } else {
+        sample_parent(c, arena, Q.r.seed, hull, Q.cond, &Q.cond_r, Q.cond_ev);
+        Q.cond_pending = true;
+        s->parent_round = true;
+      }
     }
   }
 }
@@ -1528,6 +1729,24 @@ void admit(td_server* s, Arena& arena) {
     Q.state = 1;
     s->active.push_back(Q.ticket);
     s->stats.admitted++;
+  }
+  if (!s->parent_wait.empty()) {
+    td_ctx* c = s->c;
+    std::vector<RegionJob> hulls;
+    for (uint64_t t : s->parent_wait) {
+      SrvQuery& Q = s->q[t];
+      hulls.push_back(RegionJob{Q.r.seed, Q.cond_r, Q.cond});
+    }
+    std::vector<Region> rcs;
+    sample_parents(c, arena, hulls, &rcs);
+    for (size_t i = 0; i < s->parent_wait.size(); ++i) {
+      SrvQuery& Q = s->q[s->parent_wait[i]];
+      Q.cond_r = rcs[i];
+      TD_HIP(hipEventRecord(Q.cond_ev, c->parent->stream));
+      Q.cond_pending = true;
+    }
+    s->parent_wait.clear();
+    s->parent_round = true;
   }
 }
 
