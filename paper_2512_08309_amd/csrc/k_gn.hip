@@ -16,6 +16,8 @@ namespace td {
 namespace {
 
 constexpr int kMaxCin = 1024;
+constexpr int kWinMaxCin = 512;
+constexpr int kWinMaxElems = 32768;   // 16 pixels x 8 channels per thread
 
 __host__ __device__ inline int gn_nchunk(int lh, int lw, int cin, int up0) {
   long hw = 1L << (lh + lw);
@@ -163,6 +165,133 @@ __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
   }
 }
 
+// GroupNorm of whole windows in one pass, for windows whose virtual input
+// (h * w * C_in elements) fits in the registers of one workgroup: the
+// workgroup of window b loads it once, reduces per-channel sums and sums of
+// squares in FP64 (per thread over its pixels, then over threads in a fixed
+// order, then over the group's channels), forms the same affine as
+// gn_finalize_kernel and writes act(x * scale + shift) as BF16 or FP32.
+// One launch and one read instead of statistics, finalize and apply.
+template <int NS, bool F32>
+__global__ __launch_bounds__(256) void gn_apply_window_kernel(GnArgs g, int act, uint16_t* out, float* out32) {
+  __shared__ double ls[256 * 8];
+  __shared__ double lq[256 * 8];
+  __shared__ double cs[kWinMaxCin];
+  __shared__ double cq[kWinMaxCin];
+  __shared__ double gmean[kWinMaxCin], grstd[kWinMaxCin];
+  __shared__ float scl[kWinMaxCin], shf[kWinMaxCin];
+  const int tid = threadIdx.x, b = blockIdx.x;
+  const int cin = g.c0 + g.c1, q8 = cin / 8;
+  const int lhw = g.lh + g.lw, hw = 1 << lhw;
+  const int q = tid % q8, c = 8 * q, pstep = 256 / q8;
+  const int ns = hw / pstep;   // pixels per thread (<= NS)
+  float v[NS][8];
+  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0}, sq[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    if (k < ns) {
+    const int p = tid / q8 + k * pstep;
+    const int y = p >> g.lw, x = p & ((1 << g.lw) - 1);
+    const float* src;
+    if (c < g.c0) {
+      if (g.up0)
+        src = g.src0 + ((((size_t)b << (lhw - 2)) + ((size_t)(y >> 1) << (g.lw - 1)) + (x >> 1)) * g.c0 + c);
+      else
+        src = g.src0 + (((size_t)b << lhw) + p) * g.c0 + c;
+    } else {
+      src = g.src1 + (((size_t)b << lhw) + p) * g.c1 + (c - g.c0);
+    }
+    const float4 v0 = *reinterpret_cast<const float4*>(src);
+    const float4 v1 = *reinterpret_cast<const float4*>(src + 4);
+    v[k][0] = v0.x; v[k][1] = v0.y; v[k][2] = v0.z; v[k][3] = v0.w;
+    v[k][4] = v1.x; v[k][5] = v1.y; v[k][6] = v1.z; v[k][7] = v1.w;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const double d = v[k][j];
+      s[j] += d;
+      sq[j] += d * d;
+    }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    ls[tid * 8 + j] = s[j];
+    lq[tid * 8 + j] = sq[j];
+  }
+  __syncthreads();
+  for (int ch = tid; ch < cin; ch += 256) {
+    const int qq = ch / 8, jj = ch % 8;
+    double ts = 0, tq = 0;
+    for (int l = 0; l < pstep; ++l) {
+      ts += ls[(qq + l * q8) * 8 + jj];
+      tq += lq[(qq + l * q8) * 8 + jj];
+    }
+    cs[ch] = ts;
+    cq[ch] = tq;
+  }
+  __syncthreads();
+  const int cgp = cin / g.groups;
+  const double n = (double)hw * cgp;
+  for (int gr = tid; gr < g.groups; gr += 256) {
+    double ts = 0, tq = 0;
+    for (int ch = gr * cgp; ch < (gr + 1) * cgp; ++ch) {
+      ts += cs[ch];
+      tq += cq[ch];
+    }
+    const double mean = ts / n;
+    double var = tq / n - mean * mean;
+    if (var < 0) var = 0;
+    gmean[gr] = mean;
+    grstd[gr] = 1.0 / sqrt(var + (double)g.eps);
+  }
+  __syncthreads();
+  for (int ch = tid; ch < cin; ch += 256) {
+    const int gr = ch / cgp;
+    const double sc = (double)g.gamma[ch] * grstd[gr];
+    scl[ch] = (float)sc;
+    shf[ch] = (float)((double)g.beta[ch] - gmean[gr] * sc);
+  }
+  __syncthreads();
+  float sc8[8], sh8[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    sc8[j] = scl[c + j];
+    sh8[j] = shf[c + j];
+  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    if (k >= ns) continue;
+    const int p = tid / q8 + k * pstep;
+    float o[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      o[j] = v[k][j];
+      if (act) {
+        o[j] = o[j] * sc8[j] + sh8[j];
+        if (act == 2) o[j] = silu_f(o[j]);
+      }
+    }
+    const size_t off = (((size_t)b << lhw) + p) * cin + c;
+    if constexpr (F32) {
+      float4* d = reinterpret_cast<float4*>(out32 + off);
+      d[0] = make_float4(o[0], o[1], o[2], o[3]);
+      d[1] = make_float4(o[4], o[5], o[6], o[7]);
+    } else {
+      uint4 u = {pack_bf16(o[0], o[1]), pack_bf16(o[2], o[3]), pack_bf16(o[4], o[5]), pack_bf16(o[6], o[7])};
+      *reinterpret_cast<uint4*>(out + off) = u;
+    }
+  }
+}
+
+template <int NS>
+void launch_gaw(hipStream_t st, const GnArgs& g, int act, uint16_t* out, float* out32) {
+  if (out32)
+    hipLaunchKernelGGL((gn_apply_window_kernel<NS, true>), dim3(g.nb), dim3(256), 0, st, g, act, out, out32);
+  else
+    hipLaunchKernelGGL((gn_apply_window_kernel<NS, false>), dim3(g.nb), dim3(256), 0, st, g, act, out, out32);
+  TD_LAUNCHED();
+}
+
 }  // namespace
 
 void launch_apply(hipStream_t st, const ApplyArgs& a) {
@@ -179,6 +308,31 @@ void launch_apply(hipStream_t st, const ApplyArgs& a) {
   TD_LAUNCHED();
   const double el = 8.0 * n;
   prof_end(st, a.out32 ? K_APPLY32 : K_APPLY, 4.0 * el, el * ((a.out32 ? 4.0 : 2.0) + (a.up0 ? 4.0 * a.c1 / cin + 1.0 * a.c0 / cin : 4.0)));
+}
+
+bool gn_apply_window_fits(int lh, int lw, int c0, int c1, int up0, int groups) {
+  const int cin = c0 + c1;
+  const long elems = (1L << (lh + lw)) * cin;
+  if (cin % 8 || c0 % 8 || c1 % 8 || cin > kWinMaxCin || cin % groups) return false;
+  if (up0 && (lh < 1 || lw < 1)) return false;
+  const int q8 = cin / 8;
+  if (256 % q8 || (1L << (lh + lw)) % (256 / q8)) return false;   // whole pixels per thread
+  return elems <= kWinMaxElems && elems >= 2048;
+}
+
+void launch_gn_apply_window(hipStream_t st, const GnArgs& g, int act, uint16_t* out, float* out32) {
+  TD_CHECK(gn_apply_window_fits(g.lh, g.lw, g.c0, g.c1, g.up0, g.groups), -5, "gn_apply_window: window does not fit");
+  TD_CHECK((out != nullptr) != (out32 != nullptr), -5, "gn_apply_window: exactly one of the BF16 and FP32 outputs");
+  if (!g.nb) return;
+  const int cin = g.c0 + g.c1;
+  const int ns = (int)((1L << (g.lh + g.lw)) / (256 / (cin / 8)));
+  prof_begin(st);
+  if (ns <= 4) launch_gaw<4>(st, g, act, out, out32);
+  else if (ns <= 8) launch_gaw<8>(st, g, act, out, out32);
+  else launch_gaw<16>(st, g, act, out, out32);
+  const double el = (double)g.nb * (1L << (g.lh + g.lw)) * cin;
+  prof_end(st, out32 ? K_APPLY32 : K_APPLY, 4.0 * el,
+           el * ((out32 ? 4.0 : 2.0) + (g.up0 ? 4.0 * g.c1 / cin + 1.0 * g.c0 / cin : 4.0)));
 }
 
 size_t gn_partial_doubles(int nb, int lh, int lw, int cin, int groups) {

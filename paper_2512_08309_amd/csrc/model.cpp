@@ -614,6 +614,32 @@ void Model::gn(hipStream_t st, const float* s0, int c0, int up0, const float* s1
   launch_gn(st, a);
 }
 
+// GroupNorm of a conv input followed by its apply (act 1 affine, 2 + SiLU),
+// written as BF16 (out) or FP32 (out32): one pass per window when the
+// window's input fits in a workgroup, else statistics, then apply.
+void Model::gn_apply(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int nb, int lr,
+                     const float* g, const float* b, int act, uint16_t* out, float* out32) {
+  if (gn_apply_window_fits(lr, lr, c0, c1, up0, d.groups)) {
+    GnArgs a{};
+    a.src0 = s0;
+    a.src1 = s1;
+    a.c0 = c0;
+    a.c1 = c1;
+    a.up0 = up0;
+    a.nb = nb;
+    a.lh = lr;
+    a.lw = lr;
+    a.groups = d.groups;
+    a.eps = d.gn_eps;
+    a.gamma = g;
+    a.beta = b;
+    launch_gn_apply_window(st, a, act, out, out32);
+    return;
+  }
+  gn(st, s0, c0, up0, s1, c1, nb, lr, lr, g, b);
+  apply(st, s0, c0, up0, s1, c1, act, nb, lr, out, out32);
+}
+
 void Model::conv_lp(hipStream_t st, const uint16_t* act, int cin, int nb, int lr, int cout, int taps,
                     const uint16_t* wt, const uint8_t* w8, const float* w8s, int kp, const float* bias,
                     const float* res, float* out) {
@@ -683,8 +709,7 @@ void Model::resblock(hipStream_t st, const ResBlockW& w, int k, const float* s0,
   TD_CHECK(c0 + c1 == w.cin, -5, "resblock: channel mismatch");
   if (prec_) {
     const float* bias1 = bias_eff_ + w.bias_off + (size_t)k * w.cout;
-    gn(st, s0, c0, up0, s1, c1, nb, lr, lr, w.gn1_g, w.gn1_b);
-    apply(st, s0, c0, up0, s1, c1, 2, nb, lr, B.A);
+    gn_apply(st, s0, c0, up0, s1, c1, nb, lr, w.gn1_g, w.gn1_b, 2, B.A, nullptr);
     conv_lp(st, B.A, w.cin, nb, lr, w.cout, 9, w.w1_lp, w.w1_8, w.s1_8, w.kp1, bias1, nullptr, B.T);
     const float* res = s0;
     if (w.has_skip) {
@@ -694,15 +719,13 @@ void Model::resblock(hipStream_t st, const ResBlockW& w, int k, const float* s0,
     } else {
       TD_CHECK(c1 == 0 && !up0, -5, "identity skip needs a plain input");
     }
-    gn(st, B.T, w.cout, 0, nullptr, 0, nb, lr, lr, w.gn2_g, w.gn2_b);
-    apply(st, B.T, w.cout, 0, nullptr, 0, 2, nb, lr, B.A);
+    gn_apply(st, B.T, w.cout, 0, nullptr, 0, nb, lr, w.gn2_g, w.gn2_b, 2, B.A, nullptr);
     conv_lp(st, B.A, w.cout, nb, lr, w.cout, 9, w.w2_lp, w.w2_8, w.s2_8, w.kp2, w.b2, res, out);
     return;
   }
   // FP32: GroupNorm + SiLU are applied once per input element into F, not
   // once per tap inside the 3x3 conv's staging
-  gn(st, s0, c0, up0, s1, c1, nb, lr, lr, w.gn1_g, w.gn1_b);
-  apply(st, s0, c0, up0, s1, c1, 2, nb, lr, nullptr, B.F);
+  gn_apply(st, s0, c0, up0, s1, c1, nb, lr, w.gn1_g, w.gn1_b, 2, nullptr, B.F);
   conv3_f32(st, B.F, w.cin, nb, lr, w.cout, w.w1, bias_eff_ + w.bias_off + (size_t)k * w.cout, nullptr, B.T);
   const float* res = s0;
   if (w.has_skip) {
@@ -725,23 +748,22 @@ void Model::resblock(hipStream_t st, const ResBlockW& w, int k, const float* s0,
   } else {
     TD_CHECK(c1 == 0 && !up0, -5, "identity skip needs a plain input");
   }
-  gn(st, B.T, w.cout, 0, nullptr, 0, nb, lr, lr, w.gn2_g, w.gn2_b);
-  apply(st, B.T, w.cout, 0, nullptr, 0, 2, nb, lr, nullptr, B.F);
+  gn_apply(st, B.T, w.cout, 0, nullptr, 0, nb, lr, w.gn2_g, w.gn2_b, 2, nullptr, B.F);
   conv3_f32(st, B.F, w.cout, nb, lr, w.cout, w.w2, w.b2, res, out);
 }
 
 void Model::attention(hipStream_t st, const AttnW& w, const float* in, int nb, int lvl, float* out) {
   const int lr = ilog2(d.H >> lvl);
   LevelBufs& B = lb_[lvl];
-  gn(st, in, w.C, 0, nullptr, 0, nb, lr, lr, w.gn_g, w.gn_b);
   if (prec_) {
-    apply(st, in, w.C, 0, nullptr, 0, 1, nb, lr, B.A);
+    gn_apply(st, in, w.C, 0, nullptr, 0, nb, lr, w.gn_g, w.gn_b, 1, B.A, nullptr);
     conv_lp(st, B.A, w.C, nb, lr, 3 * w.C, 1, w.wqkv_lp, w.wqkv_8, w.sqkv_8, w.kpq, w.bqkv, nullptr, B.Q);
     launch_attention(st, B.Q, B.O, nb, 1 << (2 * lr), w.C, d.heads);
     apply(st, B.O, w.C, 0, nullptr, 0, 0, nb, lr, B.A);
     conv_lp(st, B.A, w.C, nb, lr, w.C, 1, w.wproj_lp, w.wproj_8, w.sproj_8, w.kpp, w.bproj, in, out);
     return;
   }
+  gn(st, in, w.C, 0, nullptr, 0, nb, lr, lr, w.gn_g, w.gn_b);
   ConvArgs q{};
   q.src0 = in;
   q.c0 = w.C;

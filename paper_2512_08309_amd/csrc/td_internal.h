@@ -184,6 +184,12 @@ struct GnArgs {
 };
 size_t gn_partial_doubles(int nb, int lh, int lw, int cin, int groups);
 void launch_gn(hipStream_t st, const GnArgs& a);
+// GroupNorm statistics and apply (+ SiLU for act 2; act 1 affine only) of
+// whole small windows in one pass, written as BF16 (out) or FP32 (out32);
+// the partial/scale/shift fields of g are not used.  Fits when the window's
+// virtual input is at most 32K elements (see gn_apply_window_fits).
+bool gn_apply_window_fits(int lh, int lw, int c0, int c1, int up0, int groups);
+void launch_gn_apply_window(hipStream_t st, const GnArgs& g, int act, uint16_t* out, float* out32);
 
 void launch_avgpool(hipStream_t st, const float* in, float* out, int nb, int h,
                     int w, int C);
