@@ -325,10 +325,8 @@ Region parent_region(const ModelDesc& d, const Region& r) {
   return Region{x0, y0, floordiv64(r.x0 + r.w - 1, f) - x0 + 1, floordiv64(r.y0 + r.h - 1, f) - y0 + 1};
 }
 
-void touch(td_ctx* c, Entry& e, const Key& k) {
-  c->lru.erase(e.lru);
-  c->lru.push_front(k);
-  e.lru = c->lru.begin();
+void touch(td_ctx* c, Entry& e, const Key&) {
+  c->lru.splice(c->lru.begin(), c->lru, e.lru);   // iterators stay valid
 }
 
 void evict_to_budget(td_ctx* c) {
@@ -1420,8 +1418,8 @@ struct td_server {
   std::deque<uint64_t> queued;
   std::vector<uint64_t> active;
   std::unordered_map<uint64_t, td::SrvQuery> q;
-  std::unordered_map<int, td::SrvTask> tasks;
-  int next_task = 0;
+  std::vector<td::SrvTask> tasks;   // slab indexed by task id; ids are reused
+  std::vector<int> free_tasks;
   std::unordered_map<td::Key, int, td::KeyHash> pending;   // not yet enqueued
   std::map<int, std::deque<int>> ready;                    // level -> ready task ids (FIFO)
   size_t mem_used = 0;
@@ -1501,23 +1499,30 @@ void plan_query(td_server* s, SrvQuery& Q, Arena& arena) {
       for (int64_t iy = S.L.k.iy0; iy <= S.L.k.iy1; ++iy)
         for (int64_t ix = S.L.k.ix0; ix <= S.L.k.ix1; ++ix) {
           Key key{Q.r.seed, t, ix, iy};
-          auto m = c->map.find(key);
-          if (m != c->map.end()) {
-            m->second.pins++;
-            touch(c, m->second, key);
+          auto ins = c->map.try_emplace(key);
+          if (!ins.second) {
+            ins.first->second.pins++;
+            touch(c, ins.first->second, key);
             c->stats.hits++;
             continue;
           }
-          int id = s->next_task++;
-          SrvTask T;
+          int id;
+          if (!s->free_tasks.empty()) {
+            id = s->free_tasks.back();
+            s->free_tasks.pop_back();
+          } else {
+            id = (int)s->tasks.size();
+            s->tasks.emplace_back();
+          }
+          SrvTask& T = s->tasks[id];
+          T = SrvTask{};
           T.key = key;
           T.slot = c->pool.take();
           T.q = Q.ticket;
           T.li = (int)Q.lv.size();
           c->lru.push_front(key);
-          c->map[key] = Entry{T.slot, 1, c->lru.begin()};
+          ins.first->second = Entry{T.slot, 1, c->lru.begin()};
           s->pending[key] = id;
-          s->tasks[id] = T;
           S.own.push_back(id);
           S.L.fresh.push_back({ix, iy});
           mnx = std::min(mnx, ix);
@@ -1712,7 +1717,7 @@ bool run_round_batch(td_server* s, Arena& arena) {
     s->pending.erase(T.key);
     s->q[T.q].lv[T.li].n_enq++;
   }
-  for (int id : ids) s->tasks.erase(id);
+  for (int id : ids) s->free_tasks.push_back(id);
   if (dq.empty()) s->ready.erase(best);
   return true;
 }
@@ -1817,6 +1822,8 @@ td_status td_server_create(td_ctx* c, size_t hbm_budget, int32_t max_inflight, t
     s->budget = hbm_budget;
     s->max_inflight = max_inflight;
     s->maxb = std::min(auto_batch(c), 4096);
+    c->map.reserve(std::max<size_t>(c->map.size(), (size_t)1 << 21));   // no rehash while serving
+    s->pending.reserve((size_t)1 << 16);
     c->model->ensure_workspace(s->maxb);
     for (int i = 0; i < kRing; ++i) {
       TD_HIP(hipEventCreateWithFlags(&s->ring_ev[i], hipEventDisableTiming));
