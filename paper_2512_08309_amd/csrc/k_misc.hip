@@ -178,49 +178,89 @@ __global__ void pos_emb_kernel(const float* __restrict__ cn, int nk, int dim, fl
 }
 
 // ---------------------------------------------------------------- attention
-// One workgroup per (window, head); T <= 64 tokens, head dim d <= 64.
+// One workgroup per (window, head); T <= 64 tokens, head dim d <= 64, both
+// zero-padded to 64 in LDS.  FP32 MFMA (v_mfma_f32_16x16x4_f32): wave w owns
+// query rows 16w..16w+15.  S = Q K^T for its rows (4 column tiles x 16
+// k-steps), scaled; the row softmax (masked to the T valid keys) reduces
+// across the 16 lanes that hold a row with xor shuffles; P goes through LDS
+// into the A-operand layout and O = P V (4 tiles x 16 k-steps).  A lane of
+// an MFMA holds D[4 (lane / 16) + v][lane % 16] of a tile.
+typedef float f4v_a __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(256) void attention_kernel(const float* __restrict__ qkv, float* __restrict__ out,
                                                         int T, int C, int heads) {
-  __shared__ float Q[64 * 65], Kt[64 * 65], V[64 * 65], S[64 * 65];
+  constexpr int LD = 65;
+  __shared__ float Q[64 * LD], Kt[64 * LD], V[64 * LD], P[64 * LD];
   const int b = blockIdx.x, h = blockIdx.y;
   const int d = C / heads;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int g = lane >> 4, r16 = lane & 15;
   const float* base = qkv + (size_t)b * T * 3 * C;
-  for (int e = threadIdx.x; e < T * d; e += 256) {
-    int t = e / d, i = e % d;
-    const float* row = base + (size_t)t * 3 * C + h * d + i;
-    Q[t * 65 + i] = row[0];
-    Kt[t * 65 + i] = row[C];
-    V[t * 65 + i] = row[2 * C];
-  }
-  __syncthreads();
-  const float scale = 1.0f / sqrtf((float)d);
-  for (int e = threadIdx.x; e < T * T; e += 256) {
-    int i = e / T, j = e % T;
-    float acc = 0.f;
-    for (int k = 0; k < d; ++k) acc += Q[i * 65 + k] * Kt[j * 65 + k];
-    S[i * 65 + j] = acc * scale;
-  }
-  __syncthreads();
-  if (threadIdx.x < T) {
-    float* r = S + threadIdx.x * 65;
-    float m = r[0];
-    for (int j = 1; j < T; ++j) m = fmaxf(m, r[j]);
-    float s = 0.f;
-    for (int j = 0; j < T; ++j) {
-      float ev = expf(r[j] - m);
-      r[j] = ev;
-      s += ev;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int t = e >> 6, i = e & 63;
+    float q = 0.f, k = 0.f, v = 0.f;
+    if (t < T && i < d) {
+      const float* row = base + (size_t)t * 3 * C + h * d + i;
+      q = row[0];
+      k = row[C];
+      v = row[2 * C];
     }
-    float inv = 1.0f / s;
-    for (int j = 0; j < T; ++j) r[j] *= inv;
+    Q[t * LD + i] = q;
+    Kt[t * LD + i] = k;
+    V[t * LD + i] = v;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < T * d; e += 256) {
-    int i = e / d, k = e % d;
-    float acc = 0.f;
-    for (int j = 0; j < T; ++j) acc += S[i * 65 + j] * V[j * 65 + k];
-    out[((size_t)b * T + i) * C + h * d + k] = acc;
+  const int r0 = 16 * w;
+  f4v_a s[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) s[j] = (f4v_a){0.f, 0.f, 0.f, 0.f};
+  for (int kk = 0; kk < 16; ++kk) {
+    const int k = 4 * kk + g;
+    const float a = Q[(r0 + r16) * LD + k];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, Kt[(16 * j + r16) * LD + k], s[j], 0, 0, 0);
   }
+  const float scale = 1.0f / sqrtf((float)d);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    float mx = -3.0e38f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      s[j][v] = (16 * j + r16 < T) ? s[j][v] * scale : -3.0e38f;
+      mx = fmaxf(mx, s[j][v]);
+    }
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    float sum = 0.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float ev = (16 * j + r16 < T) ? expf(s[j][v] - mx) : 0.f;
+      s[j][v] = ev;
+      sum += ev;
+    }
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) sum += __shfl_xor(sum, o);
+    const float inv = 1.0f / sum;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) P[(r0 + 4 * g + v) * LD + 16 * j + r16] = s[j][v] * inv;
+  }
+  __syncthreads();
+  f4v_a o[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) o[t] = (f4v_a){0.f, 0.f, 0.f, 0.f};
+  for (int kk = 0; kk < 16; ++kk) {
+    const int j = 4 * kk + g;
+    const float a = P[(r0 + r16) * LD + j];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) o[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, V[j * LD + 16 * t + r16], o[t], 0, 0, 0);
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = r0 + 4 * g + v, f = 16 * t + r16;
+      if (i < T && f < d) out[((size_t)b * T + i) * C + h * d + f] = o[t][v];
+    }
 }
 
 }  // namespace
