@@ -177,8 +177,10 @@ def serving_stream(td, torch, weights_path, parent_path, n, rate, seed=17, budge
 
 def micro_bench(td, torch, ctx, reps=5):
     """HBM-bound kernels on their own: the Laplacian decode of a 1058^2 x 4 fBm
-    terrain latent (seed 21) to an 8192^2 heightfield, and the seed noise G on
-    8192^2 x 4 values (counter word 0); achieved GB/s of the bytes each must write."""
+    terrain latent (seed 21) to an 8192^2 heightfield, the seed noise G on
+    8192^2 x 4 values (counter word 0), and the Laplacian encode of that
+    heightfield back to a latent; achieved GB/s of the bytes each must write
+    (decode, noise) or read (encode)."""
     from synth.fbm import terrain_latent
     lx, ly = 13 - 17, -1000001 - 17
     lat = torch.from_numpy(terrain_latent(21, lx, ly, 1058, 1058)).cuda().contiguous()
@@ -200,8 +202,22 @@ def micro_bench(td, torch, ctx, reps=5):
     e1.record()
     torch.cuda.synchronize()
     noise_ms = e0.elapsed_time(e1) / reps
+    X0, Y0 = 8 * 13, 8 * -1000001
+    gx, gy, gw, gh = ctx.lap_encode(None, X0, Y0, 8192, 8192)
+    lat_out = torch.empty((gh, gw, lat.shape[2]), device="cuda")
+    ctx.lap_encode(out, X0, Y0, 8192, 8192, lat_out, stream)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        ctx.lap_encode(out, X0, Y0, 8192, 8192, lat_out, stream)
+    e1.record()
+    torch.cuda.synchronize()
+    enc_ms = e0.elapsed_time(e1) / reps
     return {"decode_8192": {"ms": dec_ms, "GB_per_s_written": 8192 * 8192 * 4 / (dec_ms * 1e-3) / 1e9,
                             "note": "all four decode kernels; 268 MB of heightfield written"},
+            "encode_8192": {"ms": enc_ms, "GB_per_s_read": 8192 * 8192 * 4 / (enc_ms * 1e-3) / 1e9,
+                            "note": "all four encode kernels on the decoded 8192^2 heightfield (268 MB read "
+                                    "once algorithmically; the kernels read it twice) to a %dx%d latent" % (gw, gh)},
             "noise_8192x4": {"ms": noise_ms, "GB_per_s_written": noise.numel() * 4 / (noise_ms * 1e-3) / 1e9,
                              "note": "Philox + bit-exact IEEE Box-Muller per pair: ALU-bound"}}
 

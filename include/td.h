@@ -215,6 +215,22 @@ td_status td_lap_decode(td_ctx *ctx, const float *latent_dev, int64_t lx0,
                         int64_t Y0, int32_t W, int32_t H, float *out_dev,
                         void *hip_stream);
 
+/* Laplacian encode (Sec. 5.2; the inverse construction the decode undoes):
+ * elevation height_dev [H][W] float32 on the 8-aligned full-resolution
+ * region [X0, X0+W) x [Y0, Y0+H) -> z = sign(h) sqrt|h|, L = G5 * down8(z)
+ * (valid), and per output latent pixel the low band L / sigma_low and the
+ * residual coefficients <z - up8(L), beta_k> / sigma_res (k = 1..3) of its
+ * 8x8 block, written to latent_dev [oh][ow][C] float32 (channels beyond 4
+ * zero).  The output shrinks by the blur radius plus one block on each
+ * side: geom receives {ox0, oy0, ow, oh} = {X0/8 + R + 1, Y0/8 + R + 1,
+ * W/8 - 2R - 2, H/8 - 2R - 2} with R the blur radius of the loaded weights.
+ * latent_dev may be NULL to query geom only.  TD_E_INVAL for an unaligned
+ * or too small region or latent_len < ow * oh * C.  Enqueued on hip_stream
+ * (NULL: the context's stream). */
+td_status td_lap_encode(td_ctx *ctx, const float *height_dev, int64_t X0,
+                        int64_t Y0, int32_t W, int32_t H, float *latent_dev,
+                        size_t latent_len, int64_t geom[4], void *hip_stream);
+
 /* Window-range function kappa of the formal appendix for one axis pair:
  * windows [ix*stride+offset, +size) meeting [x0,x0+w) x [y0,y0+h).
  * Writes {ix_min, ix_max, iy_min, iy_max}; returns TD_OK, or TD_E_INVAL if

@@ -1288,6 +1288,51 @@ td_status td_lap_decode(td_ctx* c, const float* latent_dev, int64_t lx0, int64_t
   });
 }
 
+td_status td_lap_encode(td_ctx* c, const float* height_dev, int64_t X0, int64_t Y0, int32_t W, int32_t H,
+                        float* latent_dev, size_t latent_len, int64_t geom[4], void* hip_stream) {
+  if (!c || !geom) return TD_E_INVAL;
+  return guarded(c, [&] {
+    need_model(c);
+    const ModelDesc& d = c->model->d;
+    TD_CHECK(d.factor == 8, TD_E_STATE, "encode: the decode factor must be 8");
+    TD_CHECK(W >= 1 && H >= 1 && W % 8 == 0 && H % 8 == 0 && floordiv64(X0, 8) * 8 == X0 &&
+                 floordiv64(Y0, 8) * 8 == Y0, TD_E_INVAL, "encode: the region must be 8-aligned");
+    check_region(X0, Y0, W, H);
+    const int R = d.blur_radius;
+    const int64_t ow = W / 8 - 2 * R - 2, oh = H / 8 - 2 * R - 2;
+    TD_CHECK(ow >= 1 && oh >= 1, TD_E_INVAL, "encode: region too small for the blur and up8 aprons");
+    geom[0] = X0 / 8 + R + 1;
+    geom[1] = Y0 / 8 + R + 1;
+    geom[2] = ow;
+    geom[3] = oh;
+    if (!latent_dev) return;
+    TD_CHECK(height_dev, TD_E_INVAL, "encode: null height");
+    TD_CHECK(latent_len >= (size_t)(ow * oh * d.C), TD_E_INVAL, "encode: latent buffer too small");
+    TD_HIP(hipSetDevice(c->device));
+    hipStream_t st = !hip_stream ? c->stream : hip_stream == TD_STREAM_DEFAULT ? nullptr : (hipStream_t)hip_stream;
+    if (c->pending) {
+      TD_HIP(hipEventSynchronize(c->done));
+      c->pending = false;
+    }
+    const size_t nb = (size_t)(W / 8) * (H / 8);
+    grow(c->dec, c->dec_cap, 2 * nb);
+    EncodeArgs a{};
+    a.height = height_dev;
+    a.W = W;
+    a.H = H;
+    a.C = d.C;
+    a.sigma_low = (float)d.sigma_low;
+    a.sigma_res = (float)d.sigma_res;
+    a.taps = c->model->decode_taps();
+    a.radius = R;
+    a.atoms = c->model->decode_atoms();
+    a.work0 = c->dec;
+    a.work1 = c->dec + nb;
+    a.latent = latent_dev;
+    launch_encode(st, a);
+  });
+}
+
 td_status td_kappa(int64_t x0, int64_t y0, int64_t w, int64_t h, int32_t size, int32_t stride, int32_t offset,
                    int64_t out[4]) {
   if (!out || size < 1 || stride < 1 || w < 1 || h < 1) return TD_E_INVAL;

@@ -1,5 +1,6 @@
 // Laplacian decode of a terrain latent (Sec. 5.2) with the signed-sqrt
-// inverse (signed-sqrt appendix).
+// inverse (signed-sqrt appendix), and the encode that builds such a latent
+// from elevation (at the end of the file).
 //
 //   L = sigma_low * J0[.., 0]                   low band (signed-sqrt metres)
 //   Hres(X, Y) = sum_k sigma_res * J0[Y/8, X/8, k] * beta_k(X mod 8, Y mod 8)
@@ -153,6 +154,69 @@ __global__ __launch_bounds__(256) void decode_out_kernel(const float* __restrict
   }
 }
 
+// ---------------------------------------------------------------- encode
+// Elevation -> latent on an 8-aligned full-resolution region: z = sign(h)
+// sqrt|h|; D = down8(z); L = G5 * D (valid: the region shrinks by R blocks a
+// side); for each output block (one more block in, for up8) the low band
+// L / sigma_low and the residual coefficients <z - up8(L), beta_k> /
+// sigma_res of the 8 x 8 block.  Heights are read twice (stages e1 and e3).
+__device__ __forceinline__ float ssqrt(float h) { return copysignf(sqrtf(fabsf(h)), h); }
+
+// (e1) D(bx, by) = mean over block (bx, by) of sign(h) sqrt|h|
+__global__ __launch_bounds__(256) void enc_down_kernel(const float* __restrict__ h, int W, int nbx, int nby,
+                                                       float* __restrict__ D) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= nbx * nby) return;
+  const int by = e / nbx, bx = e % nbx;
+  const float* p = h + (size_t)(8 * by) * W + 8 * bx;
+  float s = 0.f;
+  for (int r = 0; r < 8; ++r) {
+    const float4 a = *reinterpret_cast<const float4*>(p + (size_t)r * W);
+    const float4 b = *reinterpret_cast<const float4*>(p + (size_t)r * W + 4);
+    s += ((ssqrt(a.x) + ssqrt(a.y)) + (ssqrt(a.z) + ssqrt(a.w))) + ((ssqrt(b.x) + ssqrt(b.y)) + (ssqrt(b.z) + ssqrt(b.w)));
+  }
+  D[e] = s * (1.f / 64.f);
+}
+
+// (e3) output block (R + 1 + i, R + 1 + j) of the region: L is [nly][nlx]
+// at block offset R; writes lat[j][i][0..C)
+__global__ __launch_bounds__(256) void enc_res_kernel(const float* __restrict__ h, int W, const float* __restrict__ L,
+                                                      int nlx, int ow, int oh, int R, int C, float inv_sl,
+                                                      float inv_sr, const float* __restrict__ atoms,
+                                                      float* __restrict__ lat) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= ow * oh) return;
+  const int j = e / ow, i = e % ow;
+  const int bx = R + 1 + i, by = R + 1 + j;             // block in the region
+  const int lx = bx - R, ly = by - R;                   // the same block in L
+  float l3[3][3];
+  for (int dy = 0; dy < 3; ++dy)
+    for (int dx = 0; dx < 3; ++dx) l3[dy][dx] = L[(size_t)(ly - 1 + dy) * nlx + (lx - 1 + dx)];
+  const int nk = C - 1 < 3 ? C - 1 : 3;
+  float r[3] = {0.f, 0.f, 0.f};
+  const float* p = h + (size_t)(8 * by) * W + 8 * bx;
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const int ty = v < 4 ? 0 : 1;                        // rows (ly - 1 + ty, ly + ty) of L
+    const float fy = (float)(v < 4 ? 2 * v + 9 : 2 * v - 7) * 0.0625f;
+    const float4 q0 = *reinterpret_cast<const float4*>(p + (size_t)v * W);
+    const float4 q1 = *reinterpret_cast<const float4*>(p + (size_t)v * W + 4);
+    const float hv[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int tx = u < 4 ? 0 : 1;
+      const float fx = (float)(u < 4 ? 2 * u + 9 : 2 * u - 7) * 0.0625f;
+      const float a0 = (1.f - fy) * l3[ty][tx] + fy * l3[ty + 1][tx];
+      const float a1 = (1.f - fy) * l3[ty][tx + 1] + fy * l3[ty + 1][tx + 1];
+      const float res = ssqrt(hv[u]) - ((1.f - fx) * a0 + fx * a1);
+      for (int k = 0; k < nk; ++k) r[k] += res * atoms[k * 64 + v * 8 + u];
+    }
+  }
+  float* o = lat + (size_t)e * C;
+  o[0] = l3[1][1] * inv_sl;
+  for (int k = 1; k < C; ++k) o[k] = k <= nk ? r[k - 1] * inv_sr : 0.f;
+}
+
 }  // namespace
 
 size_t decode_work_floats(const DecodeArgs& a) {
@@ -187,6 +251,28 @@ void launch_decode(hipStream_t st, const DecodeArgs& a) {
                      (int)(s.yl - a.ly0), xo, yo, a.W, a.H, a.out);
   TD_LAUNCHED();
   prof_end(st, K_DECODE, 20.0 * a.W * a.H, 4.0 * (double)a.W * a.H + 4.0 * (double)nxD * nyD * a.C);
+}
+
+void launch_encode(hipStream_t st, const EncodeArgs& a) {
+  const int R = a.radius;
+  TD_CHECK(a.W % 8 == 0 && a.H % 8 == 0, -1, "encode: region sides must be multiples of 8");
+  const int nbx = a.W / 8, nby = a.H / 8;
+  const int nlx = nbx - 2 * R, nly = nby - 2 * R, ow = nlx - 2, oh = nly - 2;
+  TD_CHECK(ow >= 1 && oh >= 1, -1, "encode: region too small for the blur and up8 aprons");
+  prof_begin(st);
+  hipLaunchKernelGGL(enc_down_kernel, dim3((nbx * nby + 255) / 256), dim3(256), 0, st, a.height, a.W, nbx, nby,
+                     a.work0);
+  TD_LAUNCHED();
+  hipLaunchKernelGGL(blur_v_kernel, dim3((nbx * nly + 255) / 256), dim3(256), 0, st, a.work0, nbx, nly, a.taps, R,
+                     a.work1);
+  TD_LAUNCHED();
+  hipLaunchKernelGGL(blur_h_kernel, dim3((nlx * nly + 255) / 256), dim3(256), 0, st, a.work1, nbx, nlx, nly, a.taps,
+                     R, a.work0);
+  TD_LAUNCHED();
+  hipLaunchKernelGGL(enc_res_kernel, dim3((ow * oh + 255) / 256), dim3(256), 0, st, a.height, a.W, a.work0, nlx, ow,
+                     oh, R, a.C, 1.f / a.sigma_low, 1.f / a.sigma_res, a.atoms, a.latent);
+  TD_LAUNCHED();
+  prof_end(st, K_ENCODE, 12.0 * a.W * a.H, 8.0 * (double)a.W * a.H + 4.0 * (double)ow * oh * a.C);
 }
 
 }  // namespace td

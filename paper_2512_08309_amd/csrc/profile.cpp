@@ -10,7 +10,7 @@ const char* kclass_name(int k) {
                                     "conv_out_edm", "window_attention", "avgpool", "noise_philox",
                                     "blend", "laplace_decode", "linear_gaussian_step", "embedding",
                                     "conv3x3_mfma_bf16", "conv1x1_mfma_bf16", "gn_apply_bf16", "window_gather",
-                                    "conv_wgrad_f32", "gn_apply_f32"};
+                                    "conv_wgrad_f32", "gn_apply_f32", "laplace_encode"};
   return (k >= 0 && k < K_NCLASS) ? n[k] : "?";
 }
 

@@ -39,7 +39,7 @@ struct Error {
 // bytes of the launch).  When no profiler is installed the hooks are no-ops.
 enum KClass {
   K_CONV3 = 0, K_CONV1, K_GN, K_CONV_IN, K_CONV_OUT, K_ATTN, K_POOL, K_NOISE, K_BLEND, K_DECODE, K_LG, K_EMB,
-  K_CONV3_LP, K_CONV1_LP, K_APPLY, K_GATHER, K_WGRAD, K_APPLY32, K_NCLASS
+  K_CONV3_LP, K_CONV1_LP, K_APPLY, K_GATHER, K_WGRAD, K_APPLY32, K_ENCODE, K_NCLASS
 };
 const char* kclass_name(int k);
 struct Profiler;
@@ -254,5 +254,20 @@ struct DecodeArgs {
 };
 size_t decode_work_floats(const DecodeArgs& a);
 void launch_decode(hipStream_t st, const DecodeArgs& a);
+
+// Laplacian encode of elevation on an 8-aligned region [H][W] into the latent
+// of blocks (R + 1 .. W/8 - R - 2) x (R + 1 .. H/8 - R - 2), [oh][ow][C].
+struct EncodeArgs {
+  const float* height;   // [H][W]
+  int W, H, C;
+  float sigma_low, sigma_res;
+  const float* taps;     // 2R+1 Gaussian taps
+  int radius;
+  const float* atoms;    // [3][8][8]
+  float* work0;          // (W/8) x (H/8) floats each
+  float* work1;
+  float* latent;         // [oh][ow][C]
+};
+void launch_encode(hipStream_t st, const EncodeArgs& a);
 
 }  // namespace td

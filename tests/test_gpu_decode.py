@@ -90,3 +90,36 @@ def test_calls_on_torch_default_stream_are_ordered_with_torch(ctx):
     got.fill_(-1.0)
     ctx.sample_region_async(5, 3, 4, 40, 24, 0, got, s)
     assert float((got - want).abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("region", [(-800, 1600, 384, 320), (8 * 999991, -8 * 1000003, 296, 400)])
+def test_encode_matches_oracle(ctx, region):
+    """Laplacian encode of an elevation field (the oracle's decode of an fBm
+    latent, rounded to float32) against the oracle's encode of the same
+    float32 heights: geometry exact, values rel L2 <= 1e-5."""
+    import torch
+    X0, Y0, W, H = region
+    lx0, ly0, lw, lh = laplace.required_latent(region, DEC)
+    lat = terrain_latent(21, lx0, ly0, lw, lh, 4)
+    h32 = laplace.decode(lat.astype(np.float64), (lx0, ly0), region, DEC).astype(np.float32)
+    ref, origin = laplace.encode(h32.astype(np.float64), region, DEC, 4)
+    geom = ctx.lap_encode(None, X0, Y0, W, H)
+    assert geom == (origin[0], origin[1], ref.shape[1], ref.shape[0])
+    out = torch.empty((geom[3], geom[2], 4), device="cuda")
+    ctx.lap_encode(torch.from_numpy(h32).cuda(), X0, Y0, W, H, out)
+    torch.cuda.synchronize()
+    err = rel_l2(out.cpu().numpy(), ref)
+    print("encode rel L2 %.2e" % err)
+    assert err <= 1e-5
+
+
+def test_encode_rejects_bad_regions(ctx):
+    import torch
+    from paper_2512_08309_amd import td
+    h = torch.zeros((320, 384), device="cuda")
+    out = torch.empty((8, 8, 4), device="cuda")
+    for X0, Y0, W, H in [(4, 0, 384, 320), (0, 0, 380, 320), (0, 0, 256, 256)]:
+        with pytest.raises(td.TDError):
+            ctx.lap_encode(None, X0, Y0, W, H)
+    with pytest.raises(td.TDError):        # output too small for (384 / 8 - 32) x (320 / 8 - 32) x 4
+        ctx.lap_encode(h, 0, 0, 384, 320, out)
