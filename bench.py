@@ -175,6 +175,24 @@ def serving_stream(td, torch, weights_path, parent_path, n, rate, seed=17, budge
             "cache_hits": cs["hits"], "windows_evaluated": cs["misses"], "wall_s": wall}
 
 
+def paper_context(lat):
+    """The paper's own speed figure, quoted as context (other hardware, its
+    trained models, a 512^2 tile at 90 m per pixel), and the same traversal
+    arithmetic applied to the neighbour-query latency of the C1 stream here
+    (a 64^2 latent = 512^2 px tile of synthetic random-init models): not a
+    like-for-like comparison."""
+    tile_m = 512 * 90.0
+    ctx = {"paper": "generation 9x faster than orbital velocity (7,700 m/s): time to second tile 0.66 s for a "
+                    "512^2 tile at 90 m per pixel (46 km), consumer GPU, the paper's trained models"}
+    if lat:
+        t = lat["neighbour"]["p50_ms"] * 1e-3
+        ctx["here"] = {"neighbour_query_p50_s": t, "traversal_m_per_s": tile_m / t,
+                       "x_orbital_velocity": tile_m / t / 7700.0,
+                       "note": "C1 neighbour latent query (64^2 latent, 512^2 px at 8x) of the latency stream; "
+                               "synthetic 2-level UNet, not the paper's models"}
+    return ctx
+
+
 def micro_bench(td, torch, ctx, reps=5):
     """HBM-bound kernels on their own: the Laplacian decode of a 1058^2 x 4 fBm
     terrain latent (seed 21) to an 8192^2 heightfield, the seed noise G on
@@ -484,6 +502,7 @@ def main():
         "micro": micro,
         "cpu_baseline": cpu,
         "output_finite": finite,
+        "paper_context": paper_context(lat),
     }
     print(json.dumps(res))
 
