@@ -188,25 +188,34 @@ __global__ __launch_bounds__(256) void colsum_part_kernel(const float* __restric
 }
 
 // Weight gradient of a 3x3 (taps 9, zero padding) or 1x1 conv over the
-// pixel range of split s: part[s][t][i][o] = sum_m A(t)[m][i] dY[m][o].
-// Tile 64 (ci) x 64 (co) per workgroup, 4 x 4 outputs per thread; pixels
-// staged 16 at a time through LDS.
-constexpr int WG_PIX = 16;
+// pixel range of split s: part[s][t][i][o] = sum_m A(t)[m][i] dY[m][o], a
+// GEMM with the pixels as K.  Tile 64 (ci) x 64 (co) per workgroup; pixels
+// staged WG_PIX at a time through LDS as [pixel][channel], which is the
+// operand layout of v_mfma_f32_16x16x4_f32 (A = A(t)^T, B = dY, 4 pixels
+// per step).  Wave w owns ci rows 16w..16w+15 and all 64 co columns.  The
+// row stride of 80 floats puts the two rows a half-wave reads in disjoint
+// LDS banks.
+constexpr int WG_PIX = 32;
+constexpr int WG_LD = 80;
+typedef float wg_f4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void wgrad_kernel(const float* __restrict__ A, const float* __restrict__ dY,
                                                     int lh, int lw, int ci, int co, int taps, size_t M,
                                                     int per, float* __restrict__ part) {
-  __shared__ float As[WG_PIX][64];
-  __shared__ float Ds[WG_PIX][64];
+  __shared__ float As[WG_PIX * WG_LD];
+  __shared__ float Ds[WG_PIX * WG_LD];
   const int t = blockIdx.z % taps, s = blockIdx.z / taps;
   const int i0 = blockIdx.x * 64, o0 = blockIdx.y * 64;
-  const int tid = threadIdx.x, ti = tid % 16, to = tid / 16;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int g = lane >> 4, r16 = lane & 15;
   const int W = 1 << lw, Hh = 1 << lh;
   int dy = 0, dx = 0;
   if (taps == 9) {
     dy = t / 3 - 1;
     dx = t % 3 - 1;
   }
-  float acc[4][4] = {};
+  wg_f4 acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j] = (wg_f4){0.f, 0.f, 0.f, 0.f};
   const size_t m0 = (size_t)s * per;
   const size_t m1 = m0 + per < M ? m0 + per : M;
   for (size_t mb = m0; mb < m1; mb += WG_PIX) {
@@ -221,31 +230,26 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const float* __restrict__ A,
         }
         if (o0 + k < co) dv = dY[m * co + o0 + k];
       }
-      As[p][k] = av;
-      Ds[p][k] = dv;
+      As[p * WG_LD + k] = av;
+      Ds[p * WG_LD + k] = dv;
     }
     __syncthreads();
-#pragma unroll 4
-    for (int p = 0; p < WG_PIX; ++p) {
-      float a[4], d[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        a[q] = As[p][ti + 16 * q];
-        d[q] = Ds[p][to + 16 * q];
-      }
+    for (int kk = 0; kk < WG_PIX / 4; ++kk) {
+      const int p = 4 * kk + g;
+      const float a = As[p * WG_LD + 16 * w + r16];
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[q][r] += a[q] * d[r];
+      for (int j = 0; j < 4; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, Ds[p * WG_LD + 16 * j + r16], acc[j], 0, 0, 0);
     }
     __syncthreads();
   }
+  // lane holds D[4g + v][r16] of tile (w, j): ci row i0 + 16w + 4g + v, co column o0 + 16j + r16
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+  for (int j = 0; j < 4; ++j)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = i0 + ti + 16 * q, o = o0 + to + 16 * r;
-      if (i < ci && o < co) part[(((size_t)s * taps + t) * ci + i) * co + o] = acc[q][r];
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + 16 * w + 4 * g + v, o = o0 + 16 * j + r16;
+      if (i < ci && o < co) part[(((size_t)s * taps + t) * ci + i) * co + o] = acc[j][v];
     }
 }
 
