@@ -209,7 +209,9 @@ td_status td_noise_region(uint64_t seed, int64_t x0, int64_t y0, int32_t w, int3
  * signed-sqrt appendix) of a latent held in device memory, [lh][lw][C]
  * float32 with latent origin (lx0, ly0), onto the full-resolution region
  * [X0, X0+W) x [Y0, Y0+H): out_dev is [H][W] float32.  The latent must
- * cover the 17-pixel apron; TD_E_INVAL otherwise.  Enqueued on hip_stream. */
+ * cover the 17-pixel apron; TD_E_INVAL otherwise.  Enqueued on hip_stream.
+ * The decode and td_lap_encode use one scratch buffer of the context: calls
+ * on different streams must be ordered by the caller. */
 td_status td_lap_decode(td_ctx *ctx, const float *latent_dev, int64_t lx0,
                         int64_t ly0, int32_t lw, int32_t lh, int64_t X0,
                         int64_t Y0, int32_t W, int32_t H, float *out_dev,
