@@ -162,7 +162,6 @@ class Trainer {
   const float* x_ = nullptr;
   float* e2_ = nullptr;         // noise embedding of the tape's sigma
   float* Ain_ = nullptr;        // c_in x
-  float* Dout_ = nullptr;
   int* origins_ = nullptr;
   int origins_cap_ = 0;
   std::unordered_map<const float*, float*> grad_;
