@@ -16,7 +16,10 @@
  *  - Latent outputs are float32, planar [C][h][w] (C = latent channels);
  *    height outputs are float32 [h][w] in metres.
  *  - Every call returns td_status; nothing throws across the ABI.  On error,
- *    td_last_error(ctx) describes the failure.
+ *    td_last_error(ctx) describes the failure.  A query that fails after
+ *    its arguments were accepted (an allocation, a launch) drops the
+ *    context's cache, which only ever changes speed, never values; the
+ *    context stays usable.
  *  - A context is not thread-safe: one caller at a time.
  *  - Buffers are owned by the caller; the context owns its weights, its
  *    device cache and its workspaces, all freed by td_destroy.
@@ -277,7 +280,10 @@ td_status td_kernel_stats(td_ctx *ctx, td_kernel_stat_t *out, int32_t cap,
  * several queries are evaluated once).  Results equal those of the same
  * queries made one at a time (seed consistency, Sec. 3.5; Parallelization
  * theorem of the appendix).  The server uses the context's model, cache
- * and stream; one thread drives it. */
+ * and stream; one thread drives it.  After a td_server_progress error the
+ * server refuses further rounds (TD_E_STATE); td_server_destroy then also
+ * drops the context's cache (windows in flight may never have been
+ * written). */
 typedef struct td_server td_server;
 
 typedef struct {

@@ -215,6 +215,7 @@ struct td_ctx {
   float* cond = nullptr;      // parent latent of the current query, [h][w][Cc]
   size_t cond_cap = 0;
   hipEvent_t xev = nullptr;   // orders this stream and the parent's
+  hipEvent_t uev = nullptr;   // orders a caller's stream and this one
   // consistency sampling: the teacher whose one-step estimate judges ours
   td_ctx* judge = nullptr;
   std::vector<td_ctx*> judged_by;
@@ -480,7 +481,7 @@ CondSrc cond_src(const ModelDesc& d, const float* base, int64_t pitch, int64_t f
 }
 
 // J_level on region r written to dev_out (layout 0: [h][w][C], 1: [C][h][w]).
-void sample_latent(td_ctx* c, Arena& arena, uint64_t seed, Region r, int level, int layout, float* dev_out) {
+void sample_latent_body(td_ctx* c, Arena& arena, uint64_t seed, Region r, int level, int layout, float* dev_out) {
   const ModelDesc& d = c->model->d;
   hipStream_t st = c->stream;
   c->stats.queries++;
@@ -630,7 +631,7 @@ void sample_latent(td_ctx* c, Arena& arena, uint64_t seed, Region r, int level, 
 // are gathered from their regions' canvases into shared batches.  Window
 // values do not depend on the batch they run in, so each result equals the
 // region's own sample_latent.
-void sample_latent_multi(td_ctx* c, Arena& arena, const std::vector<RegionJob>& jobs) {
+void sample_latent_multi_body(td_ctx* c, Arena& arena, const std::vector<RegionJob>& jobs) {
   const ModelDesc& d = c->model->d;
   TD_CHECK(d.Cc == 0, TD_E_STATE, "internal: batched regions of a conditioned model");
   hipStream_t st = c->stream;
@@ -819,6 +820,33 @@ void decode_into(td_ctx* c, const float* latent, const Region& lat, const Region
   launch_decode(st, a);
 }
 
+// A query that fails part-way (an allocation, a launch, a rejected level)
+// can leave windows pinned, or claimed in the map without their contribution
+// having been written.  The cache only ever changes speed, not values, so it
+// is dropped once the stream has drained instead of being repaired.
+void abandon_cache(td_ctx* c) {
+  (void)hipStreamSynchronize(c->stream);
+  drop_cache(c);
+}
+
+void sample_latent(td_ctx* c, Arena& arena, uint64_t seed, Region r, int level, int layout, float* dev_out) {
+  try {
+    sample_latent_body(c, arena, seed, r, level, layout, dev_out);
+  } catch (...) {
+    abandon_cache(c);
+    throw;
+  }
+}
+
+void sample_latent_multi(td_ctx* c, Arena& arena, const std::vector<RegionJob>& jobs) {
+  try {
+    sample_latent_multi_body(c, arena, jobs);
+  } catch (...) {
+    abandon_cache(c);
+    throw;
+  }
+}
+
 void sample_any(td_ctx* c, uint64_t seed, int64_t x0, int64_t y0, int32_t w, int32_t h, int32_t level,
                 float* dev_out, size_t out_len) {
   need_model(c);
@@ -865,6 +893,9 @@ td_status guarded(td_ctx* c, F&& f) {
     return TD_OK;
   } catch (const Error& e) {
     if (c) c->err = e.msg;
+    // a failed runtime call is reported once, here: clear it so that the
+    // next launch check does not report it again
+    if (e.status == TD_E_NOMEM || e.status == TD_E_DEVICE) (void)hipGetLastError();
     return (td_status)e.status;
   } catch (const std::bad_alloc&) {
     if (c) c->err = "host allocation failed";
@@ -900,6 +931,7 @@ td_status td_create(int hip_device, td_ctx** out) {
     TD_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     TD_HIP(hipEventCreateWithFlags(&c->done, hipEventDisableTiming));
     TD_HIP(hipEventCreateWithFlags(&c->xev, hipEventDisableTiming));
+    TD_HIP(hipEventCreateWithFlags(&c->uev, hipEventDisableTiming));
   });
   if (s != TD_OK) {
     td_destroy(c);
@@ -935,10 +967,11 @@ void td_destroy(td_ctx* c) {
   c->model.reset();
   c->arena.release();
   c->prof.reset();
-  for (float* p : {c->canvas, c->tmp, c->dec, c->outbuf, c->cond})
+  for (float* p : {c->canvas, c->tmp, c->dec, c->outbuf, c->cond, c->gath})
     if (p) (void)hipFree(p);
   if (c->done) (void)hipEventDestroy(c->done);
   if (c->xev) (void)hipEventDestroy(c->xev);
+  if (c->uev) (void)hipEventDestroy(c->uev);
   if (c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -1032,14 +1065,13 @@ td_status td_sample_region_async(td_ctx* c, uint64_t seed, int64_t x0, int64_t y
     hipStream_t user = hip_stream == TD_STREAM_DEFAULT ? nullptr : (hipStream_t)hip_stream;
     if (hip_stream && user != c->stream) {
       // order after the caller's stream, run on ours, then make theirs wait
-      hipEvent_t ev;
-      TD_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-      TD_HIP(hipEventRecord(ev, user));
-      TD_HIP(hipStreamWaitEvent(c->stream, ev, 0));
+      // (a wait takes the event's state at the time of the call, so one
+      // event serves both directions)
+      TD_HIP(hipEventRecord(c->uev, user));
+      TD_HIP(hipStreamWaitEvent(c->stream, c->uev, 0));
       sample_any(c, seed, x0, y0, w, h, level, dev_out, out_len);
-      TD_HIP(hipEventRecord(ev, c->stream));
-      TD_HIP(hipStreamWaitEvent(user, ev, 0));
-      TD_HIP(hipEventDestroy(ev));
+      TD_HIP(hipEventRecord(c->uev, c->stream));
+      TD_HIP(hipStreamWaitEvent(user, c->uev, 0));
     } else {
       sample_any(c, seed, x0, y0, w, h, level, dev_out, out_len);
     }
@@ -1478,6 +1510,7 @@ struct td_server {
   // sampled (one batched parent call per round)
   std::vector<uint64_t> parent_wait;
   uint64_t round = 0;
+  bool failed = false;   // a round threw part-way: in-flight state is not trusted
   float* batch_in = nullptr;
   size_t batch_cap = 0;
   std::multimap<size_t, float*> free_canvas;   // capacity -> free canvas
@@ -1890,6 +1923,12 @@ void td_server_destroy(td_server* s) {
   (void)hipStreamSynchronize(c->stream);
   if (c->parent) (void)hipStreamSynchronize(c->parent->stream);   // parent latents still being written
   // release what unfinished queries hold: pins and not-yet-evaluated slots
+  // (after a failed round, windows may have been claimed and never written:
+  // the whole cache goes)
+  if (s->failed) {
+    drop_cache(c);
+    s->pending.clear();
+  }
   for (auto& kv : s->pending) {
     auto m = c->map.find(kv.first);
     if (m != c->map.end()) {
@@ -1941,8 +1980,14 @@ td_status td_server_progress(td_server* s, int32_t rounds, int32_t* in_flight) {
   if (!s || rounds < 0) return TD_E_INVAL;
   td_ctx* c = s->c;
   return guarded(c, [&] {
+    TD_CHECK(!s->failed, TD_E_STATE, "an earlier round failed: destroy the server");
     TD_HIP(hipSetDevice(c->device));
-    for (int i = 0; i < rounds; ++i) server_round(s);
+    try {
+      for (int i = 0; i < rounds; ++i) server_round(s);
+    } catch (...) {
+      s->failed = true;
+      throw;
+    }
     if (in_flight) *in_flight = (int32_t)(s->active.size() + s->queued.size());
   });
 }

@@ -811,6 +811,7 @@ td_status tguard(td_trainer* t, F&& f) {
     return TD_OK;
   } catch (const td::Error& e) {
     if (t) t->err = e.msg;
+    if (e.status == TD_E_NOMEM || e.status == TD_E_DEVICE) (void)hipGetLastError();   // reported once
     return (td_status)e.status;
   } catch (const std::exception& e) {
     if (t) t->err = e.what();

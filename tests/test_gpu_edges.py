@@ -97,3 +97,32 @@ def test_argument_errors_leave_the_context_usable(lg):
     assert td.lib.td_sample_region(c.ctx, 4, 0, 0, 4, 4, 0, td._fptr(small), small.size) == td.TD_E_INVAL
     after = c.sample_region(4, 10, 20, 30, 40, 0)
     assert np.array_equal(before, after)
+
+
+def test_failed_query_drops_the_cache_and_the_context_recovers(weights):
+    """A query that fails after planning (its batch workspace cannot be
+    allocated: 2^20 windows of the 16/32 UNet is far beyond HBM) must not
+    leave pinned or never-computed windows behind: the cache is dropped,
+    the error is reported once, and the next query equals a fresh context's."""
+    require_gpu()
+    from paper_2512_08309_amd import td
+    path = weights("c1")
+    with td.Context(0) as c:
+        c.load_weights(path)
+        c.set_option("batch", 64)
+        c.sample_region(3, 0, 0, 16, 16, 0)                    # warms part of the next cone
+        assert c.cache_stats()["bytes_used"] > 0
+        c.set_option("batch", 1 << 20)
+        with pytest.raises(td.TDError) as e:
+            c.sample_region(3, -8, -8, 40, 40, 0)
+        assert e.value.status == td.TD_E_NOMEM, str(e.value)
+        assert c.cache_stats()["bytes_used"] == 0
+        c.set_option("batch", 64)
+        got = c.sample_region(3, -8, -8, 40, 40, 0)
+        c.cache_set_budget(1 << 20)                             # every window evictable again
+        c.sample_region(3, 500, 500, 16, 16, 0)
+        assert c.cache_stats()["bytes_used"] <= 1 << 20
+    with td.Context(0) as f:
+        f.load_weights(path)
+        want = f.sample_region(3, -8, -8, 40, 40, 0)
+    assert np.array_equal(got, want)
