@@ -81,3 +81,39 @@ def test_mix_equals_alone(weights, config, inflight, budget, parent):
         assert cs["misses"] < cold
         print(config, "inflight", inflight, "rounds", st["rounds"], "windows", st["batched_windows"],
               "cold-sum", cold, "mean batch %.1f" % (st["batched_windows"] / st["rounds"]))
+
+
+def test_failed_round_stops_the_server_and_drops_the_cache(weights):
+    """A round that throws part-way (here the parent model is replaced while
+    a child query is in flight, which the next admission rejects) leaves the
+    server refusing further rounds; destroying it drops the child's cache,
+    and the context then answers like a fresh one."""
+    require_gpu()
+    import torch
+    from paper_2512_08309_amd import td
+    with td.Context(0) as p, td.Context(0) as c:
+        p.load_weights(weights("lgc"))
+        c.load_weights(weights("lgh")).set_conditioning(p)
+        C = c.info("channels")
+        outs = [torch.empty((C, 40, 40), device="cuda") for _ in range(2)]
+        srv = td.Server(c, 64 << 30, 4)
+        try:
+            srv.submit(5, 0, 0, 40, 40, 0, outs[0])
+            assert srv.progress(1) == 1                      # 8 levels: still in flight
+            srv.submit(5, 100, 0, 40, 40, 0, outs[1])
+            p.load_weights(weights("lgc", seed=1))
+            with pytest.raises(td.TDError) as e:
+                srv.progress(1)
+            assert e.value.status == td.TD_E_STATE, str(e.value)
+            with pytest.raises(td.TDError) as e:
+                srv.progress(1)
+            assert e.value.status == td.TD_E_STATE and "earlier round" in str(e.value)
+        finally:
+            srv.close()
+        assert c.cache_stats()["bytes_used"] == 0
+        got = c.sample_region(5, 0, 0, 40, 40, 0)
+    with td.Context(0) as p2, td.Context(0) as c2:
+        p2.load_weights(weights("lgc", seed=1))
+        c2.load_weights(weights("lgh")).set_conditioning(p2)
+        want = c2.sample_region(5, 0, 0, 40, 40, 0)
+    assert np.array_equal(got, want)
