@@ -59,9 +59,80 @@ __global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ 
   }
 }
 
+// The same layer with the weights in registers: a thread owns one pair of
+// output channels (its 2 x 9 x (CI + CC) weights live in VGPRs) and walks
+// the tile's pixels; the c0 / 2 lanes that share a pixel read the same halo
+// values (LDS broadcast).  The accumulation order per output is the one
+// above, so both kernels give the same bits.  Needs 256 % (c0 / 2) == 0.
+template <int CI, int CC>
+__global__ __launch_bounds__(256) void conv_in_reg_kernel(const float* __restrict__ canvas, int canvas_w,
+                                                          const int* __restrict__ origins,
+                                                          const float* __restrict__ cond, int H, int c0,
+                                                          float c_in, const float* __restrict__ wt,
+                                                          const float* __restrict__ bias, float* __restrict__ out) {
+  constexpr int CT = CI + CC;
+  constexpr int NH = 18 * 18 * CT;
+  __shared__ float halo[NH];
+  const int b = blockIdx.y;
+  const int tiles_x = H / 16;
+  const int tx0 = (blockIdx.x % tiles_x) * 16, ty0 = (blockIdx.x / tiles_x) * 16;
+  const int ox = origins[2 * b], oy = origins[2 * b + 1];
+#pragma unroll
+  for (int j = 0; j < (NH + 255) / 256; ++j) {
+    const int e = threadIdx.x + 256 * j;
+    if (e < NH) {
+      const int c = e % CT, p = e / CT;
+      const int y = ty0 + p / 18 - 1, x = tx0 + p % 18 - 1;
+      float v = 0.f;
+      if (y >= 0 && y < H && x >= 0 && x < H) {
+        if (c < CI) v = c_in * canvas[((size_t)(oy + y) * canvas_w + ox + x) * CI + c];
+        else v = cond[(((size_t)b * H + y) * H + x) * CC + (c - CI)];
+      }
+      halo[e] = v;
+    }
+  }
+  const int npair = c0 >> 1;
+  const int co = 2 * (threadIdx.x % npair);
+  float w0[9 * CT], w1[9 * CT];
+#pragma unroll
+  for (int k = 0; k < 9 * CT; ++k) {
+    w0[k] = wt[(size_t)k * c0 + co];
+    w1[k] = wt[(size_t)k * c0 + co + 1];
+  }
+  const float b0 = bias[co], b1 = bias[co + 1];
+  __syncthreads();
+  for (int p = threadIdx.x / npair; p < 256; p += 256 / npair) {
+    const int py = p / 16, px = p % 16;
+    float a0 = b0, a1 = b1;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const float* hp = halo + ((py + t / 3) * 18 + px + t % 3) * CT;
+#pragma unroll
+      for (int c = 0; c < CT; ++c) {
+        const float v = hp[c];
+        a0 += v * w0[t * CT + c];
+        a1 += v * w1[t * CT + c];
+      }
+    }
+    *reinterpret_cast<float2*>(out + (((size_t)b * H + ty0 + py) * H + tx0 + px) * c0 + co) = make_float2(a0, a1);
+  }
+}
+
 // ---------------------------------------------------------------- conv_out
+// One workgroup per (window, 16x16 output tile), one output pixel per
+// thread.  The input channels go through LDS in chunks of CK: each chunk's
+// (16+2)^2 x CK halo is read as 16-byte segments (a thread keeps the same
+// 4-channel segment for every pixel it loads, so its GroupNorm scale and
+// shift are one float4 each), normalised and SiLU-activated, zero outside
+// the window.  The next chunk's segments are loaded into registers while the
+// current chunk is being multiplied, so a chunk costs one memory latency,
+// not one per element.
 template <int CO, int CK>
 __global__ __launch_bounds__(256) void conv_out_kernel(OutArgs a) {
+  constexpr int C4 = CK / 4;                    // 16-byte segments per halo pixel
+  constexpr int NSEG = 18 * 18 * C4;            // segments per chunk
+  constexpr int PT = (NSEG + 255) / 256;        // per thread
+  static_assert(256 % C4 == 0, "a thread's segment index must be the same for every pixel it loads");
   __shared__ float halo[18 * 18 * (CK + 1)];
   __shared__ float wl[9 * CK * CO];
   const int b = blockIdx.y;
@@ -75,25 +146,46 @@ __global__ __launch_bounds__(256) void conv_out_kernel(OutArgs a) {
   const float* hb = a.h + (size_t)b * H * H * c0;
   const float* sc = a.gn_scale + (size_t)b * c0;
   const float* sh = a.gn_shift + (size_t)b * c0;
+  const int q4 = 4 * (threadIdx.x % C4);        // first channel of this thread's segment
+  int hoff[PT];                                 // LDS offset of the segment (-1: none)
+  int goff[PT];                                 // float offset in the window (-1: outside)
+#pragma unroll
+  for (int j = 0; j < PT; ++j) {
+    const int e = threadIdx.x + 256 * j;
+    const int p = e / C4, hy = p / 18, hx = p % 18;
+    const int y = ty0 + hy - 1, x = tx0 + hx - 1;
+    hoff[j] = e < NSEG ? p * (CK + 1) + q4 : -1;
+    goff[j] = (e < NSEG && y >= 0 && y < H && x >= 0 && x < H) ? (y * H + x) * c0 + q4 : -1;
+  }
+  const float4 z4 = {0.f, 0.f, 0.f, 0.f};
+  float4 r[PT];
+  auto load = [&](int ci0) {
+#pragma unroll
+    for (int j = 0; j < PT; ++j)
+      r[j] = goff[j] >= 0 ? *reinterpret_cast<const float4*>(hb + goff[j] + ci0) : z4;
+  };
+  load(0);
   for (int ci0 = 0; ci0 < c0; ci0 += CK) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < 18 * 18 * CK; e += 256) {
-      int c = e % CK, p = e / CK;
-      int hy = p / 18, hx = p % 18;
-      int y = ty0 + hy - 1, x = tx0 + hx - 1;
-      float v = 0.f;
-      if (y >= 0 && y < H && x >= 0 && x < H) {
-        float r = hb[((size_t)y * H + x) * c0 + ci0 + c];
-        v = silu_f(r * sc[ci0 + c] + sh[ci0 + c]);
-      }
-      halo[p * (CK + 1) + c] = v;
+    __syncthreads();                            // every thread is done with the last chunk
+    const float4 s4 = *reinterpret_cast<const float4*>(sc + ci0 + q4);
+    const float4 h4 = *reinterpret_cast<const float4*>(sh + ci0 + q4);
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {
+      if (hoff[j] < 0) continue;
+      float* d = halo + hoff[j];
+      const bool in = goff[j] >= 0;
+      d[0] = in ? silu_f(r[j].x * s4.x + h4.x) : 0.f;
+      d[1] = in ? silu_f(r[j].y * s4.y + h4.y) : 0.f;
+      d[2] = in ? silu_f(r[j].z * s4.z + h4.z) : 0.f;
+      d[3] = in ? silu_f(r[j].w * s4.w + h4.w) : 0.f;
     }
     for (int e = threadIdx.x; e < 9 * CK * CO; e += 256) {
-      int o = e % CO, r = e / CO;
-      int c = r % CK, t = r / CK;
+      int o = e % CO, rr = e / CO;
+      int c = rr % CK, t = rr / CK;
       wl[e] = a.wt[((size_t)t * c0 + ci0 + c) * CO + o];
     }
     __syncthreads();
+    if (ci0 + CK < c0) load(ci0 + CK);          // in flight during the products below
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
       const float* hp = halo + ((py + t / 3) * 18 + px + t % 3) * (CK + 1);
@@ -274,11 +366,19 @@ void launch_conv_in(hipStream_t st, const float* canvas, int canvas_w, const int
   const int ct = cimg + ccond;
   dim3 grid((H / 16) * (H / 16), nwin);
   size_t shm = (18 * 18 * ct + 9 * ct * c0) * sizeof(float);
-  TD_CHECK(shm <= 64 * 1024, -5, "conv_in: too many channels");
+  // register-weight kernel where a pixel's lanes tile the workgroup exactly
+  const bool reg = c0 % 2 == 0 && c0 <= 512 && 256 % (c0 / 2) == 0;
+  TD_CHECK(reg || shm <= 64 * 1024, -5, "conv_in: too many channels");
   prof_begin(st);
-#define TD_CONV_IN(CI, CC)                                                                                   \
-  hipLaunchKernelGGL((conv_in_kernel<CI, CC>), grid, dim3(256), shm, st, canvas, canvas_w, origins, cond, H, \
-                     c0, c_in, wt, bias, out)
+#define TD_CONV_IN(CI, CC)                                                                                        \
+  do {                                                                                                            \
+    if (reg)                                                                                                      \
+      hipLaunchKernelGGL((conv_in_reg_kernel<CI, CC>), grid, dim3(256), 0, st, canvas, canvas_w, origins, cond, H, \
+                         c0, c_in, wt, bias, out);                                                                \
+    else                                                                                                          \
+      hipLaunchKernelGGL((conv_in_kernel<CI, CC>), grid, dim3(256), shm, st, canvas, canvas_w, origins, cond, H,   \
+                         c0, c_in, wt, bias, out);                                                                \
+  } while (0)
   if (cimg == 4 && ccond == 0) TD_CONV_IN(4, 0);
   else if (cimg == 1 && ccond == 0) TD_CONV_IN(1, 0);
   else if (cimg == 1 && ccond == 1) TD_CONV_IN(1, 1);
