@@ -126,15 +126,18 @@ __global__ __launch_bounds__(256) void conv_in_reg_kernel(const float* __restric
 // shift are one float4 each), normalised and SiLU-activated, zero outside
 // the window.  The next chunk's segments are loaded into registers while the
 // current chunk is being multiplied, so a chunk costs one memory latency,
-// not one per element.
+// not one per element.  Halo rows are CK + 4 floats (16-byte aligned; eight
+// consecutive lanes of a 16-byte read cover all 32 banks once); the weights
+// are the same for every lane and are read with uniform addresses straight
+// from global memory, so the products touch LDS once per 4 channels.
 template <int CO, int CK>
 __global__ __launch_bounds__(256) void conv_out_kernel(OutArgs a) {
   constexpr int C4 = CK / 4;                    // 16-byte segments per halo pixel
   constexpr int NSEG = 18 * 18 * C4;            // segments per chunk
   constexpr int PT = (NSEG + 255) / 256;        // per thread
   static_assert(256 % C4 == 0, "a thread's segment index must be the same for every pixel it loads");
-  __shared__ float halo[18 * 18 * (CK + 1)];
-  __shared__ float wl[9 * CK * CO];
+  constexpr int LD = CK + 4;
+  __shared__ __attribute__((aligned(16))) float halo[18 * 18 * LD];
   const int b = blockIdx.y;
   const int H = a.H, c0 = a.c0;
   const int tiles_x = H / 16;
@@ -154,15 +157,16 @@ __global__ __launch_bounds__(256) void conv_out_kernel(OutArgs a) {
     const int e = threadIdx.x + 256 * j;
     const int p = e / C4, hy = p / 18, hx = p % 18;
     const int y = ty0 + hy - 1, x = tx0 + hx - 1;
-    hoff[j] = e < NSEG ? p * (CK + 1) + q4 : -1;
+    hoff[j] = e < NSEG ? p * LD + q4 : -1;
     goff[j] = (e < NSEG && y >= 0 && y < H && x >= 0 && x < H) ? (y * H + x) * c0 + q4 : -1;
   }
   const float4 z4 = {0.f, 0.f, 0.f, 0.f};
   float4 r[PT];
+  // unconditional 16-byte loads (pixels outside the window read the
+  // window's first segment and are zeroed when stored to LDS)
   auto load = [&](int ci0) {
 #pragma unroll
-    for (int j = 0; j < PT; ++j)
-      r[j] = goff[j] >= 0 ? *reinterpret_cast<const float4*>(hb + goff[j] + ci0) : z4;
+    for (int j = 0; j < PT; ++j) r[j] = *reinterpret_cast<const float4*>(hb + (goff[j] < 0 ? 0 : goff[j]) + ci0);
   };
   load(0);
   for (int ci0 = 0; ci0 < c0; ci0 += CK) {
@@ -172,29 +176,29 @@ __global__ __launch_bounds__(256) void conv_out_kernel(OutArgs a) {
 #pragma unroll
     for (int j = 0; j < PT; ++j) {
       if (hoff[j] < 0) continue;
-      float* d = halo + hoff[j];
-      const bool in = goff[j] >= 0;
-      d[0] = in ? silu_f(r[j].x * s4.x + h4.x) : 0.f;
-      d[1] = in ? silu_f(r[j].y * s4.y + h4.y) : 0.f;
-      d[2] = in ? silu_f(r[j].z * s4.z + h4.z) : 0.f;
-      d[3] = in ? silu_f(r[j].w * s4.w + h4.w) : 0.f;
-    }
-    for (int e = threadIdx.x; e < 9 * CK * CO; e += 256) {
-      int o = e % CO, rr = e / CO;
-      int c = rr % CK, t = rr / CK;
-      wl[e] = a.wt[((size_t)t * c0 + ci0 + c) * CO + o];
+      float4 v = z4;
+      if (goff[j] >= 0) {
+        v.x = silu_f(r[j].x * s4.x + h4.x);
+        v.y = silu_f(r[j].y * s4.y + h4.y);
+        v.z = silu_f(r[j].z * s4.z + h4.z);
+        v.w = silu_f(r[j].w * s4.w + h4.w);
+      }
+      *reinterpret_cast<float4*>(halo + hoff[j]) = v;
     }
     __syncthreads();
     if (ci0 + CK < c0) load(ci0 + CK);          // in flight during the products below
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-      const float* hp = halo + ((py + t / 3) * 18 + px + t % 3) * (CK + 1);
-      const float* wp = wl + t * CK * CO;
-#pragma unroll 8
-      for (int c = 0; c < CK; ++c) {
-        float v = hp[c];
+      const float* hp = halo + ((py + t / 3) * 18 + px + t % 3) * LD;
+      const float* wp = a.wt + ((size_t)t * c0 + ci0) * CO;   // [c][o] of this tap and chunk
+#pragma unroll 2
+      for (int c4 = 0; c4 < CK / 4; ++c4) {
+        const float4 v4 = *reinterpret_cast<const float4*>(hp + 4 * c4);
+        const float v[4] = {v4.x, v4.y, v4.z, v4.w};
 #pragma unroll
-        for (int o = 0; o < CO; ++o) acc[o] += v * wp[c * CO + o];
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int o = 0; o < CO; ++o) acc[o] += v[q] * wp[(4 * c4 + q) * CO + o];
       }
     }
   }
