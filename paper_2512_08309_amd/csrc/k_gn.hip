@@ -47,6 +47,9 @@ __global__ __launch_bounds__(256) void gn_partial_kernel(GnArgs a, int nchunk) {
     const int q = tid % nq, pl = tid / nq;
     double s[4] = {0, 0, 0, 0}, sq[4] = {0, 0, 0, 0};
     const float* base = src + ((size_t)b * npix_img + p0) * Cs + 4 * q;
+    // unrolled so that several loads are in flight; every sum still takes
+    // its terms in pixel order
+#pragma unroll 8
     for (int p = pl; p < per; p += npl) {
       float4 v = *reinterpret_cast<const float4*>(base + (size_t)p * Cs);
       double d0 = v.x, d1 = v.y, d2 = v.z, d3 = v.w;
