@@ -13,63 +13,18 @@ namespace {
 __device__ __forceinline__ float silu_f(float v) { return __fdividef(v, 1.0f + __expf(-v)); }
 
 // ---------------------------------------------------------------- conv_in
-// One workgroup per (window, 16x16 output tile).  LDS: (16+2)^2 x (CI + CC)
-// inputs (c_in-scaled latent channels, then the conditioning channels; zero
-// outside the window: the network pads with zeros), and the 9 x (CI + CC)
-// x c0 weights.
+// One workgroup per (window, 16x16 output tile).  LDS holds the (16+2)^2 x
+// (CI + CC) inputs: c_in-scaled latent channels, then the conditioning
+// channels, zero outside the window (the network pads with zeros).  A
+// thread owns one pair of output channels (its 2 x 9 x (CI + CC) weights
+// live in VGPRs) and walks the tile's pixels; the c0 / 2 lanes that share a
+// pixel read the same halo values (LDS broadcast).  Needs 256 % (c0 / 2) == 0.
 template <int CI, int CC>
 __global__ __launch_bounds__(256) void conv_in_kernel(const float* __restrict__ canvas, int canvas_w,
                                                       const int* __restrict__ origins,
                                                       const float* __restrict__ cond, int H, int c0,
                                                       float c_in, const float* __restrict__ wt,
                                                       const float* __restrict__ bias, float* __restrict__ out) {
-  constexpr int CT = CI + CC;
-  extern __shared__ float sm[];
-  float* halo = sm;                 // [18*18][CT]
-  float* wl = sm + 18 * 18 * CT;    // [9][CT][c0]
-  const int b = blockIdx.y;
-  const int tiles_x = H / 16;
-  const int tx0 = (blockIdx.x % tiles_x) * 16, ty0 = (blockIdx.x / tiles_x) * 16;
-  const int ox = origins[2 * b], oy = origins[2 * b + 1];
-  for (int e = threadIdx.x; e < 18 * 18 * CT; e += 256) {
-    int c = e % CT, p = e / CT;
-    int hy = p / 18, hx = p % 18;
-    int y = ty0 + hy - 1, x = tx0 + hx - 1;
-    float v = 0.f;
-    if (y >= 0 && y < H && x >= 0 && x < H) {
-      if (c < CI) v = c_in * canvas[((size_t)(oy + y) * canvas_w + ox + x) * CI + c];
-      else v = cond[(((size_t)b * H + y) * H + x) * CC + (c - CI)];
-    }
-    halo[e] = v;
-  }
-  for (int e = threadIdx.x; e < 9 * CT * c0; e += 256) wl[e] = wt[e];
-  __syncthreads();
-  for (int e = threadIdx.x; e < 256 * c0; e += 256) {
-    int co = e % c0, p = e / c0;
-    int py = p / 16, px = p % 16;
-    float acc = bias[co];
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      int dy = t / 3, dx = t % 3;
-      const float* hp = halo + ((py + dy) * 18 + px + dx) * CT;
-#pragma unroll
-      for (int c = 0; c < CT; ++c) acc += hp[c] * wl[(t * CT + c) * c0 + co];
-    }
-    out[(((size_t)b * H + ty0 + py) * H + tx0 + px) * c0 + co] = acc;
-  }
-}
-
-// The same layer with the weights in registers: a thread owns one pair of
-// output channels (its 2 x 9 x (CI + CC) weights live in VGPRs) and walks
-// the tile's pixels; the c0 / 2 lanes that share a pixel read the same halo
-// values (LDS broadcast).  The accumulation order per output is the one
-// above, so both kernels give the same bits.  Needs 256 % (c0 / 2) == 0.
-template <int CI, int CC>
-__global__ __launch_bounds__(256) void conv_in_reg_kernel(const float* __restrict__ canvas, int canvas_w,
-                                                          const int* __restrict__ origins,
-                                                          const float* __restrict__ cond, int H, int c0,
-                                                          float c_in, const float* __restrict__ wt,
-                                                          const float* __restrict__ bias, float* __restrict__ out) {
   constexpr int CT = CI + CC;
   constexpr int NH = 18 * 18 * CT;
   __shared__ float halo[NH];
@@ -369,20 +324,13 @@ void launch_conv_in(hipStream_t st, const float* canvas, int canvas_w, const int
   TD_CHECK(ccond == 0 || cond, -5, "conv_in: conditioning channels without conditioning input");
   const int ct = cimg + ccond;
   dim3 grid((H / 16) * (H / 16), nwin);
-  size_t shm = (18 * 18 * ct + 9 * ct * c0) * sizeof(float);
-  // register-weight kernel where a pixel's lanes tile the workgroup exactly
-  const bool reg = c0 % 2 == 0 && c0 <= 512 && 256 % (c0 / 2) == 0;
-  TD_CHECK(reg || shm <= 64 * 1024, -5, "conv_in: too many channels");
+  // a pixel's c0 / 2 channel-pair lanes must tile the 256-thread workgroup
+  TD_CHECK(c0 % 2 == 0 && c0 <= 512 && 256 % (c0 / 2) == 0, -5,
+           "conv_in: the first level's width must be 2^k with 2 <= 2^k <= 512");
   prof_begin(st);
-#define TD_CONV_IN(CI, CC)                                                                                        \
-  do {                                                                                                            \
-    if (reg)                                                                                                      \
-      hipLaunchKernelGGL((conv_in_reg_kernel<CI, CC>), grid, dim3(256), 0, st, canvas, canvas_w, origins, cond, H, \
-                         c0, c_in, wt, bias, out);                                                                \
-    else                                                                                                          \
-      hipLaunchKernelGGL((conv_in_kernel<CI, CC>), grid, dim3(256), shm, st, canvas, canvas_w, origins, cond, H,   \
-                         c0, c_in, wt, bias, out);                                                                \
-  } while (0)
+#define TD_CONV_IN(CI, CC)                                                                                   \
+  hipLaunchKernelGGL((conv_in_kernel<CI, CC>), grid, dim3(256), 0, st, canvas, canvas_w, origins, cond, H, c0, \
+                     c_in, wt, bias, out)
   if (cimg == 4 && ccond == 0) TD_CONV_IN(4, 0);
   else if (cimg == 1 && ccond == 0) TD_CONV_IN(1, 0);
   else if (cimg == 1 && ccond == 1) TD_CONV_IN(1, 1);
