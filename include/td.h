@@ -86,7 +86,8 @@ void td_destroy(td_ctx *ctx);
  * window size/stride/offset/epsilon, decode constants, tensor table), zero
  * padding to 64 bytes, then little-endian float32 tensors.  Replaces any
  * previous model and clears the cache (cached contributions are
- * model-specific).  TD_E_IO if unreadable, TD_E_FORMAT if malformed. */
+ * model-specific).  TD_E_IO if unreadable, TD_E_FORMAT if malformed; on
+ * any error the context keeps its previous model (or none) and its cache. */
 td_status td_load_weights(td_ctx *ctx, const char *path);
 
 /* Hierarchy (Sec. 5.1; DAGs of infinite tensors, infinite-tensor appendix):

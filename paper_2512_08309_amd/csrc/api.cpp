@@ -982,12 +982,14 @@ td_status td_load_weights(td_ctx* c, const char* path) {
     TD_CHECK(path, TD_E_INVAL, "null path");
     TD_HIP(hipSetDevice(c->device));
     TD_HIP(hipStreamSynchronize(c->stream));
+    // the new model is built first: a file that fails to load leaves the
+    // current model and its cache as they were
+    std::unique_ptr<Model> m(new Model());
+    m->load(path, c->stream);
     c->map.clear();
     c->lru.clear();
     c->pool.release();
     c->model.reset();
-    std::unique_ptr<Model> m(new Model());
-    m->load(path, c->stream);
     c->pool.configure((size_t)m->d.H * m->d.H * m->d.C);
     c->model = std::move(m);
     c->stats = td_cache_stats_t{};

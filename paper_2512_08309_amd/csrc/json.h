@@ -32,7 +32,9 @@ struct Json {
   }
   long long integer() const {
     double v = num();
-    if (v != (double)(long long)v) throw Error{-5, "weight header: expected an integer"};
+    // range first: converting a double outside int64 is undefined
+    if (!(v >= -9.0e18 && v <= 9.0e18) || v != (double)(long long)v)
+      throw Error{-5, "weight header: expected an integer"};
     return (long long)v;
   }
   const std::string& str() const {

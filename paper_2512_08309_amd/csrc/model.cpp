@@ -242,6 +242,7 @@ void Model::load(const std::string& path, hipStream_t st) {
       for (const Json& x : e.at("shape").arr()) {
         long long v = x.integer();
         TD_CHECK(v >= 0 && v < (1LL << 31), -5, "weight header: bad tensor shape");
+        TD_CHECK(v == 0 || cnt <= ((size_t)1 << 32) / (size_t)v, -5, "weight header: tensor too large");
         shp.push_back((int)v);
         cnt *= (size_t)v;
       }

@@ -126,3 +126,65 @@ def test_failed_query_drops_the_cache_and_the_context_recovers(weights):
         f.load_weights(path)
         want = f.sample_region(3, -8, -8, 40, 40, 0)
     assert np.array_equal(got, want)
+
+
+def _tdw_bytes(blob, data):
+    """A TDW1 file from a raw header blob and a data section."""
+    import struct
+    start = (8 + len(blob) + 63) // 64 * 64
+    return b"TDW1" + struct.pack("<I", len(blob)) + blob + b"\0" * (start - 8 - len(blob)) + data
+
+
+def test_malformed_weight_files_are_rejected_and_keep_the_model(weights, tmp_path):
+    """Every malformed file gives TD_E_FORMAT (a missing one TD_E_IO) with a
+    message, and the context keeps answering with the model it had; a fresh
+    context that never loaded a model refuses queries with TD_E_STATE."""
+    require_gpu()
+    import json
+    import struct
+    from paper_2512_08309_amd import td
+    good = weights("c1")
+    raw = open(good, "rb").read()
+    n = struct.unpack("<I", raw[4:8])[0]
+    hdr = json.loads(raw[8:8 + n])
+    data = raw[(8 + n + 63) // 64 * 64:]
+
+    def edited(f):
+        h = json.loads(json.dumps(hdr))
+        f(h)
+        return _tdw_bytes(json.dumps(h).encode(), data)
+
+    cases = {
+        "empty": b"",
+        "magic": b"TDW2" + raw[4:],
+        "header_length": raw[:4] + struct.pack("<I", len(raw)) + raw[8:],
+        "json_syntax": _tdw_bytes(b'{"denoiser": {"kind": ', data),
+        "json_depth": _tdw_bytes(b"[" * 100 + b"]" * 100, data),
+        "data_truncated": raw[:len(raw) - 1000],
+        "integer_range": edited(lambda h: h["denoiser"].__setitem__("in_channels", 1e30)),
+        "tensor_missing": edited(lambda h: h["tensors"].pop()),
+        "tensor_shape": edited(lambda h: h["tensors"][0].__setitem__("shape", [3, 3])),
+        "tensor_size": edited(lambda h: h["tensors"][0].__setitem__("shape", [1 << 30, 1 << 30, 4])),
+        "denoiser_kind": edited(lambda h: h["denoiser"].__setitem__("kind", "transformer")),
+    }
+    with td.Context(0) as c:
+        c.load_weights(good)
+        before = c.sample_region(6, -40, 17, 24, 20, 0)
+        with pytest.raises(td.TDError) as e:
+            c.load_weights(str(tmp_path / "no_such_file.tdw"))
+        assert e.value.status == td.TD_E_IO
+        for name, content in cases.items():
+            p = tmp_path / (name + ".tdw")
+            p.write_bytes(content)
+            with pytest.raises(td.TDError) as e:
+                c.load_weights(str(p))
+            assert e.value.status == td.TD_E_FORMAT, (name, str(e.value))
+            assert str(e.value), name
+        assert np.array_equal(c.sample_region(6, -40, 17, 24, 20, 0), before)
+    with td.Context(0) as fresh:
+        p = tmp_path / "magic.tdw"
+        with pytest.raises(td.TDError):
+            fresh.load_weights(str(p))
+        with pytest.raises(td.TDError) as e:
+            fresh.sample_region(6, 0, 0, 4, 4, 0)
+        assert e.value.status == td.TD_E_STATE
