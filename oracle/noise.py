@@ -29,9 +29,10 @@ checked against numpy's Philox4x64-10 bit generator (same round structure,
 64-bit constants); the 32-bit instance used here runs through that same
 function.  The series are checked against float64 ln/sin/cos within a few
 float32 ulps, and the outputs against N(0,1) by moments, a KS test and the
-analytic tail bound |z| <= sqrt(48 ln 2).  The 4x32 constants themselves are
-"parity unpinned": no published Philox4x32 known-answer vectors are
-available offline.
+analytic tail bound |z| <= sqrt(48 ln 2).  The 4x32 key-schedule increments
+are pinned by their closed forms (golden ratio, sqrt 3 - 1); the two 4x32
+multipliers are "parity unpinned": they were chosen by search, and no
+published Philox4x32 known-answer vectors are available offline.
 """
 from fractions import Fraction
 

@@ -21,6 +21,21 @@ def test_generic_philox_matches_numpy_philox4x64(key, ctr):
         assert noise.philox_generic(words, key, **noise.PHILOX4x64) == got[4 * blk:4 * blk + 4]
 
 
+def test_philox_key_schedule_constants_from_their_definitions():
+    """The Weyl increments of the key schedule are floor(2^w (sqrt 5 - 1) / 2)
+    (the golden ratio) and floor(2^w (sqrt 3 - 1)), for both word widths;
+    exact integer square roots, so the 32-bit pair is pinned by the
+    mathematics and agrees with the top halves of the numpy-pinned 64-bit
+    pair.  (The 32-bit multipliers were chosen by search and have no such
+    definition.)"""
+    for spec in (noise.PHILOX4x32, noise.PHILOX4x64):
+        w = spec["width"]
+        golden = (math.isqrt(5 << (2 * w)) - (1 << w)) // 2
+        root3 = math.isqrt(3 << (2 * w)) - (1 << w)
+        assert spec["weyl"] == (golden, root3)
+    assert [k >> 32 for k in noise.PHILOX4x64["weyl"]] == list(noise.PHILOX4x32["weyl"])
+
+
 def test_vectorised_philox4x32_matches_generic():
     rng = np.random.default_rng(3)
     c = rng.integers(0, 2 ** 32, size=(4, 300), dtype=np.uint64)
