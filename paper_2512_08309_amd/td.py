@@ -123,6 +123,24 @@ def _fptr(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
 
 
+def _dev(t, name, shape=None, numel=None):
+    """Device address of a contiguous float32 torch tensor on a GPU.  The
+    checks raise instead of asserting: a host tensor, another dtype or a
+    strided view would otherwise reach a kernel as a wrong address."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s: expected a torch tensor on the GPU" % name)
+    if t.dtype != torch.float32:
+        raise ValueError("%s: expected float32, got %s" % (name, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s: expected a contiguous tensor" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s: expected shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    if numel is not None and t.numel() < numel:
+        raise ValueError("%s: needs at least %d elements, has %d" % (name, numel, t.numel()))
+    return ctypes.c_void_p(t.data_ptr())
+
+
 TD_STREAM_DEFAULT = 1   # the device's default (null) stream
 
 
@@ -164,16 +182,17 @@ def td_sample_region(ctx, seed, x0, y0, w, h, level, out=None):
     shape = (h, w) if level == TD_LEVEL_HEIGHT else (td_get_info(ctx, "channels"), h, w)
     if out is None:
         out = np.empty(shape, dtype=np.float32)
-    assert out.dtype == np.float32 and out.flags.c_contiguous
+    if out.dtype != np.float32 or not out.flags.c_contiguous:
+        raise ValueError("out: expected a C-contiguous float32 array")
     _check(ctx, lib.td_sample_region(ctx, seed & (2 ** 64 - 1), x0, y0, w, h, level, _fptr(out), out.size))
     return out
 
 
 def td_sample_region_async(ctx, seed, x0, y0, w, h, level, dev_out, stream=None):
     """dev_out: contiguous float32 torch tensor on the context's device."""
-    assert dev_out.dtype.is_floating_point and dev_out.element_size() == 4 and dev_out.is_contiguous()
-    _check(ctx, lib.td_sample_region_async(ctx, seed & (2 ** 64 - 1), x0, y0, w, h, level,
-                                           ctypes.c_void_p(dev_out.data_ptr()), dev_out.numel(), _stream(stream)))
+    p = _dev(dev_out, "dev_out")
+    _check(ctx, lib.td_sample_region_async(ctx, seed & (2 ** 64 - 1), x0, y0, w, h, level, p, dev_out.numel(),
+                                           _stream(stream)))
     return dev_out
 
 
@@ -210,19 +229,27 @@ def td_set_conditioning(child, parent):
     _check(child, lib.td_set_conditioning(child, parent))
 
 
+def _window_shape(ctx, x_dev):
+    """[n][H][H][C] of a batch of the context's windows, n from x_dev."""
+    H, C = td_get_info(ctx, "window"), td_get_info(ctx, "channels")
+    return (int(x_dev.shape[0]) if x_dev.dim() == 4 else -1, H, H, C)
+
+
 def td_denoise_steps(ctx, x_dev, k0, k1, out_dev):
     """Sampler steps k0..k1-1 on independent windows [n][H][H][C] (device tensors)."""
-    assert x_dev.is_contiguous() and out_dev.is_contiguous() and x_dev.shape == out_dev.shape
-    _check(ctx, lib.td_denoise_steps(ctx, ctypes.c_void_p(x_dev.data_ptr()), x_dev.shape[0], k0, k1,
-                                     ctypes.c_void_p(out_dev.data_ptr())))
+    win = _window_shape(ctx, x_dev)
+    px, po = _dev(x_dev, "x_dev", win), _dev(out_dev, "out_dev", win)
+    _check(ctx, lib.td_denoise_steps(ctx, px, win[0], k0, k1, po))
     return out_dev
 
 
 def td_noise_region(seed, x0, y0, out_dev, step=0, scale=1.0, stream=None):
     """scale * G(seed, ., ., c, step) into a contiguous device tensor [h][w][C]."""
+    if out_dev.dim() != 3:
+        raise ValueError("out_dev: expected [h][w][C]")
     h, w, C = out_dev.shape
-    status = lib.td_noise_region(seed & (2 ** 64 - 1), x0, y0, w, h, C, step, scale,
-                                 ctypes.c_void_p(out_dev.data_ptr()), _stream(stream))
+    status = lib.td_noise_region(seed & (2 ** 64 - 1), x0, y0, w, h, C, step, scale, _dev(out_dev, "out_dev"),
+                                 _stream(stream))
     if status != TD_OK:
         raise TDError(status, "td_noise_region")
     return out_dev
@@ -236,22 +263,26 @@ def td_set_judge(student, teacher, threshold):
 def td_denoise_windows(ctx, x_dev, k, out_dev, cond_dev=None):
     """x_dev, out_dev: contiguous float32 torch tensors [n][H][H][C] on the
     device; cond_dev: [n][H][H][C_y] for a conditioned model, else None."""
-    assert x_dev.is_contiguous() and out_dev.is_contiguous() and x_dev.shape == out_dev.shape
+    win = _window_shape(ctx, x_dev)
+    px, po = _dev(x_dev, "x_dev", win), _dev(out_dev, "out_dev", win)
     cp = None
     if cond_dev is not None:
-        assert cond_dev.is_contiguous() and cond_dev.shape[:3] == x_dev.shape[:3]
-        cp = ctypes.c_void_p(cond_dev.data_ptr())
-    _check(ctx, lib.td_denoise_windows(ctx, ctypes.c_void_p(x_dev.data_ptr()), cp, x_dev.shape[0], k,
-                                       ctypes.c_void_p(out_dev.data_ptr())))
+        # an unconditioned model given conditioning is refused by the library
+        # itself (TD_E_INVAL, nothing launched): only the buffer is checked then
+        cc = td_get_info(ctx, "cond_channels")
+        cp = _dev(cond_dev, "cond_dev", win[:3] + (cc,) if cc else None)
+    _check(ctx, lib.td_denoise_windows(ctx, px, cp, win[0], k, po))
     return out_dev
 
 
 def td_lap_decode(ctx, latent_dev, lx0, ly0, X0, Y0, W, H, out_dev, stream=None):
     """latent_dev: float32 [lh][lw][C] tensor; out_dev: float32 [H][W] tensor."""
+    if latent_dev.dim() != 3:
+        raise ValueError("latent_dev: expected [lh][lw][C]")
     lh, lw = latent_dev.shape[0], latent_dev.shape[1]
-    assert latent_dev.is_contiguous() and out_dev.is_contiguous() and out_dev.numel() >= W * H
-    _check(ctx, lib.td_lap_decode(ctx, ctypes.c_void_p(latent_dev.data_ptr()), lx0, ly0, lw, lh, X0, Y0, W, H,
-                                  ctypes.c_void_p(out_dev.data_ptr()), _stream(stream)))
+    pl = _dev(latent_dev, "latent_dev", (lh, lw, td_get_info(ctx, "channels")))
+    _check(ctx, lib.td_lap_decode(ctx, pl, lx0, ly0, lw, lh, X0, Y0, W, H, _dev(out_dev, "out_dev", numel=W * H),
+                                  _stream(stream)))
     return out_dev
 
 
@@ -263,9 +294,9 @@ def td_lap_encode(ctx, height_dev, X0, Y0, W, H, out_dev=None, stream=None):
     if out_dev is None:
         _check(ctx, lib.td_lap_encode(ctx, None, X0, Y0, W, H, None, 0, geom, None))
     else:
-        assert height_dev.is_contiguous() and out_dev.is_contiguous() and height_dev.numel() >= W * H
-        _check(ctx, lib.td_lap_encode(ctx, ctypes.c_void_p(height_dev.data_ptr()), X0, Y0, W, H,
-                                      ctypes.c_void_p(out_dev.data_ptr()), out_dev.numel(), geom, _stream(stream)))
+        ph = _dev(height_dev, "height_dev", numel=W * H)
+        _check(ctx, lib.td_lap_encode(ctx, ph, X0, Y0, W, H, _dev(out_dev, "out_dev"), out_dev.numel(), geom,
+                                      _stream(stream)))
     return tuple(int(v) for v in geom)
 
 
@@ -306,8 +337,7 @@ def td_server_destroy(srv):
 
 def td_server_submit(ctx, srv, seed, x0, y0, w, h, level, dev_out):
     """Queue a latent query whose result goes to dev_out (float32 torch tensor [C][h][w])."""
-    assert dev_out.is_contiguous() and dev_out.element_size() == 4
-    r = td_request(seed & (2 ** 64 - 1), x0, y0, w, h, level, dev_out.data_ptr(), dev_out.numel())
+    r = td_request(seed & (2 ** 64 - 1), x0, y0, w, h, level, _dev(dev_out, "dev_out").value, dev_out.numel())
     t = ctypes.c_uint64()
     _check(ctx, lib.td_server_submit(srv, ctypes.byref(r), ctypes.byref(t)))
     return t.value
@@ -493,6 +523,11 @@ class Trainer:
         n = ctypes.c_size_t()
         self._check(lib.td_train_param_count(self.tr, ctypes.byref(n)))
         self.n_params = n.value
+        import json
+        head, _ = read_tdw_data(path)
+        hdr = json.loads(head[8:8 + int.from_bytes(head[4:8], "little")])
+        self.H, self.C = int(hdr["window"]["size"]), int(hdr["denoiser"]["in_channels"])
+        self._out_shape = None     # [n][H][H][C] of the last forward (its backward's dD)
 
     def _check(self, status):
         if status != TD_OK:
@@ -507,30 +542,38 @@ class Trainer:
     def load_params(self, path):
         import torch
         _, data = read_tdw_data(path)
-        assert data.size >= self.n_params
+        if data.size < self.n_params:
+            raise ValueError("%s holds %d parameters, the network needs %d" % (path, data.size, self.n_params))
         return torch.from_numpy(data[:self.n_params].copy()).cuda()
 
     def forward(self, params, x, sigma, out, stream=None):
-        assert params.is_contiguous() and x.is_contiguous() and out.is_contiguous()
-        self._check(lib.td_train_forward(self.tr, ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(x.data_ptr()),
-                                         x.shape[0], float(sigma), ctypes.c_void_p(out.data_ptr()), _torch_stream(stream)))
+        win = (int(x.shape[0]) if x.dim() == 4 else -1, self.H, self.H, self.C)
+        pp = _dev(params, "params", numel=self.n_params)
+        px, po = _dev(x, "x", win), _dev(out, "out", win)
+        self._check(lib.td_train_forward(self.tr, pp, px, win[0], float(sigma), po, _torch_stream(stream)))
+        self._out_shape = win
         return out
 
     def backward(self, params, dD, grads, stream=None):
-        self._check(lib.td_train_backward(self.tr, ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(dD.data_ptr()),
-                                          ctypes.c_void_p(grads.data_ptr()), _torch_stream(stream)))
+        if self._out_shape is None:
+            raise ValueError("backward needs a forward first")
+        pp, pg = _dev(params, "params", numel=self.n_params), _dev(grads, "grads", numel=self.n_params)
+        self._check(lib.td_train_backward(self.tr, pp, _dev(dD, "dD", self._out_shape), pg, _torch_stream(stream)))
         return grads
 
     def mse(self, D, y, dD, weight=1.0, want_loss=True, stream=None):
         loss = ctypes.c_double()
-        self._check(lib.td_train_mse(self.tr, ctypes.c_void_p(D.data_ptr()), ctypes.c_void_p(y.data_ptr()), D.numel(),
-                                     float(weight), ctypes.c_void_p(dD.data_ptr()),
+        pD = _dev(D, "D")
+        py_, pdD = _dev(y, "y", tuple(D.shape)), _dev(dD, "dD", tuple(D.shape))
+        self._check(lib.td_train_mse(self.tr, pD, py_, D.numel(), float(weight), pdD,
                                      ctypes.byref(loss) if want_loss else None, _torch_stream(stream)))
         return loss.value if want_loss else None
 
     def adamw(self, params, grads, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.01, stream=None):
-        self._check(lib.td_train_adamw(self.tr, ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(grads.data_ptr()),
-                                       ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(v.data_ptr()), params.numel(),
+        n = params.numel()
+        pp, pg = _dev(params, "params"), _dev(grads, "grads", numel=n)
+        pm, pv = _dev(m, "m", numel=n), _dev(v, "v", numel=n)
+        self._check(lib.td_train_adamw(self.tr, pp, pg, pm, pv, n,
                                        lr, beta1, beta2, eps, weight_decay, step, _torch_stream(stream)))
 
     def close(self):

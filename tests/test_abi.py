@@ -86,3 +86,16 @@ def test_stream_argument_mapping():
     assert td._stream(S(0)).value == td.TD_STREAM_DEFAULT == 1
     assert td._stream(S(0x7f00aa00)).value == 0x7f00aa00
     assert td._stream(0x1234).value == 0x1234
+
+
+def test_device_buffer_arguments_refuse_host_memory():
+    """A host array or CPU tensor never reaches the library as a device
+    address: the binding raises before the call."""
+    import numpy as np
+    import torch
+    from paper_2512_08309_amd import td
+    for bad in (torch.zeros(16), np.zeros(16, dtype=np.float32), [0.0] * 16):
+        with pytest.raises(ValueError):
+            td._dev(bad, "buf")
+    with pytest.raises(ValueError):
+        td.td_noise_region(1, 0, 0, torch.zeros((4, 4, 1)))

@@ -188,3 +188,28 @@ def test_malformed_weight_files_are_rejected_and_keep_the_model(weights, tmp_pat
         with pytest.raises(td.TDError) as e:
             fresh.sample_region(6, 0, 0, 4, 4, 0)
         assert e.value.status == td.TD_E_STATE
+
+
+def test_device_buffer_checks(lg):
+    """Wrong dtype, strided views and wrong window shapes are refused by the
+    binding (ValueError) before anything is launched; the context stays usable."""
+    import torch
+    td, c, m, _ = lg
+    before = c.sample_region(4, 10, 20, 30, 40, 0)
+    C, H = c.info("channels"), c.info("window")
+    bad_outputs = [torch.empty((C, 40, 30), dtype=torch.float64, device="cuda"),
+                   torch.empty((C, 40, 60), device="cuda")[:, :, ::2],
+                   torch.empty((C, 40, 30), dtype=torch.float16, device="cuda")]
+    for out in bad_outputs:
+        with pytest.raises(ValueError):
+            c.sample_region_async(4, 10, 20, 30, 40, 0, out)
+    x = torch.zeros((2, H, H, C), device="cuda")
+    with pytest.raises(ValueError):
+        td.td_denoise_windows(c.ctx, x, 0, torch.zeros((2, H, H + 1, C), device="cuda"))
+    with pytest.raises(ValueError):
+        td.td_denoise_windows(c.ctx, torch.zeros((2, H, H, C + 1), device="cuda"), 0, x)
+    with pytest.raises(ValueError):
+        td.td_lap_decode(c.ctx, torch.zeros((50, 50, C + 1), device="cuda"), 0, 0, 0, 0, 8, 8,
+                         torch.zeros((8, 8), device="cuda"))
+    torch.cuda.synchronize()
+    assert np.array_equal(c.sample_region(4, 10, 20, 30, 40, 0), before)
