@@ -387,16 +387,19 @@ void blend_into(td_ctx* c, Arena& arena, uint64_t seed, const Level& lv, const R
   }
 }
 
-// Windows per denoiser launch: as many as a 32 GB workspace holds, at most
-// 1024 for the 4-channel networks (measured on the 8192^2 cold query: 1024
+// Windows per denoiser launch.  4-channel networks: as many as a 32 GB
+// workspace holds, at most 1024 (measured on the 8192^2 cold query: 1024
 // windows 3,380 window-denoises/s, 768 3,370, 512 3,357; the deepest level's
-// launches then fill the chip twice instead of once) and 4096 otherwise.
+// launches then fill the chip twice instead of once).  Others: a 16 GB
+// workspace, at most 4096.  The workspace is sized for this batch at a
+// context's first query, so the budget is per live context.
 int auto_batch(td_ctx* c) {
   if (c->batch > 0) return c->batch;
   size_t per = c->model->workspace_bytes_per_window();
   if (!per) return 1 << 20;
-  size_t b = ((size_t)32 << 30) / per;
-  return (int)std::max<size_t>(1, std::min<size_t>(b, c->model->d.C == 4 ? 1024 : 4096));
+  const bool four = c->model->d.C == 4;
+  size_t b = ((size_t)(four ? 32 : 16) << 30) / per;
+  return (int)std::max<size_t>(1, std::min<size_t>(b, four ? 1024 : 4096));
 }
 
 void check_region(int64_t x0, int64_t y0, int64_t w, int64_t h) {
