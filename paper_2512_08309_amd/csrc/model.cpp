@@ -175,7 +175,7 @@ void Model::load(const std::string& path, hipStream_t st) {
     d.sched.clear();
     for (const Json& v : sg) d.sched.push_back(v.num());
     for (int k = 0; k < d.K; ++k)
-      TD_CHECK(d.sched[k] > 0 && (k == 0 || d.sched[k] < d.sched[k - 1]), -5,
+      TD_CHECK(d.sched[k] > 0 && std::isfinite(d.sched[k]) && (k == 0 || d.sched[k] < d.sched[k - 1]), -5,
                "weight header: consistency sigmas must be positive and decreasing");
     d.sched.push_back(0.0);
     d.smax = d.sched[0];
@@ -217,6 +217,14 @@ void Model::load(const std::string& path, hipStream_t st) {
            "weight header: bad sampler/window constants");
   TD_CHECK(d.factor == 8 && d.blur_radius >= 0 && d.blur_radius <= 64, -5, "weight header: unsupported decode");
   TD_CHECK(d.smax > d.smin && d.smin > 0 && d.rho > 0 && d.sigma_data > 0, -5, "weight header: bad schedule");
+  // comparisons already refuse NaN; infinities are refused here, and the
+  // float constants that no comparison above covers get their ranges
+  TD_CHECK(std::isfinite(d.smax) && std::isfinite(d.rho) && std::isfinite(d.sigma_data), -5,
+           "weight header: schedule constants must be finite");
+  TD_CHECK(d.win_eps >= 0 && d.win_eps <= 1, -5, "weight header: window eps must be in [0, 1]");
+  TD_CHECK(d.sigma_low > 0 && std::isfinite(d.sigma_low) && d.sigma_res > 0 && std::isfinite(d.sigma_res) &&
+               d.blur_sigma > 0 && std::isfinite(d.blur_sigma),
+           -5, "weight header: decode scales must be positive and finite");
   if (!d.consistency) d.sched = edm_sigmas(d.K, d.smax, d.smin, d.rho);
   // a re-noised level adds noise to every pixel, which needs every pixel covered
   TD_CHECK(!d.consistency || d.S <= d.H, -5, "weight header: consistency sampling needs stride <= window size");
@@ -293,7 +301,7 @@ void Model::load(const std::string& path, hipStream_t st) {
 
   if (d.kind == "linear_gaussian") {
     d.prior_std = dn.at("prior_std").num();
-    TD_CHECK(d.prior_std > 0, -5, "weight header: prior_std must be positive");
+    TD_CHECK(d.prior_std > 0 && std::isfinite(d.prior_std), -5, "weight header: prior_std must be positive");
   } else if (d.kind == "unet") {
     for (const Json& c : dn.at("channels").arr()) d.ch.push_back((int)c.integer());
     d.nres = (int)dn.at("num_res_blocks").integer();
@@ -305,6 +313,8 @@ void Model::load(const std::string& path, hipStream_t st) {
     d.emb_mult = (int)dn.at("emb_mult").integer();
     d.pe_max_period = dn.at("pe_max_period").num();
     TD_CHECK(!d.ch.empty() && d.nres >= 1 && d.heads >= 1 && d.groups >= 1, -5, "weight header: bad UNet");
+    TD_CHECK(d.gn_eps > 0 && std::isfinite(d.gn_eps) && d.pe_max_period > 0 && std::isfinite(d.pe_max_period), -5,
+             "weight header: gn_eps and pe_max_period must be positive and finite");
     TD_CHECK(ilog2(d.H) >= 4 && (d.H >> (d.ch.size() - 1)) >= 1, -5,
              "UNet windows must be a power of two >= 16 and divisible by 2^(levels-1)");
     build_unet(host, shapes, st);
