@@ -165,7 +165,10 @@ td_status td_cache_stats(td_ctx *ctx, td_cache_stats_t *out);
 td_status td_cache_peek(td_ctx *ctx, uint64_t seed, int32_t level, int64_t ix,
                         int64_t iy, float *out, size_t out_len);
 
-/* Options: "batch" = max windows per batched denoiser round (>= 1);
+/* Options: "batch" = max windows per batched denoiser round, 1..2^20
+ * (default: as many as a 32 GB workspace holds for 4-channel networks, at
+ * most 1024, else a 16 GB one, at most 4096; the context allocates the
+ * workspace for this many windows at its first query and keeps it);
  * "cache_budget" = as td_cache_set_budget; "precision" = 0 FP32 network
  * (default), 1 BF16 convolution operands with FP32 accumulation (GroupNorm
  * statistics, attention, the input/output layers, blend, Euler update and
