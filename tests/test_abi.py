@@ -99,3 +99,12 @@ def test_device_buffer_arguments_refuse_host_memory():
             td._dev(bad, "buf")
     with pytest.raises(ValueError):
         td.td_noise_region(1, 0, 0, torch.zeros((4, 4, 1)))
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built library the binding raises instead of falling back
+    to anything else (there is no CPU path)."""
+    from paper_2512_08309_amd import td
+    monkeypatch.setattr(td, "LIB_PATH", str(tmp_path / "libtd.so"))
+    with pytest.raises(ImportError, match="not built"):
+        td._load()
