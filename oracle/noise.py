@@ -30,9 +30,12 @@ checked against numpy's Philox4x64-10 bit generator (same round structure,
 function.  The series are checked against float64 ln/sin/cos within a few
 float32 ulps, and the outputs against N(0,1) by moments, a KS test and the
 analytic tail bound |z| <= sqrt(48 ln 2).  The 4x32 key-schedule increments
-are pinned by their closed forms (golden ratio, sqrt 3 - 1); the two 4x32
-multipliers are "parity unpinned": they were chosen by search, and no
-published Philox4x32 known-answer vectors are available offline.
+are pinned by their closed forms (golden ratio, sqrt 3 - 1), and the whole
+4x32 instance (its two multipliers included) by known answers from an
+independent implementation, rocRAND's host-callable Philox4x32-10 engine,
+compiled by the test from its public header (over 2,000 seeds and counters,
+zero and all-ones words, and G's counter layout).  This module neither
+imports nor calls rocRAND.
 """
 from fractions import Fraction
 

@@ -1,5 +1,7 @@
 """Pins of the oracle's noise hash G (no GPU)."""
 import math
+import os
+import subprocess
 
 import numpy as np
 import pytest
@@ -27,13 +29,50 @@ def test_philox_key_schedule_constants_from_their_definitions():
     exact integer square roots, so the 32-bit pair is pinned by the
     mathematics and agrees with the top halves of the numpy-pinned 64-bit
     pair.  (The 32-bit multipliers were chosen by search and have no such
-    definition.)"""
+    definition; the known-answer test below pins them.)"""
     for spec in (noise.PHILOX4x32, noise.PHILOX4x64):
         w = spec["width"]
         golden = (math.isqrt(5 << (2 * w)) - (1 << w)) // 2
         root3 = math.isqrt(3 << (2 * w)) - (1 << w)
         assert spec["weyl"] == (golden, root3)
     assert [k >> 32 for k in noise.PHILOX4x64["weyl"]] == list(noise.PHILOX4x32["weyl"])
+
+
+def _rocrand_kat(tmp_path, rows):
+    """Runs rocRAND's host-callable Philox4x32-10 engine (compiled from the
+    public header by tests/philox_rocrand_kat.cpp) on (seed, c0..c3) rows."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    src = os.path.join(os.path.dirname(__file__), "philox_rocrand_kat.cpp")
+    if not (os.path.exists(hipcc) and os.path.exists("/opt/rocm/include/rocrand/rocrand_philox4x32_10.h")):
+        pytest.skip("hipcc or the rocRAND headers are not installed")
+    exe = str(tmp_path / "kat")
+    subprocess.run([hipcc, "-O1", src, "-o", exe], check=True, capture_output=True)
+    inp = "".join("%d %d %d %d %d\n" % r for r in rows)
+    out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout
+    return [[int(v) for v in line.split()] for line in out.splitlines()]
+
+
+def test_philox4x32_known_answers_from_rocrand(tmp_path):
+    """Pins the whole 4x32 instance, multipliers included, against an
+    independent implementation: rocRAND's Philox4x32-10 engine.  Seeds and
+    counters cover zero, all-ones words, carries into the high key word and
+    the counter layout G uses (u32 x, u32 y, step, c div 4)."""
+    rng = np.random.default_rng(20240)
+    rows = [(0, 0, 0, 0, 0), (2 ** 64 - 1, 2 ** 32 - 1, 2 ** 32 - 1, 2 ** 32 - 1, 2 ** 32 - 1),
+            (0x0123456789ABCDEF, 3, 0, 0, 0), (7, (-1000003) & 0xFFFFFFFF, 999983, 0, 0),
+            (0x00DEADBEEF123457, (2 ** 31 - 1), (-(2 ** 31)) & 0xFFFFFFFF, 2, 1)]
+    for _ in range(2000):
+        seed = int(rng.integers(0, 2 ** 63)) * 2 + int(rng.integers(0, 2))
+        rows.append((seed,) + tuple(int(v) for v in rng.integers(0, 2 ** 32, size=4)))
+    want = _rocrand_kat(tmp_path, rows)
+    assert len(want) == len(rows)
+    for r, w in zip(rows[:200], want[:200]):
+        assert noise.philox4x32_scalar(r[1:], (r[0] & 0xFFFFFFFF, r[0] >> 32)) == w
+    seeds = np.array([r[0] for r in rows], dtype=np.uint64)
+    ctr = [np.array([r[1 + i] for r in rows], dtype=np.uint64) for i in range(4)]
+    got = noise.philox4x32(*ctr, seeds & np.uint64(0xFFFFFFFF), seeds >> np.uint64(32))
+    assert np.array_equal(np.stack([np.asarray(g, dtype=np.uint64) for g in got], 1),
+                          np.array(want, dtype=np.uint64))
 
 
 def test_vectorised_philox4x32_matches_generic():
