@@ -1,8 +1,13 @@
-"""Reduced precision (BF16 convolution operands, FP32 accumulation) against
-the FP64 oracle.
+"""Reduced precision (BF16 convolution operands, FP32 accumulation; FP8-e4m3
+weights with per-output-channel FP32 scales) against the FP64 oracle.
 
-The bars are the precision target of the workload (relative heightfield
-error <= 2e-2); the tests print the measured errors so they can be quoted.
+Every mode is held to the precision target of the workload (relative error
+<= 2e-2).  BF16 meets it.  FP8-e4m3 weights do not on these random-init
+networks (measured 4.2e-2 to 7.0e-2 per denoiser, 5.7e-2 at J_0 of the
+128x128 crop): those cases are strict expected failures that name the
+measured error.  Separate tests named as regression guards hold the FP8
+mode to the level it measures (8e-2), so a further loss of accuracy still
+fails.  The tests print the measured errors so they can be quoted.
 """
 import numpy as np
 import pytest
@@ -35,18 +40,19 @@ def lp_ctx(weights):
         c.close()
 
 
-# Relative error bars vs the FP64 oracle.  BF16 is held to the workload's
-# target (heightfield RMSE <= 2e-2).  FP8 e4m3 weights (3 mantissa bits)
-# measure ~5e-2 on this random-init network and do NOT meet that target; the
-# bar below only guards against regressions of the measured level.
-BARS = {1: 2e-2, 2: 8e-2}
-HEIGHT_BARS = {1: 2e-2, 2: 8e-2}
+# The workload's target: relative error vs the FP64 oracle <= 2e-2.
+TARGET = 2e-2
+# Regression guard of the FP8-weight mode: the level it measures (e4m3 has 3
+# mantissa bits), not a precision claim.
+FP8_GUARD = 8e-2
+FP8_MISS = pytest.mark.xfail(strict=True, reason="FP8-e4m3 weights miss the 2e-2 target on these random-init "
+                             "networks: measured 4.2e-2 to 7.0e-2 per denoiser, 5.7e-2 at J_0 of the 128x128 "
+                             "C1 crop, 1.4e-1 heightfield on the 8192^2 query")
+PRECS = [1, pytest.param(2, marks=FP8_MISS)]
+DENOISER_CASES = [("c1", 0, 8), ("c1", 5, 8), ("c2", 0, 2), ("c2", 15, 2), ("cc", 0, 4), ("cc", 6, 4)]
 
 
-@pytest.mark.parametrize("prec", [1, 2])
-@pytest.mark.parametrize("config,k,n", [("c1", 0, 8), ("c1", 5, 8), ("c2", 0, 2), ("c2", 15, 2), ("cc", 0, 4),
-                                        ("cc", 6, 4)])
-def test_lowp_denoiser_close_to_oracle(lp_ctx, weights, config, k, n, prec):
+def _denoiser_error(lp_ctx, weights, config, k, n, prec):
     import torch
     from oracle.tdw import read_tdw
     from oracle.unet import UNetDenoiser
@@ -61,15 +67,31 @@ def test_lowp_denoiser_close_to_oracle(lp_ctx, weights, config, k, n, prec):
     ref = UNetDenoiser(hdr, t)(x.astype(np.float64), m.sched[k], None)
     err = rel_l2(out.cpu().numpy(), ref)
     print("precision %d denoiser %s sigma_%d rel L2 %.3e" % (prec, config, k, err))
-    assert err <= BARS[prec]
+    return err
 
 
-@pytest.mark.parametrize("prec", [1, 2])
-def test_lowp_c1_crop_error_every_level(lp_ctx, weights, prec):
-    """128x128 C1 crop at (3, 9): error of every level J_t and of the heightfield."""
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("config,k,n", DENOISER_CASES)
+def test_lowp_denoiser_close_to_oracle(lp_ctx, weights, config, k, n, prec):
+    assert _denoiser_error(lp_ctx, weights, config, k, n, prec) <= TARGET
+
+
+@pytest.mark.parametrize("config,k,n", DENOISER_CASES)
+def test_fp8_weights_denoiser_regression_guard(lp_ctx, weights, config, k, n):
+    assert _denoiser_error(lp_ctx, weights, config, k, n, 2) <= FP8_GUARD
+
+
+_CROP_REF = {}
+
+
+def _crop_errors(lp_ctx, weights, prec):
+    """128x128 C1 crop at (3, 9): error of every level J_t and of the
+    heightfield; the FP32 path is checked against its own bar on the way."""
     m = Model(weights("c1"))
     region = (3, 9, 128, 128)
-    ref = sample_levels(m, 5, *region, 0)
+    if "c1" not in _CROP_REF:
+        _CROP_REF["c1"] = sample_levels(m, 5, *region, 0)
+    ref = _CROP_REF["c1"]
     c32 = lp_ctx("c1", 0)
     c16 = lp_ctx("c1", prec)
     errs16, errs32 = {}, {}
@@ -81,7 +103,6 @@ def test_lowp_c1_crop_error_every_level(lp_ctx, weights, prec):
     print("per-level rel L2 vs FP64 oracle, fp32:", {t: "%.2e" % e for t, e in errs32.items()})
     assert errs16[m.K] < 1e-7 and errs32[m.K] < 1e-7    # the noise level (FP32 rounding of sigma_0 * G)
     assert max(errs32.values()) <= 1e-4
-    assert max(errs16.values()) <= HEIGHT_BARS[prec]
     # heightfield of the interior (decode needs the 17 px apron inside the crop)
     out = (8 * 20, 8 * 26, 8 * 90, 8 * 90)
     lx0, ly0, lw, lh = laplace.required_latent(out, DEC)
@@ -93,7 +114,19 @@ def test_lowp_c1_crop_error_every_level(lp_ctx, weights, prec):
     h32 = c32.sample_region(5, *out, td.TD_LEVEL_HEIGHT)
     e16, e32 = rel_l2(h16, href), rel_l2(h32, href)
     print("heightfield rel RMSE vs FP64 oracle: precision %d %.3e, fp32 %.3e" % (prec, e16, e32))
-    assert e32 <= 1e-4 and e16 <= HEIGHT_BARS[prec]
+    assert e32 <= 1e-4
+    return errs16, e16
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_lowp_c1_crop_error_every_level(lp_ctx, weights, prec):
+    errs, eh = _crop_errors(lp_ctx, weights, prec)
+    assert max(errs.values()) <= TARGET and eh <= TARGET
+
+
+def test_fp8_weights_crop_regression_guard(lp_ctx, weights):
+    errs, eh = _crop_errors(lp_ctx, weights, 2)
+    assert max(errs.values()) <= FP8_GUARD and eh <= FP8_GUARD
 
 
 def test_bf16_seed_consistency_bit_exact(lp_ctx):
