@@ -208,9 +208,13 @@ td_status td_denoise_steps(td_ctx *ctx, const float *x_dev, int32_t n, int32_t k
  * dev_out as [h][w][channels] float32 on `hip_stream` (NULL: default
  * stream): the seed noise of the seeds paragraph of the formal appendix
  * with any counter word `step` (0 is J_T's; the student's re-noising uses
- * 1).  Asynchronous. */
+ * 1).  accumulate = 0 overwrites dev_out; accumulate = 1 adds the noise to
+ * what dev_out holds (dev_out += scale * G: the re-noising x + sigma G of
+ * multistep consistency sampling, used by distillation).  Asynchronous.
+ * TD_E_INVAL for a null buffer, empty sides, more than 2^30 pixels or an
+ * accumulate value other than 0 or 1. */
 td_status td_noise_region(uint64_t seed, int64_t x0, int64_t y0, int32_t w, int32_t h, int32_t channels,
-                          uint32_t step, float scale, float *dev_out, void *hip_stream);
+                          uint32_t step, float scale, int32_t accumulate, float *dev_out, void *hip_stream);
 
 /* Laplacian decode (Sec. 5.2, with the signed-sqrt inverse of the
  * signed-sqrt appendix) of a latent held in device memory, [lh][lw][C]

@@ -1299,10 +1299,13 @@ td_status td_denoise_steps(td_ctx* c, const float* x_dev, int32_t n, int32_t k0,
 }
 
 td_status td_noise_region(uint64_t seed, int64_t x0, int64_t y0, int32_t w, int32_t h, int32_t channels,
-                          uint32_t step, float scale, float* dev_out, void* hip_stream) {
-  if (!dev_out || w < 1 || h < 1 || channels < 1 || (int64_t)w * h > (1LL << 30)) return TD_E_INVAL;
+                          uint32_t step, float scale, int32_t accumulate, float* dev_out, void* hip_stream) {
+  if (!dev_out || w < 1 || h < 1 || channels < 1 || (int64_t)w * h > (1LL << 30) ||
+      (accumulate != 0 && accumulate != 1))
+    return TD_E_INVAL;
   try {
-    launch_noise(hip_stream == TD_STREAM_DEFAULT ? nullptr : (hipStream_t)hip_stream, seed, x0, y0, w, h, channels, step, scale, 0, dev_out);
+    launch_noise(hip_stream == TD_STREAM_DEFAULT ? nullptr : (hipStream_t)hip_stream, seed, x0, y0, w, h, channels,
+                 step, scale, 0, dev_out, accumulate);
   } catch (const Error& e) {
     return (td_status)e.status;
   }

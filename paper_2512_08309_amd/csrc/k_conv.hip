@@ -296,6 +296,7 @@ void launch_conv(hipStream_t st, const ConvArgs& a) {
   TD_CHECK(a.taps == 9 || a.taps == 1, -5, "conv: taps must be 9 or 1");
   TD_CHECK(!a.up0 || (a.lh >= 1 && a.lw >= 1), -5, "conv: upsampled source needs h, w >= 2");
   TD_CHECK(a.lh + a.lw <= 20, -5, "conv: image too large");
+  check_conv_rows(a.nb, a.lh + a.lw);
   if (a.nb == 0) return;
   TD_CHECK(a.cout % 16 == 0 && a.cout > 0, -5, "conv: output channels must be a multiple of 16");
   const double M = (double)a.nb * (1 << (a.lh + a.lw));

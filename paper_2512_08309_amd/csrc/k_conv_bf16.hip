@@ -488,11 +488,13 @@ void launch_conv_lp(hipStream_t st, const ConvLpArgs& a) {
   TD_CHECK(a.cin % 8 == 0 && a.cout % 16 == 0 && a.cout > 0, -5,
            "bf16 conv: needs C_in % 8 == 0 and C_out % 16 == 0");
   TD_CHECK(a.taps == 9 || a.taps == 1, -5, "bf16 conv: taps must be 9 or 1");
+  TD_CHECK(a.lh + a.lw <= 20, -5, "bf16 conv: image too large");
+  check_conv_rows(a.nb, a.lh + a.lw);
   if (!a.nb) return;
   const bool fast = a.cin % 32 == 0;
   const int BK = 32;
   TD_CHECK(a.kp % BK == 0 && a.kp >= a.taps * a.cin, -5, "bf16 conv: bad padded K");
-  const double Md = (double)(a.nb << (a.lh + a.lw));
+  const double Md = (double)((int64_t)a.nb << (a.lh + a.lw));
   prof_begin(st);
   TD_CHECK(!a.w8 || a.wscale, -5, "fp8 weights need per-channel scales");
   // 3x3 with C_in % 32 == 0 and BF16 weights: direct-to-LDS ring (measured

@@ -31,6 +31,15 @@ struct Error {
     if (!(cond)) throw ::td::Error{(status), (msg)};                          \
   } while (0)
 
+// Row count of a batched convolution, windows x pixels: the kernels index
+// rows and tiles in 32-bit ints, so it must stay below 2^31 with a tile of
+// slack.  The automatic batch keeps it far below; an explicit batch option
+// can ask for more, which is refused here before any launch.
+inline void check_conv_rows(int nb, int lhw) {
+  TD_CHECK(nb >= 0 && lhw >= 0 && lhw <= 20 && ((int64_t)nb << lhw) <= (int64_t)0x7fffffff - 4096, -1,
+           "conv: windows x pixels per launch must stay below 2^31");
+}
+
 // Launch check: catches bad launch configurations immediately.
 #define TD_LAUNCHED() TD_HIP(hipGetLastError())
 

@@ -26,7 +26,9 @@ import numpy as np
 
 
 def make_pairs(td, torch, teacher_path, n, seed0=1, chunk=1024, precision=0):
-    """(x, y, e) device tensors [n][H][H][C]: teacher inputs, outputs, re-noise."""
+    """(x, y, seeds): device tensors [n][H][H][C] of teacher inputs and
+    outputs, and the pair seeds seed0 .. seed0 + n - 1 (the re-noise of pair i
+    is G(seed_i) on counter word 1, drawn by the library when it is used)."""
     with td.Context(0) as t:
         t.load_weights(teacher_path)
         t.set_option("precision", precision)
@@ -34,21 +36,29 @@ def make_pairs(td, torch, teacher_path, n, seed0=1, chunk=1024, precision=0):
         sigma0 = 80.0
         x = torch.empty((n, H, H, C), device="cuda")
         y = torch.empty_like(x)
-        e = torch.empty_like(x)
+        seeds = np.arange(seed0, seed0 + n, dtype=np.int64)
         for i in range(n):
-            td.td_noise_region(seed0 + i, 0, 0, x[i], step=0, scale=sigma0)
-            td.td_noise_region(seed0 + i, 0, 0, e[i], step=1, scale=1.0)
+            td.td_noise_region(int(seeds[i]), 0, 0, x[i], step=0, scale=sigma0)
         torch.cuda.synchronize()
         for i0 in range(0, n, chunk):
             i1 = min(n, i0 + chunk)
             t.denoise_steps(x[i0:i1], 0, K, y[i0:i1])
             print("[distill] teacher pairs %d / %d" % (i1, n), file=sys.stderr, flush=True)
         torch.cuda.synchronize()
-    return x, y, e
+    return x, y, seeds
 
 
-def train(td, torch, student_path, x, y, e, steps, batch=64, lr=2e-4, seed=0, log_every=50, sigmas=(80.0, 0.35),
-          precision=1):
+def renoise(td, base, seeds, sigma):
+    """base[b] + sigma * G(seeds[b]) on counter word 1 for every window b, in
+    place (the noise kernel's accumulate mode): multistep consistency
+    sampling's re-noising of an estimate at the next noise level."""
+    for b, sd in enumerate(seeds):
+        td.td_noise_region(int(sd), 0, 0, base[b], step=1, scale=sigma, accumulate=True)
+    return base
+
+
+def train(td, torch, student_path, x, y, seeds, steps, batch=64, lr=2e-4, seed=0, log_every=50,
+          sigmas=(80.0, 0.35), precision=1):
     """AdamW on the student's flat FP32 master parameters (BF16 convolution
     operands with precision 1); returns (params, loss history)."""
     tr = td.Trainer(student_path).set_precision(precision)
@@ -64,10 +74,11 @@ def train(td, torch, student_path, x, y, e, steps, batch=64, lr=2e-4, seed=0, lo
     for step in range(1, steps + 1):
         if pos + batch > n:
             perm, pos = rng.permutation(n), 0
-        idx = torch.from_numpy(perm[pos:pos + batch]).cuda()
+        sel = perm[pos:pos + batch]
+        idx = torch.from_numpy(sel).cuda()
         pos += batch
         xb, yb = x.index_select(0, idx), y.index_select(0, idx)
-        x2 = yb + sigmas[1] * e.index_select(0, idx)
+        x2 = renoise(td, yb.clone(), seeds[sel], sigmas[1])
         G.zero_()
         tr.forward(P, xb, sigmas[0], D)
         l1 = tr.mse(D, yb, dD, weight=0.5, want_loss=(step % log_every == 0 or step == 1))
@@ -84,25 +95,26 @@ def train(td, torch, student_path, x, y, e, steps, batch=64, lr=2e-4, seed=0, lo
     return P, hist
 
 
-def student_windows(td, torch, student_path, P, x, e, sigmas=(80.0, 0.35), chunk=256):
+def student_windows(td, torch, student_path, P, x, seeds, sigmas=(80.0, 0.35), chunk=256):
     """The student's two-step sample of independent windows: D(x; s0), re-noised
-    with s1 e, then D(.; s1) (consistency sampling without blending)."""
+    with s1 G(seed) on counter word 1, then D(.; s1) (consistency sampling
+    without blending)."""
     tr = td.Trainer(student_path)
     out = torch.empty_like(x)
     for i0 in range(0, x.shape[0], chunk):
         xb = x[i0:i0 + chunk].contiguous()
         d1 = torch.empty_like(xb)
         tr.forward(P, xb, sigmas[0], d1)
-        x2 = (d1 + sigmas[1] * e[i0:i0 + chunk]).contiguous()
+        x2 = renoise(td, d1, seeds[i0:i0 + chunk], sigmas[1])
         tr.forward(P, x2, sigmas[1], out[i0:i0 + chunk])
     torch.cuda.synchronize()
     tr.close()
     return out
 
 
-def evaluate(td, torch, student_path, P, x, y, e):
+def evaluate(td, torch, student_path, P, x, y, seeds):
     """Relative RMSE of the student's two-step windows against the teacher's."""
-    s = student_windows(td, torch, student_path, P, x, e)
+    s = student_windows(td, torch, student_path, P, x, seeds)
     return float(torch.linalg.norm((s - y).flatten()) / torch.linalg.norm(y.flatten()))
 
 
@@ -129,10 +141,10 @@ def main():
     ap.add_argument("--precision", type=int, default=1, help="1: BF16 convolution operands, 0: FP32")
     a = ap.parse_args()
     t0 = time.perf_counter()
-    x, y, e = make_pairs(td, torch, a.teacher, a.pairs + a.holdout, precision=a.teacher_precision)
+    x, y, seeds = make_pairs(td, torch, a.teacher, a.pairs + a.holdout, precision=a.teacher_precision)
     t1 = time.perf_counter()
-    xt, yt, et = x[:a.pairs], y[:a.pairs], e[:a.pairs]
-    xh, yh, eh = x[a.pairs:], y[a.pairs:], e[a.pairs:]
+    xt, yt, et = x[:a.pairs], y[:a.pairs], seeds[:a.pairs]
+    xh, yh, eh = x[a.pairs:], y[a.pairs:], seeds[a.pairs:]
     P0 = td.Trainer(a.student_init).load_params(a.student_init)
     before = evaluate(td, torch, a.student_init, P0, xh, yh, eh)
     P, hist = train(td, torch, a.student_init, xt, yt, et, a.steps, a.batch, a.lr, precision=a.precision)

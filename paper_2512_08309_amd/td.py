@@ -79,7 +79,8 @@ def _load():
         "td_get_info": ([vp, ctypes.c_char_p, ctypes.POINTER(i64)], ctypes.c_int),
         "td_denoise_windows": ([vp, vp, vp, i32, i32, vp], ctypes.c_int),
         "td_denoise_steps": ([vp, vp, i32, i32, i32, vp], ctypes.c_int),
-        "td_noise_region": ([u64, i64, i64, i32, i32, i32, ctypes.c_uint32, ctypes.c_float, vp, vp], ctypes.c_int),
+        "td_noise_region": ([u64, i64, i64, i32, i32, i32, ctypes.c_uint32, ctypes.c_float, i32, vp, vp],
+                            ctypes.c_int),
         "td_lap_decode": ([vp, vp, i64, i64, i32, i32, i64, i64, i32, i32, vp, vp], ctypes.c_int),
         "td_lap_encode": ([vp, vp, i64, i64, i32, i32, vp, sz, ctypes.POINTER(i64), vp], ctypes.c_int),
         "td_kappa": ([i64, i64, i64, i64, i32, i32, i32, ctypes.POINTER(i64)], ctypes.c_int),
@@ -243,13 +244,14 @@ def td_denoise_steps(ctx, x_dev, k0, k1, out_dev):
     return out_dev
 
 
-def td_noise_region(seed, x0, y0, out_dev, step=0, scale=1.0, stream=None):
-    """scale * G(seed, ., ., c, step) into a contiguous device tensor [h][w][C]."""
+def td_noise_region(seed, x0, y0, out_dev, step=0, scale=1.0, stream=None, accumulate=False):
+    """scale * G(seed, ., ., c, step) into a contiguous device tensor [h][w][C]
+    (accumulate=True: added to what the tensor holds)."""
     if out_dev.dim() != 3:
         raise ValueError("out_dev: expected [h][w][C]")
     h, w, C = out_dev.shape
-    status = lib.td_noise_region(seed & (2 ** 64 - 1), x0, y0, w, h, C, step, scale, _dev(out_dev, "out_dev"),
-                                 _stream(stream))
+    status = lib.td_noise_region(seed & (2 ** 64 - 1), x0, y0, w, h, C, step, scale, 1 if accumulate else 0,
+                                 _dev(out_dev, "out_dev"), _stream(stream))
     if status != TD_OK:
         raise TDError(status, "td_noise_region")
     return out_dev

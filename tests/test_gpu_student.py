@@ -186,3 +186,18 @@ def test_noise_region_any_counter_word():
     torch.cuda.synchronize()
     want = np.float32(0.35) * onoise.noise_region(77, -5, 1000, 13, 9, 4, step=1)
     assert np.array_equal(out.cpu().numpy(), want)
+
+
+def test_noise_region_accumulate():
+    """accumulate = 1 adds scale * G to the buffer (the re-noising of
+    distillation): one float32 multiply and one add per value, bit-exact."""
+    require_gpu()
+    import torch
+    from oracle import noise as onoise
+    from paper_2512_08309_amd import td
+    base = np.random.default_rng(4).standard_normal((9, 13, 4)).astype(np.float32)
+    out = torch.from_numpy(base).cuda()
+    td.td_noise_region(77, -5, 1000, out, step=1, scale=0.35, accumulate=True)
+    torch.cuda.synchronize()
+    want = base + np.float32(0.35) * onoise.noise_region(77, -5, 1000, 13, 9, 4, step=1)
+    assert np.array_equal(out.cpu().numpy(), want)

@@ -160,9 +160,9 @@ def test_distillation_pipeline(weights, tmp_path):
     require_gpu()
     import torch
     from paper_2512_08309_amd import distill, td
-    x, y, e = distill.make_pairs(td, torch, weights("c2k2"), 64)
+    x, y, seeds = distill.make_pairs(td, torch, weights("c2k2"), 64)
     assert torch.isfinite(y).all() and float(y.std()) > 0
-    P, hist = distill.train(td, torch, weights("s2"), x, y, e, steps=12, batch=16, lr=1e-3, log_every=4)
+    P, hist = distill.train(td, torch, weights("s2"), x, y, seeds, steps=12, batch=16, lr=1e-3, log_every=4)
     print("distillation loss", hist)
     assert hist[-1][1] < hist[0][1]
     out = str(tmp_path / "student.tdw")
