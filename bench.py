@@ -12,24 +12,42 @@ before every step, so every step does the full cold work.
 Reported: window-denoises/s (denoiser evaluations per second of the timed
 steps), the roofline of the dominant kernel (the FP32 MFMA 3x3 convolution)
 from event timing of every launch inside the timed steps, the other kernel
-classes, p50/p99 latency of a stream of small queries (first query and its
-neighbour, as in time-to-first/second-tile), and the FP64 oracle timed on
-the host cores on a bounded sample.
+classes, and, as further legs: reduced precision with its error against the
+FP64 oracle, p50/p99 latency of tile streams (first tile and its
+neighbour, as in time-to-first/second-tile), the distilled student, the
+serving loop, a truncated blend schedule, and the FP64 oracle timed on the
+host cores.
+
+Run-time budget: the warm-up and timed steps always run; the further legs
+run in a fixed priority order while their estimated cost fits the wall-clock
+budget (--budget-s, counted from the start of the process), and a leg that
+does not fit is recorded as skipped with its estimate.  The oracle legs run
+on the host cores in a child process during the untimed warm-up steps and
+are joined before the timed steps start.
 """
 import argparse
 import json
 import os
+import subprocess
 import sys
+import tempfile
 import time
 
+T_START = time.perf_counter()
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
+# Precision crop of the reduced-precision comparison: C1 model, 128 x 128
+# latent at (3, 9), seed 5, every level; heightfield of its interior.
+CROP = (3, 9, 128, 128)
+CROP_SEED = 5
+CROP_HEIGHT = (8 * 20, 8 * 26, 8 * 90, 8 * 90)
 
 
-def parse():
+def parse(argv=None):
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=1)
@@ -39,8 +57,11 @@ def parse():
     p.add_argument("--workload", choices=["height", "latent"], default="height")
     p.add_argument("--batch", type=int, default=0)
     p.add_argument("--seed", type=int, default=7)
-    p.add_argument("--latency-pairs", type=int, default=100)
-    p.add_argument("--cpu-windows", type=int, default=16)
+    p.add_argument("--budget-s", type=float, default=470.0,
+                   help="wall-clock budget of the whole run; legs after the timed steps that do not fit are skipped")
+    p.add_argument("--latency-pairs", type=int, default=1000, help="tile pairs of the C1 latency stream")
+    p.add_argument("--c2-latency-pairs", type=int, default=4, help="tile pairs of the C2 latency stream")
+    p.add_argument("--cpu-windows", type=int, default=64, help="C2 windows of the timed oracle sample")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--bf16-steps", type=int, default=1,
                    help="cold steps timed again per reduced-precision mode (0 = skip)")
@@ -50,60 +71,196 @@ def parse():
     p.add_argument("--serve-rate", type=float, default=256.0, help="Poisson arrival rate, queries/s")
     p.add_argument("--serve-rate-sustained", type=float, default=32.0,
                    help="a second, lower arrival rate the server keeps up with (0 = skip)")
-    p.add_argument("--student-steps", type=int, default=300,
+    p.add_argument("--student-steps", type=int, default=150,
                    help="AdamW steps of the in-bench student distillation (0 = skip the student leg)")
-    p.add_argument("--student-pairs", type=int, default=4096, help="teacher pairs of the in-bench distillation")
+    p.add_argument("--student-pairs", type=int, default=2048, help="teacher pairs of the in-bench distillation")
     p.add_argument("--micro-only", action="store_true",
                    help="only the decode / noise micro-benchmarks (8192^2 heightfield, 8192^2 x 4 noise)")
     p.add_argument("--calib-copy-mib", type=int, default=0,
                    help="run one plain elementwise copy (read N MiB, write N MiB) before the steps, as the "
                         "reference dispatch that scales hardware byte counters")
-    return p.parse_args()
+    p.add_argument("--cpu-legs", default="", help=argparse.SUPPRESS)
+    p.add_argument("--c1-weights", default="", help=argparse.SUPPRESS)
+    p.add_argument("--c2-weights", default="", help=argparse.SUPPRESS)
+    return p.parse_args(argv)
 
 
-def cpu_baseline(weights_path, n):
-    """Oracle (FP64 NumPy) denoiser on n windows at sigma_0, timed on host cores."""
+class Budget:
+    """Wall-clock budget counted from the start of the process."""
+
+    def __init__(self, total):
+        self.total = total
+
+    def left(self):
+        return self.total - (time.perf_counter() - T_START)
+
+    def skip(self, est):
+        """None if a leg of estimated cost `est` seconds fits, else the record
+        that says why it was skipped."""
+        if est <= self.left():
+            return None
+        return {"skipped": "run-time budget: needs ~%.0f s, %.0f s left of %.0f s" % (est, max(self.left(), 0.0),
+                                                                                       self.total)}
+
+
+# ----------------------------------------------------------------- host legs
+# The oracle (FP64 NumPy) on the host cores, in a child process that never
+# touches the GPU: started before the warm-up steps, joined before the timed
+# steps.
+
+def _nproc():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_legs(a):
     import numpy as np
-    from threadpoolctl import threadpool_info
+    from threadpoolctl import threadpool_info, threadpool_limits
 
-    from oracle.sampler import Model
-    m = Model(weights_path)
-    x = 80.0 * np.random.default_rng(0).standard_normal((n, m.H, m.H, m.C))
-    m.denoiser(x[:1], m.sched[0], None)          # warm BLAS
-    t0 = time.perf_counter()
-    m.denoiser(x, m.sched[0], None)
-    dt = time.perf_counter() - t0
-    threads = max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"] or [1])
-    return {"value": n / dt, "unit": "window-denoises/s", "cores": threads, "kind": "oracle",
-            "sample": "%d windows of the same model through the FP64 oracle denoiser at sigma_0 (one batched "
-                      "level round; the sampler's blend/Euler is <0.1%% of its work), %.1f s" % (n, dt)}
+    from oracle import laplace
+    from oracle.sampler import Model, sample, sample_levels
+    ncores = _nproc()
+    res = {"nproc": ncores}
+    with threadpool_limits(limits=ncores, user_api="blas"):
+        threads = max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"] or [1])
+        res["blas_threads"] = threads
+        if not a.no_cpu_baseline:
+            m = Model(a.c2_weights)
+            x = 80.0 * np.random.default_rng(0).standard_normal((a.cpu_windows, m.H, m.H, m.C))
+            m.denoiser(x[:1], m.sched[0], None)          # warm BLAS
+            t0 = time.perf_counter()
+            m.denoiser(x, m.sched[0], None)
+            dt = time.perf_counter() - t0
+            res["c2_sample"] = {"windows": a.cpu_windows, "s": dt}
+            print("[cpu] C2 oracle sample %.1f s" % dt, file=sys.stderr, flush=True)
+            m1 = Model(a.c1_weights)
+            t0 = time.perf_counter()
+            sample(m1, 0, 0, 0, 64, 64, 0)
+            dt1 = time.perf_counter() - t0
+            res["c1_cold_query"] = {"windows": m1.phi_calls, "s": dt1}
+            print("[cpu] C1 oracle cold query %.1f s" % dt1, file=sys.stderr, flush=True)
+        if a.bf16_steps > 0:
+            m1 = Model(a.c1_weights)
+            t0 = time.perf_counter()
+            lv = sample_levels(m1, CROP_SEED, *CROP, 0)
+            dec = m1.header["decode"]
+            lx0, ly0, lw, lh = laplace.required_latent(CROP_HEIGHT, dec)
+            x0, y0 = CROP[0], CROP[1]
+            lat = lv[0][ly0 - y0:ly0 - y0 + lh, lx0 - x0:lx0 - x0 + lw]
+            href = laplace.decode(lat, (lx0, ly0), CROP_HEIGHT, dec)
+            np.savez(os.path.join(a.cpu_legs, "crop_ref.npz"), height=href,
+                     **{"level_%d" % t: v for t, v in lv.items()})
+            print("[cpu] oracle precision crop %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
+    with open(os.path.join(a.cpu_legs, "cpu.json"), "w") as f:
+        json.dump(res, f)
 
 
-def latency_stream(td, torch, weights_path, pairs, seed=11):
-    """TTFT/TTST-style stream: random 64x64 queries in [-1e6, 1e6) and their right neighbours."""
+def start_cpu_legs(a, c1_path, c2_path, workdir):
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-legs", workdir, "--c1-weights", c1_path,
+           "--c2-weights", c2_path, "--cpu-windows", str(a.cpu_windows), "--bf16-steps", str(a.bf16_steps)]
+    if a.no_cpu_baseline:
+        cmd.append("--no-cpu-baseline")
+    return subprocess.Popen(cmd, cwd=ROOT)
+
+
+def cpu_baseline_entry(cpu):
+    """The bench line's cpu_baseline: the oracle's C2 window-denoises/s."""
+    s = cpu.get("c2_sample")
+    if not s:
+        return None
+    c1 = cpu.get("c1_cold_query", {})
+    return {"value": s["windows"] / s["s"], "unit": "window-denoises/s", "cores": cpu["blas_threads"],
+            "nproc": cpu["nproc"], "kind": "oracle",
+            "sample": "%d windows of the 4-channel C2 model through the FP64 oracle denoiser at sigma_0 (one batched "
+                      "level round; the blend/Euler is <0.1%% of the sampler's work), %.1f s; run on the host cores "
+                      "during the GPU's untimed warm-up steps" % (s["windows"], s["s"]),
+            "c1_cold_query": {"s": c1.get("s"), "windows": c1.get("windows"),
+                              "window_denoises_per_s": (c1["windows"] / c1["s"]) if c1 else None,
+                              "note": "the oracle's full cold 64x64 query of the 1-channel model at (0, 0), seed 0 "
+                                      "(every level of its cone), timed in full"}}
+
+
+# ----------------------------------------------------------------- GPU legs
+
+def rel(torch, got, ref):
+    return float(torch.linalg.vector_norm((got - ref).double()) / torch.linalg.vector_norm(ref.double()))
+
+
+def precision_errors(td, torch, c1_path, ref_path, modes):
+    """Error of every level of the precision crop and of its heightfield
+    against the FP64 oracle, per precision mode (0 = FP32)."""
+    import numpy as np
+    ref = np.load(ref_path)
+    out = {}
+    for prec in [0] + modes:
+        with td.Context(0) as c:
+            c.load_weights(c1_path)
+            c.set_option("precision", prec)
+            K = c.info("levels")
+            lv = {}
+            for t in range(K, -1, -1):
+                got = c.sample_region(CROP_SEED, *CROP, t)
+                r = np.moveaxis(ref["level_%d" % t], -1, 0)
+                lv[str(t)] = float(np.linalg.norm(got - r) / np.linalg.norm(r))
+            h = c.sample_region(CROP_SEED, *CROP_HEIGHT, td.TD_LEVEL_HEIGHT)
+            eh = float(np.linalg.norm(h - ref["height"]) / np.linalg.norm(ref["height"]))
+        out[prec] = {"crop": "1-channel C1 model (K=8), 128x128 latent at (3, 9), seed 5; heightfield of the "
+                             "720x720 px interior at (160, 208)",
+                     "rel_l2_vs_fp64_oracle_by_level": lv, "rel_l2_vs_fp64_oracle_max_level": max(lv.values()),
+                     "rel_rmse_heightfield_vs_fp64_oracle": eh}
+    return out
+
+
+def latency_stream(td, torch, weights_path, pairs, seed, deadline, precision=0, label="C1", ctx=None):
+    """TTFT/TTST-style stream: 512x512 px elevation tiles (64x64 latent, the
+    paper's tile at 8x) at random tile-aligned positions in [-1e6, 1e6)
+    latent px and their right neighbours; end-to-end through
+    td_sample_region_async (planning, every level of the cone, decode).
+    Stops early at `deadline` (perf_counter time); n says how many ran.
+    ctx: an already used context of the model (else a new one is made and
+    warmed on one tile)."""
     import numpy as np
     rng = np.random.default_rng(seed)
-    xs = rng.integers(-10 ** 6, 10 ** 6, size=(pairs, 2))
+    xs = rng.integers(-10 ** 6 // 64, 10 ** 6 // 64, size=(pairs, 2)) * 64
     first, second = [], []
-    with td.Context(0) as c:
-        c.load_weights(weights_path)
-        C = c.info("channels")
-        out = torch.empty((C, 64, 64), dtype=torch.float32, device="cuda")
-        st = torch.cuda.current_stream()
-        c.sample_region_async(seed, 0, 0, 64, 64, 0, out, st)      # warm kernels / workspace
-        torch.cuda.synchronize()
+    out = torch.empty((512, 512), dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream()
+    own = ctx is None
+    c = td.Context(0) if own else ctx
+    try:
+        if own:
+            c.load_weights(weights_path)
+            c.set_option("precision", precision)
+            c.sample_region_async(seed, 0, 0, 512, 512, td.TD_LEVEL_HEIGHT, out, st)   # kernels, workspace
+            torch.cuda.synchronize()
+        c.cache_clear()
         for x, y in xs:
+            if time.perf_counter() > deadline:
+                break
             for dx, sink in ((0, first), (64, second)):
                 t0 = time.perf_counter()
-                c.sample_region_async(seed, int(x) + dx, int(y), 64, 64, 0, out, st)
+                c.sample_region_async(seed, 8 * (int(x) + dx), 8 * int(y), 512, 512, td.TD_LEVEL_HEIGHT, out, st)
                 torch.cuda.synchronize()
                 sink.append(1e3 * (time.perf_counter() - t0))
+        cs = c.cache_stats()
+        c.cache_clear()
+    finally:
+        if own:
+            c.close()
+
     def pct(v):
-        return {"p50_ms": float(np.percentile(v, 50)), "p99_ms": float(np.percentile(v, 99)), "n": len(v)}
-    return {"workload": "1-channel model, windows 32/16, K=8, 2-level UNet 16/32; %d random 64x64 latent queries "
-                        "in [-1e6,1e6) seed %d, each followed by its right neighbour; end-to-end through "
-                        "td_sample_region_async incl. planning" % (pairs, seed),
-            "first": pct(first), "neighbour": pct(second)}
+        if not v:
+            return {"n": 0}
+        return {"p50_ms": float(np.percentile(v, 50)), "p99_ms": float(np.percentile(v, 99)),
+                "max_ms": float(np.max(v)), "n": len(v)}
+    return {"workload": "%s model, %s; %d random 512x512 px elevation tiles (64x64 latent + decode apron) at "
+                        "tile-aligned positions in [-1e6,1e6) latent px, seed %d, each followed by its right "
+                        "neighbour; end-to-end through td_sample_region_async (planning, cone, decode), default "
+                        "cache budget" % (label, "FP32" if precision == 0 else "BF16", len(first), seed),
+            "first": pct(first), "neighbour": pct(second), "windows_evaluated": cs["misses"],
+            "planned_pairs": pairs}
 
 
 def serving_stream(td, torch, weights_path, parent_path, n, rate, seed=17, budget=64 << 30, inflight=64,
@@ -178,18 +335,18 @@ def serving_stream(td, torch, weights_path, parent_path, n, rate, seed=17, budge
 def paper_context(lat):
     """The paper's own speed figure, quoted as context (other hardware, its
     trained models, a 512^2 tile at 90 m per pixel), and the same traversal
-    arithmetic applied to the neighbour-query latency of the C1 stream here
-    (a 64^2 latent = 512^2 px tile of synthetic random-init models): not a
+    arithmetic applied to the neighbour-tile latency of the C1 stream here
+    (512^2 px elevation tiles of synthetic random-init models): not a
     like-for-like comparison."""
     tile_m = 512 * 90.0
     ctx = {"paper": "generation 9x faster than orbital velocity (7,700 m/s): time to second tile 0.66 s for a "
                     "512^2 tile at 90 m per pixel (46 km), consumer GPU, the paper's trained models"}
-    if lat:
+    if lat and lat.get("neighbour", {}).get("n"):
         t = lat["neighbour"]["p50_ms"] * 1e-3
-        ctx["here"] = {"neighbour_query_p50_s": t, "traversal_m_per_s": tile_m / t,
+        ctx["here"] = {"neighbour_tile_p50_s": t, "traversal_m_per_s": tile_m / t,
                        "x_orbital_velocity": tile_m / t / 7700.0,
-                       "note": "C1 neighbour latent query (64^2 latent, 512^2 px at 8x) of the latency stream; "
-                               "synthetic 2-level UNet, not the paper's models"}
+                       "note": "C1 neighbour elevation tile (512^2 px) of the latency stream; synthetic 2-level "
+                               "UNet, not the paper's models"}
     return ctx
 
 
@@ -240,18 +397,31 @@ def micro_bench(td, torch, ctx, reps=5):
                              "note": "Philox + bit-exact IEEE Box-Muller per pair: ALU-bound"}}
 
 
-def student_leg(td, torch, teacher, teacher_path, student_init, a, region, level, out, ref32, stream, wps32, dt32):
+def timed_cold(ctx, torch, a, region, level, out, stream):
+    """First use on a small query (kernels, workspace), then one timed cold
+    query of the region; returns (seconds, cache stats)."""
+    ctx.sample_region_async(a.seed, 0, 0, 64, 64, 0, torch.empty((ctx.info("channels"), 64, 64), device="cuda"),
+                            stream)
+    torch.cuda.synchronize()
+    ctx.cache_clear()
+    t0 = time.perf_counter()
+    ctx.sample_region_async(a.seed, *region, level, out, stream)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, ctx.cache_stats()
+
+
+def student_leg(td, torch, teacher, teacher_path, student_init, a, region, level, out, ref32, stream, ms32):
     """Distil the half-width two-step student from the 20-step teacher (a short
     run: a.student_pairs pairs, a.student_steps AdamW steps at batch 64, lr
     2e-4), then time the same cold query with it: alone, judged by the FP32
-    teacher (fallback above 0.05 RMS), and with BF16 convolutions."""
-    import tempfile
+    teacher (fallback above 0.05 RMS), and with BF16 convolutions.  ms32 is
+    the FP32 plain sampler's time per query (ms_per_step)."""
     from paper_2512_08309_amd import distill
     t0 = time.perf_counter()
     x, y, e = distill.make_pairs(td, torch, teacher_path, a.student_pairs, precision=1)
     xh, yh, eh = distill.make_pairs(td, torch, teacher_path, 256, seed0=1 + a.student_pairs, precision=1)
     t1 = time.perf_counter()
-    P, hist = distill.train(td, torch, student_init, x, y, e, a.student_steps, batch=64, lr=2e-4, log_every=100)
+    P, hist = distill.train(td, torch, student_init, x, y, e, a.student_steps, batch=64, lr=2e-4, log_every=50)
     t2 = time.perf_counter()
     held = distill.evaluate(td, torch, student_init, P, xh, yh, eh)
     del x, y, e
@@ -262,30 +432,22 @@ def student_leg(td, torch, teacher, teacher_path, student_init, a, region, level
                             "pair_s": round(t1 - t0, 1), "train_s": round(t2 - t1, 1),
                             "ms_per_train_step": round(1e3 * (t2 - t1) / a.student_steps, 1),
                             "loss_first_last": [hist[0][1], hist[-1][1]],
-                            "heldout_window_rel_rmse_vs_teacher": held}}
+                            "heldout_window_rel_rmse_vs_teacher": held},
+           "fp32_plain_ms_per_query": ms32}
     with tempfile.TemporaryDirectory() as d:
         path = os.path.join(d, "student.tdw")
         distill.save(td, student_init, P, path)
         with td.Context(0) as s:
             s.load_weights(path)
-            for name, judge, prec in (("student_fp32", None, 0), ("student_judged_fp32", teacher, 0),
-                                      ("student_bf16", None, 1)):
+            for name, judge, prec in (("student_fp32", None, 0), ("student_bf16", None, 1),
+                                      ("student_judged_fp32", teacher, 0)):
                 s.set_option("precision", prec)
                 s.set_judge(judge, 0.05)
-                s.sample_region_async(a.seed, *region, level, out, stream)      # first use
-                torch.cuda.synchronize()
-                s.cache_clear()
-                t0 = time.perf_counter()
-                s.sample_region_async(a.seed, *region, level, out, stream)
-                torch.cuda.synchronize()
-                dts = time.perf_counter() - t0
-                st = s.cache_stats()
-                rel = float(torch.linalg.vector_norm((out - ref32).double()) /
-                            torch.linalg.vector_norm(ref32.double()))
-                res[name] = {"ms_per_step": 1e3 * dts, "query_speedup_vs_fp32_plain": dt32 / dts,
+                dts, st = timed_cold(s, torch, a, region, level, out, stream)
+                res[name] = {"ms_per_query": 1e3 * dts, "query_speedup_vs_fp32_plain": ms32 / (1e3 * dts),
                              "window_denoises_per_s": st["denoiser_evals"] / dts, "windows": st["misses"],
                              "judge_fallbacks": st["judge_fallbacks"],
-                             "rel_rmse_heightfield_vs_fp32_plain": rel}
+                             "rel_rmse_heightfield_vs_fp32_plain": rel(torch, out, ref32)}
                 print("[bench] %s done" % name, file=sys.stderr, flush=True)
             s.set_judge(None, 0.0)
     res["note"] = ("random-init teacher and a short distillation: the student does not reach the 2e-2 heightfield "
@@ -295,20 +457,31 @@ def student_leg(td, torch, teacher, teacher_path, student_init, a, region, level
 
 def main():
     a = parse()
+    if a.cpu_legs:
+        cpu_legs(a)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
         print("bench.py runs on exactly one GPU: this build measures the per-GPU share of the sampling path "
               "(sharding across GPUs is described in DESIGN.md but not built); got --gpus %d" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
+    budget = Budget(a.budget_s)
+    from synth.models import cached_weights
+    wdir = os.path.join(ROOT, ".td_weights")
+    wpath = cached_weights(a.config, wdir, 0)
+    c1_path = cached_weights("c1", wdir, 0)
+    c2_path = cached_weights("c2", wdir, 0)
+    tmp = tempfile.TemporaryDirectory()
+    cpu_proc = None
+    if not a.micro_only and (not a.no_cpu_baseline or a.bf16_steps > 0):
+        cpu_proc = start_cpu_legs(a, c1_path, c2_path, tmp.name)
+
     import torch
 
     from paper_2512_08309_amd import td
-    from synth.models import cached_weights
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    wdir = os.path.join(ROOT, ".td_weights")
-    wpath = cached_weights(a.config, wdir, 0)
     ctx = td.Context(0).load_weights(wpath)
     if a.micro_only:
         print(json.dumps({"micro": micro_bench(td, torch, ctx)}))
@@ -344,6 +517,15 @@ def main():
     for i in range(a.warmup):
         print("[bench] warmup step %d" % i, file=sys.stderr, flush=True)
         step()
+    cpu = {}
+    if cpu_proc is not None:
+        print("[bench] joining the host (oracle) legs", file=sys.stderr, flush=True)
+        rc = cpu_proc.wait()
+        if rc == 0:
+            with open(os.path.join(tmp.name, "cpu.json")) as f:
+                cpu = json.load(f)
+        else:
+            cpu = {"error": "oracle child process exited with %d" % rc}
     ctx.set_option("timing", 1)
     ctx.kernel_stats(reset=True)
     torch.cuda.synchronize()
@@ -356,9 +538,13 @@ def main():
     dt = time.perf_counter() - t0
     ks = ctx.kernel_stats()
     ctx.set_option("timing", 0)
+    step_s = dt / a.steps
     finite = bool(torch.isfinite(out).all().item())
     ref32 = out.clone()
-    micro = micro_bench(td, torch, ctx)
+    legs = ["micro", "reduced_precision", "latency", "student", "serving", "truncated_T", "latency_c2"]
+    done = {}
+
+    done["micro"] = budget.skip(2.0) or micro_bench(td, torch, ctx)
 
     lowp = None
     if a.bf16_steps > 0:
@@ -366,37 +552,121 @@ def main():
         names = {1: "bf16", 2: "bf16_fp8w"}
         descr = {1: "BF16 convolution operands (activations and weights), FP32 accumulation",
                  2: "BF16 activations, FP8 e4m3 weights with per-output-channel FP32 scales, FP32 accumulation"}
-        for mode in [int(v) for v in a.lowp_modes.split(",") if v]:
+        modes = [int(v) for v in a.lowp_modes.split(",") if v]
+        est = 2.0 + a.bf16_steps * step_s / 3.0
+        for mode in modes:
+            sk = budget.skip(est)
+            if sk:
+                lowp[names[mode]] = sk
+                continue
             ctx.set_option("precision", mode)
-            step()                                   # first use: workspace and kernels
+            ctx.sample_region_async(a.seed, 0, 0, 64, 64, 0, torch.empty((C, 64, 64), device="cuda"), stream)
+            torch.cuda.synchronize()                   # first use: converted weights, kernels
             ctx.set_option("timing", 1)
             ctx.kernel_stats(reset=True)
             w16 = 0
-            t0 = time.perf_counter()
+            t1 = time.perf_counter()
             for i in range(a.bf16_steps):
                 w16 += step()
                 print("[bench] precision %d step %d done" % (mode, i), file=sys.stderr, flush=True)
-            dt16 = time.perf_counter() - t0
+            dt16 = time.perf_counter() - t1
+            est = 2.0 + dt16
             ks16 = ctx.kernel_stats()
             ctx.set_option("timing", 0)
-            rel = float(torch.linalg.vector_norm((out - ref32).double()) / torch.linalg.vector_norm(ref32.double()))
             c16 = ks16.get("conv3x3_mfma_bf16", {"ms": 0.0, "flops": 0.0, "launches": 0})
             lowp[names[mode]] = {
                 "precision": descr[mode] + "; GN statistics, attention, input/output layers, blend/Euler and "
                                            "decode FP32",
                 "value": w16 / dt16, "ms_per_step": 1e3 * dt16 / a.bf16_steps,
                 "speedup_vs_fp32": (w16 / dt16) / (windows / dt),
-                "rel_rmse_heightfield_vs_fp32_gpu": rel,
+                "rel_rmse_heightfield_vs_fp32_gpu": rel(torch, out, ref32),
                 "conv3x3_TFLOP/s": round(c16["flops"] / (c16["ms"] * 1e-3) / 1e12, 1) if c16["ms"] else None,
-                "conv3x3_frac_of_bf16_peak_2500": round(c16["flops"] / (c16["ms"] * 1e-3) / 2.5e15, 4)
-                if c16["ms"] else None,
+                "conv3x3_frac_of_bf16_peak": round(c16["flops"] / (c16["ms"] * 1e-3) / 1e12 /
+                                                   PEAK_BF16_MFMA_TFLOPS, 4) if c16["ms"] else None,
                 "kernels_ms": {k: round(v["ms"], 1) for k, v in sorted(ks16.items(), key=lambda kv: -kv[1]["ms"])}}
         ctx.set_option("precision", 0)
-    student = None
+        ref_path = os.path.join(tmp.name, "crop_ref.npz")
+        if os.path.exists(ref_path):
+            sk = budget.skip(5.0)
+            if sk:
+                lowp["vs_fp64_oracle"] = sk
+            else:
+                errs = precision_errors(td, torch, c1_path, ref_path,
+                                        [m for m in modes if names[m] in lowp and "skipped" not in lowp[names[m]]])
+                lowp["fp32_vs_fp64_oracle"] = errs.pop(0)
+                for m, e in errs.items():
+                    lowp[names[m]]["vs_fp64_oracle"] = e
+        else:
+            lowp["vs_fp64_oracle"] = {"skipped": "no oracle reference (host legs failed)"}
+    done["reduced_precision"] = lowp
+
+    if a.latency_pairs > 0:
+        sk = budget.skip(8.0)
+        if sk:
+            done["latency"] = sk
+        else:
+            print("[bench] latency stream (C1)", file=sys.stderr, flush=True)
+            deadline = time.perf_counter() + min(25.0, budget.left() - 5.0)
+            done["latency"] = latency_stream(td, torch, c1_path, a.latency_pairs, 11, deadline)
+
     if a.student_steps > 0 and a.config == "c2":
-        print("[bench] student distillation", file=sys.stderr, flush=True)
-        student = student_leg(td, torch, ctx, wpath, cached_weights("s2", wdir, 0), a, region, level, out, ref32,
-                              stream, windows / dt, dt)
+        est = 0.0025 * (a.student_pairs + 256) + 0.09 * a.student_steps + 6.0 + 0.7 * step_s
+        sk = budget.skip(est)
+        if sk:
+            done["student"] = sk
+        else:
+            print("[bench] student distillation", file=sys.stderr, flush=True)
+            done["student"] = student_leg(td, torch, ctx, wpath, cached_weights("s2", wdir, 0), a, region, level,
+                                          out, ref32, stream, 1e3 * step_s)
+
+    if a.serve_queries > 0:
+        sk = budget.skip(5.0 + (a.serve_queries / a.serve_rate_sustained if a.serve_rate_sustained > 0 else 0))
+        if sk:
+            done["serving"] = sk
+        else:
+            print("[bench] serving stream", file=sys.stderr, flush=True)
+            srv = serving_stream(td, torch, cached_weights("c1h", wdir, 0), cached_weights("cc", wdir, 0),
+                                 a.serve_queries, a.serve_rate)
+            if a.serve_rate_sustained > 0:
+                print("[bench] serving stream (sustained rate)", file=sys.stderr, flush=True)
+                srv = {"offered_%g_qps" % a.serve_rate: srv,
+                       "offered_%g_qps" % a.serve_rate_sustained:
+                           serving_stream(td, torch, cached_weights("c1h", wdir, 0), cached_weights("cc", wdir, 0),
+                                          a.serve_queries, a.serve_rate_sustained)}
+            done["serving"] = srv
+
+    if a.truncated:
+        # cost of the same query when the windows are blended at T < K levels
+        # (Sec. 3.4): analytic cone counts, and one timed cold step
+        def cone(size, T):
+            return td.td_cone_windows(lx, ly, size, size, 0, T, H, S)
+        trunc = {"cone_windows_by_T": {str(T): {str(sz): cone(sz, T) for sz in (128, 512, 1024)}
+                                       for T in (1, 2, 5, 20)},
+                 "note": "window evaluations of a cold latent query of side 128/512/1024 at (13,-1000001); "
+                         "each evaluation runs K/T = 20/T Euler steps of the network"}
+        sk = budget.skip(2.0 + 0.5 * step_s)
+        if sk:
+            trunc["timed"] = sk
+        else:
+            with td.Context(0) as tctx:
+                tctx.load_weights(cached_weights(a.truncated, wdir, 0))
+                dtt, stt = timed_cold(tctx, torch, a, region, level, out, stream)
+                trunc["timed"] = {"config": a.truncated, "T": tctx.info("levels"), "ms_per_step": 1e3 * dtt,
+                                  "windows": stt["misses"], "denoiser_evals": stt["denoiser_evals"],
+                                  "denoiser_evals_per_s": stt["denoiser_evals"] / dtt,
+                                  "speedup_vs_T20_step": step_s / dtt,
+                                  "rel_rmse_heightfield_vs_T20": rel(torch, out, ref32)}
+        done["truncated_T"] = trunc
+
+    if a.c2_latency_pairs > 0:
+        sk = budget.skip(3.0 + 0.6 * step_s)
+        if sk:
+            done["latency_c2"] = sk
+        else:
+            print("[bench] latency stream (C2)", file=sys.stderr, flush=True)
+            deadline = time.perf_counter() + budget.left() - 3.0 - 0.6 * step_s
+            done["latency_c2"] = latency_stream(td, torch, wpath, a.c2_latency_pairs, 13, deadline, label="C2",
+                                                ctx=ctx)
     ctx.close()
 
     conv = ks.get("conv3x3_mfma_f32", {"launches": 0, "ms": 0.0, "flops": 0.0})
@@ -410,54 +680,6 @@ def main():
             e["GB/s"] = round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1)
         kernels[name] = e
 
-    trunc = None
-    if a.truncated:
-        # cost of the same query when the windows are blended at T < K levels
-        # (Sec. 3.4): analytic cone counts, and one timed cold step for a.truncated
-        def cone(size, T):
-            return td.td_cone_windows(lx, ly, size, size, 0, T, H, S)
-        trunc = {"cone_windows_by_T": {str(T): {str(sz): cone(sz, T) for sz in (128, 512, 1024)}
-                                       for T in (1, 2, 5, 20)},
-                 "note": "window evaluations of a cold latent query of side 128/512/1024 at (13,-1000001); "
-                         "each evaluation runs K/T = 20/T Euler steps of the network"}
-        tctx = td.Context(0).load_weights(cached_weights(a.truncated, wdir, 0))
-        tctx.set_option("timing", 1)
-        tctx.sample_region_async(a.seed, *region, level, out, stream)     # first use
-        torch.cuda.synchronize()
-        tctx.cache_clear()
-        t0 = time.perf_counter()
-        tctx.sample_region_async(a.seed, *region, level, out, stream)
-        torch.cuda.synchronize()
-        dtt = time.perf_counter() - t0
-        stt = tctx.cache_stats()
-        trunc["timed"] = {"config": a.truncated, "T": tctx.info("levels"), "ms_per_step": 1e3 * dtt,
-                          "windows": stt["misses"], "denoiser_evals": stt["denoiser_evals"],
-                          "denoiser_evals_per_s": stt["denoiser_evals"] / dtt,
-                          "speedup_vs_T20_step": (1e3 * dt / a.steps) / (1e3 * dtt),
-                          "rel_rmse_heightfield_vs_T20": float(torch.linalg.vector_norm((out - ref32).double()) /
-                                                               torch.linalg.vector_norm(ref32.double()))}
-        tctx.close()
-
-    lat = None
-    if a.latency_pairs > 0:
-        print("[bench] latency stream", file=sys.stderr, flush=True)
-        lat = latency_stream(td, torch, cached_weights("c1", wdir, 0), a.latency_pairs)
-    serve = None
-    if a.serve_queries > 0:
-        print("[bench] serving stream", file=sys.stderr, flush=True)
-        serve = serving_stream(td, torch, cached_weights("c1h", wdir, 0), cached_weights("cc", wdir, 0),
-                               a.serve_queries, a.serve_rate)
-        if a.serve_rate_sustained > 0:
-            print("[bench] serving stream (sustained rate)", file=sys.stderr, flush=True)
-            serve = {"offered_%g_qps" % a.serve_rate: serve,
-                     "offered_%g_qps" % a.serve_rate_sustained:
-                         serving_stream(td, torch, cached_weights("c1h", wdir, 0), cached_weights("cc", wdir, 0),
-                                        a.serve_queries, a.serve_rate_sustained)}
-    cpu = None
-    if not a.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(wpath, a.cpu_windows)
-
     res = {
         "metric": "window-denoises/s",
         "value": windows / dt,
@@ -465,7 +687,7 @@ def main():
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": 1e3 * dt / a.steps,
+        "ms_per_step": 1e3 * step_s,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -473,9 +695,9 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": ("cold %s query, full-res %dx%d px (latent %d^2 + 17 px apron) at latent (%d, %d), seed %d"
-                         % ("elevation" if level == td.TD_LEVEL_HEIGHT else "latent", region[2], region[3],
-                            a.size, lx, ly, a.seed)) if level == td.TD_LEVEL_HEIGHT else
-                        ("cold latent query %dx%d at (%d, %d), seed %d" % (a.size, a.size, lx, ly, a.seed)),
+                         % ("elevation", region[2], region[3], a.size, lx, ly, a.seed))
+            if level == td.TD_LEVEL_HEIGHT else
+            ("cold latent query %dx%d at (%d, %d), seed %d" % (a.size, a.size, lx, ly, a.seed)),
             "latent_channels": C, "steps_K": K, "window": H, "stride": S,
             "unet": "4-level 128/256/256/512, 2 res-blocks, 8-head attention at 8x8, random init"
             if a.config.startswith("c2") else a.config,
@@ -494,16 +716,19 @@ def main():
             "launches": conv["launches"],
         },
         "kernels": kernels,
-        "latency": lat,
-        "reduced_precision": lowp,
-        "truncated_T": trunc,
-        "serving": serve,
-        "student": student,
-        "micro": micro,
-        "cpu_baseline": cpu,
+        "cpu_baseline": cpu_baseline_entry(cpu) if cpu else None,
         "output_finite": finite,
-        "paper_context": paper_context(lat),
+        "run_budget": {"budget_s": a.budget_s, "elapsed_s": round(time.perf_counter() - T_START, 1),
+                       "leg_order": legs,
+                       "note": "legs after the timed steps run in this order while their estimated cost fits the "
+                               "budget; skipped legs say so"},
     }
+    for k in legs:
+        res[k] = done.get(k)
+    res["paper_context"] = paper_context(done.get("latency"))
+    if cpu and "error" in cpu:
+        res["cpu_baseline_error"] = cpu["error"]
+    tmp.cleanup()
     print(json.dumps(res))
 
 
