@@ -103,10 +103,11 @@ class Budget:
                                                                                        self.total)}
 
 
-# ----------------------------------------------------------------- host legs
-# The oracle (FP64 NumPy) on the host cores, in a child process that never
-# touches the GPU: started before the warm-up steps, joined before the timed
-# steps.
+# ----------------------------------------------------------------- host leg
+# The cpu_baseline leg: the oracle (FP64 NumPy) on the host cores, in a child
+# process that never touches the GPU, started before the warm-up steps and
+# joined before the timed steps.  It times the oracle, and writes the oracle's
+# values of the precision crop that the reduced-precision legs compare with.
 
 def _nproc():
     try:
@@ -115,7 +116,7 @@ def _nproc():
         return os.cpu_count() or 1
 
 
-def cpu_legs(a):
+def cpu_baseline(a):
     import numpy as np
     from threadpoolctl import threadpool_info, threadpool_limits
 
@@ -458,7 +459,7 @@ def student_leg(td, torch, teacher, teacher_path, student_init, a, region, level
 def main():
     a = parse()
     if a.cpu_legs:
-        cpu_legs(a)
+        cpu_baseline(a)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
