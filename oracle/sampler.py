@@ -25,8 +25,11 @@ TEST INFRASTRUCTURE (oracle).
   = (teacher, threshold)), a window whose denoised estimate differs from the
   teacher's one-step estimate D_teacher(x; s_k) by more than the threshold
   in RMS over the window takes, instead of its estimate, the teacher's plain
-  sampler run on that window from s_k to 0: Euler steps through s_k, then
-  the teacher's schedule values below s_k, then 0.
+  sample J_0 on the window's region (same seed): the plain sampler as the
+  fallback (Sec. 3.4 lets Phi be a few-step model; Sec. 5.3 and the
+  distillation appendix distil the core model into two steps).  With
+  threshold 0 every window falls back at both steps, and J_0 of the judged
+  student is the teacher's plain J_0 (J_1 is it plus s_1 G(step = 1)).
 * Hierarchy (Sec. 5.1; DAGs of infinite tensors, infinite-tensor appendix):
   a model whose header has "cond" = {channels, factor f} is the child of a
   parent model (Model.parent).  Window i of the child receives, besides
@@ -112,20 +115,10 @@ def cond_windows(src, windows, model):
     return np.stack(out)
 
 
-def teacher_trajectory(teacher, x, sigma, windows, cond):
-    """The teacher's plain (Euler) sampler on windows x at noise level sigma,
-    down to 0 through its own schedule values below sigma."""
-    seq = [sigma] + [v for v in teacher.sched[:-1] if v < sigma] + [0.0]
-    for a, b in zip(seq, seq[1:]):
-        D = teacher.denoiser(x, a, windows, cond if teacher.cond else None)
-        x = x + euler_factor(a, b) * (x - D)
-    return x
-
-
-def judged(model, D, x, sigma, windows, cond):
-    """The student's estimate per window, or the teacher's plain sampler where
-    the student differs from the teacher's one-step estimate by more than the
-    threshold (RMS over the window)."""
+def judged(model, D, x, sigma, windows, cond, seed):
+    """The student's estimate per window, or the teacher's plain sample J_0 on
+    the window's region where the student differs from the teacher's one-step
+    estimate by more than the threshold (RMS over the window)."""
     teacher, thr = model.judge
     DT = teacher.denoiser(x, sigma, windows, cond if teacher.cond else None)
     r = np.sqrt(((D - DT) ** 2).mean(axis=(1, 2, 3)))
@@ -135,9 +128,9 @@ def judged(model, D, x, sigma, windows, cond):
     if not use.any():
         return D
     out = D.copy()
-    idx = np.nonzero(use)[0]
-    out[idx] = teacher_trajectory(teacher, x[idx], sigma, [windows[i] for i in idx],
-                                  None if cond is None else cond[idx])
+    for i in np.nonzero(use)[0]:
+        ix, iy = windows[i]
+        out[i] = sample(teacher, seed, ix * model.s + model.o, iy * model.s + model.o, model.H, model.H, 0)
     return out
 
 
@@ -163,7 +156,7 @@ def level_step(model, j_next, region_next, region, windows, t, cond_src=None, se
                 phi = phi + euler_factor(sig, sig_next) * (phi - D)
                 continue
             if model.judge is not None:
-                D = judged(model, D, phi, sig, windows, cond)
+                D = judged(model, D, phi, sig, windows, cond, seed)
             phi = D
             if sig_next > 0:
                 phi = phi + sig_next * np.stack([

@@ -6,10 +6,12 @@ teacher fallback judge.
   0.35 G_1(p) and J_0(p) = m(p) + a_1 (J_1(p) - m(p)) with a_k = s^2 /
   (s^2 + sigma_k^2), G_1 the noise on counter word 1, m the brute-force
   weighted window mean.
-* The judge at threshold 0 replaces every window by the teacher's plain
-  sampler from the student's noise level (``lg``, s = 0.5, 8 EDM steps: all
-  of them from 80, then 0.35 -> the teacher's levels below 0.35 -> 0), at an
-  infinite threshold by none: both closed forms.
+* The judge at threshold 0 replaces every window's estimate by the
+  teacher's plain sample J_0 on the window's region (``lg``, s = 0.5, 8 EDM
+  steps), at an infinite threshold by none: both closed forms.  At
+  threshold 0 the judged student's J_0 is the teacher's plain J_0 (the
+  linear-Gaussian closed form of the 8-step EDM sampler) and its J_1 that
+  plus s_1 G_1, since the blend of position-consistent fields returns them.
 """
 import math
 
@@ -31,18 +33,23 @@ def euler_product(seq, s):
 
 
 def closed_form(m, seed, x0, y0, w, h, level, s, teacher_sched=None):
+    """J_level of two-step consistency sampling with a linear-Gaussian prior
+    of std s; with teacher_sched, every estimate is the teacher's plain J_0
+    (EDM Euler through teacher_sched, which starts at the student's s_0)."""
     sig = m.sched
-    if teacher_sched is None:   # the student's own estimates
-        f = [s * s / (s * s + v * v) for v in sig[:2]]
-    else:                       # the teacher's plain sampler from each of the student's levels
-        f = [euler_product([v] + [u for u in teacher_sched[:-1] if u < v] + [0.0], s) for v in sig[:2]]
     g0 = noise.noise_region(seed, x0, y0, w, h, 4, step=0).astype(np.float64)
     g1 = noise.noise_region(seed, x0, y0, w, h, 4, step=1).astype(np.float64)
     out = {}
     for yy, xx, c in [(0, 0, 0), (h - 1, w - 1, 3), (5, 11, 1), (16, 2, 2), (8, 8, 0)]:
         mu = brute_mu_bar(x0 + xx, y0 + yy, c, m.H, m.s, m.o, m.eps)
-        j1 = mu + f[0] * (sig[0] * g0[yy, xx, c] - mu) + sig[1] * g1[yy, xx, c]
-        out[(yy, xx, c)] = j1 if level == 1 else mu + f[1] * (j1 - mu)
+        if teacher_sched is None:   # the student's own estimates
+            f = [s * s / (s * s + v * v) for v in sig[:2]]
+            j1 = mu + f[0] * (sig[0] * g0[yy, xx, c] - mu) + sig[1] * g1[yy, xx, c]
+            out[(yy, xx, c)] = j1 if level == 1 else mu + f[1] * (j1 - mu)
+        else:                       # the teacher's plain J_0 at both steps
+            assert teacher_sched[0] == sig[0]
+            j0t = mu + (sig[0] * g0[yy, xx, c] - mu) * euler_product(teacher_sched, s)
+            out[(yy, xx, c)] = j0t + sig[1] * g1[yy, xx, c] if level == 1 else j0t
     return out
 
 
@@ -55,16 +62,29 @@ def test_consistency_linear_gaussian_closed_form(weights, seed, x0, y0, level):
         assert got[yy, xx, c] == pytest.approx(want, rel=1e-12, abs=1e-12)
 
 
+@pytest.mark.parametrize("level", [0, 1])
 @pytest.mark.parametrize("thr,s", [(0.0, 0.5), (math.inf, 0.7)])
-def test_judge_extremes(weights, thr, s):
+def test_judge_extremes(weights, thr, s, level):
     m = Model(weights("lgs"))
     teacher = Model(weights("lg"))
     m.judge = (teacher, thr)
-    got = sample(m, 2, -9, 40, 23, 17, 0)
+    got = sample(m, 2, -9, 40, 23, 17, level)
     ts = teacher.sched if thr == 0 else None
-    for (yy, xx, c), want in closed_form(m, 2, -9, 40, 23, 17, 0, s, ts).items():
+    for (yy, xx, c), want in closed_form(m, 2, -9, 40, 23, 17, level, s, ts).items():
         assert got[yy, xx, c] == pytest.approx(want, rel=1e-12, abs=1e-12)
     assert (m.fallbacks == m.phi_calls) if thr == 0 else m.fallbacks == 0
+
+
+def test_judge_at_threshold_zero_is_the_teachers_plain_sample(weights):
+    """Every pixel, not only the closed-form probes: the judged student's J_0
+    equals the teacher's own plain sample of the same region and seed."""
+    m = Model(weights("lgs"))
+    teacher = Model(weights("lg"))
+    m.judge = (teacher, 0.0)
+    got = sample(m, 6, 1000001, -33, 41, 19, 0)
+    want = sample(Model(weights("lg")), 6, 1000001, -33, 41, 19, 0)
+    assert np.max(np.abs(got - want)) <= 1e-12 * max(1.0, np.max(np.abs(want)))
+    assert m.fallbacks == m.phi_calls > 0
 
 
 def test_consistency_schedule_validation():
