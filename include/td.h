@@ -67,8 +67,8 @@ typedef struct {
   uint64_t queries;       /* td_sample_region* calls served                */
   uint64_t denoiser_evals;/* network evaluations (windows x Euler steps)   */
   uint64_t windows_evaluated[64];
-  uint64_t judge_fallbacks;/* consistency windows that took the teacher's  */
-                           /* estimate (td_set_judge)                      */
+  uint64_t judge_fallbacks;/* consistency windows that fell back to the    */
+                           /* teacher's plain sample (td_set_judge)        */
 } td_cache_stats_t;
 
 /* Elevation query level: decoded height in metres on full-resolution pixels
@@ -112,11 +112,15 @@ td_status td_set_conditioning(td_ctx *child, td_ctx *parent);
  * every step is also denoised by `teacher` at the same noise level (one
  * teacher network evaluation), and a window whose estimate differs from the
  * teacher's by more than `threshold` in RMS over the window (all pixels and
- * channels, FP32) takes the teacher's estimate; td_cache_stats counts those
- * windows in judge_fallbacks.  The teacher needs the student's channels and
- * window layout; its network runs on the student's stream in the teacher's
- * workspace, ordered after the teacher's own work (do not query the teacher
- * from another thread meanwhile).  NULL teacher turns the judge off.
+ * channels, FP32) falls back to the plain sampler: it takes the teacher's
+ * plain sample J_0 on the window's region for the same seed, computed by
+ * the teacher context's own lazy sampler and cache (Sec. 5.3: the plain
+ * sampler stands behind the distilled two-step model).  td_cache_stats
+ * counts those windows in judge_fallbacks.  The teacher needs the student's
+ * channels and window layout; its one-step network runs on the student's
+ * stream in the teacher's workspace, its fallback samples on its own
+ * stream, both ordered after the teacher's own work (do not query the
+ * teacher from another thread meanwhile).  NULL teacher turns the judge off.
  * Clears the student's cache; reloading the teacher clears it again at the
  * student's next query.  TD_E_INVAL if the student is not a consistency
  * model, threshold < 0 or the devices differ; TD_E_STATE at query time if

@@ -25,7 +25,8 @@ TEST INFRASTRUCTURE (oracle).
   = (teacher, threshold)), a window whose denoised estimate differs from the
   teacher's one-step estimate D_teacher(x; s_k) by more than the threshold
   in RMS over the window takes, instead of its estimate, the teacher's plain
-  sample J_0 on the window's region (same seed): the plain sampler as the
+  sample J_0 on the window's region (same seed; read from one teacher sample
+  over the flagged windows' bounding region): the plain sampler as the
   fallback (Sec. 3.4 lets Phi be a few-step model; Sec. 5.3 and the
   distillation appendix distil the core model into two steps).  With
   threshold 0 every window falls back at both steps, and J_0 of the judged
@@ -127,10 +128,18 @@ def judged(model, D, x, sigma, windows, cond, seed):
     model.fallbacks += int(use.sum())
     if not use.any():
         return D
+    # J_0 of the teacher on each flagged window's region, read from one
+    # sample over their bounding region: the same values, since a region's
+    # sample is the crop of any larger region's (seed consistency theorem of
+    # the formal appendix; pinned by the crop-independence tests)
+    idx = np.nonzero(use)[0]
+    ox = np.array([windows[i][0] * model.s + model.o for i in idx], dtype=np.int64)
+    oy = np.array([windows[i][1] * model.s + model.o for i in idx], dtype=np.int64)
+    bx, by = int(ox.min()), int(oy.min())
+    big = sample(teacher, seed, bx, by, int(ox.max()) + model.H - bx, int(oy.max()) + model.H - by, 0)
     out = D.copy()
-    for i in np.nonzero(use)[0]:
-        ix, iy = windows[i]
-        out[i] = sample(teacher, seed, ix * model.s + model.o, iy * model.s + model.o, model.H, model.H, 0)
+    for i, px, py in zip(idx, ox - bx, oy - by):
+        out[i] = big[py:py + model.H, px:px + model.H]
     return out
 
 

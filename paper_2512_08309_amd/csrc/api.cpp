@@ -205,6 +205,8 @@ struct td_ctx {
   size_t outbuf_cap = 0;
   float* gath = nullptr;      // batched window inputs of sample_latent_multi
   size_t gath_cap = 0;
+  float* fb = nullptr;        // the judge's J_0 on the hull of fallen-back windows
+  size_t fb_cap = 0;
   std::unique_ptr<td::Profiler> prof;
   // hierarchy: the parent whose final latent conditions this model, the
   // children it conditions, and a generation that changes with the values
@@ -266,6 +268,8 @@ Region region_union(const Region& a, const Region& b) {
   return Region{x0, y0, x1 - x0, y1 - y0};
 }
 
+void judge_fallback(void* user, const FallbackReq* req, int n, float* out, hipStream_t st);
+
 void check_judge(td_ctx* c, bool may_clear) {
   td_ctx* j = c->judge;
   if (!j) {
@@ -285,7 +289,7 @@ void check_judge(td_ctx* c, bool may_clear) {
     drop_cache(c);
     c->judge_gen = j->gen;
   }
-  c->model->set_judge(j->model.get(), c->judge_thr, c->d_fallbacks);
+  c->model->set_judge(j->model.get(), c->judge_thr, c->d_fallbacks, judge_fallback, c);
 }
 
 // Orders the judge's stream around work on c's stream that uses the judge's
@@ -607,6 +611,8 @@ void sample_latent_body(td_ctx* c, Arena& arena, uint64_t seed, Region r, int le
       wb.d_slots = (float* const*)s.second;
       wb.n = nb;
       wb.mode = 0;
+      wb.h_widx = hw;
+      wb.seed = seed;
       if (d.Cc) {
         std::vector<CondSrc> cs(nb);
         for (int j = 0; j < nb; ++j)
@@ -766,6 +772,8 @@ void sample_latent_multi_body(td_ctx* c, Arena& arena, const std::vector<RegionJ
       TD_HIP(hipMemcpyAsync(wix.second, wix.first, (size_t)nb * 2 * sizeof(int), hipMemcpyHostToDevice, st));
       TD_HIP(hipMemcpyAsync(slo.second, slo.first, (size_t)nb * sizeof(float*), hipMemcpyHostToDevice, st));
       launch_gather(st, (const float* const*)src.second, (const int*)pit.second, nb, d.H, d.C, c->gath);
+      std::vector<uint64_t> seeds(nb);
+      for (int j = 0; j < nb; ++j) seeds[j] = jobs[work[b0 + j].first].seed;
       WindowBatch wb;
       wb.canvas = c->gath;
       wb.canvas_w = d.H;
@@ -774,6 +782,8 @@ void sample_latent_multi_body(td_ctx* c, Arena& arena, const std::vector<RegionJ
       wb.d_slots = (float* const*)slo.second;
       wb.n = nb;
       wb.mode = 0;
+      wb.h_widx = hw;
+      wb.h_seeds = seeds.data();
       c->model->run_level(st, wb, t);
       c->stats.batches++;
     }
@@ -852,6 +862,56 @@ void sample_latent_multi(td_ctx* c, Arena& arena, const std::vector<RegionJob>& 
     abandon_cache(c);
     throw;
   }
+}
+
+// Fallback of a judged consistency model (Sec. 3.4 lets Phi be a few-step
+// model; Sec. 5.3 distils the plain sampler into two steps, which then
+// stands behind it): a flagged window takes the judge's plain sample J_0
+// on the window's region, same seed, written to out[j] as [H][H][C].  It
+// runs on the judge's stream and cache after everything enqueued on `st`,
+// and `st` waits for it.  Windows of one seed are sampled as one region,
+// their bounding box, when they fill at least a quarter of it (or the judge
+// is conditioned); otherwise as one multi-region query of window regions.
+void judge_fallback(void* user, const FallbackReq* req, int n, float* out, hipStream_t st) {
+  td_ctx* c = static_cast<td_ctx*>(user);
+  td_ctx* j = c->judge;
+  TD_CHECK(j && j->model, TD_E_STATE, "internal: fallback without a judge");
+  TD_CHECK(j->device == c->device, TD_E_STATE, "judge and student must share a device");
+  const ModelDesc& d = c->model->d;
+  const size_t per = (size_t)d.H * d.H * d.C;
+  TD_HIP(hipEventRecord(c->xev, st));
+  TD_HIP(hipStreamWaitEvent(j->stream, c->xev, 0));
+  // the judge's own earlier work (and its metadata copies) has finished
+  TD_HIP(hipStreamSynchronize(j->stream));
+  j->arena.reset();
+  check_parent(j, true);
+  std::map<uint64_t, std::vector<int>> by_seed;
+  for (int i = 0; i < n; ++i) by_seed[req[i].seed].push_back(i);
+  std::vector<RegionJob> jobs;
+  for (const auto& g : by_seed) {
+    Region hull{0, 0, 0, 0};
+    for (int i : g.second)
+      hull = region_union(hull, Region{req[i].ix * d.S + d.O, req[i].iy * d.S + d.O, d.H, d.H});
+    const bool whole = j->model->d.Cc || (int64_t)g.second.size() * d.H * d.H * 4 >= hull.w * hull.h;
+    if (!whole) {
+      for (int i : g.second)
+        jobs.push_back(RegionJob{g.first, Region{req[i].ix * d.S + d.O, req[i].iy * d.S + d.O, d.H, d.H},
+                                 out + (size_t)i * per});
+      continue;
+    }
+    check_region(hull.x0, hull.y0, hull.w, hull.h);
+    grow(c->fb, c->fb_cap, (size_t)hull.w * hull.h * d.C);
+    sample_latent(j, j->arena, g.first, hull, 0, 0, c->fb);
+    for (int i : g.second) {
+      const size_t ox = (size_t)(req[i].ix * d.S + d.O - hull.x0), oy = (size_t)(req[i].iy * d.S + d.O - hull.y0);
+      TD_HIP(hipMemcpy2DAsync(out + (size_t)i * per, (size_t)d.H * d.C * sizeof(float),
+                              c->fb + (oy * hull.w + ox) * d.C, (size_t)hull.w * d.C * sizeof(float),
+                              (size_t)d.H * d.C * sizeof(float), d.H, hipMemcpyDeviceToDevice, j->stream));
+    }
+  }
+  if (!jobs.empty()) sample_latent_multi(j, j->arena, jobs);
+  TD_HIP(hipEventRecord(j->xev, j->stream));
+  TD_HIP(hipStreamWaitEvent(st, j->xev, 0));
 }
 
 void sample_any(td_ctx* c, uint64_t seed, int64_t x0, int64_t y0, int32_t w, int32_t h, int32_t level,
@@ -974,7 +1034,7 @@ void td_destroy(td_ctx* c) {
   c->model.reset();
   c->arena.release();
   c->prof.reset();
-  for (float* p : {c->canvas, c->tmp, c->dec, c->outbuf, c->cond, c->gath})
+  for (float* p : {c->canvas, c->tmp, c->dec, c->outbuf, c->cond, c->gath, c->fb})
     if (p) (void)hipFree(p);
   if (c->done) (void)hipEventDestroy(c->done);
   if (c->xev) (void)hipEventDestroy(c->xev);
@@ -1789,6 +1849,8 @@ bool run_round_batch(td_server* s, Arena& arena) {
                      T.key.iy);
   }
   if (d.Cc) cond_batch(c, arena, cs.data(), nb);
+  std::vector<uint64_t> seeds(nb);
+  for (int j = 0; j < nb; ++j) seeds[j] = s->q[s->tasks[ids[j]].q].r.seed;
   WindowBatch wb;
   wb.canvas = s->batch_in;
   wb.canvas_w = d.H;
@@ -1797,6 +1859,8 @@ bool run_round_batch(td_server* s, Arena& arena) {
   wb.d_slots = (float* const*)slo.second;
   wb.n = nb;
   wb.mode = 0;
+  wb.h_widx = hw;
+  wb.h_seeds = seeds.data();
   if (d.Cc) wb.cond = c->model->cond_buffer();
   c->model->run_level(st, wb, best);
   c->stats.batches++;

@@ -180,27 +180,6 @@ __global__ __launch_bounds__(256) void judge_kernel(const float* __restrict__ ds
   }
 }
 
-// The flagged windows idx[j] (j < nf) of a canvas batch, packed: out[j] =
-// window j's input, widx_out[j] = its window index.
-__global__ __launch_bounds__(256) void compact_kernel(const float* __restrict__ canvas, int canvas_w,
-                                                      const int* __restrict__ origins, const int* __restrict__ widx,
-                                                      const int* __restrict__ idx, int H, int C,
-                                                      float* __restrict__ out, int* __restrict__ widx_out) {
-  const int j = blockIdx.y;
-  const int b = idx[j];
-  const int per = H * H * C;
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e == 0) {
-    widx_out[2 * j] = widx[2 * b];
-    widx_out[2 * j + 1] = widx[2 * b + 1];
-  }
-  if (e >= per) return;
-  const int c = e % C, p = e / C;
-  const int v = p / H, u = p - v * H;
-  const int ox = origins[2 * b], oy = origins[2 * b + 1];
-  out[(size_t)j * per + e] = canvas[((size_t)(oy + v) * canvas_w + ox + u) * C + c];
-}
-
 // slots[b] = W (x) (pos[b] < 0 ? ds[b] : fb[pos[b]])
 __global__ __launch_bounds__(256) void select_kernel(const float* __restrict__ ds, const float* __restrict__ fb,
                                                      const int* __restrict__ pos, int H, int C,
@@ -226,15 +205,6 @@ void launch_judge(hipStream_t st, const float* ds, const float* dt, int nwin, in
   TD_LAUNCHED();
   const double n = (double)nwin * H * H * C;
   prof_end(st, K_BLEND, 3.0 * n, 8.0 * n);
-}
-
-void launch_compact(hipStream_t st, const float* canvas, int canvas_w, const int* origins, const int* widx,
-                    const int* idx, int nf, int H, int C, float* out, int* widx_out) {
-  if (!nf) return;
-  const int per = H * H * C;
-  hipLaunchKernelGGL(compact_kernel, dim3((per + 255) / 256, nf), dim3(256), 0, st, canvas, canvas_w, origins, widx,
-                     idx, H, C, out, widx_out);
-  TD_LAUNCHED();
 }
 
 void launch_select(hipStream_t st, const float* ds, const float* fb, const int* pos, int nwin, int H, int C,

@@ -492,10 +492,13 @@ int Model::sigma_slot(hipStream_t st, double sigma) {
 
 double Model::sigma_of(int k) const { return k < d.K ? d.sched[k] : extra_sigma_.at(k - d.K); }
 
-void Model::set_judge(Model* teacher, float threshold, unsigned long long* counter) {
+void Model::set_judge(Model* teacher, float threshold, unsigned long long* counter, FallbackFn fallback,
+                      void* user) {
   judge_ = teacher;
   judge_thr_ = threshold;
   judge_count_ = counter;
+  fallback_ = fallback;
+  fallback_user_ = user;
 }
 
 size_t Model::workspace_bytes_per_window() const {
@@ -541,21 +544,12 @@ void Model::ensure_workspace(int max_batch) {
   state_origins_ = nullptr;
   cond_ = d.Cc ? take((size_t)max_batch * d.H * d.H * d.Cc) : nullptr;
   judge_s_ = judge_t_ = nullptr;
-  judge_flags_ = judge_idx_ = judge_pos_ = judge_widx_ = judge_origins_ = nullptr;
+  judge_flags_ = judge_pos_ = nullptr;
   if (d.consistency) {
     judge_s_ = take((size_t)max_batch * d.H * d.H * d.C);
     judge_t_ = take((size_t)max_batch * d.H * d.H * d.C);
     judge_flags_ = (int*)take((size_t)max_batch);
-    judge_idx_ = (int*)take((size_t)max_batch);
     judge_pos_ = (int*)take((size_t)max_batch);
-    judge_widx_ = (int*)take((size_t)max_batch * 2);
-    judge_origins_ = (int*)take((size_t)max_batch * 2);
-    std::vector<int> o(2 * (size_t)max_batch);
-    for (int b = 0; b < max_batch; ++b) {
-      o[2 * b] = 0;
-      o[2 * b + 1] = b * d.H;
-    }
-    TD_HIP(hipMemcpy(judge_origins_, o.data(), o.size() * sizeof(int), hipMemcpyHostToDevice));
   }
   if (d.T < d.K) {
     state_ = take((size_t)max_batch * d.H * d.H * d.C);
@@ -846,35 +840,21 @@ void Model::run_batch(hipStream_t st, const WindowBatch& wb, int k) {
     judge_->ensure_workspace(std::max(judge_->max_batch(), wb.n));
     judge_->run_batch(st, t, judge_->sigma_slot(st, d.sched[k]));
     launch_judge(st, judge_s_, judge_t_, wb.n, d.H, d.C, judge_thr_, judge_flags_, judge_count_);
-    // the flagged windows take the teacher's plain sampler from sigma_k to 0
-    std::vector<int> flags(wb.n), idx, pos(wb.n, -1);
+    // a flagged window takes the teacher's plain sample J_0 on its region
+    std::vector<int> flags(wb.n), pos(wb.n, -1);
+    std::vector<FallbackReq> req;
     TD_HIP(hipMemcpyAsync(flags.data(), judge_flags_, (size_t)wb.n * sizeof(int), hipMemcpyDeviceToHost, st));
     TD_HIP(hipStreamSynchronize(st));
     for (int b = 0; b < wb.n; ++b)
       if (flags[b]) {
-        pos[b] = (int)idx.size();
-        idx.push_back(b);
+        TD_CHECK(wb.h_widx, -6, "internal: judged batch without host window indices");
+        pos[b] = (int)req.size();
+        req.push_back(FallbackReq{wb.h_seeds ? wb.h_seeds[b] : wb.seed, wb.h_widx[2 * b], wb.h_widx[2 * b + 1]});
       }
     TD_HIP(hipMemcpy(judge_pos_, pos.data(), pos.size() * sizeof(int), hipMemcpyHostToDevice));
-    if (!idx.empty()) {
-      const int nf = (int)idx.size();
-      TD_HIP(hipMemcpy(judge_idx_, idx.data(), idx.size() * sizeof(int), hipMemcpyHostToDevice));
-      launch_compact(st, wb.canvas, wb.canvas_w, wb.d_origins, wb.d_widx, judge_idx_, nf, d.H, d.C, judge_t_,
-                     judge_widx_);
-      std::vector<double> seq{d.sched[k]};
-      for (int j = 0; j < judge_->d.K; ++j)
-        if (judge_->d.sched[j] < d.sched[k]) seq.push_back(judge_->d.sched[j]);
-      seq.push_back(0.0);
-      WindowBatch f;
-      f.canvas = judge_t_;
-      f.canvas_w = d.H;
-      f.d_origins = judge_origins_;
-      f.d_widx = judge_widx_;
-      f.n = nf;
-      f.mode = 2;
-      f.dout = judge_t_;   // each step reads a window element before writing it
-      for (size_t j = 0; j + 1 < seq.size(); ++j)
-        judge_->run_net(st, f, judge_->sigma_slot(st, seq[j]), seq[j + 1]);
+    if (!req.empty()) {
+      TD_CHECK(fallback_, -6, "internal: judged model without a fallback sampler");
+      fallback_(fallback_user_, req.data(), (int)req.size(), judge_t_, st);
     }
     launch_select(st, judge_s_, judge_t_, judge_pos_, wb.n, d.H, d.C, w1d_, wb.d_slots);
     return;

@@ -86,7 +86,22 @@ struct WindowBatch {
   const float* cond = nullptr;      // [n][H][H][Cc] conditioning windows (Cc > 0)
   int n = 0;
   int mode = 0;                     // 0: contributions W (x) Phi, 1: raw D, 2: Phi to dout
+  // host copies for a judged consistency model (mode 0): window indices
+  // [n][2], and the query seed (one for the batch, or per window)
+  const int* h_widx = nullptr;
+  uint64_t seed = 0;
+  const uint64_t* h_seeds = nullptr;
 };
+
+// A judged window that falls back: its query seed and window index.
+struct FallbackReq {
+  uint64_t seed;
+  int64_t ix, iy;
+};
+// Writes the judge's plain sample J_0 on the region of window req[j] to
+// out[j] ([H][H][C]) for j < n; enqueued after everything on `st`, which
+// waits for it.
+using FallbackFn = void (*)(void* user, const FallbackReq* req, int n, float* out, hipStream_t st);
 
 class Model {
  public:
@@ -102,9 +117,11 @@ class Model {
   int sigma_slot(hipStream_t st, double sigma);
   double sigma_of(int k) const;
   // Consistency sampling with a teacher judge: a window whose estimate
-  // differs from the teacher's by more than `threshold` RMS takes the
-  // teacher's; `counter` (device) counts such windows.  teacher null: off.
-  void set_judge(Model* teacher, float threshold, unsigned long long* counter);
+  // differs from the teacher's one-step estimate by more than `threshold`
+  // RMS takes the teacher's plain sample J_0 on its region, supplied by
+  // `fallback`; `counter` (device) counts such windows.  teacher null: off.
+  void set_judge(Model* teacher, float threshold, unsigned long long* counter, FallbackFn fallback = nullptr,
+                 void* user = nullptr);
   // Phi of blend level t: the Euler steps points[T-t-1] .. points[T-t]-1 on
   // every window of the batch, the last one writing b.mode's output.
   void run_level(hipStream_t st, const WindowBatch& b, int t);
@@ -155,9 +172,10 @@ class Model {
   Model* judge_ = nullptr;
   float judge_thr_ = 0.f;
   unsigned long long* judge_count_ = nullptr;
+  FallbackFn fallback_ = nullptr;
+  void* fallback_user_ = nullptr;
   float *judge_s_ = nullptr, *judge_t_ = nullptr;   // student / teacher estimates of a batch
-  int *judge_flags_ = nullptr, *judge_idx_ = nullptr, *judge_pos_ = nullptr, *judge_widx_ = nullptr,
-      *judge_origins_ = nullptr;
+  int *judge_flags_ = nullptr, *judge_pos_ = nullptr;
   // sigma_next_override >= 0: the Euler step goes to that level (mode 2)
   void run_net(hipStream_t st, const WindowBatch& b, int k, double sigma_next_override = -1.0);
   float* state_ = nullptr;        // window states between the steps of one Phi

@@ -115,10 +115,6 @@ void launch_lg_step(hipStream_t st, const WinGeom& g, const float* canvas,
 // counter (device, nullable) counts the flagged windows.
 void launch_judge(hipStream_t st, const float* ds, const float* dt, int nwin, int H, int C, float thr, int* flags,
                   unsigned long long* counter);
-// Packs windows idx[0..nf) of a canvas batch into out [nf][H][H][C] and
-// their window indices into widx_out [nf][2].
-void launch_compact(hipStream_t st, const float* canvas, int canvas_w, const int* origins, const int* widx,
-                    const int* idx, int nf, int H, int C, float* out, int* widx_out);
 // slots[b] = W (x) (pos[b] < 0 ? ds[b] : fb[pos[b]]) for b < nwin.
 void launch_select(hipStream_t st, const float* ds, const float* fb, const int* pos, int nwin, int H, int C,
                    const float* w1d, float* const* slots);

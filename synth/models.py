@@ -22,7 +22,9 @@ workloads the method is measured on:
             consistency sampling at sigma 80 and 0.35; ``lgs`` is an analytic
             two-step model (prior std 0.7) whose teacher stand-in is ``lg``;
             ``st`` is a small network of the student's shape (32/32, windows
-            16) for gradient checks.
+            16) for gradient checks; ``c2n`` is a narrow teacher with the
+            student's channels and window layout (16/32, K = 2), small
+            enough for the oracle to sample its fallbacks in seconds.
 
 Initialisation: every tensor is Gaussian from numpy's PCG64 seeded with the
 given seed, drawn in file order.  Conv / linear weights ~ N(0, 1/fan_in);
@@ -102,6 +104,13 @@ CONFIGS["st"] = {   # a small student-shaped network for gradient checks
                  "emb_mult": 4, "pe_max_period": 10000.0},
     "sampler": dict(CONSISTENCY_2),
     "window": {"size": 16, "stride": 8, "offset": 0, "eps": 0.01},
+}
+CONFIGS["c2n"] = {   # a narrow teacher of the student's layout (judge parity)
+    "denoiser": {"kind": "unet", "in_channels": 4, "channels": [16, 32], "num_res_blocks": 1,
+                 "attn_levels": [], "mid_attn": False, "num_heads": 1, "gn_groups": 8, "gn_eps": 1e-5,
+                 "emb_mult": 4, "pe_max_period": 10000.0},
+    "sampler": dict(SAMPLER_EDM, steps=2),
+    "window": {"size": 64, "stride": 32, "offset": 0, "eps": 0.01},
 }
 CONFIGS["lgs"] = {
     "denoiser": {"kind": "linear_gaussian", "in_channels": 4, "prior_std": 0.7},

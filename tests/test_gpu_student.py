@@ -102,8 +102,10 @@ def test_unet_student_matches_oracle(ctxs, weights):
 
 
 def test_unet_student_with_teacher_judge_matches_oracle(ctxs, weights):
-    c, t = ctxs("s2"), ctxs("c2")
-    m2, thr, ref = judged_reference(weights, "s2", "c2", 1, (7, 7, 16, 16))
+    """Mixed fallbacks: the flagged windows take the narrow teacher's plain
+    J_0 on their regions (the oracle samples each one)."""
+    c, t = ctxs("s2"), ctxs("c2n")
+    m2, thr, ref = judged_reference(weights, "s2", "c2n", 1, (7, 7, 16, 16))
     c.set_judge(t, thr)
     c.cache_clear()
     try:
@@ -113,6 +115,31 @@ def test_unet_student_with_teacher_judge_matches_oracle(ctxs, weights):
         c.set_judge(None, 0.0)
     assert rel_l2(got, ref) <= 1e-4
     assert st["judge_fallbacks"] == m2.fallbacks
+    assert 0 < m2.fallbacks < m2.phi_calls
+
+
+@pytest.mark.parametrize("student,teacher,region", [("s2", "c2", (-40, 77, 70, 52)),
+                                                    ("lgs", "lg", (1000003, -29, 41, 37))])
+def test_threshold_zero_is_teacher_plain_sample(ctxs, student, teacher, region):
+    """Threshold 0: every window falls back at both steps, so the judged
+    student's J_0 is the teacher's plain J_0 (the 20-step C2 sampler for s2)
+    and its J_1 that plus 0.35 G on counter word 1."""
+    from oracle import noise as onoise
+    c, t = ctxs(student), ctxs(teacher)
+    want0 = t.sample_region(6, *region, 0)
+    c.set_judge(t, 0.0)
+    c.cache_clear()
+    try:
+        got0 = c.sample_region(6, *region, 0)
+        st = c.cache_stats()
+        c.cache_clear()
+        got1 = c.sample_region(6, *region, 1)
+    finally:
+        c.set_judge(None, 0.0)
+    assert st["judge_fallbacks"] == st["misses"] > 0
+    assert rel_l2(got0, want0) <= 1e-6
+    g1 = planar(onoise.noise_region(6, region[0], region[1], region[2], region[3], 4, step=1))
+    assert rel_l2(got1, want0 + np.float32(0.35) * g1) <= 1e-6
 
 
 def test_student_seed_consistency_bit_exact(ctxs):
