@@ -232,6 +232,24 @@ td_status td_lap_decode(td_ctx *ctx, const float *latent_dev, int64_t lx0,
                         int64_t Y0, int32_t W, int32_t H, float *out_dev,
                         void *hip_stream);
 
+/* td_lap_decode without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): same arguments, kernels and results, but its
+ * scratch is a fixed 16 MiB array per GPU, set up by td_create, instead of
+ * the context's grown buffer.  The decode needs 2 n_x n_y floats of it,
+ * n_x by n_y being the latent pixels the region's low band spans plus the
+ * 15-pixel blur radius on each side (about W/8 + 32 by H/8 + 32); the array
+ * holds 2^22 floats.  Every square region the library accepts (up to 2^26
+ * px) fits; a long strip may not (2^20 x 64 px needs 2 x 5.2 M floats), and
+ * then the call gives TD_E_INVAL and launches nothing.  Per-launch timing is
+ * not recorded.  Every call on one GPU shares that GPU's array (it keeps
+ * the last call's contents; the decode writes all of it before reading):
+ * calls that overlap on one GPU, on any streams or contexts, race and must
+ * be ordered by the caller. */
+td_status td_lap_decode_noalloc(td_ctx *ctx, const float *latent_dev, int64_t lx0, int64_t ly0, int32_t lw,
+                                int32_t lh, int64_t X0, int64_t Y0, int32_t W, int32_t H, float *out_dev,
+                                void *hip_stream);
+
 /* Laplacian encode (Sec. 5.2; the inverse construction the decode undoes):
  * elevation height_dev [H][W] float32 on the 8-aligned full-resolution
  * region [X0, X0+W) x [Y0, Y0+H) -> z = sign(h) sqrt|h|, L = G5 * down8(z)

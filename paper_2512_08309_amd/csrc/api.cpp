@@ -811,7 +811,7 @@ Region decode_apron(const ModelDesc& d, const Region& full) {
   return Region{xl - R - 1, yl - R - 1, xh - xl + 2 * R + 3, yh - yl + 2 * R + 3};
 }
 
-void decode_into(td_ctx* c, const float* latent, const Region& lat, const Region& full, float* out, hipStream_t st) {
+DecodeArgs decode_args(td_ctx* c, const float* latent, const Region& lat, const Region& full, float* out) {
   const ModelDesc& d = c->model->d;
   DecodeArgs a{};
   a.latent = latent;
@@ -830,6 +830,11 @@ void decode_into(td_ctx* c, const float* latent, const Region& lat, const Region
   a.taps = c->model->decode_taps();
   a.radius = d.blur_radius;
   a.atoms = c->model->decode_atoms();
+  return a;
+}
+
+void decode_into(td_ctx* c, const float* latent, const Region& lat, const Region& full, float* out, hipStream_t st) {
+  DecodeArgs a = decode_args(c, latent, lat, full, out);
   size_t wf = decode_work_floats(a);
   grow(c->dec, c->dec_cap, 2 * wf);
   a.work0 = c->dec;
@@ -999,6 +1004,7 @@ td_status td_create(int hip_device, td_ctx** out) {
     TD_HIP(hipEventCreateWithFlags(&c->done, hipEventDisableTiming));
     TD_HIP(hipEventCreateWithFlags(&c->xev, hipEventDisableTiming));
     TD_HIP(hipEventCreateWithFlags(&c->uev, hipEventDisableTiming));
+    init_decode_scratch(hip_device);
   });
   if (s != TD_OK) {
     td_destroy(c);
@@ -1389,6 +1395,37 @@ td_status td_lap_decode(td_ctx* c, const float* latent_dev, int64_t lx0, int64_t
     TD_CHECK(need.x0 >= lx0 && need.y0 >= ly0 && need.x0 + need.w <= lx0 + lw && need.y0 + need.h <= ly0 + lh,
              TD_E_INVAL, "latent does not cover the 17-pixel decode apron");
     decode_into(c, latent_dev, Region{lx0, ly0, lw, lh}, Region{X0, Y0, W, H}, out_dev, st);
+  });
+}
+
+td_status td_lap_decode_noalloc(td_ctx* c, const float* latent_dev, int64_t lx0, int64_t ly0, int32_t lw,
+                                int32_t lh, int64_t X0, int64_t Y0, int32_t W, int32_t H, float* out_dev,
+                                void* hip_stream) {
+  if (!c) return TD_E_INVAL;
+  return guarded(c, [&] {
+    g_prof = nullptr;   // per-launch timing would create events
+    need_model(c);
+    TD_CHECK(latent_dev && out_dev && lw > 0 && lh > 0, TD_E_INVAL, "bad arguments");
+    check_region(X0, Y0, W, H);
+    TD_HIP(hipSetDevice(c->device));
+    hipStream_t st = !hip_stream ? c->stream : hip_stream == TD_STREAM_DEFAULT ? nullptr : (hipStream_t)hip_stream;
+    if (c->pending) {
+      TD_HIP(hipEventSynchronize(c->done));
+      c->pending = false;
+    }
+    Region need = decode_apron(c->model->d, Region{X0, Y0, W, H});
+    TD_CHECK(need.x0 >= lx0 && need.y0 >= ly0 && need.x0 + need.w <= lx0 + lw && need.y0 + need.h <= ly0 + lh,
+             TD_E_INVAL, "latent does not cover the 17-pixel decode apron");
+    DecodeArgs a = decode_args(c, latent_dev, Region{lx0, ly0, lw, lh}, Region{X0, Y0, W, H}, out_dev);
+    const size_t wf = decode_work_floats(a);
+    TD_CHECK(2 * wf <= kDecodeScratchFloats, TD_E_INVAL,
+             "region too large for the fixed decode scratch: needs 2 x " + std::to_string(wf) + " floats, has " +
+                 std::to_string(kDecodeScratchFloats));
+    float* scratch = decode_scratch(c->device);
+    TD_CHECK(scratch, TD_E_STATE, "decode scratch not set up on this device");
+    a.work0 = scratch;   // both fully written by the decode before they are read
+    a.work1 = scratch + wf;
+    launch_decode(st, a);
   });
 }
 

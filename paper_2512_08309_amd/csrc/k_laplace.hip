@@ -18,6 +18,8 @@
 // the latent read once).
 #include "td_internal.h"
 
+#include <mutex>
+
 namespace td {
 namespace {
 
@@ -218,6 +220,33 @@ __global__ __launch_bounds__(256) void enc_res_kernel(const float* __restrict__ 
 }
 
 }  // namespace
+
+// Fixed decode scratch for callers that cannot allocate device memory
+// (td_lap_decode_noalloc): one array per GPU, whose device address is looked
+// up once per device.  In host code the array's name is not a device
+// address; only the looked-up pointer is passed to kernels.
+static __device__ __align__(256) float scratch[kDecodeScratchFloats];
+
+namespace {
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+void init_decode_scratch(int device) {
+  TD_CHECK(device >= 0 && device < kMaxDevices, -1, "device ordinal beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return;
+  void* p = nullptr;
+  TD_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));   // the current device's copy
+  TD_CHECK(p, -3, "decode scratch has no device address");
+  g_scratch_ptr[device] = static_cast<float*>(p);
+}
+
+float* decode_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 size_t decode_work_floats(const DecodeArgs& a) {
   Span s = span_of(a);

@@ -258,6 +258,13 @@ struct DecodeArgs {
   float* work1;
 };
 size_t decode_work_floats(const DecodeArgs& a);
+// The fixed decode scratch of a device (16 MiB): init_decode_scratch looks
+// up its address once per device (call with that device current);
+// decode_scratch returns it (null before).
+constexpr size_t kDecodeScratchFloats = (size_t)1 << 22;
+constexpr int kMaxDevices = 64;
+void init_decode_scratch(int device);
+float* decode_scratch(int device);
 void launch_decode(hipStream_t st, const DecodeArgs& a);
 
 // Laplacian encode of elevation on an 8-aligned region [H][W] into the latent

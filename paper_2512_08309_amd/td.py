@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "TD_OK", -1: "TD_E_INVAL", -2: "TD_E_NOMEM", -3: "TD_E_DEVICE
 EXPORTS = ["td_create", "td_destroy", "td_load_weights", "td_set_conditioning", "td_set_judge", "td_sample_region",
            "td_sample_region_async",
            "td_cache_set_budget", "td_cache_clear", "td_cache_stats", "td_cache_peek", "td_set_option",
-           "td_get_info", "td_denoise_windows", "td_denoise_steps", "td_noise_region", "td_lap_decode", "td_lap_encode", "td_kappa", "td_cone_windows", "td_kernel_stats",
+           "td_get_info", "td_denoise_windows", "td_denoise_steps", "td_noise_region", "td_lap_decode", "td_lap_decode_noalloc", "td_lap_encode", "td_kappa", "td_cone_windows", "td_kernel_stats",
            "td_server_create", "td_server_destroy", "td_server_submit", "td_server_progress", "td_server_poll",
            "td_server_stats", "td_last_error", "td_train_create", "td_train_destroy", "td_train_last_error",
            "td_train_param_count", "td_train_set_precision", "td_train_forward", "td_train_backward", "td_train_mse", "td_train_adamw"]
@@ -82,6 +82,7 @@ def _load():
         "td_noise_region": ([u64, i64, i64, i32, i32, i32, ctypes.c_uint32, ctypes.c_float, i32, vp, vp],
                             ctypes.c_int),
         "td_lap_decode": ([vp, vp, i64, i64, i32, i32, i64, i64, i32, i32, vp, vp], ctypes.c_int),
+        "td_lap_decode_noalloc": ([vp, vp, i64, i64, i32, i32, i64, i64, i32, i32, vp, vp], ctypes.c_int),
         "td_lap_encode": ([vp, vp, i64, i64, i32, i32, vp, sz, ctypes.POINTER(i64), vp], ctypes.c_int),
         "td_kappa": ([i64, i64, i64, i64, i32, i32, i32, ctypes.POINTER(i64)], ctypes.c_int),
         "td_cone_windows": ([i64, i64, i64, i64, i32, i32, i32, i32, i32, ctypes.POINTER(u64)], ctypes.c_int),
@@ -288,6 +289,17 @@ def td_lap_decode(ctx, latent_dev, lx0, ly0, X0, Y0, W, H, out_dev, stream=None)
     return out_dev
 
 
+def td_lap_decode_noalloc(ctx, latent_dev, lx0, ly0, X0, Y0, W, H, out_dev, stream=None):
+    """td_lap_decode with the GPU's fixed scratch (no device allocation)."""
+    if latent_dev.dim() != 3:
+        raise ValueError("latent_dev: expected [lh][lw][C]")
+    lh, lw = latent_dev.shape[0], latent_dev.shape[1]
+    pl = _dev(latent_dev, "latent_dev", (lh, lw, td_get_info(ctx, "channels")))
+    _check(ctx, lib.td_lap_decode_noalloc(ctx, pl, lx0, ly0, lw, lh, X0, Y0, W, H,
+                                          _dev(out_dev, "out_dev", numel=W * H), _stream(stream)))
+    return out_dev
+
+
 def td_lap_encode(ctx, height_dev, X0, Y0, W, H, out_dev=None, stream=None):
     """Geometry (ox0, oy0, ow, oh) of the latent the encode of the 8-aligned
     region writes; with out_dev (float32 [oh][ow][C] tensor) also the encode
@@ -445,6 +457,9 @@ class Context:
 
     def lap_decode(self, latent_dev, lx0, ly0, X0, Y0, W, H, out_dev, stream=None):
         return td_lap_decode(self.ctx, latent_dev, lx0, ly0, X0, Y0, W, H, out_dev, stream)
+
+    def lap_decode_noalloc(self, latent_dev, lx0, ly0, X0, Y0, W, H, out_dev, stream=None):
+        return td_lap_decode_noalloc(self.ctx, latent_dev, lx0, ly0, X0, Y0, W, H, out_dev, stream)
 
     def lap_encode(self, height_dev, X0, Y0, W, H, out_dev=None, stream=None):
         return td_lap_encode(self.ctx, height_dev, X0, Y0, W, H, out_dev, stream)
