@@ -74,6 +74,8 @@ def parse(argv=None):
     p.add_argument("--student-steps", type=int, default=150,
                    help="AdamW steps of the in-bench student distillation (0 = skip the student leg)")
     p.add_argument("--student-pairs", type=int, default=2048, help="teacher pairs of the in-bench distillation")
+    p.add_argument("--judge-thresholds", default="0.35,0.5,1",
+                   help="further fallback thresholds of the judged student, timed while the budget allows")
     p.add_argument("--micro-only", action="store_true",
                    help="only the decode / noise micro-benchmarks (8192^2 heightfield, 8192^2 x 4 noise)")
     p.add_argument("--calib-copy-mib", type=int, default=0,
@@ -411,7 +413,7 @@ def timed_cold(ctx, torch, a, region, level, out, stream):
     return time.perf_counter() - t0, ctx.cache_stats()
 
 
-def student_leg(td, torch, teacher, teacher_path, student_init, a, region, level, out, ref32, stream, ms32):
+def student_leg(td, torch, teacher, teacher_path, student_init, a, region, level, out, ref32, stream, ms32, budget):
     """Distil the half-width two-step student from the 20-step teacher (a short
     run: a.student_pairs pairs, a.student_steps AdamW steps at batch 64, lr
     2e-4), then time the same cold query with it: alone, judged by the FP32
@@ -450,6 +452,21 @@ def student_leg(td, torch, teacher, teacher_path, student_init, a, region, level
                              "judge_fallbacks": st["judge_fallbacks"],
                              "rel_rmse_heightfield_vs_fp32_plain": rel(torch, out, ref32)}
                 print("[bench] %s done" % name, file=sys.stderr, flush=True)
+            # the threshold -> (fallback rate, error, speed) curve of the judge
+            curve = []
+            for thr in [float(v) for v in a.judge_thresholds.split(",") if v]:
+                sk = budget.skip(1.3 * ms32 * 1e-3 + 2.0)
+                if sk:
+                    curve.append(dict(sk, threshold=thr))
+                    continue
+                s.set_judge(teacher, thr)
+                dts, st = timed_cold(s, torch, a, region, level, out, stream)
+                curve.append({"threshold": thr, "ms_per_query": 1e3 * dts,
+                              "query_speedup_vs_fp32_plain": ms32 / (1e3 * dts),
+                              "fallback_rate": st["judge_fallbacks"] / max(st["misses"], 1),
+                              "rel_rmse_heightfield_vs_fp32_plain": rel(torch, out, ref32)})
+                print("[bench] judge threshold %g done" % thr, file=sys.stderr, flush=True)
+            res["student_judged_fp32_threshold_curve"] = curve
             s.set_judge(None, 0.0)
     res["note"] = ("random-init teacher and a short distillation: the student does not reach the 2e-2 heightfield "
                    "RMSE; its speed is measured at the error it has")
@@ -618,7 +635,7 @@ def main():
         else:
             print("[bench] student distillation", file=sys.stderr, flush=True)
             done["student"] = student_leg(td, torch, ctx, wpath, cached_weights("s2", wdir, 0), a, region, level,
-                                          out, ref32, stream, 1e3 * step_s)
+                                          out, ref32, stream, 1e3 * step_s, budget)
 
     if a.serve_queries > 0:
         sk = budget.skip(5.0 + (a.serve_queries / a.serve_rate_sustained if a.serve_rate_sustained > 0 else 0))

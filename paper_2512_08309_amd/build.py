@@ -17,7 +17,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 HIP_SOURCES = ["k_noise.hip", "k_blend.hip", "k_conv.hip", "k_conv_bf16.hip", "k_gn.hip", "k_misc.hip",
                "k_laplace.hip", "k_train.hip"]
-CPP_SOURCES = ["model.cpp", "api.cpp", "profile.cpp", "train.cpp"]
+CPP_SOURCES = ["header.cpp", "model.cpp", "api.cpp", "profile.cpp", "train.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

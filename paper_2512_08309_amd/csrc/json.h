@@ -8,7 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "td_internal.h"
+#include "td_error.h"
 
 namespace td {
 

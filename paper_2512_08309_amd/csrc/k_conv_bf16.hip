@@ -32,6 +32,7 @@
 // LDS ring (global_load_lds_dwordx4), two stages ahead of the MFMAs; see
 // conv_bf16_dl_kernel.
 #include <type_traits>
+#include <utility>
 
 #include "td_internal.h"
 
@@ -450,6 +451,240 @@ __global__ __launch_bounds__(256, MINB) void conv_bf16_dl_kernel(ConvLpArgs a, i
   }
 }
 
+
+template <int N>
+__device__ __forceinline__ void lgkm_wait4(u4v& a0, u4v& a1, u4v& a2, u4v& a3) {
+  asm volatile("s_waitcnt lgkmcnt(%4)" : "+v"(a0), "+v"(a1), "+v"(a2), "+v"(a3) : "n"(N));
+}
+
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+// ---------------------------------------------------------------------------
+// Halo-staged 3x3 convolution (square images of side 8..64, C_in % 32 == 0,
+// C_out % 128 == 0, BF16 weights) on v_mfma_f32_32x32x16_bf16.
+//
+// A workgroup computes 256 output pixels (whole rows of one image, or
+// whole 8x8 images) x 128 output channels.  For each 32-channel input chunk
+// stages the tile's halo -- its rows plus one above and below, its columns
+// plus the zero columns on either side -- into LDS once (loaded into
+// registers at the start of the previous chunk, written at its end), and
+// the nine taps read their A operands from that patch at shifted pixel
+// positions: each input element is staged once per chunk instead of once
+// per tap.
+//
+// The B operands (weights) do not go through LDS: they are stored at load
+// time in MFMA fragment order (conv_lp_frag_index) and loaded straight into
+// registers P K-steps ahead of their use.
+//
+// Four waves (2 x 2), each 128 pixels x 64 channels: 4 x 2 tiles of 32 x 32,
+// 8 MFMAs per 16-value K step against 4 LDS operand reads.  K runs chunk by
+// chunk, tap by tap within a chunk, in a fixed order: results do not depend
+// on the batch.
+//
+// LDS patch layout: halo pixel q holds its 32 chunk channels in 64 bytes at
+// byte 80 q (16 bytes of padding per pixel).  Eight consecutive pixels --
+// the lanes one LDS cycle serves -- then start at distinct 16-byte positions
+// of the 128-byte bank line, so operand reads are conflict free, and a tap
+// moves every lane's address by the same constant (an instruction offset).
+template <int L>
+struct HaloGeom {
+  static constexpr int W = 1 << L;
+  static constexpr int HW = W * W;
+  static constexpr int NI = HW >= 256 ? 1 : 256 / HW;        // images per tile
+  static constexpr int ROWS = HW >= 256 ? 256 / W : W;        // output rows per image
+  static constexpr int QW = W + 2, RH = ROWS + 2;             // halo width and rows
+  static constexpr int NQ = NI * RH * QW;                     // halo pixels
+  static constexpr int NINS = (5 * NQ + 63) / 64;             // 1 KB copies per chunk
+  static constexpr int NPL = (NINS + 3) / 4;                  // copies per wave
+};
+
+// 16 bytes of LDS read at a register address plus a constant offset (see
+// ds_read16 for why this is asm).
+template <int OFF>
+__device__ __forceinline__ u4v ds_read16_off(uint32_t addr) {
+  u4v v;
+  asm volatile("ds_read_b128 %0, %1 offset:%2" : "=v"(v) : "v"(addr), "n"(OFF));
+  return v;
+}
+
+// LDS writes done and every wave arrived, without waiting for outstanding
+// global loads (the weight prefetches).
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// f(std::integral_constant<int, r>) for r = 0 .. N-1, in order.
+template <class F, int... R>
+__device__ __forceinline__ void unroll_seq(F& f, std::integer_sequence<int, R...>) {
+  (f(std::integral_constant<int, R>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void unroll(F& f) {
+  unroll_seq(f, std::make_integer_sequence<int, N>{});
+}
+
+template <int L, int P>
+__global__ __launch_bounds__(256, 2) void conv_bf16_halo_kernel(ConvLpArgs a, int n_tiles_n) {
+  using G = HaloGeom<L>;
+  constexpr int W = G::W, QW = G::QW, RH = G::RH;
+  constexpr int TM = 4, TN = 2;                    // 32 x 32 tiles per wave
+  constexpr int SLOTS = G::NPL * 256;              // 16-byte slots per patch buffer
+  static_assert(18 % P == 0, "the B ring must divide the 18 K steps of a chunk");
+  __shared__ __attribute__((aligned(16))) u4v patch[2][SLOTS];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int bid = blockIdx.x, nblk = gridDim.x;
+  const int tile = ((nblk & 7) == 0) ? (bid & 7) * (nblk >> 3) + (bid >> 3) : bid;
+  const int tn = tile % n_tiles_n, tm = tile / n_tiles_n;
+  const int m0 = tm * 256, n0 = tn * 128;
+  const int M = a.nb << (2 * L);
+  const int cin = a.cin;
+  const int KB = 9 * cin / 16;                     // 16-value K blocks
+  const u4v* act = reinterpret_cast<const u4v*>(a.act);
+  const u4v* wf = reinterpret_cast<const u4v*>(a.wfrag);
+
+  // ---- halo slots owned by this thread: slot 64 (wave + 4 j) + lane, which
+  // is segment slot % 5 of halo pixel slot / 5 (segment 4 is padding; slots
+  // past the halo are loaded and stored too, as zeros, so that every wave
+  // issues the same loads with no branches around them).
+  // hoff: its 16-byte index in the activations at chunk 0, or ~0 for zeros.
+  const int b0 = m0 >> (2 * L);                    // first image of the tile
+  const int row0 = (G::NI == 1) ? ((m0 >> L) & (W - 1)) : 0;
+  uint32_t hoff[G::NPL];
+#pragma unroll
+  for (int j = 0; j < G::NPL; ++j) {
+    const int ins = wave + 4 * j;
+    const int slot = 64 * ins + lane;
+    const int q = slot / 5, seg = slot - 5 * q;
+    const int img = q / (RH * QW), rem = q - img * (RH * QW);
+    const int hy = rem / QW, hx = rem - hy * QW;
+    const int y = row0 + hy - 1, x = hx - 1, b = b0 + img;
+    const bool ok = ins < G::NINS && seg < 4 && q < G::NQ && b < a.nb && y >= 0 && y < W && x >= 0 && x < W;
+    hoff[j] = ok ? (uint32_t)((((size_t)b * W + y) * W + x) * (cin / 8) + seg) : ~0u;
+  }
+  u4v hreg[G::NPL];
+  typedef const __attribute__((address_space(1))) u4v gu4v;
+  gu4v* gact = (gu4v*)act;
+  gu4v* gzero = (gu4v*)in_sgprs(g_zero16);
+  auto load_halo = [&](int c0) {
+#pragma unroll
+    for (int j = 0; j < G::NPL; ++j) hreg[j] = *(hoff[j] != ~0u ? gact + ((size_t)hoff[j] + c0 / 8) : gzero);
+  };
+  auto store_halo = [&](int buf) {
+#pragma unroll
+    for (int j = 0; j < G::NPL; ++j) patch[buf][64 * (wave + 4 * j) + lane] = hreg[j];
+  };
+
+  // ---- A operands: tile i of this wave, lane pixel (lane & 31); the base
+  // is the up-left neighbour's byte address plus the lane's K group
+  uint32_t abase[TM];
+  const uint32_t pbase = lds_addr(&patch[0][0]);
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    const int pl = wm * 128 + 32 * i + (lane & 31);
+    const int img = pl >> (2 * L), y = (pl >> L) & (W - 1), x = pl & (W - 1);
+    abase[i] = pbase + 80 * ((img * RH + y) * QW + x) + 16 * (lane >> 5);
+  }
+
+  // ---- B fragments: block n32 = n0 / 32 + 2 wn + j, K block kb
+  const u4v* wrow[TN];
+#pragma unroll
+  for (int j = 0; j < TN; ++j) wrow[j] = wf + ((size_t)((n0 >> 5) + 2 * wn + j) * KB) * 64 + lane;
+  const int nchunk = cin / 32;
+  const int NS = nchunk * 18;
+  u4v bq[P][TN];
+  auto issue_b = [&](int slot, int step) {
+    // steps past the last one (last chunk only) load block 0, unused
+    const int ch = step / 18, r = step - 18 * ch;
+    const int kb = step < NS ? ((r >> 1) * cin + 32 * ch) / 16 + (r & 1) : 0;
+#pragma unroll
+    for (int j = 0; j < TN; ++j) bq[slot][j] = wrow[j][(size_t)kb * 64];
+  };
+
+  f16v acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+  load_halo(0);
+  store_halo(0);
+#pragma unroll
+  for (int s = 0; s < P; ++s) issue_b(s, s);
+  __syncthreads();
+
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int buf = ch & 1;
+    // the next chunk's halo (the last chunk reloads its own, unused: no
+    // branch around the loads)
+    load_halo(ch + 1 < nchunk ? 32 * (ch + 1) : 32 * ch);
+    const uint32_t boff = buf * (SLOTS * 16);
+    uint32_t ab[TM];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) ab[i] = abase[i] + boff;
+    // the A operands of step r + 1 are read while the MFMAs of step r run
+    auto read_a = [&](auto rc, u4v* av) {
+      constexpr int r = decltype(rc)::value;
+      constexpr int tap = r >> 1, half = r & 1;
+      constexpr int OFF = 80 * ((tap / 3) * QW + tap % 3) + 32 * half;
+#pragma unroll
+      for (int i = 0; i < TM; ++i) av[i] = ds_read16_off<OFF>(ab[i]);
+    };
+    u4v acur[TM], anext[TM];
+    read_a(std::integral_constant<int, 0>{}, acur);
+    auto step = [&](auto rc) {
+      constexpr int r = decltype(rc)::value;
+      if constexpr (r + 1 < 18) read_a(std::integral_constant<int, r + 1>{}, anext);
+      u4v bv[TN];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bv[j] = bq[r % P][j];
+      issue_b(r % P, 18 * ch + r + P);
+      // LDS reads complete in order: at most the next step's TM are pending
+      if constexpr (r + 1 < 18) lgkm_wait4<TM>(acur[0], acur[1], acur[2], acur[3]);
+      else lgkm_wait4<0>(acur[0], acur[1], acur[2], acur[3]);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8v, acur[i]),
+                                                              __builtin_bit_cast(bf8v, bv[j]), acc[i][j], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int i = 0; i < TM; ++i) acur[i] = anext[i];
+    };
+    unroll<18>(step);
+    // the next chunk's patch goes to the other buffer, which every wave
+    // finished reading before the previous barrier
+    store_halo(buf ^ 1);
+    lds_barrier();
+  }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // the unused last prefetches
+
+  // ---- epilogue: tile (i, j) register e holds row 8 (e / 4) + 4 (lane / 32)
+  // + e % 4, column lane % 32
+  const int kg = lane >> 5;
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const int n = n0 + 64 * wn + 32 * j + (lane & 31);
+    const float bias = a.bias ? a.bias[n] : 0.f;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int m = m0 + 128 * wm + 32 * i + 8 * (e >> 2) + 4 * kg + (e & 3);
+        if (m >= M) continue;
+        const size_t off = (size_t)m * a.cout + n;
+        float o = acc[i][j][e] + bias;
+        if (a.res) o += a.res[off];
+        a.out[off] = o;
+      }
+  }
+}
+
 template <int BM, int BN, int WM, int WN, int MINB>
 void launch_dl(hipStream_t st, const ConvLpArgs& a) {
   const int M = a.nb << (a.lh + a.lw);
@@ -458,6 +693,14 @@ void launch_dl(hipStream_t st, const ConvLpArgs& a) {
     hipLaunchKernelGGL((conv_bf16_dl_kernel<9, BM, BN, WM, WN, MINB>), dim3(mt * nt), dim3(256), 0, st, a, nt);
   else
     hipLaunchKernelGGL((conv_bf16_dl_kernel<1, BM, BN, WM, WN, MINB>), dim3(mt * nt), dim3(256), 0, st, a, nt);
+  TD_LAUNCHED();
+}
+
+template <int L>
+void launch_halo(hipStream_t st, const ConvLpArgs& a) {
+  const int M = a.nb << (2 * L);
+  const int mt = (M + 255) / 256, nt = a.cout / 128;
+  hipLaunchKernelGGL((conv_bf16_halo_kernel<L, 2>), dim3(mt * nt), dim3(256), 0, st, a, nt);
   TD_LAUNCHED();
 }
 
@@ -501,7 +744,13 @@ void launch_conv_lp(hipStream_t st, const ConvLpArgs& a) {
   // 605 vs 594 TFLOP/s on the 128-channel 64x64 layers; a 256-row tile at
   // two workgroups per CU measured 578).  1x1 convolutions keep the register-
   // staged kernel, which measured faster for them (322 vs 295 TFLOP/s).
-  if (fast && !a.w8 && a.taps == 9 && a.cout % 128 == 0) launch_dl<128, 128, 2, 2, 3>(st, a);
+  const bool halo = a.wfrag && !a.w8 && a.taps == 9 && a.lh == a.lw && a.lw >= 3 && a.lw <= 6 &&
+                    a.cin % 32 == 0 && a.cout % 128 == 0;
+  if (halo && a.lw == 6) launch_halo<6>(st, a);
+  else if (halo && a.lw == 5) launch_halo<5>(st, a);
+  else if (halo && a.lw == 4) launch_halo<4>(st, a);
+  else if (halo) launch_halo<3>(st, a);
+  else if (fast && !a.w8 && a.taps == 9 && a.cout % 128 == 0) launch_dl<128, 128, 2, 2, 3>(st, a);
   else if (fast && !a.w8 && a.taps == 9 && a.cout % 64 == 0) launch_dl<128, 64, 2, 2, 3>(st, a);
   else if (a.cout % 128 == 0) launch_lp_w<128, 2, 2>(st, a, fast);
   else if (a.cout % 64 == 0) launch_lp_w<64, 2, 2>(st, a, fast);

@@ -14,27 +14,6 @@
 
 namespace td {
 
-namespace {
-
-int ilog2(int v) {
-  int l = 0;
-  while ((1 << l) < v) ++l;
-  return (1 << l) == v ? l : -1;
-}
-
-std::vector<double> edm_sigmas(int K, double smax, double smin, double rho) {
-  std::vector<double> s;
-  if (K == 1) {
-    s = {smax, 0.0};
-    return s;
-  }
-  double a = std::pow(smax, 1.0 / rho), b = std::pow(smin, 1.0 / rho);
-  for (int k = 0; k < K; ++k) s.push_back(std::pow(a + (double)k / (K - 1) * (b - a), rho));
-  s.push_back(0.0);
-  return s;
-}
-
-}  // namespace
 
 Model::~Model() {
   for (void* p : allocs_) (void)hipFree(p);
@@ -74,6 +53,21 @@ const uint16_t* Model::upload_lp(const std::vector<float>& w, int co, int ci, in
       for (int t = 0; t < taps; ++t) r[(size_t)o * *kp + t * ci + i] = to_bf16(w[((size_t)o * ci + i) * taps + t]);
   void* p = nullptr;
   TD_HIP(hipMalloc(&p, std::max<size_t>(r.size(), 1) * sizeof(uint16_t)));
+  allocs_.push_back(p);
+  TD_HIP(hipMemcpy(p, r.data(), r.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+  return (const uint16_t*)p;
+}
+
+// File layout [co][ci][3][3] -> fragment order of the halo-staged 3x3 kernel
+// (conv_lp_frag_index), BF16.
+const uint16_t* Model::upload_frag(const std::vector<float>& w, int co, int ci) {
+  TD_CHECK(ci % 16 == 0 && co % 32 == 0, -5, "fragment-ordered weights need C_in % 16 == 0 and C_out % 32 == 0");
+  std::vector<uint16_t> r((size_t)co * 9 * ci);
+  for (int o = 0; o < co; ++o)
+    for (int i = 0; i < ci; ++i)
+      for (int t = 0; t < 9; ++t) r[conv_lp_frag_index(o, t * ci + i, ci)] = to_bf16(w[((size_t)o * ci + i) * 9 + t]);
+  void* p = nullptr;
+  TD_HIP(hipMalloc(&p, r.size() * sizeof(uint16_t)));
   allocs_.push_back(p);
   TD_HIP(hipMemcpy(p, r.data(), r.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
   return (const uint16_t*)p;
@@ -152,118 +146,9 @@ void Model::load(const std::string& path, hipStream_t st) {
   TD_CHECK(f.good(), -4, "cannot open weight file: " + path);
   std::stringstream ss;
   ss << f.rdbuf();
-  std::string raw = ss.str();
-  TD_CHECK(raw.size() >= 8 && raw.compare(0, 4, "TDW1") == 0, -5, "not a TDW1 weight file: " + path);
-  uint32_t n = 0;
-  std::memcpy(&n, raw.data() + 4, 4);
-  TD_CHECK((size_t)n + 8 <= raw.size(), -5, "weight file header truncated");
-  std::string htxt = raw.substr(8, n);
-  Json h = JsonParser(htxt).parse();
-  size_t data_start = (8 + (size_t)n + 63) / 64 * 64;
-
-  const Json& dn = h.at("denoiser");
-  d.kind = dn.at("kind").str();
-  d.C = (int)dn.at("in_channels").integer();
-  const Json& sp = h.at("sampler");
-  d.K = (int)sp.at("steps").integer();
-  d.consistency = sp.has("kind") && sp.at("kind").str() == "consistency";
-  if (sp.has("kind"))
-    TD_CHECK(d.consistency || sp.at("kind").str() == "edm", -5, "weight header: unknown sampler kind");
-  if (d.consistency) {
-    const auto& sg = sp.at("sigmas").arr();
-    TD_CHECK((int)sg.size() == d.K && d.K >= 1, -5, "weight header: consistency sigmas must number steps");
-    d.sched.clear();
-    for (const Json& v : sg) d.sched.push_back(v.num());
-    for (int k = 0; k < d.K; ++k)
-      TD_CHECK(d.sched[k] > 0 && std::isfinite(d.sched[k]) && (k == 0 || d.sched[k] < d.sched[k - 1]), -5,
-               "weight header: consistency sigmas must be positive and decreasing");
-    d.sched.push_back(0.0);
-    d.smax = d.sched[0];
-    d.smin = d.sched[d.K - 1];
-    d.rho = 1;
-    TD_CHECK(!sp.has("blend"), -5, "weight header: consistency sampling blends every step");
-  } else {
-    d.smax = sp.at("sigma_max").num();
-    d.smin = sp.at("sigma_min").num();
-    d.rho = sp.at("rho").num();
-  }
-  d.sigma_data = sp.at("sigma_data").num();
-  d.noise_step = 0;
-  if (sp.has("noise_step")) {
-    const int64_t ns = sp.at("noise_step").integer();
-    TD_CHECK(ns >= 0 && ns <= 0xffffffffLL, -5, "weight header: noise_step must be a 32-bit counter word");
-    d.noise_step = (uint32_t)ns;
-  }
-  d.Cc = d.cond_factor = 0;
-  if (h.has("cond")) {
-    const Json& cj = h.at("cond");
-    d.Cc = (int)cj.at("channels").integer();
-    d.cond_factor = (int)cj.at("factor").integer();
-    TD_CHECK(d.Cc >= 1 && d.Cc <= 4 && d.cond_factor >= 1 && d.cond_factor <= 64, -5,
-             "weight header: conditioning needs 1..4 channels and a factor in 1..64");
-  }
-  const Json& wn = h.at("window");
-  d.H = (int)wn.at("size").integer();
-  d.S = (int)wn.at("stride").integer();
-  d.O = (int)wn.at("offset").integer();
-  d.win_eps = wn.at("eps").num();
-  const Json& dc = h.at("decode");
-  d.factor = (int)dc.at("factor").integer();
-  d.sigma_low = dc.at("sigma_low").num();
-  d.sigma_res = dc.at("sigma_res").num();
-  d.blur_sigma = dc.at("blur_sigma").num();
-  d.blur_radius = (int)dc.at("blur_radius").integer();
-  TD_CHECK(d.C >= 1 && d.K >= 1 && d.K <= 64 && d.H >= 1 && d.S >= 1 && d.H <= 4096, -5,
-           "weight header: bad sampler/window constants");
-  TD_CHECK(d.factor == 8 && d.blur_radius >= 0 && d.blur_radius <= 64, -5, "weight header: unsupported decode");
-  TD_CHECK(d.smax > d.smin && d.smin > 0 && d.rho > 0 && d.sigma_data > 0, -5, "weight header: bad schedule");
-  // comparisons already refuse NaN; infinities are refused here, and the
-  // float constants that no comparison above covers get their ranges
-  TD_CHECK(std::isfinite(d.smax) && std::isfinite(d.rho) && std::isfinite(d.sigma_data), -5,
-           "weight header: schedule constants must be finite");
-  TD_CHECK(d.win_eps >= 0 && d.win_eps <= 1, -5, "weight header: window eps must be in [0, 1]");
-  TD_CHECK(d.sigma_low > 0 && std::isfinite(d.sigma_low) && d.sigma_res > 0 && std::isfinite(d.sigma_res) &&
-               d.blur_sigma > 0 && std::isfinite(d.blur_sigma),
-           -5, "weight header: decode scales must be positive and finite");
-  if (!d.consistency) d.sched = edm_sigmas(d.K, d.smax, d.smin, d.rho);
-  // a re-noised level adds noise to every pixel, which needs every pixel covered
-  TD_CHECK(!d.consistency || d.S <= d.H, -5, "weight header: consistency sampling needs stride <= window size");
-  d.points.clear();
-  if (sp.has("blend")) {
-    for (const Json& b : sp.at("blend").arr()) d.points.push_back((int)b.integer());
-  } else {
-    for (int k = 0; k <= d.K; ++k) d.points.push_back(k);
-  }
-  TD_CHECK(d.points.size() >= 2 && d.points.front() == 0 && d.points.back() == d.K, -5,
-           "weight header: blend points must run from 0 to steps");
-  for (size_t i = 1; i < d.points.size(); ++i)
-    TD_CHECK(d.points[i] > d.points[i - 1], -5, "weight header: blend points must increase");
-  d.T = (int)d.points.size() - 1;
-
-  // tensors
-  std::map<std::string, std::vector<float>> host;
-  std::map<std::string, std::vector<int>> shapes;
-  if (h.has("tensors")) {
-    for (const Json& e : h.at("tensors").arr()) {
-      std::vector<int> shp;
-      size_t cnt = 1;
-      for (const Json& x : e.at("shape").arr()) {
-        long long v = x.integer();
-        TD_CHECK(v >= 0 && v < (1LL << 31), -5, "weight header: bad tensor shape");
-        TD_CHECK(v == 0 || cnt <= ((size_t)1 << 32) / (size_t)v, -5, "weight header: tensor too large");
-        shp.push_back((int)v);
-        cnt *= (size_t)v;
-      }
-      long long off = e.at("offset").integer();
-      TD_CHECK(off >= 0 && data_start + (size_t)off + cnt * 4 <= raw.size(), -5,
-               "weight file truncated at tensor " + e.at("name").str());
-      std::vector<float> v(cnt);
-      std::memcpy(v.data(), raw.data() + data_start + off, cnt * 4);
-      host[e.at("name").str()] = std::move(v);
-      shapes[e.at("name").str()] = shp;
-      d.params += cnt;
-    }
-  }
+  WeightFile wf;
+  parse_weight_file(ss.str(), path, &wf);
+  d = wf.d;
 
   // window weights w(u) = eps + (1-eps)(1 - |2u-(H-1)|/(H-1))  (Sec. 6 setup)
   std::vector<float> w1(d.H);
@@ -299,28 +184,7 @@ void Model::load(const std::string& path, hipStream_t st) {
     atoms_ = (float*)upload(at);
   }
 
-  if (d.kind == "linear_gaussian") {
-    d.prior_std = dn.at("prior_std").num();
-    TD_CHECK(d.prior_std > 0 && std::isfinite(d.prior_std), -5, "weight header: prior_std must be positive");
-  } else if (d.kind == "unet") {
-    for (const Json& c : dn.at("channels").arr()) d.ch.push_back((int)c.integer());
-    d.nres = (int)dn.at("num_res_blocks").integer();
-    for (const Json& a : dn.at("attn_levels").arr()) d.attn_levels.push_back((int)a.integer());
-    d.mid_attn = dn.at("mid_attn").boolean();
-    d.heads = (int)dn.at("num_heads").integer();
-    d.groups = (int)dn.at("gn_groups").integer();
-    d.gn_eps = (float)dn.at("gn_eps").num();
-    d.emb_mult = (int)dn.at("emb_mult").integer();
-    d.pe_max_period = dn.at("pe_max_period").num();
-    TD_CHECK(!d.ch.empty() && d.nres >= 1 && d.heads >= 1 && d.groups >= 1, -5, "weight header: bad UNet");
-    TD_CHECK(d.gn_eps > 0 && std::isfinite(d.gn_eps) && d.pe_max_period > 0 && std::isfinite(d.pe_max_period), -5,
-             "weight header: gn_eps and pe_max_period must be positive and finite");
-    TD_CHECK(ilog2(d.H) >= 4 && (d.H >> (d.ch.size() - 1)) >= 1, -5,
-             "UNet windows must be a power of two >= 16 and divisible by 2^(levels-1)");
-    build_unet(host, shapes, st);
-  } else {
-    throw Error{-5, "unknown denoiser kind: " + d.kind};
-  }
+  if (d.kind == "unet") build_unet(wf.host, wf.shapes, st);
   TD_HIP(hipStreamSynchronize(st));
 }
 
@@ -388,6 +252,10 @@ void Model::build_unet(const std::map<std::string, std::vector<float>>& host,
     w.b2 = vec(p + "conv2.bias", cout);
     w.w1_lp = lp(p + "conv1.weight", cout, cin, 3, &w.kp1);
     w.w2_lp = lp(p + "conv2.weight", cout, cout, 3, &w.kp2);
+    if (cout % 128 == 0) {
+      if (cin % 32 == 0) w.w1_fr = upload_frag(get(p + "conv1.weight", {cout, cin, 3, 3}), cout, cin);
+      if (cout % 32 == 0) w.w2_fr = upload_frag(get(p + "conv2.weight", {cout, cout, 3, 3}), cout, cout);
+    }
     w.w1_8 = f8(p + "conv1.weight", cout, cin, 3, &w.s1_8);
     w.w2_8 = f8(p + "conv2.weight", cout, cout, 3, &w.s2_8);
     w.has_skip = cin != cout;
@@ -647,7 +515,7 @@ void Model::gn_apply(hipStream_t st, const float* s0, int c0, int up0, const flo
 
 void Model::conv_lp(hipStream_t st, const uint16_t* act, int cin, int nb, int lr, int cout, int taps,
                     const uint16_t* wt, const uint8_t* w8, const float* w8s, int kp, const float* bias,
-                    const float* res, float* out) {
+                    const float* res, float* out, const uint16_t* wfrag) {
   ConvLpArgs a{};
   if (prec_ == 2) {
     a.wt = w8;
@@ -655,6 +523,7 @@ void Model::conv_lp(hipStream_t st, const uint16_t* act, int cin, int nb, int lr
     a.wscale = w8s;
   } else {
     a.wt = wt;
+    a.wfrag = wfrag;
   }
   a.act = act;
   a.cin = cin;
@@ -715,7 +584,7 @@ void Model::resblock(hipStream_t st, const ResBlockW& w, int k, const float* s0,
   if (prec_) {
     const float* bias1 = bias_eff_ + w.bias_off + (size_t)k * w.cout;
     gn_apply(st, s0, c0, up0, s1, c1, nb, lr, w.gn1_g, w.gn1_b, 2, B.A, nullptr);
-    conv_lp(st, B.A, w.cin, nb, lr, w.cout, 9, w.w1_lp, w.w1_8, w.s1_8, w.kp1, bias1, nullptr, B.T);
+    conv_lp(st, B.A, w.cin, nb, lr, w.cout, 9, w.w1_lp, w.w1_8, w.s1_8, w.kp1, bias1, nullptr, B.T, w.w1_fr);
     const float* res = s0;
     if (w.has_skip) {
       apply(st, s0, c0, up0, s1, c1, 0, nb, lr, B.A0);
@@ -725,7 +594,7 @@ void Model::resblock(hipStream_t st, const ResBlockW& w, int k, const float* s0,
       TD_CHECK(c1 == 0 && !up0, -5, "identity skip needs a plain input");
     }
     gn_apply(st, B.T, w.cout, 0, nullptr, 0, nb, lr, w.gn2_g, w.gn2_b, 2, B.A, nullptr);
-    conv_lp(st, B.A, w.cout, nb, lr, w.cout, 9, w.w2_lp, w.w2_8, w.s2_8, w.kp2, w.b2, res, out);
+    conv_lp(st, B.A, w.cout, nb, lr, w.cout, 9, w.w2_lp, w.w2_8, w.s2_8, w.kp2, w.b2, res, out, w.w2_fr);
     return;
   }
   // FP32: GroupNorm + SiLU are applied once per input element into F, not

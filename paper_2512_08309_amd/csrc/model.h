@@ -6,48 +6,10 @@
 #include <string>
 #include <vector>
 
+#include "header.h"
 #include "td_internal.h"
 
 namespace td {
-
-struct ModelDesc {
-  std::string kind;        // "unet" or "linear_gaussian"
-  int C = 0;               // latent channels
-  // UNet
-  std::vector<int> ch;
-  int nres = 0;
-  std::vector<int> attn_levels;
-  bool mid_attn = false;
-  int heads = 1, groups = 1, emb_mult = 4;
-  float gn_eps = 1e-5f;
-  double pe_max_period = 10000.0;
-  // analytic denoiser
-  double prior_std = 0.5;
-  // hierarchy: conditioning channels read from a parent model's final
-  // latent, nearest-upsampled by cond_factor (0 channels: unconditioned)
-  int Cc = 0, cond_factor = 0;
-  uint32_t noise_step = 0;    // counter word of this model's J_T noise
-  // sampler: EDM Euler, or few-step consistency sampling (Phi = D, the
-  // next level re-noised with G on counter word k + 1 at the blend)
-  bool consistency = false;
-  int K = 0;
-  double smax = 80, smin = 0.002, rho = 7, sigma_data = 0.5;
-  std::vector<double> sched;  // sigma_0..sigma_{K-1}, 0
-  std::vector<int> points;    // blend points b_0 = 0 < ... < b_T = K (schedule indices)
-  int T = 0;                  // blend levels (= K unless truncated)
-  // windows
-  int H = 0, S = 0, O = 0;
-  double win_eps = 0.01;
-  // decode
-  int factor = 8, blur_radius = 15;
-  double sigma_low = 20, sigma_res = 2, blur_sigma = 5;
-  size_t params = 0;
-  bool attn_at(int l) const {
-    for (int a : attn_levels)
-      if (a == l) return true;
-    return false;
-  }
-};
 
 struct ResBlockW {
   int cin = 0, cout = 0;
@@ -59,6 +21,9 @@ struct ResBlockW {
   // reduced precision: [cout][kp] BF16 weights (K = tap * cin + c_in)
   const uint16_t *w1_lp = nullptr, *w2_lp = nullptr, *wskip_lp = nullptr;
   int kp1 = 0, kp2 = 0, kps = 0;
+  // the 3x3 weights again in MFMA fragment order (null where the halo-staged
+  // kernel does not apply)
+  const uint16_t *w1_fr = nullptr, *w2_fr = nullptr;
   // FP8 e4m3 weights, same layout, with per-output-channel scales
   const uint8_t *w1_8 = nullptr, *w2_8 = nullptr, *wskip_8 = nullptr;
   const float *s1_8 = nullptr, *s2_8 = nullptr, *sskip_8 = nullptr;
@@ -184,11 +149,12 @@ class Model {
   float* dalloc(size_t n);
   const float* upload(const std::vector<float>& v);
   const uint16_t* upload_lp(const std::vector<float>& w, int co, int ci, int k, int* kp);
+  const uint16_t* upload_frag(const std::vector<float>& w, int co, int ci);
   const uint8_t* upload_fp8(const std::vector<float>& w, int co, int ci, int k, const float** scale);
   int cin_max(int lvl) const;
   void conv_lp(hipStream_t st, const uint16_t* act, int cin, int nb, int lr, int cout, int taps,
                const uint16_t* wt, const uint8_t* w8, const float* w8s, int kp, const float* bias,
-               const float* res, float* out);
+               const float* res, float* out, const uint16_t* wfrag = nullptr);
   void apply(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int act, int nb,
              int lr, uint16_t* out, float* out32 = nullptr);
   void gn_apply(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int nb, int lr,

@@ -8,14 +8,11 @@
 #include <string>
 #include <vector>
 
+#include "td_error.h"
+
 namespace td {
 
 // ---------------------------------------------------------------- errors --
-
-struct Error {
-  int status;
-  std::string msg;
-};
 
 #define TD_HIP(expr)                                                          \
   do {                                                                        \
@@ -24,11 +21,6 @@ struct Error {
       throw ::td::Error{e_ == hipErrorOutOfMemory ? -2 : -3,                  \
                         std::string(#expr) + ": " + hipGetErrorString(e_)};   \
     }                                                                         \
-  } while (0)
-
-#define TD_CHECK(cond, status, msg)                                           \
-  do {                                                                        \
-    if (!(cond)) throw ::td::Error{(status), (msg)};                          \
   } while (0)
 
 // Row count of a batched convolution, windows x pixels: the kernels index
@@ -151,8 +143,21 @@ struct ConvLpArgs {
   const float* bias;     // [cout]
   const float* res;      // [nb][h][w][cout] FP32 or null
   float* out;            // [nb][h][w][cout] FP32
+  // 3x3 BF16 weights in MFMA fragment order (conv_lp_frag_index), or null;
+  // used for square images of side 8..64 with C_in % 32 == 0 and
+  // C_out % 128 == 0
+  const void* wfrag;
 };
 void launch_conv_lp(hipStream_t st, const ConvLpArgs& a);
+// Element index, in the fragment-ordered weights of a 3x3 convolution, of
+// output channel o and K index k = tap * cin + c_in: for output block o / 32
+// and K block k / 16, the 64 lanes' 8-value B operands of
+// v_mfma_f32_32x32x16_bf16 back to back (lane L: column L % 32, K values
+// 8 (L / 32) .. + 7 of the block).
+inline size_t conv_lp_frag_index(int o, int k, int cin) {
+  const int kb = k / 16, r = k % 16, lane = (o % 32) + 32 * (r / 8);
+  return (((size_t)(o / 32) * (9 * cin / 16) + kb) * 64 + lane) * 8 + r % 8;
+}
 // K padding a weight matrix for launch_conv_lp needs.
 inline int conv_lp_kp(int taps, int cin) { return (taps * cin + 31) / 32 * 32; }
 
