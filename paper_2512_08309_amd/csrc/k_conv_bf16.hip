@@ -461,7 +461,8 @@ typedef float f16v __attribute__((ext_vector_type(16)));
 
 // ---------------------------------------------------------------------------
 // Halo-staged 3x3 convolution (square images of side 8..64, C_in % 32 == 0,
-// C_out % 128 == 0, BF16 weights) on v_mfma_f32_32x32x16_bf16.
+// C_out % 128 == 0, BF16 weights) on v_mfma_f32_32x32x16_bf16; the same
+// kernel with TAPS = 1 and no halo border runs the 1x1 convolutions.
 //
 // A workgroup computes 256 output pixels (whole rows of one image, or
 // whole 8x8 images) x 128 output channels.  For each 32-channel input chunk
@@ -486,13 +487,14 @@ typedef float f16v __attribute__((ext_vector_type(16)));
 // the lanes one LDS cycle serves -- then start at distinct 16-byte positions
 // of the 128-byte bank line, so operand reads are conflict free, and a tap
 // moves every lane's address by the same constant (an instruction offset).
-template <int L>
+template <int L, int TAPS>
 struct HaloGeom {
   static constexpr int W = 1 << L;
   static constexpr int HW = W * W;
   static constexpr int NI = HW >= 256 ? 1 : 256 / HW;        // images per tile
   static constexpr int ROWS = HW >= 256 ? 256 / W : W;        // output rows per image
-  static constexpr int QW = W + 2, RH = ROWS + 2;             // halo width and rows
+  static constexpr int BORDER = TAPS == 9 ? 1 : 0;            // halo pixels on each side
+  static constexpr int QW = W + 2 * BORDER, RH = ROWS + 2 * BORDER;   // halo width and rows
   static constexpr int NQ = NI * RH * QW;                     // halo pixels
   static constexpr int NINS = (5 * NQ + 63) / 64;             // 1 KB copies per chunk
   static constexpr int NPL = (NINS + 3) / 4;                  // copies per wave
@@ -523,14 +525,20 @@ __device__ __forceinline__ void unroll(F& f) {
   unroll_seq(f, std::make_integer_sequence<int, N>{});
 }
 
-template <int L, int P>
+template <int L, int P, int TAPS>
 __global__ __launch_bounds__(256, 2) void conv_bf16_halo_kernel(ConvLpArgs a, int n_tiles_n) {
-  using G = HaloGeom<L>;
+  using G = HaloGeom<L, TAPS>;
+  constexpr int STEPS = 2 * TAPS;                  // 16-value K steps per 32-channel chunk
   constexpr int W = G::W, QW = G::QW, RH = G::RH;
   constexpr int TM = 4, TN = 2;                    // 32 x 32 tiles per wave
   constexpr int SLOTS = G::NPL * 256;              // 16-byte slots per patch buffer
-  static_assert(18 % P == 0, "the B ring must divide the 18 K steps of a chunk");
-  __shared__ __attribute__((aligned(16))) u4v patch[2][SLOTS];
+  static_assert(STEPS % P == 0, "the B ring must divide the K steps of a chunk");
+  // two patch buffers; after the main loop the same LDS holds the BF16
+  // output tile (256 rows of TROW bytes) and the GroupNorm exchange
+  constexpr int TROW = 272;                        // 256 bytes + 16: rows 4 apart fall on other banks
+  constexpr int TILE_BYTES = 256 * TROW, RED_BYTES = 2 * 2 * 32 * 2 * 8;
+  constexpr int LDS_SLOTS = (2 * SLOTS > (TILE_BYTES + RED_BYTES) / 16) ? 2 * SLOTS : (TILE_BYTES + RED_BYTES) / 16;
+  __shared__ __attribute__((aligned(16))) u4v lds[LDS_SLOTS];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
@@ -540,7 +548,7 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_halo_kernel(ConvLpArgs a, in
   const int m0 = tm * 256, n0 = tn * 128;
   const int M = a.nb << (2 * L);
   const int cin = a.cin;
-  const int KB = 9 * cin / 16;                     // 16-value K blocks
+  const int KB = TAPS * cin / 16;                  // 16-value K blocks
   const u4v* act = reinterpret_cast<const u4v*>(a.act);
   const u4v* wf = reinterpret_cast<const u4v*>(a.wfrag);
 
@@ -559,7 +567,7 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_halo_kernel(ConvLpArgs a, in
     const int q = slot / 5, seg = slot - 5 * q;
     const int img = q / (RH * QW), rem = q - img * (RH * QW);
     const int hy = rem / QW, hx = rem - hy * QW;
-    const int y = row0 + hy - 1, x = hx - 1, b = b0 + img;
+    const int y = row0 + hy - G::BORDER, x = hx - G::BORDER, b = b0 + img;
     const bool ok = ins < G::NINS && seg < 4 && q < G::NQ && b < a.nb && y >= 0 && y < W && x >= 0 && x < W;
     hoff[j] = ok ? (uint32_t)((((size_t)b * W + y) * W + x) * (cin / 8) + seg) : ~0u;
   }
@@ -573,13 +581,13 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_halo_kernel(ConvLpArgs a, in
   };
   auto store_halo = [&](int buf) {
 #pragma unroll
-    for (int j = 0; j < G::NPL; ++j) patch[buf][64 * (wave + 4 * j) + lane] = hreg[j];
+    for (int j = 0; j < G::NPL; ++j) lds[buf * SLOTS + 64 * (wave + 4 * j) + lane] = hreg[j];
   };
 
   // ---- A operands: tile i of this wave, lane pixel (lane & 31); the base
   // is the up-left neighbour's byte address plus the lane's K group
   uint32_t abase[TM];
-  const uint32_t pbase = lds_addr(&patch[0][0]);
+  const uint32_t pbase = lds_addr(&lds[0]);
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
     const int pl = wm * 128 + 32 * i + (lane & 31);
@@ -592,11 +600,11 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_halo_kernel(ConvLpArgs a, in
 #pragma unroll
   for (int j = 0; j < TN; ++j) wrow[j] = wf + ((size_t)((n0 >> 5) + 2 * wn + j) * KB) * 64 + lane;
   const int nchunk = cin / 32;
-  const int NS = nchunk * 18;
+  const int NS = nchunk * STEPS;
   u4v bq[P][TN];
   auto issue_b = [&](int slot, int step) {
     // steps past the last one (last chunk only) load block 0, unused
-    const int ch = step / 18, r = step - 18 * ch;
+    const int ch = step / STEPS, r = step - STEPS * ch;
     const int kb = step < NS ? ((r >> 1) * cin + 32 * ch) / 16 + (r & 1) : 0;
 #pragma unroll
     for (int j = 0; j < TN; ++j) bq[slot][j] = wrow[j][(size_t)kb * 64];
@@ -637,13 +645,13 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_halo_kernel(ConvLpArgs a, in
     read_a(std::integral_constant<int, 0>{}, acur);
     auto step = [&](auto rc) {
       constexpr int r = decltype(rc)::value;
-      if constexpr (r + 1 < 18) read_a(std::integral_constant<int, r + 1>{}, anext);
+      if constexpr (r + 1 < STEPS) read_a(std::integral_constant<int, r + 1>{}, anext);
       u4v bv[TN];
 #pragma unroll
       for (int j = 0; j < TN; ++j) bv[j] = bq[r % P][j];
-      issue_b(r % P, 18 * ch + r + P);
+      issue_b(r % P, STEPS * ch + r + P);
       // LDS reads complete in order: at most the next step's TM are pending
-      if constexpr (r + 1 < 18) lgkm_wait4<TM>(acur[0], acur[1], acur[2], acur[3]);
+      if constexpr (r + 1 < STEPS) lgkm_wait4<TM>(acur[0], acur[1], acur[2], acur[3]);
       else lgkm_wait4<0>(acur[0], acur[1], acur[2], acur[3]);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -656,7 +664,7 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_halo_kernel(ConvLpArgs a, in
 #pragma unroll
       for (int i = 0; i < TM; ++i) acur[i] = anext[i];
     };
-    unroll<18>(step);
+    unroll<STEPS>(step);
     // the next chunk's patch goes to the other buffer, which every wave
     // finished reading before the previous barrier
     store_halo(buf ^ 1);
@@ -665,23 +673,107 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_halo_kernel(ConvLpArgs a, in
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // the unused last prefetches
 
   // ---- epilogue: tile (i, j) register e holds row 8 (e / 4) + 4 (lane / 32)
-  // + e % 4, column lane % 32
+  // + e % 4, column lane % 32.  The output is stored as FP32 (plus the
+  // residual), or as BF16 through an LDS transpose so that each lane writes
+  // 16 contiguous bytes.  With a.stats, the GroupNorm sums of the output's
+  // FP32 values per (window, tile of the window, group) are formed in a
+  // fixed order: over the lane's rows (FP32), then in FP64 with the lane
+  // holding the other rows of its column, over the group's columns, and over
+  // the tile's two row halves (one window per tile when a window spans whole
+  // tiles).
   const int kg = lane >> 5;
+  const bool want_stats = a.stats != nullptr;
+  char* const otile = reinterpret_cast<char*>(lds);
+  double s1[TN][2], s2[TN][2];
 #pragma unroll
   for (int j = 0; j < TN; ++j) {
-    const int n = n0 + 64 * wn + 32 * j + (lane & 31);
+    const int nl = 64 * wn + 32 * j + (lane & 31), n = n0 + nl;
     const float bias = a.bias ? a.bias[n] : 0.f;
+    float f1[2] = {0.f, 0.f}, f2[2] = {0.f, 0.f};
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
-        const int m = m0 + 128 * wm + 32 * i + 8 * (e >> 2) + 4 * kg + (e & 3);
-        if (m >= M) continue;
-        const size_t off = (size_t)m * a.cout + n;
+        const int pr = 128 * wm + 32 * i + 8 * (e >> 2) + 4 * kg + (e & 3);
+        const int m = m0 + pr;
         float o = acc[i][j][e] + bias;
-        if (a.res) o += a.res[off];
-        a.out[off] = o;
+        if (a.out16) {
+          *reinterpret_cast<uint16_t*>(otile + pr * TROW + 2 * nl) = __builtin_bit_cast(uint16_t, (__bf16)o);
+        } else if (m < M) {
+          const size_t off = (size_t)m * a.cout + n;
+          if (a.res) o += a.res[off];
+          a.out[off] = o;
+        }
+        const int part = G::NI == 1 ? 0 : (i >> 1);   // 8x8 windows: rows of two windows
+        if (m < M) {
+          f1[part] += o;
+          f2[part] += o * o;
+        }
       }
+    s1[j][0] = f1[0];
+    s1[j][1] = f1[1];
+    s2[j][0] = f2[0];
+    s2[j][1] = f2[1];
+  }
+  if (a.out16) {
+    __syncthreads();
+    const int c16 = tid & 15;
+#pragma unroll 4
+    for (int k = 0; k < 16; ++k) {
+      const int pr = (tid >> 4) + 16 * k, m = m0 + pr;
+      if (m < M)
+        *reinterpret_cast<u4v*>(a.out16 + (size_t)m * a.cout + n0 + 8 * c16) =
+            *reinterpret_cast<const u4v*>(otile + pr * TROW + 16 * c16);
+    }
+  }
+  if (want_stats) {
+    const int gs = a.cout / a.groups;                // channels per group: 1..32, a power of two
+    const int slots = conv_lp_stat_slots(2 * L);
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        s1[j][p] += __shfl_xor(s1[j][p], 32);
+        s2[j][p] += __shfl_xor(s2[j][p], 32);
+        for (int off = 1; off < gs; off <<= 1) {
+          s1[j][p] += __shfl_xor(s1[j][p], off);
+          s2[j][p] += __shfl_xor(s2[j][p], off);
+        }
+      }
+    const bool writer = lane < 32 && (lane & (gs - 1)) == 0;
+    if (G::NI == 1) {
+      // the two row halves of the tile: wave wm = 1 hands its sums to wm = 0
+      double* red = reinterpret_cast<double*>(otile + TILE_BYTES);   // past the output tile
+      if (wm == 1 && writer)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          red[((wn * TN + j) * 32 + lane) * 2] = s1[j][0];
+          red[((wn * TN + j) * 32 + lane) * 2 + 1] = s2[j][0];
+        }
+      __syncthreads();
+      if (wm == 0 && writer) {
+        const int slot = (m0 >> 8) & (slots - 1);
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const int g = (n0 + 64 * wn + 32 * j + lane) / gs;
+          double* d = a.stats + (((size_t)b0 * slots + slot) * a.groups + g) * 2;
+          d[0] = s1[j][0] + red[((wn * TN + j) * 32 + lane) * 2];
+          d[1] = s2[j][0] + red[((wn * TN + j) * 32 + lane) * 2 + 1];
+        }
+      }
+    } else if (writer) {
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          const int b = b0 + 2 * wm + p;
+          if (b >= a.nb) continue;
+          const int g = (n0 + 64 * wn + 32 * j + lane) / gs;
+          double* d = a.stats + ((size_t)b * a.groups + g) * 2;
+          d[0] = s1[j][p];
+          d[1] = s2[j][p];
+        }
+    }
   }
 }
 
@@ -700,7 +792,8 @@ template <int L>
 void launch_halo(hipStream_t st, const ConvLpArgs& a) {
   const int M = a.nb << (2 * L);
   const int mt = (M + 255) / 256, nt = a.cout / 128;
-  hipLaunchKernelGGL((conv_bf16_halo_kernel<L, 2>), dim3(mt * nt), dim3(256), 0, st, a, nt);
+  if (a.taps == 9) hipLaunchKernelGGL((conv_bf16_halo_kernel<L, 2, 9>), dim3(mt * nt), dim3(256), 0, st, a, nt);
+  else hipLaunchKernelGGL((conv_bf16_halo_kernel<L, 2, 1>), dim3(mt * nt), dim3(256), 0, st, a, nt);
   TD_LAUNCHED();
 }
 
@@ -727,6 +820,15 @@ void launch_lp_w(hipStream_t st, const ConvLpArgs& a, bool fast) {
 
 }  // namespace
 
+bool conv_lp_fused_ok(const ConvLpArgs& a) {
+  const bool halo = a.wfrag && !a.w8 && a.lh == a.lw && a.lw >= 3 && a.lw <= 6 && a.cin % 32 == 0 &&
+                    a.cout % 128 == 0;
+  if (!halo || (a.out16 && a.res)) return false;
+  if (!a.stats) return true;
+  const int gs = a.groups > 0 && a.cout % a.groups == 0 ? a.cout / a.groups : 0;
+  return gs >= 1 && gs <= 32 && (gs & (gs - 1)) == 0;
+}
+
 void launch_conv_lp(hipStream_t st, const ConvLpArgs& a) {
   TD_CHECK(a.cin % 8 == 0 && a.cout % 16 == 0 && a.cout > 0, -5,
            "bf16 conv: needs C_in % 8 == 0 and C_out % 16 == 0");
@@ -744,8 +846,10 @@ void launch_conv_lp(hipStream_t st, const ConvLpArgs& a) {
   // 605 vs 594 TFLOP/s on the 128-channel 64x64 layers; a 256-row tile at
   // two workgroups per CU measured 578).  1x1 convolutions keep the register-
   // staged kernel, which measured faster for them (322 vs 295 TFLOP/s).
-  const bool halo = a.wfrag && !a.w8 && a.taps == 9 && a.lh == a.lw && a.lw >= 3 && a.lw <= 6 &&
-                    a.cin % 32 == 0 && a.cout % 128 == 0;
+  const bool halo = a.wfrag && !a.w8 && a.lh == a.lw && a.lw >= 3 && a.lw <= 6 && a.cin % 32 == 0 &&
+                    a.cout % 128 == 0;
+  TD_CHECK(!(a.out16 || a.stats) || conv_lp_fused_ok(a), -5,
+           "bf16 conv: a BF16 output or GroupNorm sums need the halo-staged kernel");
   if (halo && a.lw == 6) launch_halo<6>(st, a);
   else if (halo && a.lw == 5) launch_halo<5>(st, a);
   else if (halo && a.lw == 4) launch_halo<4>(st, a);
@@ -757,7 +861,7 @@ void launch_conv_lp(hipStream_t st, const ConvLpArgs& a) {
   else if (a.cout % 32 == 0) launch_lp_w<32, 4, 1>(st, a, fast);
   else launch_lp_w<16, 4, 1>(st, a, fast);
   prof_end(st, a.taps == 9 ? K_CONV3_LP : K_CONV1_LP, 2.0 * Md * a.cout * a.taps * a.cin,
-           2.0 * Md * a.cin + 2.0 * a.kp * a.cout + 4.0 * Md * a.cout * (a.res ? 2 : 1));
+           2.0 * Md * a.cin + 2.0 * a.kp * a.cout + (a.out16 ? 2.0 : 4.0) * Md * a.cout + (a.res ? 4.0 * Md * a.cout : 0.0));
 }
 
 }  // namespace td

@@ -168,6 +168,35 @@ __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
   }
 }
 
+// act(x * scale + shift) of a BF16 tensor, 8 channels per thread, into BF16.
+__global__ __launch_bounds__(256) void apply_bf16_kernel(const uint4* __restrict__ src, int C, const float* scale,
+                                                         const float* shift, int act, int lhw, size_t n,
+                                                         uint4* __restrict__ out) {
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const int q8 = C / 8;
+  const int c = 8 * (int)(e % q8);
+  const int b = (int)((e / q8) >> lhw);
+  const uint4 u = src[e];
+  const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+  const float* sc = scale + (size_t)b * C + c;
+  const float* sh = shift + (size_t)b * C + c;
+  uint32_t o[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    float v0 = __uint_as_float(w[k] << 16), v1 = __uint_as_float(w[k] & 0xffff0000u);
+    v0 = v0 * sc[2 * k] + sh[2 * k];
+    v1 = v1 * sc[2 * k + 1] + sh[2 * k + 1];
+    if (act == 2) {
+      v0 = silu_f(v0);
+      v1 = silu_f(v1);
+    }
+    o[k] = pack_bf16(v0, v1);
+  }
+  const uint4 r = {o[0], o[1], o[2], o[3]};
+  out[e] = r;
+}
+
 // GroupNorm of whole windows in one pass, for windows whose virtual input
 // (h * w * C_in elements) fits in the registers of one workgroup: the
 // workgroup of window b loads it once, reduces per-channel sums and sums of
@@ -311,6 +340,25 @@ void launch_apply(hipStream_t st, const ApplyArgs& a) {
   TD_LAUNCHED();
   const double el = 8.0 * n;
   prof_end(st, a.out32 ? K_APPLY32 : K_APPLY, 4.0 * el, el * ((a.out32 ? 4.0 : 2.0) + (a.up0 ? 4.0 * a.c1 / cin + 1.0 * a.c0 / cin : 4.0)));
+}
+
+void launch_apply_bf16(hipStream_t st, const uint16_t* src, int C, const float* scale, const float* shift, int act,
+                       int nb, int lh, int lw, uint16_t* out) {
+  TD_CHECK(C % 8 == 0 && act >= 1 && act <= 2, -5, "apply_bf16: channels must be multiples of 8");
+  const size_t n = ((size_t)nb << (lh + lw)) * (C / 8);
+  if (!n) return;
+  prof_begin(st);
+  hipLaunchKernelGGL(apply_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                     reinterpret_cast<const uint4*>(src), C, scale, shift, act, lh + lw, n, reinterpret_cast<uint4*>(out));
+  TD_LAUNCHED();
+  prof_end(st, K_APPLY, 32.0 * n, 32.0 * n);
+}
+
+void launch_gn_finalize(hipStream_t st, const GnArgs& a, int nchunk) {
+  TD_CHECK(nchunk >= 1 && nchunk <= 16 && (a.c0 + a.c1) % a.groups == 0, -5, "groupnorm finalize: bad partials");
+  if (!a.nb) return;
+  hipLaunchKernelGGL(gn_finalize_kernel, dim3(a.nb), dim3(256), 0, st, a, nchunk);
+  TD_LAUNCHED();
 }
 
 bool gn_apply_window_fits(int lh, int lw, int c0, int c1, int up0, int groups) {

@@ -58,14 +58,16 @@ const uint16_t* Model::upload_lp(const std::vector<float>& w, int co, int ci, in
   return (const uint16_t*)p;
 }
 
-// File layout [co][ci][3][3] -> fragment order of the halo-staged 3x3 kernel
-// (conv_lp_frag_index), BF16.
-const uint16_t* Model::upload_frag(const std::vector<float>& w, int co, int ci) {
+// File layout [co][ci][k][k] -> fragment order of the halo-staged kernel
+// (conv_lp_frag_index, K = k * k * ci), BF16.
+const uint16_t* Model::upload_frag(const std::vector<float>& w, int co, int ci, int k) {
   TD_CHECK(ci % 16 == 0 && co % 32 == 0, -5, "fragment-ordered weights need C_in % 16 == 0 and C_out % 32 == 0");
-  std::vector<uint16_t> r((size_t)co * 9 * ci);
+  const int taps = k * k;
+  std::vector<uint16_t> r((size_t)co * taps * ci);
   for (int o = 0; o < co; ++o)
     for (int i = 0; i < ci; ++i)
-      for (int t = 0; t < 9; ++t) r[conv_lp_frag_index(o, t * ci + i, ci)] = to_bf16(w[((size_t)o * ci + i) * 9 + t]);
+      for (int t = 0; t < taps; ++t)
+        r[conv_lp_frag_index(o, t * ci + i, taps * ci)] = to_bf16(w[((size_t)o * ci + i) * taps + t]);
   void* p = nullptr;
   TD_HIP(hipMalloc(&p, r.size() * sizeof(uint16_t)));
   allocs_.push_back(p);
@@ -253,8 +255,8 @@ void Model::build_unet(const std::map<std::string, std::vector<float>>& host,
     w.w1_lp = lp(p + "conv1.weight", cout, cin, 3, &w.kp1);
     w.w2_lp = lp(p + "conv2.weight", cout, cout, 3, &w.kp2);
     if (cout % 128 == 0) {
-      if (cin % 32 == 0) w.w1_fr = upload_frag(get(p + "conv1.weight", {cout, cin, 3, 3}), cout, cin);
-      if (cout % 32 == 0) w.w2_fr = upload_frag(get(p + "conv2.weight", {cout, cout, 3, 3}), cout, cout);
+      if (cin % 32 == 0) w.w1_fr = upload_frag(get(p + "conv1.weight", {cout, cin, 3, 3}), cout, cin, 3);
+      if (cout % 32 == 0) w.w2_fr = upload_frag(get(p + "conv2.weight", {cout, cout, 3, 3}), cout, cout, 3);
     }
     w.w1_8 = f8(p + "conv1.weight", cout, cin, 3, &w.s1_8);
     w.w2_8 = f8(p + "conv2.weight", cout, cout, 3, &w.s2_8);
@@ -263,6 +265,7 @@ void Model::build_unet(const std::map<std::string, std::vector<float>>& host,
       w.wskip = conv_layout(p + "skip.weight", cout, cin, 1);
       w.bskip = vec(p + "skip.bias", cout);
       w.wskip_lp = lp(p + "skip.weight", cout, cin, 1, &w.kps);
+      if (cout % 128 == 0 && cin % 32 == 0) w.wskip_fr = upload_frag(get(p + "skip.weight", {cout, cin, 1, 1}), cout, cin, 1);
       w.wskip_8 = f8(p + "skip.weight", cout, cin, 1, &w.sskip_8);
     }
     TD_CHECK(cin % d.groups == 0 && cout % d.groups == 0, -5, "GroupNorm groups must divide channels");
@@ -280,6 +283,10 @@ void Model::build_unet(const std::map<std::string, std::vector<float>>& host,
     w.bproj = vec(p + "proj.bias", C);
     w.wqkv_lp = lp(p + "qkv.weight", 3 * C, C, 1, &w.kpq);
     w.wproj_lp = lp(p + "proj.weight", C, C, 1, &w.kpp);
+    if (C % 128 == 0) {
+      w.wqkv_fr = upload_frag(get(p + "qkv.weight", {3 * C, C, 1, 1}), 3 * C, C, 1);
+      w.wproj_fr = upload_frag(get(p + "proj.weight", {C, C, 1, 1}), C, C, 1);
+    }
     w.wqkv_8 = f8(p + "qkv.weight", 3 * C, C, 1, &w.sqkv_8);
     w.wproj_8 = f8(p + "proj.weight", C, C, 1, &w.sproj_8);
     at_[p] = w;
@@ -539,6 +546,42 @@ void Model::conv_lp(hipStream_t st, const uint16_t* act, int cin, int nb, int lr
   launch_conv_lp(st, a);
 }
 
+bool Model::conv1_fused(hipStream_t st, const ResBlockW& w, const uint16_t* act, int nb, int lr, const float* bias,
+                        uint16_t* out16) {
+  if (prec_ != 1 || !w.w1_fr) return false;
+  ConvLpArgs a{};
+  a.act = act;
+  a.cin = w.cin;
+  a.nb = nb;
+  a.lh = lr;
+  a.lw = lr;
+  a.cout = w.cout;
+  a.taps = 9;
+  a.kp = w.kp1;
+  a.wt = w.w1_lp;
+  a.wfrag = w.w1_fr;
+  a.bias = bias;
+  a.out16 = out16;
+  a.stats = gn_part_;
+  a.groups = d.groups;
+  if (!conv_lp_fused_ok(a)) return false;
+  launch_conv_lp(st, a);
+  GnArgs g{};
+  g.c0 = w.cout;
+  g.nb = nb;
+  g.lh = lr;
+  g.lw = lr;
+  g.groups = d.groups;
+  g.eps = d.gn_eps;
+  g.gamma = w.gn2_g;
+  g.beta = w.gn2_b;
+  g.partial = gn_part_;
+  g.scale = gn_scale_;
+  g.shift = gn_shift_;
+  launch_gn_finalize(st, g, conv_lp_stat_slots(2 * lr));
+  return true;
+}
+
 void Model::apply(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int act, int nb, int lr,
                   uint16_t* out, float* out32) {
   ApplyArgs a{};
@@ -584,16 +627,22 @@ void Model::resblock(hipStream_t st, const ResBlockW& w, int k, const float* s0,
   if (prec_) {
     const float* bias1 = bias_eff_ + w.bias_off + (size_t)k * w.cout;
     gn_apply(st, s0, c0, up0, s1, c1, nb, lr, w.gn1_g, w.gn1_b, 2, B.A, nullptr);
-    conv_lp(st, B.A, w.cin, nb, lr, w.cout, 9, w.w1_lp, w.w1_8, w.s1_8, w.kp1, bias1, nullptr, B.T, w.w1_fr);
+    // conv1's output goes to GroupNorm 2 only: stored as BF16 with its
+    // statistics from the epilogue where the halo-staged kernel applies
+    uint16_t* T16 = reinterpret_cast<uint16_t*>(B.T);
+    const bool fused = conv1_fused(st, w, B.A, nb, lr, bias1, T16);
+    if (!fused) conv_lp(st, B.A, w.cin, nb, lr, w.cout, 9, w.w1_lp, w.w1_8, w.s1_8, w.kp1, bias1, nullptr, B.T, w.w1_fr);
     const float* res = s0;
     if (w.has_skip) {
       apply(st, s0, c0, up0, s1, c1, 0, nb, lr, B.A0);
-      conv_lp(st, B.A0, w.cin, nb, lr, w.cout, 1, w.wskip_lp, w.wskip_8, w.sskip_8, w.kps, w.bskip, nullptr, B.R);
+      conv_lp(st, B.A0, w.cin, nb, lr, w.cout, 1, w.wskip_lp, w.wskip_8, w.sskip_8, w.kps, w.bskip, nullptr, B.R,
+              w.wskip_fr);
       res = B.R;
     } else {
       TD_CHECK(c1 == 0 && !up0, -5, "identity skip needs a plain input");
     }
-    gn_apply(st, B.T, w.cout, 0, nullptr, 0, nb, lr, w.gn2_g, w.gn2_b, 2, B.A, nullptr);
+    if (fused) launch_apply_bf16(st, T16, w.cout, gn_scale_, gn_shift_, 2, nb, lr, lr, B.A);
+    else gn_apply(st, B.T, w.cout, 0, nullptr, 0, nb, lr, w.gn2_g, w.gn2_b, 2, B.A, nullptr);
     conv_lp(st, B.A, w.cout, nb, lr, w.cout, 9, w.w2_lp, w.w2_8, w.s2_8, w.kp2, w.b2, res, out, w.w2_fr);
     return;
   }
@@ -631,10 +680,10 @@ void Model::attention(hipStream_t st, const AttnW& w, const float* in, int nb, i
   LevelBufs& B = lb_[lvl];
   if (prec_) {
     gn_apply(st, in, w.C, 0, nullptr, 0, nb, lr, w.gn_g, w.gn_b, 1, B.A, nullptr);
-    conv_lp(st, B.A, w.C, nb, lr, 3 * w.C, 1, w.wqkv_lp, w.wqkv_8, w.sqkv_8, w.kpq, w.bqkv, nullptr, B.Q);
+    conv_lp(st, B.A, w.C, nb, lr, 3 * w.C, 1, w.wqkv_lp, w.wqkv_8, w.sqkv_8, w.kpq, w.bqkv, nullptr, B.Q, w.wqkv_fr);
     launch_attention(st, B.Q, B.O, nb, 1 << (2 * lr), w.C, d.heads);
     apply(st, B.O, w.C, 0, nullptr, 0, 0, nb, lr, B.A);
-    conv_lp(st, B.A, w.C, nb, lr, w.C, 1, w.wproj_lp, w.wproj_8, w.sproj_8, w.kpp, w.bproj, in, out);
+    conv_lp(st, B.A, w.C, nb, lr, w.C, 1, w.wproj_lp, w.wproj_8, w.sproj_8, w.kpp, w.bproj, in, out, w.wproj_fr);
     return;
   }
   gn(st, in, w.C, 0, nullptr, 0, nb, lr, lr, w.gn_g, w.gn_b);

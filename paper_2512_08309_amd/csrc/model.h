@@ -21,9 +21,9 @@ struct ResBlockW {
   // reduced precision: [cout][kp] BF16 weights (K = tap * cin + c_in)
   const uint16_t *w1_lp = nullptr, *w2_lp = nullptr, *wskip_lp = nullptr;
   int kp1 = 0, kp2 = 0, kps = 0;
-  // the 3x3 weights again in MFMA fragment order (null where the halo-staged
+  // the weights again in MFMA fragment order (null where the halo-staged
   // kernel does not apply)
-  const uint16_t *w1_fr = nullptr, *w2_fr = nullptr;
+  const uint16_t *w1_fr = nullptr, *w2_fr = nullptr, *wskip_fr = nullptr;
   // FP8 e4m3 weights, same layout, with per-output-channel scales
   const uint8_t *w1_8 = nullptr, *w2_8 = nullptr, *wskip_8 = nullptr;
   const float *s1_8 = nullptr, *s2_8 = nullptr, *sskip_8 = nullptr;
@@ -35,6 +35,7 @@ struct AttnW {
               *bproj = nullptr;
   const uint16_t *wqkv_lp = nullptr, *wproj_lp = nullptr;
   int kpq = 0, kpp = 0;
+  const uint16_t *wqkv_fr = nullptr, *wproj_fr = nullptr;   // MFMA fragment order
   const uint8_t *wqkv_8 = nullptr, *wproj_8 = nullptr;
   const float *sqkv_8 = nullptr, *sproj_8 = nullptr;
 };
@@ -149,12 +150,17 @@ class Model {
   float* dalloc(size_t n);
   const float* upload(const std::vector<float>& v);
   const uint16_t* upload_lp(const std::vector<float>& w, int co, int ci, int k, int* kp);
-  const uint16_t* upload_frag(const std::vector<float>& w, int co, int ci);
+  const uint16_t* upload_frag(const std::vector<float>& w, int co, int ci, int k);
   const uint8_t* upload_fp8(const std::vector<float>& w, int co, int ci, int k, const float** scale);
   int cin_max(int lvl) const;
   void conv_lp(hipStream_t st, const uint16_t* act, int cin, int nb, int lr, int cout, int taps,
                const uint16_t* wt, const uint8_t* w8, const float* w8s, int kp, const float* bias,
                const float* res, float* out, const uint16_t* wfrag = nullptr);
+  // conv1 of a BF16 residual block through the fused epilogue: BF16 output
+  // into out16 and the GroupNorm sums of gn2 into gn_part_; false (nothing
+  // launched) where the halo-staged kernel does not apply.
+  bool conv1_fused(hipStream_t st, const ResBlockW& w, const uint16_t* act, int nb, int lr, const float* bias,
+                   uint16_t* out16);
   void apply(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int act, int nb,
              int lr, uint16_t* out, float* out32 = nullptr);
   void gn_apply(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int nb, int lr,

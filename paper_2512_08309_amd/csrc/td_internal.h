@@ -143,20 +143,29 @@ struct ConvLpArgs {
   const float* bias;     // [cout]
   const float* res;      // [nb][h][w][cout] FP32 or null
   float* out;            // [nb][h][w][cout] FP32
-  // 3x3 BF16 weights in MFMA fragment order (conv_lp_frag_index), or null;
-  // used for square images of side 8..64 with C_in % 32 == 0 and
-  // C_out % 128 == 0
+  // BF16 weights in MFMA fragment order (conv_lp_frag_index), or null; used
+  // for square images of side 8..64 with C_in % 32 == 0 and C_out % 128 == 0
   const void* wfrag;
+  // Fused epilogue of that kernel only (conv_lp_fused_ok): out16 set stores
+  // the output as BF16 instead of out (no residual); stats set writes the
+  // output's GroupNorm sums (sum, sum of squares, FP64) per (window, tile of
+  // the window, group of C_out / groups channels) in the layout of the
+  // GroupNorm partials, with conv_lp_stat_slots(lh + lw) tiles per window.
+  uint16_t* out16;
+  double* stats;
+  int groups;
 };
 void launch_conv_lp(hipStream_t st, const ConvLpArgs& a);
-// Element index, in the fragment-ordered weights of a 3x3 convolution, of
-// output channel o and K index k = tap * cin + c_in: for output block o / 32
-// and K block k / 16, the 64 lanes' 8-value B operands of
-// v_mfma_f32_32x32x16_bf16 back to back (lane L: column L % 32, K values
+bool conv_lp_fused_ok(const ConvLpArgs& a);
+__host__ __device__ inline int conv_lp_stat_slots(int lhw) { return lhw > 8 ? 1 << (lhw - 8) : 1; }
+// Element index, in the fragment-ordered weights of a convolution with K =
+// taps * cin, of output channel o and K index k = tap * cin + c_in: for
+// output block o / 32 and K block k / 16, the 64 lanes' 8-value B operands
+// of v_mfma_f32_32x32x16_bf16 back to back (lane L: column L % 32, K values
 // 8 (L / 32) .. + 7 of the block).
-inline size_t conv_lp_frag_index(int o, int k, int cin) {
+inline size_t conv_lp_frag_index(int o, int k, int K) {
   const int kb = k / 16, r = k % 16, lane = (o % 32) + 32 * (r / 8);
-  return (((size_t)(o / 32) * (9 * cin / 16) + kb) * 64 + lane) * 8 + r % 8;
+  return (((size_t)(o / 32) * (K / 16) + kb) * 64 + lane) * 8 + r % 8;
 }
 // K padding a weight matrix for launch_conv_lp needs.
 inline int conv_lp_kp(int taps, int cin) { return (taps * cin + 31) / 32 * 32; }
@@ -176,6 +185,10 @@ struct ApplyArgs {
   float* out32;          // [nb][h][w][c0 + c1] FP32 (instead of out)
 };
 void launch_apply(hipStream_t st, const ApplyArgs& a);
+// act(x * scale + shift) of a BF16 tensor [nb][h][w][C] into BF16 (the
+// GroupNorm apply of a conv output stored as BF16).
+void launch_apply_bf16(hipStream_t st, const uint16_t* src, int C, const float* scale, const float* shift, int act,
+                       int nb, int lh, int lw, uint16_t* out);
 
 struct GnArgs {
   const float* src0;
@@ -194,6 +207,10 @@ struct GnArgs {
 };
 size_t gn_partial_doubles(int nb, int lh, int lw, int cin, int groups);
 void launch_gn(hipStream_t st, const GnArgs& a);
+// scale/shift (and mean/rstd when set) from partials already in a.partial
+// ([nb][nchunk][groups][2] sums and sums of squares), e.g. written by a
+// convolution's epilogue.
+void launch_gn_finalize(hipStream_t st, const GnArgs& a, int nchunk);
 // GroupNorm statistics and apply (+ SiLU for act 2; act 1 affine only) of
 // whole small windows in one pass, written as BF16 (out) or FP32 (out32);
 // the partial/scale/shift fields of g are not used.  Fits when the window's
