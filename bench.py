@@ -76,6 +76,9 @@ def parse(argv=None):
     p.add_argument("--student-pairs", type=int, default=2048, help="teacher pairs of the in-bench distillation")
     p.add_argument("--judge-thresholds", default="0.35,0.5,1",
                    help="further fallback thresholds of the judged student, timed while the budget allows")
+    p.add_argument("--query-only", type=int, default=-1, metavar="PRECISION",
+                   help="only one cold query of the workload at this precision (0 FP32, 1 BF16, 2 FP8 weights), "
+                        "for profiler runs")
     p.add_argument("--micro-only", action="store_true",
                    help="only the decode / noise micro-benchmarks (8192^2 heightfield, 8192^2 x 4 noise)")
     p.add_argument("--calib-copy-mib", type=int, default=0,
@@ -166,6 +169,28 @@ def start_cpu_legs(a, c1_path, c2_path, workdir):
     if a.no_cpu_baseline:
         cmd.append("--no-cpu-baseline")
     return subprocess.Popen(cmd, cwd=ROOT)
+
+
+def counter_traffic():
+    """HBM bytes per launch of the dominant kernel (FP32 3x3 conv) from the
+    committed counter summary, while the kernel source still matches the one
+    the counters were taken on; else None."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "conv3x3_f32_and_bf16_halo_hbm_counters.md")
+    src = os.path.join(ROOT, "paper_2512_08309_amd", "csrc", "k_conv.hip")
+    try:
+        rec = None
+        for line in open(prof):
+            if line.startswith("traffic_f32_conv3x3:"):
+                rec = json.loads(line.split(":", 1)[1])
+        if not rec:
+            return None
+        with open(src, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest()[:16] != rec["k_conv_sha256_16"]:
+                return None
+        return rec
+    except (OSError, ValueError, KeyError):
+        return None
 
 
 def cpu_baseline_entry(cpu):
@@ -492,7 +517,7 @@ def main():
     c2_path = cached_weights("c2", wdir, 0)
     tmp = tempfile.TemporaryDirectory()
     cpu_proc = None
-    if not a.micro_only and (not a.no_cpu_baseline or a.bf16_steps > 0):
+    if not a.micro_only and a.query_only < 0 and (not a.no_cpu_baseline or a.bf16_steps > 0):
         cpu_proc = start_cpu_legs(a, c1_path, c2_path, tmp.name)
 
     import torch
@@ -503,6 +528,15 @@ def main():
     ctx = td.Context(0).load_weights(wpath)
     if a.micro_only:
         print(json.dumps({"micro": micro_bench(td, torch, ctx)}))
+        ctx.close()
+        return
+    if a.query_only >= 0:
+        ctx.set_option("precision", a.query_only)
+        out = torch.empty((8 * a.size, 8 * a.size), dtype=torch.float32, device="cuda")
+        dtq, stq = timed_cold(ctx, torch, a, (8 * 13, 8 * -1000001, 8 * a.size, 8 * a.size), td.TD_LEVEL_HEIGHT, out,
+                              torch.cuda.current_stream())
+        print(json.dumps({"query_only": {"precision": a.query_only, "s": dtq, "windows": stq["misses"],
+                                         "window_denoises_per_s": stq["misses"] / dtq}}))
         ctx.close()
         return
     if a.batch:
@@ -688,6 +722,7 @@ def main():
     ctx.close()
 
     conv = ks.get("conv3x3_mfma_f32", {"launches": 0, "ms": 0.0, "flops": 0.0})
+    traffic = counter_traffic()
     achieved = conv["flops"] / (conv["ms"] * 1e-3) / 1e12 if conv["ms"] else 0.0
     kernels = {}
     for name, v in sorted(ks.items(), key=lambda kv: -kv[1]["ms"]):
@@ -729,7 +764,11 @@ def main():
             "peak": PEAK_FP32_MFMA_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4),
-            "traffic": None,
+            "traffic": traffic["bytes_per_launch"] if traffic else None,
+            "traffic_note": ("HBM bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, scaled by a plain copy "
+                             "kernel) of the %s launch, profiles/conv3x3_f32_and_bf16_halo_hbm_counters.md; the "
+                             "launches averaged in 'achieved' mix all four UNet levels" % traffic["shape"])
+            if traffic else "no counter record for the current kernel source",
             "avg_launch_us": round(1e3 * conv["ms"] / max(conv["launches"], 1), 2),
             "launches": conv["launches"],
         },

@@ -1,4 +1,5 @@
-"""Build libtd.so (HIP kernels for gfx950 + C++ runtime + C-ABI) in-tree.
+"""Build libtd.so (HIP kernels for gfx950 + C++ runtime + C-ABI) in-tree,
+and the kernel micro-benchmark driver kbench beside it.
 
 Every HIP source is compiled for gfx950 with packed-FP32 instruction
 selection disabled; host C++ sources are compiled by the same driver.
@@ -47,6 +48,14 @@ def build(verbose=True):
     if r.returncode != 0:
         raise RuntimeError("link failed: %s\n%s" % (" ".join(cmd), r.stderr))
     os.replace(tmp, LIB)
+    # the kernel micro-benchmark driver (profiler runs), linked against the library
+    kb = os.path.join(HERE, "kbench")
+    cmd = [HIPCC] + COMMON + HIP_FLAGS + [os.path.join(CSRC, "kbench.cpp"), "-o", kb + ".tmp", "-L" + HERE, "-ltd",
+                                          "-Wl,-rpath,$ORIGIN"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("kbench build failed: %s\n%s" % (" ".join(cmd), r.stderr))
+    os.replace(kb + ".tmp", kb)
     return LIB
 
 
