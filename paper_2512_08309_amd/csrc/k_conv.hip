@@ -39,6 +39,89 @@ __device__ __forceinline__ float silu_f(float v) {
   return v * __builtin_amdgcn_rcpf(1.0f + __expf(-v));
 }
 
+// GroupNorm sums of a conv output tile (128 pixels x BN channels), from each
+// lane's FP64 sums over its 16 rows for its TN consecutive channels
+// (columns n_wave + TN * (lane % 16) + j): over the four lanes holding the
+// other rows of those columns, over the group's channels, then over the
+// tile's two row halves when both belong to one window (a window of at
+// least 128 pixels); in that fixed order.  Written per (window, tile of the
+// window, group) to a.stats.  lds: at least 2 KB of LDS free for the
+// exchange (the operand buffers after the K loop).
+template <int TN, int WM>
+__device__ void conv_stats_epilogue(const ConvArgs& a, double* s1, double* s2, int m0, int n_wave, int lane, int wm,
+                                    int wn, int M, int lhw, float* lds) {
+  static_assert(WM == 2, "two row halves per tile");
+#pragma unroll
+  for (int j = 0; j < TN; ++j)
+    for (int off = 16; off < 64; off <<= 1) {
+      s1[j] += __shfl_xor(s1[j], off);
+      s2[j] += __shfl_xor(s2[j], off);
+    }
+  const int gs = a.cout / a.groups;
+  // per group: within the lane (gs <= TN) or over gs / TN neighbouring lanes
+  double g1[TN], g2[TN];
+  int ng = 0;
+  if (gs <= TN) {
+    for (int j0 = 0; j0 < TN; j0 += gs) {
+      double t1 = 0, t2 = 0;
+      for (int j = j0; j < j0 + gs; ++j) {
+        t1 += s1[j];
+        t2 += s2[j];
+      }
+      g1[ng] = t1;
+      g2[ng] = t2;
+      ++ng;
+    }
+  } else {
+    double t1 = 0, t2 = 0;
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      t1 += s1[j];
+      t2 += s2[j];
+    }
+    for (int off = 1; off < gs / TN; off <<= 1) {
+      t1 += __shfl_xor(t1, off);
+      t2 += __shfl_xor(t2, off);
+    }
+    g1[0] = t1;
+    g2[0] = t2;
+    ng = 1;
+  }
+  const int l16 = lane & 15;
+  const bool writer = lane < 16 && (gs <= TN || (l16 & (gs / TN - 1)) == 0);
+  const int gbase = (n_wave + TN * l16) / gs;   // first group of this lane's columns
+  const int hw = 1 << lhw;
+  double* red = reinterpret_cast<double*>(lds);
+  if (hw >= 128) {
+    // both row halves are one window: wave wm = 1 hands its sums to wm = 0
+    __syncthreads();
+    if (wm == 1 && writer)
+      for (int q = 0; q < ng; ++q) {
+        red[((wn * 16 + l16) * TN + q) * 2] = g1[q];
+        red[((wn * 16 + l16) * TN + q) * 2 + 1] = g2[q];
+      }
+    __syncthreads();
+    if (wm == 0 && writer && m0 < M) {
+      const int slots = conv_stat_slots(lhw);
+      const int b = m0 >> lhw, slot = (m0 >> 7) & (slots - 1);
+      for (int q = 0; q < ng; ++q) {
+        double* d = a.stats + (((size_t)b * slots + slot) * a.groups + gbase + q) * 2;
+        d[0] = g1[q] + red[((wn * 16 + l16) * TN + q) * 2];
+        d[1] = g2[q] + red[((wn * 16 + l16) * TN + q) * 2 + 1];
+      }
+    }
+  } else if (writer) {
+    // 64-pixel windows: each row half is a window of its own
+    const int m = m0 + 64 * wm;
+    if (m < M)
+      for (int q = 0; q < ng; ++q) {
+        double* d = a.stats + ((size_t)(m >> lhw) * a.groups + gbase + q) * 2;
+        d[0] = g1[q];
+        d[1] = g2[q];
+      }
+  }
+}
+
 // DENSE: one source, no upsampling, no activation (the input is already
 // activated); fewer live registers, which leaves room to double-buffer the
 // LDS operand reads of consecutive k-steps.
@@ -239,6 +322,9 @@ __global__ __launch_bounds__(256, 4) void conv_kernel(ConvArgs a, int n_tiles_n)
 
   // Epilogue: lane holds D[4*(lane/16)+v][lane%16] of every tile.
   const int nb0 = n0 + brow;
+  double st1[TN], st2[TN];   // GroupNorm sums of this lane's columns (a.stats)
+#pragma unroll
+  for (int j = 0; j < TN; ++j) st1[j] = st2[j] = 0.0;
   float bias_v[TN];
 #pragma unroll
   for (int j = 0; j < TN; ++j) bias_v[j] = a.bias ? a.bias[nb0 + j] : 0.f;
@@ -267,8 +353,16 @@ __global__ __launch_bounds__(256, 4) void conv_kernel(ConvArgs a, int n_tiles_n)
 #pragma unroll
         for (int j = 0; j < TN; ++j) a.out[off + j] = o[j];
       }
+      if (a.stats)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          st1[j] += (double)o[j];
+          st2[j] += (double)o[j] * o[j];
+        }
     }
   }
+  if constexpr (WM == 2 && TAPS == 9 && DENSE)   // the launcher allows sums for dense C_out % 128 == 0 (2 x 2 waves) only
+    if (a.stats) conv_stats_epilogue<TN, WM>(a, st1, st2, m0, n0 + wn * (BN / WN), lane, wm, wn, M, lhw, &As[0][0]);
 }
 
 template <int BN, int WM, int WN>
@@ -299,6 +393,12 @@ void launch_conv(hipStream_t st, const ConvArgs& a) {
   check_conv_rows(a.nb, a.lh + a.lw);
   if (a.nb == 0) return;
   TD_CHECK(a.cout % 16 == 0 && a.cout > 0, -5, "conv: output channels must be a multiple of 16");
+  if (a.stats) {
+    const int gs = a.groups > 0 && a.cout % a.groups == 0 ? a.cout / a.groups : 0;
+    TD_CHECK(a.taps == 9 && !a.src1 && !a.c1 && !a.up0 && !a.act && a.cout % 128 == 0 && gs >= 1 && gs <= 64 &&
+                 (gs & (gs - 1)) == 0 && a.lh + a.lw >= 6 && conv_stat_slots(a.lh + a.lw) <= 32,
+             -5, "conv: GroupNorm sums need a dense 3x3 conv with C_out % 128 == 0 and windows of at least 64 px");
+  }
   const double M = (double)a.nb * (1 << (a.lh + a.lw));
   const double in_bytes = 4.0 * (a.up0 ? M / 4 * a.c0 + M * a.c1 : M * cin);
   const double bytes = in_bytes + 4.0 * a.taps * cin * a.cout + 4.0 * M * a.cout * (a.res ? 2 : 1);

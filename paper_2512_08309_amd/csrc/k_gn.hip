@@ -355,7 +355,7 @@ void launch_apply_bf16(hipStream_t st, const uint16_t* src, int C, const float* 
 }
 
 void launch_gn_finalize(hipStream_t st, const GnArgs& a, int nchunk) {
-  TD_CHECK(nchunk >= 1 && nchunk <= 16 && (a.c0 + a.c1) % a.groups == 0, -5, "groupnorm finalize: bad partials");
+  TD_CHECK(nchunk >= 1 && nchunk <= 32 && (a.c0 + a.c1) % a.groups == 0, -5, "groupnorm finalize: bad partials");
   if (!a.nb) return;
   hipLaunchKernelGGL(gn_finalize_kernel, dim3(a.nb), dim3(256), 0, st, a, nchunk);
   TD_LAUNCHED();
@@ -387,7 +387,7 @@ void launch_gn_apply_window(hipStream_t st, const GnArgs& g, int act, uint16_t* 
 }
 
 size_t gn_partial_doubles(int nb, int lh, int lw, int cin, int groups) {
-  return (size_t)nb * 16 * groups * 2;
+  return (size_t)nb * 32 * groups * 2;   // up to 32 partials per window (convolution epilogues)
 }
 
 void launch_gn(hipStream_t st, const GnArgs& a) {

@@ -603,8 +603,10 @@ void Model::apply(hipStream_t st, const float* s0, int c0, int up0, const float*
 
 // 3x3 convolution of an already activated dense FP32 input
 void Model::conv3_f32(hipStream_t st, const float* in, int cin, int nb, int lr, int cout, const float* wt,
-                      const float* bias, const float* res, float* out) {
+                      const float* bias, const float* res, float* out, double* stats) {
   ConvArgs a{};
+  a.stats = stats;
+  a.groups = d.groups;
   a.src0 = in;
   a.c0 = cin;
   a.nb = nb;
@@ -649,7 +651,11 @@ void Model::resblock(hipStream_t st, const ResBlockW& w, int k, const float* s0,
   // FP32: GroupNorm + SiLU are applied once per input element into F, not
   // once per tap inside the 3x3 conv's staging
   gn_apply(st, s0, c0, up0, s1, c1, nb, lr, w.gn1_g, w.gn1_b, 2, nullptr, B.F);
-  conv3_f32(st, B.F, w.cin, nb, lr, w.cout, w.w1, bias_eff_ + w.bias_off + (size_t)k * w.cout, nullptr, B.T);
+  // conv1's output feeds GroupNorm 2 only: its statistics come from the
+  // conv's epilogue where the shape allows (C_out % 128 == 0)
+  const bool fused = w.cout % 128 == 0 && w.cout % d.groups == 0 && 2 * lr >= 6;
+  conv3_f32(st, B.F, w.cin, nb, lr, w.cout, w.w1, bias_eff_ + w.bias_off + (size_t)k * w.cout, nullptr, B.T,
+            fused ? gn_part_ : nullptr);
   const float* res = s0;
   if (w.has_skip) {
     ConvArgs s{};
@@ -671,7 +677,24 @@ void Model::resblock(hipStream_t st, const ResBlockW& w, int k, const float* s0,
   } else {
     TD_CHECK(c1 == 0 && !up0, -5, "identity skip needs a plain input");
   }
-  gn_apply(st, B.T, w.cout, 0, nullptr, 0, nb, lr, w.gn2_g, w.gn2_b, 2, nullptr, B.F);
+  if (fused) {
+    GnArgs g{};
+    g.c0 = w.cout;
+    g.nb = nb;
+    g.lh = lr;
+    g.lw = lr;
+    g.groups = d.groups;
+    g.eps = d.gn_eps;
+    g.gamma = w.gn2_g;
+    g.beta = w.gn2_b;
+    g.partial = gn_part_;
+    g.scale = gn_scale_;
+    g.shift = gn_shift_;
+    launch_gn_finalize(st, g, conv_stat_slots(2 * lr));
+    apply(st, B.T, w.cout, 0, nullptr, 0, 2, nb, lr, nullptr, B.F);
+  } else {
+    gn_apply(st, B.T, w.cout, 0, nullptr, 0, nb, lr, w.gn2_g, w.gn2_b, 2, nullptr, B.F);
+  }
   conv3_f32(st, B.F, w.cout, nb, lr, w.cout, w.w2, w.b2, res, out);
 }
 

@@ -166,7 +166,7 @@ class Model {
   void gn_apply(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int nb, int lr,
                 const float* g, const float* b, int act, uint16_t* out, float* out32);
   void conv3_f32(hipStream_t st, const float* in, int cin, int nb, int lr, int cout, const float* wt,
-                 const float* bias, const float* res, float* out);
+                 const float* bias, const float* res, float* out, double* stats = nullptr);
   void build_unet(const std::map<std::string, std::vector<float>>& host,
                   const std::map<std::string, std::vector<int>>& shapes, hipStream_t st);
   void gn(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int nb, int lh, int lw,

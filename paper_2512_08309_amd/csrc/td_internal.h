@@ -126,8 +126,15 @@ struct ConvArgs {
   const float* bias;     // [cout]
   const float* res;      // [nb][h][w][cout] or null
   float* out;            // [nb][h][w][cout]
+  // set: the output's GroupNorm sums (sum, sum of squares, FP64) per
+  // (window, 128-pixel tile of the window, group of C_out / groups
+  // channels), in the layout of the GroupNorm partials with
+  // conv_stat_slots(lh + lw) tiles per window (3x3, dense input only)
+  double* stats;
+  int groups;
 };
 void launch_conv(hipStream_t st, const ConvArgs& a);
+__host__ __device__ inline int conv_stat_slots(int lhw) { return lhw > 7 ? 1 << (lhw - 7) : 1; }
 
 // Reduced-precision conv: BF16 operands, FP32 accumulation and output.
 struct ConvLpArgs {
