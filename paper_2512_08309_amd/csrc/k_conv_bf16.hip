@@ -684,38 +684,28 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_halo_kernel(ConvLpArgs a, in
   const int kg = lane >> 5;
   const bool want_stats = a.stats != nullptr;
   char* const otile = reinterpret_cast<char*>(lds);
-  double s1[TN][2], s2[TN][2];
+  float f1[TN][2] = {}, f2[TN][2] = {};
+  float biasv[TN];
 #pragma unroll
-  for (int j = 0; j < TN; ++j) {
-    const int nl = 64 * wn + 32 * j + (lane & 31), n = n0 + nl;
-    const float bias = a.bias ? a.bias[n] : 0.f;
-    float f1[2] = {0.f, 0.f}, f2[2] = {0.f, 0.f};
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int pr = 128 * wm + 32 * i + 8 * (e >> 2) + 4 * kg + (e & 3);
-        const int m = m0 + pr;
-        float o = acc[i][j][e] + bias;
-        if (a.out16) {
-          *reinterpret_cast<uint16_t*>(otile + pr * TROW + 2 * nl) = __builtin_bit_cast(uint16_t, (__bf16)o);
-        } else if (m < M) {
-          const size_t off = (size_t)m * a.cout + n;
-          if (a.res) o += a.res[off];
-          a.out[off] = o;
-        }
-        const int part = G::NI == 1 ? 0 : (i >> 1);   // 8x8 windows: rows of two windows
-        if (m < M) {
-          f1[part] += o;
-          f2[part] += o * o;
-        }
-      }
-    s1[j][0] = f1[0];
-    s1[j][1] = f1[1];
-    s2[j][0] = f2[0];
-    s2[j][1] = f2[1];
-  }
+  for (int j = 0; j < TN; ++j) biasv[j] = a.bias ? a.bias[n0 + 64 * wn + 32 * j + (lane & 31)] : 0.f;
   if (a.out16) {
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int nl = 64 * wn + 32 * j + (lane & 31);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int pr = 128 * wm + 32 * i + 8 * (e >> 2) + 4 * kg + (e & 3);
+          const float o = acc[i][j][e] + biasv[j];
+          *reinterpret_cast<uint16_t*>(otile + pr * TROW + 2 * nl) = __builtin_bit_cast(uint16_t, (__bf16)o);
+          const int part = G::NI == 1 ? 0 : (i >> 1);   // 8x8 windows: rows of two windows
+          if (m0 + pr < M) {
+            f1[j][part] += o;
+            f2[j][part] += o * o;
+          }
+        }
+    }
     __syncthreads();
     const int c16 = tid & 15;
 #pragma unroll 4
@@ -725,7 +715,63 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_halo_kernel(ConvLpArgs a, in
         *reinterpret_cast<u4v*>(a.out16 + (size_t)m * a.cout + n0 + 8 * c16) =
             *reinterpret_cast<const u4v*>(otile + pr * TROW + 16 * c16);
     }
+  } else {
+    // FP32 output, 32 x 32 tile t = (j, i) at a time: one base address per
+    // tile, row offsets that are the same for every lane, and a bounds test
+    // per tile that is the same for every lane (M is a multiple of 64 and a
+    // tile's 32 rows start at a multiple of 32, so they are all below M or
+    // all past it).  The residuals of tile t + 1 are loaded before the
+    // outputs of tile t are stored: loads and stores retire in order, so a
+    // load issued behind stores waits for them, and a per-element load /
+    // store sequence pays a memory round trip per element.
+    float rb[2][16];
+    auto rows_ok = [&](int i) { return __builtin_amdgcn_readfirstlane(m0 + 128 * wm + 32 * i) < M; };
+    auto row_ptr = [&](auto* base, int i, int j) {
+      return base + (size_t)(m0 + 128 * wm + 32 * i + 4 * kg) * a.cout + n0 + 64 * wn + 32 * j + (lane & 31);
+    };
+    auto load_res = [&](auto tc) {
+      constexpr int t = decltype(tc)::value, j = t / TM, i = t % TM;
+      if (a.res && rows_ok(i)) {
+        const float* rp = row_ptr(a.res, i, j);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) rb[t & 1][e] = rp[(8 * (e >> 2) + (e & 3)) * a.cout];
+      } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) rb[t & 1][e] = 0.f;
+      }
+    };
+    auto store_tile = [&](auto tc) {
+      constexpr int t = decltype(tc)::value, j = t / TM, i = t % TM;
+      constexpr int part = G::NI == 1 ? 0 : (i >> 1);
+      if (rows_ok(i)) {
+        float* op = row_ptr(a.out, i, j);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const float o = (acc[i][j][e] + biasv[j]) + rb[t & 1][e];
+          op[(8 * (e >> 2) + (e & 3)) * a.cout] = o;
+          f1[j][part] += o;
+          f2[j][part] += o * o;
+        }
+      }
+    };
+    load_res(std::integral_constant<int, 0>{});
+    auto stage = [&](auto tc) {
+      constexpr int t = decltype(tc)::value;
+      if constexpr (t + 1 < TM * TN) load_res(std::integral_constant<int, t + 1>{});
+      __builtin_amdgcn_sched_barrier(0);
+      store_tile(tc);
+      __builtin_amdgcn_sched_barrier(0);
+    };
+    unroll<TM * TN>(stage);
   }
+  double s1[TN][2], s2[TN][2];
+#pragma unroll
+  for (int j = 0; j < TN; ++j)
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      s1[j][p] = f1[j][p];
+      s2[j][p] = f2[j][p];
+    }
   if (want_stats) {
     const int gs = a.cout / a.groups;                // channels per group: 1..32, a power of two
     const int slots = conv_lp_stat_slots(2 * L);
