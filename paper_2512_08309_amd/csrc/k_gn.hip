@@ -124,7 +124,8 @@ __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
 
 // One thread per (pixel, 8 channels): reads the virtual conv input in FP32,
 // applies the GroupNorm affine (and SiLU), writes 16 bytes of BF16 or 32
-// bytes of FP32.
+// bytes of FP32; with a.raw also the input itself as BF16 (the operand of a
+// residual block's 1x1 skip convolution), from the same read.
 template <bool F32>
 __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
   const int cin = a.c0 + a.c1, q8 = cin / 8;
@@ -149,6 +150,10 @@ __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
   float4 v0 = *reinterpret_cast<const float4*>(s);
   float4 v1 = *reinterpret_cast<const float4*>(s + 4);
   float v[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+  if (!F32 && a.raw) {
+    const uint4 r = {pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]), pack_bf16(v[4], v[5]), pack_bf16(v[6], v[7])};
+    *reinterpret_cast<uint4*>(a.raw + p * cin + c) = r;
+  }
   if (a.act) {
     const float* sc = a.scale + (size_t)b * cin + c;
     const float* sh = a.shift + (size_t)b * cin + c;
@@ -168,33 +173,45 @@ __global__ __launch_bounds__(256) void apply_kernel(ApplyArgs a) {
   }
 }
 
-// act(x * scale + shift) of a BF16 tensor, 8 channels per thread, into BF16.
+// act(x * scale + shift) of a BF16 tensor into BF16: a thread takes 8
+// channels of 4 consecutive pixels of one window, so that each scale / shift
+// pair is loaded once per 4 pixels.
 __global__ __launch_bounds__(256) void apply_bf16_kernel(const uint4* __restrict__ src, int C, const float* scale,
-                                                         const float* shift, int act, int lhw, size_t n,
+                                                         const float* shift, int act, int lhw, size_t n4,
                                                          uint4* __restrict__ out) {
   const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= n) return;
+  if (e >= n4) return;
   const int q8 = C / 8;
-  const int c = 8 * (int)(e % q8);
-  const int b = (int)((e / q8) >> lhw);
-  const uint4 u = src[e];
-  const uint32_t w[4] = {u.x, u.y, u.z, u.w};
-  const float* sc = scale + (size_t)b * C + c;
-  const float* sh = shift + (size_t)b * C + c;
-  uint32_t o[4];
+  const int q = (int)(e % q8);
+  const size_t p0 = 4 * (e / q8);   // first of the thread's pixels
+  const int c = 8 * q;
+  const int b = (int)(p0 >> lhw);
+  uint4 u[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    float v0 = __uint_as_float(w[k] << 16), v1 = __uint_as_float(w[k] & 0xffff0000u);
-    v0 = v0 * sc[2 * k] + sh[2 * k];
-    v1 = v1 * sc[2 * k + 1] + sh[2 * k + 1];
-    if (act == 2) {
-      v0 = silu_f(v0);
-      v1 = silu_f(v1);
-    }
-    o[k] = pack_bf16(v0, v1);
+  for (int i = 0; i < 4; ++i) u[i] = src[(p0 + i) * q8 + q];
+  float sc[8], sh[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    sc[k] = scale[(size_t)b * C + c + k];
+    sh[k] = shift[(size_t)b * C + c + k];
   }
-  const uint4 r = {o[0], o[1], o[2], o[3]};
-  out[e] = r;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t w[4] = {u[i].x, u[i].y, u[i].z, u[i].w};
+    uint32_t o[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      float v0 = __uint_as_float(w[k] << 16), v1 = __uint_as_float(w[k] & 0xffff0000u);
+      v0 = v0 * sc[2 * k] + sh[2 * k];
+      v1 = v1 * sc[2 * k + 1] + sh[2 * k + 1];
+      if (act == 2) {
+        v0 = silu_f(v0);
+        v1 = silu_f(v1);
+      }
+      o[k] = pack_bf16(v0, v1);
+    }
+    out[(p0 + i) * q8 + q] = uint4{o[0], o[1], o[2], o[3]};
+  }
 }
 
 // GroupNorm of whole windows in one pass, for windows whose virtual input
@@ -333,23 +350,27 @@ void launch_apply(hipStream_t st, const ApplyArgs& a) {
   if (!n) return;
   prof_begin(st);
   TD_CHECK((a.out != nullptr) != (a.out32 != nullptr), -5, "apply: exactly one of the BF16 and FP32 outputs");
+  TD_CHECK(!a.raw || a.out, -5, "apply: the raw BF16 copy goes with the BF16 output");
   if (a.out32)
     hipLaunchKernelGGL(apply_kernel<true>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
   else
     hipLaunchKernelGGL(apply_kernel<false>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
   TD_LAUNCHED();
   const double el = 8.0 * n;
-  prof_end(st, a.out32 ? K_APPLY32 : K_APPLY, 4.0 * el, el * ((a.out32 ? 4.0 : 2.0) + (a.up0 ? 4.0 * a.c1 / cin + 1.0 * a.c0 / cin : 4.0)));
+  prof_end(st, a.out32 ? K_APPLY32 : K_APPLY, 4.0 * el,
+           el * ((a.out32 ? 4.0 : 2.0) + (a.raw ? 2.0 : 0.0) + (a.up0 ? 4.0 * a.c1 / cin + 1.0 * a.c0 / cin : 4.0)));
 }
 
 void launch_apply_bf16(hipStream_t st, const uint16_t* src, int C, const float* scale, const float* shift, int act,
                        int nb, int lh, int lw, uint16_t* out) {
   TD_CHECK(C % 8 == 0 && act >= 1 && act <= 2, -5, "apply_bf16: channels must be multiples of 8");
+  TD_CHECK(lh + lw >= 2, -5, "apply_bf16: windows of at least 4 pixels");
   const size_t n = ((size_t)nb << (lh + lw)) * (C / 8);
   if (!n) return;
   prof_begin(st);
-  hipLaunchKernelGGL(apply_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-                     reinterpret_cast<const uint4*>(src), C, scale, shift, act, lh + lw, n, reinterpret_cast<uint4*>(out));
+  hipLaunchKernelGGL(apply_bf16_kernel, dim3((unsigned)((n / 4 + 255) / 256)), dim3(256), 0, st,
+                     reinterpret_cast<const uint4*>(src), C, scale, shift, act, lh + lw, n / 4,
+                     reinterpret_cast<uint4*>(out));
   TD_LAUNCHED();
   prof_end(st, K_APPLY, 32.0 * n, 32.0 * n);
 }

@@ -583,7 +583,7 @@ bool Model::conv1_fused(hipStream_t st, const ResBlockW& w, const uint16_t* act,
 }
 
 void Model::apply(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int act, int nb, int lr,
-                  uint16_t* out, float* out32) {
+                  uint16_t* out, float* out32, uint16_t* raw) {
   ApplyArgs a{};
   a.src0 = s0;
   a.src1 = s1;
@@ -598,6 +598,7 @@ void Model::apply(hipStream_t st, const float* s0, int c0, int up0, const float*
   a.lw = lr;
   a.out = out;
   a.out32 = out32;
+  a.raw = raw;
   launch_apply(st, a);
 }
 
@@ -628,7 +629,15 @@ void Model::resblock(hipStream_t st, const ResBlockW& w, int k, const float* s0,
   TD_CHECK(c0 + c1 == w.cin, -5, "resblock: channel mismatch");
   if (prec_) {
     const float* bias1 = bias_eff_ + w.bias_off + (size_t)k * w.cout;
-    gn_apply(st, s0, c0, up0, s1, c1, nb, lr, w.gn1_g, w.gn1_b, 2, B.A, nullptr);
+    // with a 1x1 skip, the statistics pass's apply also writes the skip
+    // conv's BF16 operand from the same read of the input
+    const bool raw_in_apply = w.has_skip && !gn_apply_window_fits(lr, lr, c0, c1, up0, d.groups);
+    if (raw_in_apply) {
+      gn(st, s0, c0, up0, s1, c1, nb, lr, lr, w.gn1_g, w.gn1_b);
+      apply(st, s0, c0, up0, s1, c1, 2, nb, lr, B.A, nullptr, B.A0);
+    } else {
+      gn_apply(st, s0, c0, up0, s1, c1, nb, lr, w.gn1_g, w.gn1_b, 2, B.A, nullptr);
+    }
     // conv1's output goes to GroupNorm 2 only: stored as BF16 with its
     // statistics from the epilogue where the halo-staged kernel applies
     uint16_t* T16 = reinterpret_cast<uint16_t*>(B.T);
@@ -636,7 +645,7 @@ void Model::resblock(hipStream_t st, const ResBlockW& w, int k, const float* s0,
     if (!fused) conv_lp(st, B.A, w.cin, nb, lr, w.cout, 9, w.w1_lp, w.w1_8, w.s1_8, w.kp1, bias1, nullptr, B.T, w.w1_fr);
     const float* res = s0;
     if (w.has_skip) {
-      apply(st, s0, c0, up0, s1, c1, 0, nb, lr, B.A0);
+      if (!raw_in_apply) apply(st, s0, c0, up0, s1, c1, 0, nb, lr, B.A0);
       conv_lp(st, B.A0, w.cin, nb, lr, w.cout, 1, w.wskip_lp, w.wskip_8, w.sskip_8, w.kps, w.bskip, nullptr, B.R,
               w.wskip_fr);
       res = B.R;

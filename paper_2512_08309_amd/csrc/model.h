@@ -162,7 +162,7 @@ class Model {
   bool conv1_fused(hipStream_t st, const ResBlockW& w, const uint16_t* act, int nb, int lr, const float* bias,
                    uint16_t* out16);
   void apply(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int act, int nb,
-             int lr, uint16_t* out, float* out32 = nullptr);
+             int lr, uint16_t* out, float* out32 = nullptr, uint16_t* raw = nullptr);
   void gn_apply(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int nb, int lr,
                 const float* g, const float* b, int act, uint16_t* out, float* out32);
   void conv3_f32(hipStream_t st, const float* in, int cin, int nb, int lr, int cout, const float* wt,

@@ -190,6 +190,7 @@ struct ApplyArgs {
   int nb, lh, lw;
   uint16_t* out;         // [nb][h][w][c0 + c1] BF16
   float* out32;          // [nb][h][w][c0 + c1] FP32 (instead of out)
+  uint16_t* raw;         // with out: the input itself as BF16 too (no affine), or null
 };
 void launch_apply(hipStream_t st, const ApplyArgs& a);
 // act(x * scale + shift) of a BF16 tensor [nb][h][w][C] into BF16 (the
