@@ -772,6 +772,48 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_halo_kernel(ConvLpArgs a, in
       s1[j][p] = f1[j][p];
       s2[j][p] = f2[j][p];
     }
+  if (a.chstats) {
+    // per-channel sums: lanes l and l ^ 32 hold the two row halves of
+    // column l % 32; with whole-row tiles wave wm = 1 hands its sums to wm = 0
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        s1[j][p] += __shfl_xor(s1[j][p], 32);
+        s2[j][p] += __shfl_xor(s2[j][p], 32);
+      }
+    if (G::NI == 1) {
+      double* red = reinterpret_cast<double*>(otile + TILE_BYTES);
+      if (wm == 1 && lane < 32)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          red[((wn * TN + j) * 32 + lane) * 2] = s1[j][0];
+          red[((wn * TN + j) * 32 + lane) * 2 + 1] = s2[j][0];
+        }
+      __syncthreads();
+      if (wm == 0 && lane < 32) {
+        const int slots = conv_lp_stat_slots(2 * L), slot = (m0 >> 8) & (slots - 1);
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const int n = n0 + 64 * wn + 32 * j + lane;
+          double* d = a.chstats + (((size_t)b0 * slots + slot) * a.cout + n) * 2;
+          d[0] = s1[j][0] + red[((wn * TN + j) * 32 + lane) * 2];
+          d[1] = s2[j][0] + red[((wn * TN + j) * 32 + lane) * 2 + 1];
+        }
+      }
+    } else if (lane < 32) {
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          const int b = b0 + 2 * wm + p;
+          if (b >= a.nb) continue;
+          double* d = a.chstats + ((size_t)b * a.cout + n0 + 64 * wn + 32 * j + lane) * 2;
+          d[0] = s1[j][p];
+          d[1] = s2[j][p];
+        }
+    }
+  }
   if (want_stats) {
     const int gs = a.cout / a.groups;                // channels per group: 1..32, a power of two
     const int slots = conv_lp_stat_slots(2 * L);
@@ -870,6 +912,7 @@ bool conv_lp_fused_ok(const ConvLpArgs& a) {
   const bool halo = a.wfrag && !a.w8 && a.lh == a.lw && a.lw >= 3 && a.lw <= 6 && a.cin % 32 == 0 &&
                     a.cout % 128 == 0;
   if (!halo || (a.out16 && a.res)) return false;
+  if (a.chstats && (a.out16 || a.stats)) return false;
   if (!a.stats) return true;
   const int gs = a.groups > 0 && a.cout % a.groups == 0 ? a.cout / a.groups : 0;
   return gs >= 1 && gs <= 32 && (gs & (gs - 1)) == 0;
@@ -888,13 +931,13 @@ void launch_conv_lp(hipStream_t st, const ConvLpArgs& a) {
   const double Md = (double)((int64_t)a.nb << (a.lh + a.lw));
   prof_begin(st);
   TD_CHECK(!a.w8 || a.wscale, -5, "fp8 weights need per-channel scales");
-  // 3x3 with C_in % 32 == 0 and BF16 weights: direct-to-LDS ring (measured
-  // 605 vs 594 TFLOP/s on the 128-channel 64x64 layers; a 256-row tile at
-  // two workgroups per CU measured 578).  1x1 convolutions keep the register-
-  // staged kernel, which measured faster for them (322 vs 295 TFLOP/s).
+  // square images of side 8..64 with C_in % 32 == 0, C_out % 128 == 0 and
+  // fragment-ordered BF16 weights: the halo-staged kernel (3x3 and 1x1).
+  // Other 3x3 shapes with C_in % 32 == 0: the direct-to-LDS ring; the rest
+  // (and FP8 weights): the register-staged kernel.
   const bool halo = a.wfrag && !a.w8 && a.lh == a.lw && a.lw >= 3 && a.lw <= 6 && a.cin % 32 == 0 &&
                     a.cout % 128 == 0;
-  TD_CHECK(!(a.out16 || a.stats) || conv_lp_fused_ok(a), -5,
+  TD_CHECK(!(a.out16 || a.stats || a.chstats) || conv_lp_fused_ok(a), -5,
            "bf16 conv: a BF16 output or GroupNorm sums need the halo-staged kernel");
   if (halo && a.lw == 6) launch_halo<6>(st, a);
   else if (halo && a.lw == 5) launch_halo<5>(st, a);

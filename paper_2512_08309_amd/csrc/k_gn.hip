@@ -114,6 +114,54 @@ __global__ __launch_bounds__(256) void gn_finalize_kernel(GnArgs a, int nchunk) 
   }
 }
 
+// The affine of a GroupNorm over concat(src0 (optionally upsampled), src1)
+// from per-channel sums written by the producers of src0 and src1
+// ([nb][slots][C][2], one slot per tile of the window): per window, each
+// group's sums over its channels (channel order), each channel's over its
+// slots (slot order), an upsampled source's terms weighted by 4 (its pixels
+// count four times); then the same affine as gn_finalize_kernel.
+__global__ __launch_bounds__(256) void gn_finalize_ch_kernel(GnArgs a, const double* ch0, int slots0,
+                                                             const double* ch1, int slots1) {
+  __shared__ double gs1[kMaxCin], gs2[kMaxCin];
+  const int b = blockIdx.x;
+  const int cin = a.c0 + a.c1;
+  const int cgp = cin / a.groups;
+  for (int g = threadIdx.x; g < a.groups; g += blockDim.x) {
+    double ts = 0, tq = 0;
+    for (int c = g * cgp; c < (g + 1) * cgp; ++c) {
+      const bool first = c < a.c0;
+      const int C = first ? a.c0 : a.c1, slots = first ? slots0 : slots1;
+      const double* p = (first ? ch0 : ch1) + ((size_t)b * slots * C + (first ? c : c - a.c0)) * 2;
+      double cs = 0, cq = 0;
+      for (int k = 0; k < slots; ++k) {
+        cs += p[(size_t)k * C * 2];
+        cq += p[(size_t)k * C * 2 + 1];
+      }
+      const double w = (first && a.up0) ? 4.0 : 1.0;
+      ts += cs * w;
+      tq += cq * w;
+    }
+    gs1[g] = ts;
+    gs2[g] = tq;
+  }
+  __syncthreads();
+  const double n = (double)(1L << (a.lh + a.lw)) * cgp;
+  for (int c = threadIdx.x; c < cin; c += blockDim.x) {
+    const int g = c / cgp;
+    const double mean = gs1[g] / n;
+    double var = gs2[g] / n - mean * mean;
+    if (var < 0) var = 0;
+    const double rstd = 1.0 / sqrt(var + (double)a.eps);
+    if (a.mean && c % cgp == 0) {
+      a.mean[(size_t)b * a.groups + g] = (float)mean;
+      a.rstd[(size_t)b * a.groups + g] = (float)rstd;
+    }
+    const double sc = (double)a.gamma[c] * rstd;
+    a.scale[(size_t)b * cin + c] = (float)sc;
+    a.shift[(size_t)b * cin + c] = (float)((double)a.beta[c] - mean * sc);
+  }
+}
+
 __device__ __forceinline__ float silu_f(float v) { return v * __builtin_amdgcn_rcpf(1.0f + __expf(-v)); }
 
 __device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) {
@@ -373,6 +421,18 @@ void launch_apply_bf16(hipStream_t st, const uint16_t* src, int C, const float* 
                      reinterpret_cast<uint4*>(out));
   TD_LAUNCHED();
   prof_end(st, K_APPLY, 32.0 * n, 32.0 * n);
+}
+
+void launch_gn_finalize_ch(hipStream_t st, const GnArgs& a, const double* ch0, int slots0, const double* ch1,
+                           int slots1) {
+  const int cin = a.c0 + a.c1;
+  TD_CHECK(cin >= 1 && cin <= kMaxCin && a.groups >= 1 && a.groups <= kMaxCin && cin % a.groups == 0, -5,
+           "groupnorm finalize: bad channels or groups");
+  TD_CHECK(ch0 && slots0 >= 1 && (a.c1 == 0 || (ch1 && slots1 >= 1)), -5, "groupnorm finalize: missing sums");
+  TD_CHECK(!a.up0 || a.lh + a.lw >= 2, -5, "groupnorm finalize: upsampled source needs h, w >= 2");
+  if (!a.nb) return;
+  hipLaunchKernelGGL(gn_finalize_ch_kernel, dim3(a.nb), dim3(256), 0, st, a, ch0, slots0, ch1, slots1);
+  TD_LAUNCHED();
 }
 
 void launch_gn_finalize(hipStream_t st, const GnArgs& a, int nchunk) {

@@ -393,7 +393,11 @@ size_t Model::workspace_bytes_per_window() const {
   f += 2 * 1024;                                  // GN scale/shift
   size_t lp = 0;
   if (prec_)
-    for (int l = 0; l < nl; ++l) lp += 2 * (size_t)(d.H >> l) * (d.H >> l) * cin_max(l);   // A, A0 (BF16)
+    for (int l = 0; l < nl; ++l) {
+      lp += 2 * (size_t)(d.H >> l) * (d.H >> l) * cin_max(l);   // A, A0 (BF16)
+      // per-channel sums of X, Y and the skips: 2 doubles per (slot, channel)
+      f += (size_t)(2 + d.nres) * conv_lp_stat_slots(2 * ilog2(d.H >> l)) * d.ch[l] * 4 + 64 * (2 + d.nres);
+    }
   else
     for (int l = 0; l < nl; ++l) f += (size_t)(d.H >> l) * (d.H >> l) * cin_max(l);       // F (FP32)
   return state + f * sizeof(float) + lp * sizeof(uint16_t) + (size_t)16 * d.groups * 2 * sizeof(double) + 64 * 256;
@@ -438,6 +442,7 @@ void Model::ensure_workspace(int max_batch) {
   }
   const int nl = d.kind == "unet" ? (int)d.ch.size() : 0;
   lb_.assign(nl, LevelBufs{});
+  chs_.clear();
   for (int l = 0; l < nl; ++l) {
     size_t r2 = (size_t)(d.H >> l) * (d.H >> l) * max_batch;
     size_t c = d.ch[l];
@@ -460,6 +465,15 @@ void Model::ensure_workspace(int max_batch) {
     if (prec_) {
       b.A = (uint16_t*)take((r2 * cin_max(l) + 1) / 2);
       b.A0 = (uint16_t*)take((r2 * cin_max(l) + 1) / 2);
+      const int slots = conv_lp_stat_slots(2 * ilog2(d.H >> l));
+      std::vector<const float*> tracked = {b.X, b.Y};
+      for (float* sk : b.S) tracked.push_back(sk);
+      for (const float* t : tracked) {
+        ChStats cs;
+        cs.buf = (double*)take((size_t)max_batch * slots * c * 4);
+        cs.slots = slots;
+        chs_[t] = cs;
+      }
     } else {
       b.F = take(r2 * cin_max(l));
     }
@@ -494,6 +508,36 @@ void Model::gn(hipStream_t st, const float* s0, int c0, int up0, const float* s1
   launch_gn(st, a);
 }
 
+Model::ChStats* Model::chstats_of(const float* t) {
+  auto it = chs_.find(t);
+  return it == chs_.end() ? nullptr : &it->second;
+}
+
+void Model::gn_stats(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int nb, int lh,
+                     int lw, const float* g, const float* b) {
+  const ChStats* a0 = chstats_of(s0);
+  const ChStats* a1 = s1 ? chstats_of(s1) : nullptr;
+  const bool have = a0 && a0->valid && a0->C == c0 && (!s1 || (a1 && a1->valid && a1->C == c1));
+  if (!have) {
+    gn(st, s0, c0, up0, s1, c1, nb, lh, lw, g, b);
+    return;
+  }
+  GnArgs a{};
+  a.c0 = c0;
+  a.c1 = c1;
+  a.up0 = up0;
+  a.nb = nb;
+  a.lh = lh;
+  a.lw = lw;
+  a.groups = d.groups;
+  a.eps = d.gn_eps;
+  a.gamma = g;
+  a.beta = b;
+  a.scale = gn_scale_;
+  a.shift = gn_shift_;
+  launch_gn_finalize_ch(st, a, a0->buf, a0->slots, s1 ? a1->buf : nullptr, s1 ? a1->slots : 0);
+}
+
 // GroupNorm of a conv input followed by its apply (act 1 affine, 2 + SiLU),
 // written as BF16 (out) or FP32 (out32): one pass per window when the
 // window's input fits in a workgroup, else statistics, then apply.
@@ -516,13 +560,13 @@ void Model::gn_apply(hipStream_t st, const float* s0, int c0, int up0, const flo
     launch_gn_apply_window(st, a, act, out, out32);
     return;
   }
-  gn(st, s0, c0, up0, s1, c1, nb, lr, lr, g, b);
+  gn_stats(st, s0, c0, up0, s1, c1, nb, lr, lr, g, b);
   apply(st, s0, c0, up0, s1, c1, act, nb, lr, out, out32);
 }
 
 void Model::conv_lp(hipStream_t st, const uint16_t* act, int cin, int nb, int lr, int cout, int taps,
                     const uint16_t* wt, const uint8_t* w8, const float* w8s, int kp, const float* bias,
-                    const float* res, float* out, const uint16_t* wfrag) {
+                    const float* res, float* out, const uint16_t* wfrag, bool track) {
   ConvLpArgs a{};
   if (prec_ == 2) {
     a.wt = w8;
@@ -543,7 +587,16 @@ void Model::conv_lp(hipStream_t st, const uint16_t* act, int cin, int nb, int lr
   a.bias = bias;
   a.res = res;
   a.out = out;
+  ChStats* cs = track ? chstats_of(out) : nullptr;
+  if (cs) {
+    a.chstats = cs->buf;
+    if (!conv_lp_fused_ok(a) || conv_lp_stat_slots(2 * lr) != cs->slots) a.chstats = nullptr;
+  }
   launch_conv_lp(st, a);
+  if (cs) {
+    cs->valid = a.chstats != nullptr;
+    cs->C = cout;
+  }
 }
 
 bool Model::conv1_fused(hipStream_t st, const ResBlockW& w, const uint16_t* act, int nb, int lr, const float* bias,
@@ -633,7 +686,7 @@ void Model::resblock(hipStream_t st, const ResBlockW& w, int k, const float* s0,
     // conv's BF16 operand from the same read of the input
     const bool raw_in_apply = w.has_skip && !gn_apply_window_fits(lr, lr, c0, c1, up0, d.groups);
     if (raw_in_apply) {
-      gn(st, s0, c0, up0, s1, c1, nb, lr, lr, w.gn1_g, w.gn1_b);
+      gn_stats(st, s0, c0, up0, s1, c1, nb, lr, lr, w.gn1_g, w.gn1_b);
       apply(st, s0, c0, up0, s1, c1, 2, nb, lr, B.A, nullptr, B.A0);
     } else {
       gn_apply(st, s0, c0, up0, s1, c1, nb, lr, w.gn1_g, w.gn1_b, 2, B.A, nullptr);
@@ -654,7 +707,7 @@ void Model::resblock(hipStream_t st, const ResBlockW& w, int k, const float* s0,
     }
     if (fused) launch_apply_bf16(st, T16, w.cout, gn_scale_, gn_shift_, 2, nb, lr, lr, B.A);
     else gn_apply(st, B.T, w.cout, 0, nullptr, 0, nb, lr, w.gn2_g, w.gn2_b, 2, B.A, nullptr);
-    conv_lp(st, B.A, w.cout, nb, lr, w.cout, 9, w.w2_lp, w.w2_8, w.s2_8, w.kp2, w.b2, res, out, w.w2_fr);
+    conv_lp(st, B.A, w.cout, nb, lr, w.cout, 9, w.w2_lp, w.w2_8, w.s2_8, w.kp2, w.b2, res, out, w.w2_fr, true);
     return;
   }
   // FP32: GroupNorm + SiLU are applied once per input element into F, not
@@ -715,7 +768,8 @@ void Model::attention(hipStream_t st, const AttnW& w, const float* in, int nb, i
     conv_lp(st, B.A, w.C, nb, lr, 3 * w.C, 1, w.wqkv_lp, w.wqkv_8, w.sqkv_8, w.kpq, w.bqkv, nullptr, B.Q, w.wqkv_fr);
     launch_attention(st, B.Q, B.O, nb, 1 << (2 * lr), w.C, d.heads);
     apply(st, B.O, w.C, 0, nullptr, 0, 0, nb, lr, B.A);
-    conv_lp(st, B.A, w.C, nb, lr, w.C, 1, w.wproj_lp, w.wproj_8, w.sproj_8, w.kpp, w.bproj, in, out, w.wproj_fr);
+    conv_lp(st, B.A, w.C, nb, lr, w.C, 1, w.wproj_lp, w.wproj_8, w.sproj_8, w.kpp, w.bproj, in, out, w.wproj_fr,
+            true);
     return;
   }
   gn(st, in, w.C, 0, nullptr, 0, nb, lr, lr, w.gn_g, w.gn_b);
@@ -829,6 +883,7 @@ void Model::run_net(hipStream_t st, const WindowBatch& wb, int k, double sigma_n
   }
   TD_CHECK(wb.n <= ws_batch_, -1, "batch larger than workspace");
   const int nl = (int)d.ch.size();
+  for (auto& kv : chs_) kv.second.valid = false;   // no buffer holds this run's tensors yet
   // (mode 2 writes Phi into dout; the output kernel reads x at the same
   //  element before writing it, so dout may alias the canvas)
   const int nb = wb.n;
@@ -892,7 +947,7 @@ void Model::run_net(hipStream_t st, const WindowBatch& wb, int k, double sigma_n
       hl = l;
     }
   }
-  gn(st, h, hc, 0, nullptr, 0, nb, ilog2(d.H), ilog2(d.H), out_gn_g_, out_gn_b_);
+  gn_stats(st, h, hc, 0, nullptr, 0, nb, ilog2(d.H), ilog2(d.H), out_gn_g_, out_gn_b_);
   OutArgs oa{};
   oa.h = h;
   oa.gn_scale = gn_scale_;

@@ -130,6 +130,16 @@ class Model {
   std::vector<LevelBufs> lb_;
   float *gn_scale_ = nullptr, *gn_shift_ = nullptr;
   double* gn_part_ = nullptr;
+  // Per-channel GroupNorm sums of the level buffers X, Y and S[j] (reduced
+  // precision): written by the convolution that produced the buffer's
+  // current contents (valid), [nb][slots][C][2].
+  struct ChStats {
+    double* buf = nullptr;
+    int slots = 0, C = 0;
+    bool valid = false;
+  };
+  std::map<const float*, ChStats> chs_;
+  ChStats* chstats_of(const float* t);
   float* cond_ = nullptr;         // conditioning windows of a batch
   static constexpr int kExtraSigmas = 8;
   std::vector<double> extra_sigma_;
@@ -153,9 +163,12 @@ class Model {
   const uint16_t* upload_frag(const std::vector<float>& w, int co, int ci, int k);
   const uint8_t* upload_fp8(const std::vector<float>& w, int co, int ci, int k, const float** scale);
   int cin_max(int lvl) const;
+  // With track set, the output's per-channel sums are written where the
+  // halo-staged kernel runs, and out's ChStats (if any) records whether they
+  // were.
   void conv_lp(hipStream_t st, const uint16_t* act, int cin, int nb, int lr, int cout, int taps,
                const uint16_t* wt, const uint8_t* w8, const float* w8s, int kp, const float* bias,
-               const float* res, float* out, const uint16_t* wfrag = nullptr);
+               const float* res, float* out, const uint16_t* wfrag = nullptr, bool track = false);
   // conv1 of a BF16 residual block through the fused epilogue: BF16 output
   // into out16 and the GroupNorm sums of gn2 into gn_part_; false (nothing
   // launched) where the halo-staged kernel does not apply.
@@ -171,6 +184,10 @@ class Model {
                   const std::map<std::string, std::vector<int>>& shapes, hipStream_t st);
   void gn(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int nb, int lh, int lw,
           const float* g, const float* b);
+  // gn's affine, from the producers' per-channel sums when both sources
+  // carry valid ones, else through the statistics pass
+  void gn_stats(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int nb, int lh, int lw,
+                const float* g, const float* b);
   void resblock(hipStream_t st, const ResBlockW& w, int k, const float* s0, int c0, int up0, const float* s1,
                 int c1, int nb, int lvl, float* out);
   void attention(hipStream_t st, const AttnW& w, const float* in, int nb, int lvl, float* out);

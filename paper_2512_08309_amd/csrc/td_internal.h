@@ -161,6 +161,12 @@ struct ConvLpArgs {
   uint16_t* out16;
   double* stats;
   int groups;
+  // set (FP32 output, with or without the residual): the output's per-
+  // channel sums (sum, sum of squares, FP64) per (window, tile of the
+  // window): [nb][conv_lp_stat_slots(lh + lw)][cout][2].  They let the
+  // next GroupNorm over this tensor, alone or concatenated, skip its
+  // statistics pass (launch_gn_finalize_ch).
+  double* chstats;
 };
 void launch_conv_lp(hipStream_t st, const ConvLpArgs& a);
 bool conv_lp_fused_ok(const ConvLpArgs& a);
@@ -219,6 +225,12 @@ void launch_gn(hipStream_t st, const GnArgs& a);
 // ([nb][nchunk][groups][2] sums and sums of squares), e.g. written by a
 // convolution's epilogue.
 void launch_gn_finalize(hipStream_t st, const GnArgs& a, int nchunk);
+// scale/shift (and mean/rstd) of a GroupNorm over concat(src0, src1) (src0
+// nearest-upsampled when a.up0) from the per-channel sums the producers of
+// the two tensors wrote ([nb][slots][C][2], ConvLpArgs::chstats); a.src0 and
+// a.src1 are not read.
+void launch_gn_finalize_ch(hipStream_t st, const GnArgs& a, const double* ch0, int slots0, const double* ch1,
+                           int slots1);
 // GroupNorm statistics and apply (+ SiLU for act 2; act 1 affine only) of
 // whole small windows in one pass, written as BF16 (out) or FP32 (out32);
 // the partial/scale/shift fields of g are not used.  Fits when the window's

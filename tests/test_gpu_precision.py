@@ -140,3 +140,22 @@ def test_bf16_seed_consistency_bit_exact(lp_ctx):
     finally:
         c.set_option("batch", 4096)
     assert np.array_equal(small, big[:, 21:51, 33:62])
+
+
+def test_bf16_c2_window_batch_invariant_bit_exact(lp_ctx, weights):
+    # C2 in BF16 runs every convolution on the halo-staged kernel (8x8
+    # windows share tiles four at a time) and takes most GroupNorm statistics
+    # from the producing convolution's per-tile sums: a window's estimate must
+    # not depend on the other windows of its batch.
+    import torch
+    c = lp_ctx("c2", 1)
+    m = Model(weights("c2"))
+    H, C = m.H, m.C
+    x = (m.sched[3] * np.random.default_rng(41).standard_normal((5, H, H, C))).astype(np.float32)
+    xd = torch.from_numpy(x).cuda()
+    out5 = torch.empty_like(xd)
+    c.denoise_windows(xd, 3, out5)
+    one = xd[2:3].contiguous()
+    out1 = torch.empty_like(one)
+    c.denoise_windows(one, 3, out1)
+    assert np.array_equal(out5[2].cpu().numpy(), out1[0].cpu().numpy())
