@@ -525,7 +525,10 @@ __device__ __forceinline__ void unroll(F& f) {
   unroll_seq(f, std::make_integer_sequence<int, N>{});
 }
 
-template <int L, int P, int TAPS>
+// SKIP (TAPS = 9): after the 3x3 chunks over act, 1x1 chunks over act2
+// (cin2 channels) run on the centre tap of the same patch layout; their
+// weights follow the 3x3 ones in K.
+template <int L, int P, int TAPS, bool SKIP>
 __global__ __launch_bounds__(256, 2) void conv_bf16_halo_kernel(ConvLpArgs a, int n_tiles_n) {
   using G = HaloGeom<L, TAPS>;
   constexpr int STEPS = 2 * TAPS;                  // 16-value K steps per 32-channel chunk
@@ -548,7 +551,8 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_halo_kernel(ConvLpArgs a, in
   const int m0 = tm * 256, n0 = tn * 128;
   const int M = a.nb << (2 * L);
   const int cin = a.cin;
-  const int KB = TAPS * cin / 16;                  // 16-value K blocks
+  const int cin2 = SKIP ? a.cin2 : 0;
+  const int KB = (TAPS * cin + cin2) / 16;         // 16-value K blocks
   const u4v* act = reinterpret_cast<const u4v*>(a.act);
   const u4v* wf = reinterpret_cast<const u4v*>(a.wfrag);
 
@@ -556,10 +560,10 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_halo_kernel(ConvLpArgs a, in
   // is segment slot % 5 of halo pixel slot / 5 (segment 4 is padding; slots
   // past the halo are loaded and stored too, as zeros, so that every wave
   // issues the same loads with no branches around them).
-  // hoff: its 16-byte index in the activations at chunk 0, or ~0 for zeros.
+  // hpack: 8 x its pixel index + its segment, or ~0 for zeros.
   const int b0 = m0 >> (2 * L);                    // first image of the tile
   const int row0 = (G::NI == 1) ? ((m0 >> L) & (W - 1)) : 0;
-  uint32_t hoff[G::NPL];
+  uint32_t hpack[G::NPL];
 #pragma unroll
   for (int j = 0; j < G::NPL; ++j) {
     const int ins = wave + 4 * j;
@@ -569,15 +573,23 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_halo_kernel(ConvLpArgs a, in
     const int hy = rem / QW, hx = rem - hy * QW;
     const int y = row0 + hy - G::BORDER, x = hx - G::BORDER, b = b0 + img;
     const bool ok = ins < G::NINS && seg < 4 && q < G::NQ && b < a.nb && y >= 0 && y < W && x >= 0 && x < W;
-    hoff[j] = ok ? (uint32_t)((((size_t)b * W + y) * W + x) * (cin / 8) + seg) : ~0u;
+    hpack[j] = ok ? (uint32_t)((((b * W + y) * W + x) << 3) + seg) : ~0u;
   }
   u4v hreg[G::NPL];
   typedef const __attribute__((address_space(1))) u4v gu4v;
-  gu4v* gact = (gu4v*)act;
   gu4v* gzero = (gu4v*)in_sgprs(g_zero16);
-  auto load_halo = [&](int c0) {
+  const int nch_a = cin / 32, nch = nch_a + cin2 / 32;   // 3x3 (or 1x1) chunks, all chunks
+  // the patch of chunk g (past the last: the last again, unused, so that no
+  // branch surrounds the loads)
+  auto load_halo = [&](int g) {
+    g = g < nch ? g : nch - 1;
+    const bool second = SKIP && g >= nch_a;
+    gu4v* src = (gu4v*)(second ? reinterpret_cast<const u4v*>(a.act2) : act);
+    const int q8 = second ? cin2 / 8 : cin / 8;
+    const int c8 = 4 * (second ? g - nch_a : g);
 #pragma unroll
-    for (int j = 0; j < G::NPL; ++j) hreg[j] = *(hoff[j] != ~0u ? gact + ((size_t)hoff[j] + c0 / 8) : gzero);
+    for (int j = 0; j < G::NPL; ++j)
+      hreg[j] = *(hpack[j] != ~0u ? src + ((size_t)(hpack[j] >> 3) * q8 + (hpack[j] & 7) + c8) : gzero);
   };
   auto store_halo = [&](int buf) {
 #pragma unroll
@@ -599,13 +611,18 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_halo_kernel(ConvLpArgs a, in
   const u4v* wrow[TN];
 #pragma unroll
   for (int j = 0; j < TN; ++j) wrow[j] = wf + ((size_t)((n0 >> 5) + 2 * wn + j) * KB) * 64 + lane;
-  const int nchunk = cin / 32;
-  const int NS = nchunk * STEPS;
+  const int NA = nch_a * STEPS;                    // K steps of the first source
+  const int NS = NA + 2 * (nch - nch_a);
   u4v bq[P][TN];
   auto issue_b = [&](int slot, int step) {
-    // steps past the last one (last chunk only) load block 0, unused
-    const int ch = step / STEPS, r = step - STEPS * ch;
-    const int kb = step < NS ? ((r >> 1) * cin + 32 * ch) / 16 + (r & 1) : 0;
+    // steps past the last one load block 0, unused
+    int kb = 0;
+    if (step < NA) {
+      const int ch = step / STEPS, r = step - STEPS * ch;
+      kb = ((r >> 1) * cin + 32 * ch) / 16 + (r & 1);
+    } else if (step < NS) {
+      kb = (TAPS * cin) / 16 + (step - NA);
+    }
 #pragma unroll
     for (int j = 0; j < TN; ++j) bq[slot][j] = wrow[j][(size_t)kb * 64];
   };
@@ -624,11 +641,13 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_halo_kernel(ConvLpArgs a, in
   for (int s = 0; s < P; ++s) issue_b(s, s);
   __syncthreads();
 
-  for (int ch = 0; ch < nchunk; ++ch) {
-    const int buf = ch & 1;
-    // the next chunk's halo (the last chunk reloads its own, unused: no
-    // branch around the loads)
-    load_halo(ch + 1 < nchunk ? 32 * (ch + 1) : 32 * ch);
+  // one chunk: NSTEP K steps over patch buffer g & 1, the first at global
+  // step step0; CENTER: the 1x1 chunks of the second source (centre tap)
+  auto chunk = [&](auto nstep_c, auto center_c, int g, int step0) {
+    constexpr int NSTEP = decltype(nstep_c)::value;
+    constexpr bool CENTER = decltype(center_c)::value;
+    const int buf = g & 1;
+    load_halo(g + 1);
     const uint32_t boff = buf * (SLOTS * 16);
     uint32_t ab[TM];
 #pragma unroll
@@ -636,7 +655,7 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_halo_kernel(ConvLpArgs a, in
     // the A operands of step r + 1 are read while the MFMAs of step r run
     auto read_a = [&](auto rc, u4v* av) {
       constexpr int r = decltype(rc)::value;
-      constexpr int tap = r >> 1, half = r & 1;
+      constexpr int tap = CENTER ? 4 : r >> 1, half = r & 1;
       constexpr int OFF = 80 * ((tap / 3) * QW + tap % 3) + 32 * half;
 #pragma unroll
       for (int i = 0; i < TM; ++i) av[i] = ds_read16_off<OFF>(ab[i]);
@@ -645,13 +664,13 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_halo_kernel(ConvLpArgs a, in
     read_a(std::integral_constant<int, 0>{}, acur);
     auto step = [&](auto rc) {
       constexpr int r = decltype(rc)::value;
-      if constexpr (r + 1 < STEPS) read_a(std::integral_constant<int, r + 1>{}, anext);
+      if constexpr (r + 1 < NSTEP) read_a(std::integral_constant<int, r + 1>{}, anext);
       u4v bv[TN];
 #pragma unroll
       for (int j = 0; j < TN; ++j) bv[j] = bq[r % P][j];
-      issue_b(r % P, STEPS * ch + r + P);
+      issue_b(r % P, step0 + r + P);
       // LDS reads complete in order: at most the next step's TM are pending
-      if constexpr (r + 1 < STEPS) lgkm_wait4<TM>(acur[0], acur[1], acur[2], acur[3]);
+      if constexpr (r + 1 < NSTEP) lgkm_wait4<TM>(acur[0], acur[1], acur[2], acur[3]);
       else lgkm_wait4<0>(acur[0], acur[1], acur[2], acur[3]);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -664,12 +683,17 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_halo_kernel(ConvLpArgs a, in
 #pragma unroll
       for (int i = 0; i < TM; ++i) acur[i] = anext[i];
     };
-    unroll<STEPS>(step);
+    unroll<NSTEP>(step);
     // the next chunk's patch goes to the other buffer, which every wave
     // finished reading before the previous barrier
     store_halo(buf ^ 1);
     lds_barrier();
-  }
+  };
+  for (int g = 0; g < nch_a; ++g)
+    chunk(std::integral_constant<int, STEPS>{}, std::false_type{}, g, STEPS * g);
+  if constexpr (SKIP)
+    for (int g = nch_a; g < nch; ++g)
+      chunk(std::integral_constant<int, 2>{}, std::true_type{}, g, NA + 2 * (g - nch_a));
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // the unused last prefetches
 
   // ---- epilogue: tile (i, j) register e holds row 8 (e / 4) + 4 (lane / 32)
@@ -880,8 +904,12 @@ template <int L>
 void launch_halo(hipStream_t st, const ConvLpArgs& a) {
   const int M = a.nb << (2 * L);
   const int mt = (M + 255) / 256, nt = a.cout / 128;
-  if (a.taps == 9) hipLaunchKernelGGL((conv_bf16_halo_kernel<L, 2, 9>), dim3(mt * nt), dim3(256), 0, st, a, nt);
-  else hipLaunchKernelGGL((conv_bf16_halo_kernel<L, 2, 1>), dim3(mt * nt), dim3(256), 0, st, a, nt);
+  if (a.taps == 9 && a.act2)
+    hipLaunchKernelGGL((conv_bf16_halo_kernel<L, 2, 9, true>), dim3(mt * nt), dim3(256), 0, st, a, nt);
+  else if (a.taps == 9)
+    hipLaunchKernelGGL((conv_bf16_halo_kernel<L, 2, 9, false>), dim3(mt * nt), dim3(256), 0, st, a, nt);
+  else
+    hipLaunchKernelGGL((conv_bf16_halo_kernel<L, 2, 1, false>), dim3(mt * nt), dim3(256), 0, st, a, nt);
   TD_LAUNCHED();
 }
 
@@ -908,10 +936,19 @@ void launch_lp_w(hipStream_t st, const ConvLpArgs& a, bool fast) {
 
 }  // namespace
 
+namespace {
+// the halo-staged kernel's shapes: square images of side 8..64, C_in % 32 ==
+// 0, C_out % 128 == 0, fragment-ordered BF16 weights, fewer than 2^28 pixels
+bool halo_shape(const ConvLpArgs& a) {
+  return a.wfrag && !a.w8 && a.lh == a.lw && a.lw >= 3 && a.lw <= 6 && a.cin % 32 == 0 && a.cout % 128 == 0 &&
+         ((int64_t)a.nb << (a.lh + a.lw)) < ((int64_t)1 << 28);
+}
+}  // namespace
+
 bool conv_lp_fused_ok(const ConvLpArgs& a) {
-  const bool halo = a.wfrag && !a.w8 && a.lh == a.lw && a.lw >= 3 && a.lw <= 6 && a.cin % 32 == 0 &&
-                    a.cout % 128 == 0;
+  const bool halo = halo_shape(a);
   if (!halo || (a.out16 && a.res)) return false;
+  if (a.act2 && (a.taps != 9 || a.cin2 < 32 || a.cin2 % 32 != 0)) return false;
   if (a.chstats && (a.out16 || a.stats)) return false;
   if (!a.stats) return true;
   const int gs = a.groups > 0 && a.cout % a.groups == 0 ? a.cout / a.groups : 0;
@@ -935,10 +972,9 @@ void launch_conv_lp(hipStream_t st, const ConvLpArgs& a) {
   // fragment-ordered BF16 weights: the halo-staged kernel (3x3 and 1x1).
   // Other 3x3 shapes with C_in % 32 == 0: the direct-to-LDS ring; the rest
   // (and FP8 weights): the register-staged kernel.
-  const bool halo = a.wfrag && !a.w8 && a.lh == a.lw && a.lw >= 3 && a.lw <= 6 && a.cin % 32 == 0 &&
-                    a.cout % 128 == 0;
-  TD_CHECK(!(a.out16 || a.stats || a.chstats) || conv_lp_fused_ok(a), -5,
-           "bf16 conv: a BF16 output or GroupNorm sums need the halo-staged kernel");
+  const bool halo = halo_shape(a);
+  TD_CHECK(!(a.out16 || a.stats || a.chstats || a.act2) || conv_lp_fused_ok(a), -5,
+           "bf16 conv: a BF16 output, GroupNorm sums or a fused 1x1 need the halo-staged kernel");
   if (halo && a.lw == 6) launch_halo<6>(st, a);
   else if (halo && a.lw == 5) launch_halo<5>(st, a);
   else if (halo && a.lw == 4) launch_halo<4>(st, a);
@@ -949,8 +985,10 @@ void launch_conv_lp(hipStream_t st, const ConvLpArgs& a) {
   else if (a.cout % 64 == 0) launch_lp_w<64, 2, 2>(st, a, fast);
   else if (a.cout % 32 == 0) launch_lp_w<32, 4, 1>(st, a, fast);
   else launch_lp_w<16, 4, 1>(st, a, fast);
-  prof_end(st, a.taps == 9 ? K_CONV3_LP : K_CONV1_LP, 2.0 * Md * a.cout * a.taps * a.cin,
-           2.0 * Md * a.cin + 2.0 * a.kp * a.cout + (a.out16 ? 2.0 : 4.0) * Md * a.cout + (a.res ? 4.0 * Md * a.cout : 0.0));
+  const double cin2 = a.act2 ? a.cin2 : 0.0;
+  prof_end(st, a.taps == 9 ? K_CONV3_LP : K_CONV1_LP, 2.0 * Md * a.cout * (a.taps * a.cin + cin2),
+           2.0 * Md * (a.cin + cin2) + 2.0 * (a.kp + cin2) * a.cout + (a.out16 ? 2.0 : 4.0) * Md * a.cout +
+               (a.res ? 4.0 * Md * a.cout : 0.0));
 }
 
 }  // namespace td

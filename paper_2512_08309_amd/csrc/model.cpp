@@ -75,6 +75,22 @@ const uint16_t* Model::upload_frag(const std::vector<float>& w, int co, int ci, 
   return (const uint16_t*)p;
 }
 
+const uint16_t* Model::upload_frag_cat(const std::vector<float>& w3, const std::vector<float>& w1, int co, int ci) {
+  TD_CHECK(ci % 16 == 0 && co % 32 == 0, -5, "fragment-ordered weights need C_in % 16 == 0 and C_out % 32 == 0");
+  const int K = 9 * co + ci;
+  std::vector<uint16_t> r((size_t)co * K);
+  for (int o = 0; o < co; ++o) {
+    for (int i = 0; i < co; ++i)
+      for (int t = 0; t < 9; ++t) r[conv_lp_frag_index(o, t * co + i, K)] = to_bf16(w3[((size_t)o * co + i) * 9 + t]);
+    for (int i = 0; i < ci; ++i) r[conv_lp_frag_index(o, 9 * co + i, K)] = to_bf16(w1[(size_t)o * ci + i]);
+  }
+  void* p = nullptr;
+  TD_HIP(hipMalloc(&p, r.size() * sizeof(uint16_t)));
+  allocs_.push_back(p);
+  TD_HIP(hipMemcpy(p, r.data(), r.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+  return (const uint16_t*)p;
+}
+
 namespace {
 // Nearest OCP FP8 e4m3 code (round half to even) of x, |x| <= 448 expected
 // (saturates).  Normal: (1 + m/8) 2^(e-7), e = 1..15 (e = 15, m = 7 is NaN);
@@ -265,7 +281,14 @@ void Model::build_unet(const std::map<std::string, std::vector<float>>& host,
       w.wskip = conv_layout(p + "skip.weight", cout, cin, 1);
       w.bskip = vec(p + "skip.bias", cout);
       w.wskip_lp = lp(p + "skip.weight", cout, cin, 1, &w.kps);
-      if (cout % 128 == 0 && cin % 32 == 0) w.wskip_fr = upload_frag(get(p + "skip.weight", {cout, cin, 1, 1}), cout, cin, 1);
+      if (cout % 128 == 0 && cin % 32 == 0) {
+        w.wskip_fr = upload_frag(get(p + "skip.weight", {cout, cin, 1, 1}), cout, cin, 1);
+        w.w2s_fr = upload_frag_cat(get(p + "conv2.weight", {cout, cout, 3, 3}),
+                                   get(p + "skip.weight", {cout, cin, 1, 1}), cout, cin);
+        std::vector<float> b2 = get(p + "conv2.bias", {cout}), bs = get(p + "skip.bias", {cout});
+        for (int o = 0; o < cout; ++o) b2[o] += bs[o];
+        w.b2s = upload(b2);
+      }
       w.wskip_8 = f8(p + "skip.weight", cout, cin, 1, &w.sskip_8);
     }
     TD_CHECK(cin % d.groups == 0 && cout % d.groups == 0, -5, "GroupNorm groups must divide channels");
@@ -635,6 +658,38 @@ bool Model::conv1_fused(hipStream_t st, const ResBlockW& w, const uint16_t* act,
   return true;
 }
 
+bool Model::conv2_skip_fused(hipStream_t st, const ResBlockW& w, const uint16_t* act, const uint16_t* act2, int nb,
+                             int lr, float* out) {
+  if (prec_ != 1 || !w.w2s_fr) return false;
+  ConvLpArgs a{};
+  a.act = act;
+  a.cin = w.cout;
+  a.act2 = act2;
+  a.cin2 = w.cin;
+  a.nb = nb;
+  a.lh = lr;
+  a.lw = lr;
+  a.cout = w.cout;
+  a.taps = 9;
+  a.kp = conv_lp_kp(9, w.cout);
+  a.wt = w.w2_lp;
+  a.wfrag = w.w2s_fr;
+  a.bias = w.b2s;
+  a.out = out;
+  if (!conv_lp_fused_ok(a)) return false;
+  ChStats* cs = chstats_of(out);
+  if (cs) {
+    a.chstats = cs->buf;
+    if (!conv_lp_fused_ok(a) || conv_lp_stat_slots(2 * lr) != cs->slots) a.chstats = nullptr;
+  }
+  launch_conv_lp(st, a);
+  if (cs) {
+    cs->valid = a.chstats != nullptr;
+    cs->C = w.cout;
+  }
+  return true;
+}
+
 void Model::apply(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int act, int nb, int lr,
                   uint16_t* out, float* out32, uint16_t* raw) {
   ApplyArgs a{};
@@ -699,14 +754,19 @@ void Model::resblock(hipStream_t st, const ResBlockW& w, int k, const float* s0,
     const float* res = s0;
     if (w.has_skip) {
       if (!raw_in_apply) apply(st, s0, c0, up0, s1, c1, 0, nb, lr, B.A0);
-      conv_lp(st, B.A0, w.cin, nb, lr, w.cout, 1, w.wskip_lp, w.wskip_8, w.sskip_8, w.kps, w.bskip, nullptr, B.R,
-              w.wskip_fr);
-      res = B.R;
     } else {
       TD_CHECK(c1 == 0 && !up0, -5, "identity skip needs a plain input");
     }
     if (fused) launch_apply_bf16(st, T16, w.cout, gn_scale_, gn_shift_, 2, nb, lr, lr, B.A);
     else gn_apply(st, B.T, w.cout, 0, nullptr, 0, nb, lr, w.gn2_g, w.gn2_b, 2, B.A, nullptr);
+    // with a 1x1 skip: conv2 and the skip projection in one launch where the
+    // halo-staged kernel applies (no skip output and no residual read)
+    if (w.has_skip && conv2_skip_fused(st, w, B.A, B.A0, nb, lr, out)) return;
+    if (w.has_skip) {
+      conv_lp(st, B.A0, w.cin, nb, lr, w.cout, 1, w.wskip_lp, w.wskip_8, w.sskip_8, w.kps, w.bskip, nullptr, B.R,
+              w.wskip_fr);
+      res = B.R;
+    }
     conv_lp(st, B.A, w.cout, nb, lr, w.cout, 9, w.w2_lp, w.w2_8, w.s2_8, w.kp2, w.b2, res, out, w.w2_fr, true);
     return;
   }

@@ -24,6 +24,11 @@ struct ResBlockW {
   // the weights again in MFMA fragment order (null where the halo-staged
   // kernel does not apply)
   const uint16_t *w1_fr = nullptr, *w2_fr = nullptr, *wskip_fr = nullptr;
+  // conv2 and the skip projection as one convolution (K = 9 cout + cin,
+  // fragment order) with bias b2 + bskip; null where the halo-staged
+  // kernel does not apply
+  const uint16_t* w2s_fr = nullptr;
+  const float* b2s = nullptr;
   // FP8 e4m3 weights, same layout, with per-output-channel scales
   const uint8_t *w1_8 = nullptr, *w2_8 = nullptr, *wskip_8 = nullptr;
   const float *s1_8 = nullptr, *s2_8 = nullptr, *sskip_8 = nullptr;
@@ -161,6 +166,8 @@ class Model {
   const float* upload(const std::vector<float>& v);
   const uint16_t* upload_lp(const std::vector<float>& w, int co, int ci, int k, int* kp);
   const uint16_t* upload_frag(const std::vector<float>& w, int co, int ci, int k);
+  // [co][9 co] 3x3 weights followed in K by [co][ci] 1x1 weights, fragment order
+  const uint16_t* upload_frag_cat(const std::vector<float>& w3, const std::vector<float>& w1, int co, int ci);
   const uint8_t* upload_fp8(const std::vector<float>& w, int co, int ci, int k, const float** scale);
   int cin_max(int lvl) const;
   // With track set, the output's per-channel sums are written where the
@@ -174,6 +181,11 @@ class Model {
   // launched) where the halo-staged kernel does not apply.
   bool conv1_fused(hipStream_t st, const ResBlockW& w, const uint16_t* act, int nb, int lr, const float* bias,
                    uint16_t* out16);
+  // conv2 of a BF16 residual block with a 1x1 skip: one halo-staged launch
+  // over (act, conv2 taps) then (act2, skip weights) into out, with its
+  // per-channel sums; false (nothing launched) where that kernel does not apply
+  bool conv2_skip_fused(hipStream_t st, const ResBlockW& w, const uint16_t* act, const uint16_t* act2, int nb, int lr,
+                        float* out);
   void apply(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int act, int nb,
              int lr, uint16_t* out, float* out32 = nullptr, uint16_t* raw = nullptr);
   void gn_apply(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int nb, int lr,

@@ -167,6 +167,12 @@ struct ConvLpArgs {
   // next GroupNorm over this tensor, alone or concatenated, skip its
   // statistics pass (launch_gn_finalize_ch).
   double* chstats;
+  // set (3x3, halo-staged kernel only): a 1x1 convolution of act2 ([nb][h][w]
+  // [cin2] BF16, cin2 % 32 == 0) is added in the same accumulators, its
+  // weights following the 3x3 ones in K (fragment order over K = 9 cin +
+  // cin2): a residual block's conv2 plus its skip projection in one pass.
+  const uint16_t* act2;
+  int cin2;
 };
 void launch_conv_lp(hipStream_t st, const ConvLpArgs& a);
 bool conv_lp_fused_ok(const ConvLpArgs& a);
