@@ -5,7 +5,8 @@
 //
 //   kbench f32  L CIN COUT NB RES      3x3 FP32 (launch_conv), RES = 1 adds a residual input
 //   kbench bf16 L CIN COUT NB TAPS OUT BF16 halo-staged (launch_conv_lp), TAPS 9 or 1,
-//                                      OUT 0 = FP32 output, 1 = BF16 output + GroupNorm sums
+//                                      OUT 0 = FP32 output, 1 = BF16 output + GroupNorm sums,
+//                                      2 = FP32 output + a residual input
 //
 // Square images of side 2^L, NB windows; one warm-up and one timed launch.
 #include <hip/hip_runtime.h>
@@ -93,7 +94,7 @@ int main(int argc, char** argv) {
   const int opt = std::atoi(argv[6]);
   const int taps = f32 ? 9 : opt;
   const int out_mode = (!f32 && argc > 7) ? std::atoi(argv[7]) : 0;
-  if (L < 3 || L > 6 || cin < 32 || cout < 128 || nb < 1 || (taps != 9 && taps != 1)) {
+  if (L < 3 || L > 6 || cin < 32 || cout < 128 || nb < 1 || (taps != 9 && taps != 1) || out_mode < 0 || out_mode > 2) {
     std::fprintf(stderr, "kbench: shape out of range\n");
     return 2;
   }
@@ -160,15 +161,21 @@ int main(int argc, char** argv) {
       a.wt = dwl;
       a.wfrag = dwf;
       a.bias = db;
-      if (out_mode) {
+      if (out_mode == 1) {
         KB_CHECK(hipMalloc(&a.out16, M * cout * sizeof(uint16_t)));
         KB_CHECK(hipMalloc(&a.stats, (size_t)nb * 16 * 32 * 2 * sizeof(double)));
         a.groups = 32;
       } else {
         KB_CHECK(hipMalloc(&a.out, M * cout * sizeof(float)));
       }
+      if (out_mode == 2) {
+        float* dr = nullptr;
+        KB_CHECK(hipMalloc(&dr, M * cout * sizeof(float)));
+        KB_CHECK(hipMemset(dr, 0, M * cout * sizeof(float)));
+        a.res = dr;
+      }
       ms = time_once([&] { launch_conv_lp(nullptr, a); });
-      bytes = 2.0 * M * cin + 2.0 * K * cout + (out_mode ? 2.0 : 4.0) * M * cout;
+      bytes = 2.0 * M * cin + 2.0 * K * cout + (out_mode == 1 ? 2.0 : 4.0) * M * cout + (out_mode == 2 ? 4.0 * M * cout : 0.0);
     }
   } catch (const Error& e) {
     std::fprintf(stderr, "kbench: %s\n", e.msg.c_str());

@@ -24,7 +24,8 @@ run() {   # name, counters..., -- kbench args
   echo "$name done"
 }
 for spec in "f32_l0res f32 6 128 128 1024 1" "f32_l1 f32 5 256 256 1024 0" "bf16_l0 bf16 6 128 128 1024 9 0" \
-            "bf16_l0fused bf16 6 128 128 1024 9 1" "bf16_l1 bf16 5 256 256 1024 9 0"; do
+            "bf16_l0fused bf16 6 128 128 1024 9 1" "bf16_l0res bf16 6 128 128 1024 9 2" \
+            "bf16_l1 bf16 5 256 256 1024 9 0"; do
   set -- $spec
   name=$1; shift
   run ${name}_fetch FETCH_SIZE -- "$@"
