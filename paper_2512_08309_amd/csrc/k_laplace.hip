@@ -12,10 +12,11 @@
 // resolution.  There is no padding: the latent covers a 17-pixel apron.
 //
 // Stages: (1) down8(P) per latent block as a 3x3 stencil on the latent;
-// (2) vertical then (3) horizontal 31-tap blur at latent
-// resolution; (4) the full-resolution pass, 8 x 1024-pixel tiles with their
-// inputs staged in LDS, which is the HBM-bound one (4 B written per pixel,
-// the latent read once).
+// (2) vertical then (3) horizontal 31-tap blur at latent resolution -- one
+// LDS-tiled launch for blur radii up to 24, two beyond; (4) the
+// full-resolution pass, 8 x 1024-pixel tiles with their inputs staged in
+// LDS, which is the HBM-bound one (4 B written per pixel, the latent read
+// once).
 #include "td_internal.h"
 
 #include <mutex>
@@ -46,13 +47,8 @@ inline Span span_of(const DecodeArgs& a) {
 // stencil [1, 6, 1]/8 on the latent grid; the residual contributes
 // sum_k r_k * mean(beta_k) (the atom means are zero up to rounding of the
 // table).  Block origin relative to the latent origin: (bx0 + i, by0 + j).
-__global__ __launch_bounds__(256) void down_p_kernel(const float* __restrict__ lat, int lw, int C, float sl,
-                                                     float sr, const float* __restrict__ atom_mean, int bx0,
-                                                     int by0, int nx, int ny, float* __restrict__ D) {
-  int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= nx * ny) return;
-  int j = e / nx, i = e % nx;
-  const int x = bx0 + i, y = by0 + j;
+__device__ __forceinline__ float down_p_at(const float* __restrict__ lat, int lw, int C, float sl, float sr,
+                                           const float* __restrict__ atom_mean, int x, int y) {
   const float* r0 = lat + ((size_t)(y - 1) * lw + x - 1) * C;
   const float* r1 = r0 + (size_t)lw * C;
   const float* r2 = r1 + (size_t)lw * C;
@@ -63,7 +59,16 @@ __global__ __launch_bounds__(256) void down_p_kernel(const float* __restrict__ l
   int nk = C - 1 < 3 ? C - 1 : 3;
   float h = 0.f;
   for (int k = 0; k < nk; ++k) h += r1[C + 1 + k] * atom_mean[k];
-  D[e] = d + sr * h;
+  return d + sr * h;
+}
+
+__global__ __launch_bounds__(256) void down_p_kernel(const float* __restrict__ lat, int lw, int C, float sl,
+                                                     float sr, const float* __restrict__ atom_mean, int bx0,
+                                                     int by0, int nx, int ny, float* __restrict__ D) {
+  int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= nx * ny) return;
+  int j = e / nx, i = e % nx;
+  D[e] = down_p_at(lat, lw, C, sl, sr, atom_mean, bx0 + i, by0 + j);
 }
 
 // (2) vertical blur: out[j][i] = sum_t g[t] in[j + t][i], out rows ny_out
@@ -87,6 +92,59 @@ __global__ __launch_bounds__(256) void blur_h_kernel(const float* __restrict__ i
   for (int t = 0; t <= 2 * R; ++t) s += g[t] * in[(size_t)j * nx_in + i + t];
   out[e] = s;
 }
+
+// (2) and (3) in one launch for blur radii up to kFusedR: a workgroup makes
+// a kBx x kBy tile of the blurred grid.  Its input patch of the D grid
+// [nyD][nxD] (the tile plus the 2R apron) goes to LDS, the vertical pass
+// into a second LDS array, then the horizontal pass to out [ny][nx], every
+// sum taking its taps in the order of blur_v_kernel and blur_h_kernel (the
+// results are the two kernels' bit for bit).  nxD = nx + 2R, nyD = ny + 2R.
+constexpr int kBx = 64, kBy = 32, kFusedR = 24;
+__global__ __launch_bounds__(256) void blur2d_kernel(const float* __restrict__ src, int nxD, int nyD,
+                                                     const float* __restrict__ g, int R, int nx, int ny,
+                                                     float* __restrict__ out) {
+  extern __shared__ float sm[];
+  const int TXR = kBx + 2 * R, TYR = kBy + 2 * R;
+  float* in = sm;                      // [TYR][TXR]
+  float* V = sm + TYR * TXR;           // [kBy][TXR]
+  const int x0 = blockIdx.x * kBx, y0 = blockIdx.y * kBy;
+  // U patch elements per thread in flight; positions past the grid are
+  // clamped into it (their values feed only outputs past nx, ny, which are
+  // not written), so every load is unconditional
+  constexpr int U = 8;
+  const int n_in = TYR * TXR;
+  for (int e0 = threadIdx.x; e0 < n_in; e0 += 256 * U) {
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = min(e0 + 256 * u, n_in - 1);
+      const int r = e / TXR, c = e - r * TXR;
+      const int i = min(x0 + c, nxD - 1), j = min(y0 + r, nyD - 1);
+      v[u] = src[(size_t)j * nxD + i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (e0 + 256 * u < n_in) in[e0 + 256 * u] = v[u];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kBy * TXR; e += 256) {
+    const int r = e / TXR, c = e - r * TXR;
+    float acc = 0.f;
+    for (int t = 0; t <= 2 * R; ++t) acc += g[t] * in[(r + t) * TXR + c];
+    V[e] = acc;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kBy * kBx; e += 256) {
+    const int r = e / kBx, c = e - r * kBx;
+    const int i = x0 + c, j = y0 + r;
+    if (i >= nx || j >= ny) continue;
+    float acc = 0.f;
+    for (int t = 0; t <= 2 * R; ++t) acc += g[t] * V[r * TXR + c + t];
+    out[(size_t)j * nx + i] = acc;
+  }
+}
+
+size_t blur2d_lds_bytes(int R) { return sizeof(float) * (size_t)(kBx + 2 * R) * (kBy + 2 * R + kBy); }
 
 // (4) full resolution: z = up8(L_hat) + Hres, elevation = sign(z) z^2.
 // A workgroup writes a tile of 8 rows x 1024 columns; the L_hat rows and
@@ -265,18 +323,30 @@ void launch_decode(hipStream_t st, const DecodeArgs& a) {
   const int nx = (int)(s.xh - s.xl + 1), ny = (int)(s.yh - s.yl + 1);
   const int bx0 = (int)(s.xl - R - a.lx0), by0 = (int)(s.yl - R - a.ly0);
   prof_begin(st);
-  hipLaunchKernelGGL(down_p_kernel, dim3((nxD * nyD + 255) / 256), dim3(256), 0, st, a.latent, a.lw, a.C,
-                     a.sigma_low, a.sigma_res, a.atoms + 3 * 64, bx0, by0, nxD, nyD, a.work0);
-  TD_LAUNCHED();
-  hipLaunchKernelGGL(blur_v_kernel, dim3((nxD * ny + 255) / 256), dim3(256), 0, st, a.work0, nxD, ny, a.taps, R,
-                     a.work1);
-  TD_LAUNCHED();
-  hipLaunchKernelGGL(blur_h_kernel, dim3((nx * ny + 255) / 256), dim3(256), 0, st, a.work1, nxD, nx, ny, a.taps, R,
-                     a.work0);
-  TD_LAUNCHED();
+  const float* lhat = a.work0;
+  if (R <= kFusedR) {
+    // D into work0, then both blur passes in one launch into work1
+    hipLaunchKernelGGL(down_p_kernel, dim3((nxD * nyD + 255) / 256), dim3(256), 0, st, a.latent, a.lw, a.C,
+                       a.sigma_low, a.sigma_res, a.atoms + 3 * 64, bx0, by0, nxD, nyD, a.work0);
+    TD_LAUNCHED();
+    hipLaunchKernelGGL(blur2d_kernel, dim3((nx + kBx - 1) / kBx, (ny + kBy - 1) / kBy), dim3(256),
+                       blur2d_lds_bytes(R), st, a.work0, nxD, nyD, a.taps, R, nx, ny, a.work1);
+    TD_LAUNCHED();
+    lhat = a.work1;
+  } else {
+    hipLaunchKernelGGL(down_p_kernel, dim3((nxD * nyD + 255) / 256), dim3(256), 0, st, a.latent, a.lw, a.C,
+                       a.sigma_low, a.sigma_res, a.atoms + 3 * 64, bx0, by0, nxD, nyD, a.work0);
+    TD_LAUNCHED();
+    hipLaunchKernelGGL(blur_v_kernel, dim3((nxD * ny + 255) / 256), dim3(256), 0, st, a.work0, nxD, ny, a.taps, R,
+                       a.work1);
+    TD_LAUNCHED();
+    hipLaunchKernelGGL(blur_h_kernel, dim3((nx * ny + 255) / 256), dim3(256), 0, st, a.work1, nxD, nx, ny, a.taps, R,
+                       a.work0);
+    TD_LAUNCHED();
+  }
   const int xo = (int)(a.X0 - 8 * a.lx0), yo = (int)(a.Y0 - 8 * a.ly0);
   hipLaunchKernelGGL(decode_out_kernel, dim3((a.W + kTileW - 1) / kTileW, (a.H + kTileH - 1) / kTileH), dim3(256), 0,
-                     st, a.latent, a.lw, a.lh, a.C, a.sigma_res, a.atoms, a.work0, nx, ny, (int)(s.xl - a.lx0),
+                     st, a.latent, a.lw, a.lh, a.C, a.sigma_res, a.atoms, lhat, nx, ny, (int)(s.xl - a.lx0),
                      (int)(s.yl - a.ly0), xo, yo, a.W, a.H, a.out);
   TD_LAUNCHED();
   prof_end(st, K_DECODE, 20.0 * a.W * a.H, 4.0 * (double)a.W * a.H + 4.0 * (double)nxD * nyD * a.C);
@@ -292,14 +362,23 @@ void launch_encode(hipStream_t st, const EncodeArgs& a) {
   hipLaunchKernelGGL(enc_down_kernel, dim3((nbx * nby + 255) / 256), dim3(256), 0, st, a.height, a.W, nbx, nby,
                      a.work0);
   TD_LAUNCHED();
-  hipLaunchKernelGGL(blur_v_kernel, dim3((nbx * nly + 255) / 256), dim3(256), 0, st, a.work0, nbx, nly, a.taps, R,
-                     a.work1);
-  TD_LAUNCHED();
-  hipLaunchKernelGGL(blur_h_kernel, dim3((nlx * nly + 255) / 256), dim3(256), 0, st, a.work1, nbx, nlx, nly, a.taps,
-                     R, a.work0);
-  TD_LAUNCHED();
-  hipLaunchKernelGGL(enc_res_kernel, dim3((ow * oh + 255) / 256), dim3(256), 0, st, a.height, a.W, a.work0, nlx, ow,
-                     oh, R, a.C, 1.f / a.sigma_low, 1.f / a.sigma_res, a.atoms, a.latent);
+  const float* L = a.work0;
+  if (R <= kFusedR) {
+    // L into work1 in one launch
+    hipLaunchKernelGGL(blur2d_kernel, dim3((nlx + kBx - 1) / kBx, (nly + kBy - 1) / kBy), dim3(256),
+                       blur2d_lds_bytes(R), st, a.work0, nbx, nby, a.taps, R, nlx, nly, a.work1);
+    TD_LAUNCHED();
+    L = a.work1;
+  } else {
+    hipLaunchKernelGGL(blur_v_kernel, dim3((nbx * nly + 255) / 256), dim3(256), 0, st, a.work0, nbx, nly, a.taps, R,
+                       a.work1);
+    TD_LAUNCHED();
+    hipLaunchKernelGGL(blur_h_kernel, dim3((nlx * nly + 255) / 256), dim3(256), 0, st, a.work1, nbx, nlx, nly,
+                       a.taps, R, a.work0);
+    TD_LAUNCHED();
+  }
+  hipLaunchKernelGGL(enc_res_kernel, dim3((ow * oh + 255) / 256), dim3(256), 0, st, a.height, a.W, L, nlx, ow, oh, R,
+                     a.C, 1.f / a.sigma_low, 1.f / a.sigma_res, a.atoms, a.latent);
   TD_LAUNCHED();
   prof_end(st, K_ENCODE, 12.0 * a.W * a.H, 8.0 * (double)a.W * a.H + 4.0 * (double)ow * oh * a.C);
 }
