@@ -417,7 +417,8 @@ def micro_bench(td, torch, ctx, reps=5):
     torch.cuda.synchronize()
     enc_ms = e0.elapsed_time(e1) / reps
     return {"decode_8192": {"ms": dec_ms, "GB_per_s_written": 8192 * 8192 * 4 / (dec_ms * 1e-3) / 1e9,
-                            "note": "the decode's three kernels (block means, both blur passes in one LDS-tiled launch, full resolution); 268 MB of heightfield written"},
+                            "note": "the decode's three kernels (block means, both blur passes in one LDS-tiled "
+                                    "launch, full resolution); 268 MB of heightfield written"},
             "encode_8192": {"ms": enc_ms, "GB_per_s_read": 8192 * 8192 * 4 / (enc_ms * 1e-3) / 1e9,
                             "note": "the encode's three kernels on the decoded 8192^2 heightfield (268 MB read "
                                     "once algorithmically; the kernels read it twice) to a %dx%d latent" % (gw, gh)},
