@@ -125,6 +125,10 @@ __device__ void conv_stats_epilogue(const ConvArgs& a, double* s1, double* s2, i
 // DENSE: one source, no upsampling, no activation (the input is already
 // activated); fewer live registers, which leaves room to double-buffer the
 // LDS operand reads of consecutive k-steps.
+// Zeros that the dense path's out-of-image taps read instead of the image
+// (C_in <= kConvDenseMaxCin), so that no select follows their loads.
+__device__ __attribute__((aligned(16))) float g_conv_zero[kConvDenseMaxCin + 16];
+
 template <int TAPS, int BN, int WM, int WN, bool DENSE>
 __global__ __launch_bounds__(256, 4) void conv_kernel(ConvArgs a, int n_tiles_n) {
   constexpr int BM = 128, BK = 16, KS = BK / 4;
@@ -166,8 +170,9 @@ __global__ __launch_bounds__(256, 4) void conv_kernel(ConvArgs a, int n_tiles_n)
   }
 
   // Tap state of the chunk being loaded: per-slot base pointers of the
-  // shifted pixel in both sources.  Out-of-image pixels point at a valid
-  // pixel and are zeroed after the load (branch-free, always in bounds).
+  // shifted pixel in both sources.  Out-of-image pixels point at the zero
+  // array (dense path), or at a valid pixel and are zeroed after the load
+  // (branch-free, always in bounds).
   const float* p0[2];
   const float* p1[2];
   bool pok[2];
@@ -182,6 +187,8 @@ __global__ __launch_bounds__(256, 4) void conv_kernel(ConvArgs a, int n_tiles_n)
       pok[i] = ok;
       if (!DENSE && a.up0)
         p0[i] = a.src0 + ((((size_t)ab[i] << (lhw - 2)) + ((size_t)(yc >> 1) << (lw - 1)) + (xc >> 1)) * c0 + 4 * akq[i]);
+      else if (DENSE && !ok)
+        p0[i] = g_conv_zero + 4 * akq[i];
       else
         p0[i] = a.src0 + ((((size_t)ab[i] << lhw) + ((size_t)yc << lw) + xc) * c0 + 4 * akq[i]);
       p1[i] = (!DENSE && c1) ? a.src1 + ((((size_t)ab[i] << lhw) + ((size_t)yc << lw) + xc) * c1 + 4 * akq[i]) : a.src0;
@@ -217,7 +224,7 @@ __global__ __launch_bounds__(256, 4) void conv_kernel(ConvArgs a, int n_tiles_n)
           v.x = silu_f(v.x); v.y = silu_f(v.y); v.z = silu_f(v.z); v.w = silu_f(v.w);
         }
       }
-      if (!pok[i]) v = (f4v){0.f, 0.f, 0.f, 0.f};
+      if (!DENSE && !pok[i]) v = (f4v){0.f, 0.f, 0.f, 0.f};
       float* dst = &As[buf][(4 * akq[i]) * AS + aml[i]];
       dst[0] = v.x;
       dst[AS] = v.y;
@@ -370,7 +377,8 @@ void launch_cfg(hipStream_t st, const ConvArgs& a) {
   int M = a.nb << (a.lh + a.lw);
   int mt = (M + 127) / 128;
   int nt = a.cout / BN;
-  const bool dense = !a.src1 && !a.c1 && !a.up0 && !a.act;
+  // the dense path's out-of-image taps read g_conv_zero, which covers kConvDenseMaxCin channels
+  const bool dense = !a.src1 && !a.c1 && !a.up0 && !a.act && a.c0 <= kConvDenseMaxCin;
   if (a.taps == 9 && dense)
     hipLaunchKernelGGL((conv_kernel<9, BN, WM, WN, true>), dim3(mt * nt), dim3(256), 0, st, a, nt);
   else if (a.taps == 9)
@@ -395,7 +403,8 @@ void launch_conv(hipStream_t st, const ConvArgs& a) {
   TD_CHECK(a.cout % 16 == 0 && a.cout > 0, -5, "conv: output channels must be a multiple of 16");
   if (a.stats) {
     const int gs = a.groups > 0 && a.cout % a.groups == 0 ? a.cout / a.groups : 0;
-    TD_CHECK(a.taps == 9 && !a.src1 && !a.c1 && !a.up0 && !a.act && a.cout % 128 == 0 && gs >= 1 && gs <= 64 &&
+    TD_CHECK(a.taps == 9 && !a.src1 && !a.c1 && !a.up0 && !a.act && a.c0 <= kConvDenseMaxCin && a.cout % 128 == 0 &&
+                 gs >= 1 && gs <= 64 &&
                  (gs & (gs - 1)) == 0 && a.lh + a.lw >= 6 && conv_stat_slots(a.lh + a.lw) <= 32,
              -5, "conv: GroupNorm sums need a dense 3x3 conv with C_out % 128 == 0 and windows of at least 64 px");
   }

@@ -775,7 +775,7 @@ void Model::resblock(hipStream_t st, const ResBlockW& w, int k, const float* s0,
   gn_apply(st, s0, c0, up0, s1, c1, nb, lr, w.gn1_g, w.gn1_b, 2, nullptr, B.F);
   // conv1's output feeds GroupNorm 2 only: its statistics come from the
   // conv's epilogue where the shape allows (C_out % 128 == 0)
-  const bool fused = w.cout % 128 == 0 && w.cout % d.groups == 0 && 2 * lr >= 6;
+  const bool fused = w.cout % 128 == 0 && w.cout % d.groups == 0 && 2 * lr >= 6 && w.cin <= kConvDenseMaxCin;
   conv3_f32(st, B.F, w.cin, nb, lr, w.cout, w.w1, bias_eff_ + w.bias_off + (size_t)k * w.cout, nullptr, B.T,
             fused ? gn_part_ : nullptr);
   const float* res = s0;

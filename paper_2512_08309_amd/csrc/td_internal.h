@@ -135,6 +135,9 @@ struct ConvArgs {
 };
 void launch_conv(hipStream_t st, const ConvArgs& a);
 __host__ __device__ inline int conv_stat_slots(int lhw) { return lhw > 7 ? 1 << (lhw - 7) : 1; }
+// Input channels of the dense (single-source, pre-activated) specialisation,
+// which GroupNorm sums require.
+constexpr int kConvDenseMaxCin = 8192;
 
 // Reduced-precision conv: BF16 operands, FP32 accumulation and output.
 struct ConvLpArgs {
