@@ -18,6 +18,7 @@ workloads the method is measured on:
             word 2); ``c1h`` is ``c1`` conditioned on it (its final latent,
             nearest-upsampled 8x, concatenated to the input).
 * ``lgc``, ``lgh``: the linear-Gaussian pair with the same wiring.
+* ``lgw``: ``lg`` with a wider decode blur (sigma 9, radius 30).
 * ``s2``  : the half-width student of ``c2`` (64/128/128/256), two-step
             consistency sampling at sigma 80 and 0.35; ``lgs`` is an analytic
             two-step model (prior std 0.7) whose teacher stand-in is ``lg``;
@@ -118,6 +119,10 @@ CONFIGS["lgs"] = {
     "window": {"size": 32, "stride": 16, "offset": 0, "eps": 0.01},
 }
 # truncated T (blend only after the listed schedule indices)
+# ``lg`` with a wider decode blur (sigma 9, radius 30): the decode and
+# encode take their multi-launch blur path (radius > 24)
+CONFIGS["lgw"] = copy.deepcopy(CONFIGS["lg"])
+CONFIGS["lgw"]["decode"] = dict(DECODE, blur_sigma=9.0, blur_radius=30)
 for _name, _base, _blend in [("c1t2", "c1", [0, 4, 8]), ("lgt2", "lg", [0, 3, 8]), ("c2t2", "c2", [0, 10, 20]),
                              ("c2t5", "c2", [0, 4, 8, 12, 16, 20]), ("c2t1", "c2", [0, 20])]:
     CONFIGS[_name] = copy.deepcopy(CONFIGS[_base])
@@ -198,7 +203,7 @@ def init_tensors(specs, seed):
 
 def header_for(config):
     cfg = copy.deepcopy(CONFIGS[config])
-    cfg["decode"] = dict(DECODE)
+    cfg["decode"] = dict(cfg.get("decode", DECODE))
     cfg["format"] = "tdw"
     cfg["version"] = 1
     cfg["name"] = config

@@ -123,3 +123,46 @@ def test_encode_rejects_bad_regions(ctx):
             ctx.lap_encode(None, X0, Y0, W, H)
     with pytest.raises(td.TDError):        # output too small for (384 / 8 - 32) x (320 / 8 - 32) x 4
         ctx.lap_encode(h, 0, 0, 384, 320, out)
+
+
+DEC_WIDE = dict(DEC, blur_sigma=9.0, blur_radius=30)
+
+
+@pytest.fixture(scope="module")
+def ctx_wide(weights):
+    require_gpu()
+    from paper_2512_08309_amd import td
+    c = td.Context(0).load_weights(weights("lgw"))
+    yield c
+    c.close()
+
+
+def test_decode_wide_blur_matches_oracle(ctx_wide):
+    """A blur radius past the single-launch blur's limit (30 > 24): the
+    decode's multi-launch path against the oracle."""
+    import torch
+    region = (-803, 517, 203, 77)
+    lx0, ly0, lw, lh = laplace.required_latent(region, DEC_WIDE)
+    lat = terrain_latent(21, lx0, ly0, lw, lh, 4)
+    X0, Y0, W, H = region
+    out = torch.empty((H, W), dtype=torch.float32, device="cuda")
+    ctx_wide.lap_decode(torch.from_numpy(lat).cuda(), lx0, ly0, X0, Y0, W, H, out)
+    torch.cuda.synchronize()
+    ref = laplace.decode(lat.astype(np.float64), (lx0, ly0), region, DEC_WIDE)
+    assert rel_l2(out.cpu().numpy(), ref) <= 1e-5
+
+
+def test_encode_wide_blur_matches_oracle(ctx_wide):
+    import torch
+    region = (-800, 1600, 640, 576)
+    X0, Y0, W, H = region
+    lx0, ly0, lw, lh = laplace.required_latent(region, DEC_WIDE)
+    lat = terrain_latent(21, lx0, ly0, lw, lh, 4)
+    h32 = laplace.decode(lat.astype(np.float64), (lx0, ly0), region, DEC_WIDE).astype(np.float32)
+    ref, origin = laplace.encode(h32.astype(np.float64), region, DEC_WIDE, 4)
+    geom = ctx_wide.lap_encode(None, X0, Y0, W, H)
+    assert geom == (origin[0], origin[1], ref.shape[1], ref.shape[0])
+    out = torch.empty((geom[3], geom[2], 4), device="cuda")
+    ctx_wide.lap_encode(torch.from_numpy(h32).cuda(), X0, Y0, W, H, out)
+    torch.cuda.synchronize()
+    assert rel_l2(out.cpu().numpy(), ref) <= 1e-5
