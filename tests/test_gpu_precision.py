@@ -142,13 +142,14 @@ def test_bf16_seed_consistency_bit_exact(lp_ctx):
     assert np.array_equal(small, big[:, 21:51, 33:62])
 
 
-def test_bf16_c2_window_batch_invariant_bit_exact(lp_ctx, weights):
-    # C2 in BF16 runs every convolution on the halo-staged kernel (8x8
-    # windows share tiles four at a time) and takes most GroupNorm statistics
-    # from the producing convolution's per-tile sums: a window's estimate must
-    # not depend on the other windows of its batch.
+@pytest.mark.parametrize("prec", [0, 1])
+def test_c2_window_batch_invariant_bit_exact(lp_ctx, weights, prec):
+    # C2 takes most GroupNorm statistics from the producing convolution's
+    # per-tile sums, and in BF16 runs every convolution on the halo-staged
+    # kernel (8x8 windows share tiles four at a time): a window's estimate
+    # must not depend on the other windows of its batch.
     import torch
-    c = lp_ctx("c2", 1)
+    c = lp_ctx("c2", prec)
     m = Model(weights("c2"))
     H, C = m.H, m.C
     x = (m.sched[3] * np.random.default_rng(41).standard_normal((5, H, H, C))).astype(np.float32)
