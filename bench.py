@@ -507,7 +507,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
         print("bench.py runs on exactly one GPU: this build measures the per-GPU share of the sampling path "
-              "(sharding across GPUs is described in DESIGN.md but not built); got --gpus %d" % a.gpus,
+              "(sharding across GPUs is not built); got --gpus %d" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
     budget = Budget(a.budget_s)
