@@ -506,7 +506,7 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: this build measures the per-GPU share of the sampling path "
+        print("bench.py runs on exactly one GPU and measures the per-GPU share of the sampling path "
               "(sharding across GPUs is not built); got --gpus %d" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
