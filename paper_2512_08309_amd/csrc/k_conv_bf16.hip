@@ -528,7 +528,13 @@ __device__ __forceinline__ void unroll(F& f) {
 // SKIP (TAPS = 9): after the 3x3 chunks over act, 1x1 chunks over act2
 // (cin2 channels) run on the centre tap of the same patch layout; their
 // weights follow the 3x3 ones in K.
-template <int L, int P, int TAPS, bool SKIP>
+// ACT (TAPS = 9, one source, one window per tile): the input is staged as
+// SiLU(x * scale + shift) with the window's per-channel GroupNorm affine.
+// Measured against a separate apply pass plus the plain kernel (outputs
+// bit-identical): faster for windows of side 32 and 64 (-8%, -11%), slower
+// at 16 (+13%); with SKIP the kernel spills registers (3x slower), so the
+// launcher takes it for sides 32 and 64 without SKIP only.
+template <int L, int P, int TAPS, bool SKIP, bool ACT>
 __global__ __launch_bounds__(256, 2) void conv_bf16_halo_kernel(ConvLpArgs a, int n_tiles_n) {
   using G = HaloGeom<L, TAPS>;
   constexpr int STEPS = 2 * TAPS;                  // 16-value K steps per 32-channel chunk
@@ -542,6 +548,9 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_halo_kernel(ConvLpArgs a, in
   constexpr int TILE_BYTES = 256 * TROW, RED_BYTES = 2 * 2 * 32 * 2 * 8;
   constexpr int LDS_SLOTS = (2 * SLOTS > (TILE_BYTES + RED_BYTES) / 16) ? 2 * SLOTS : (TILE_BYTES + RED_BYTES) / 16;
   __shared__ __attribute__((aligned(16))) u4v lds[LDS_SLOTS];
+  static_assert(!ACT || (TAPS == 9 && !SKIP && (1 << (2 * L)) >= 256),
+                "the staged activation: 3x3, one source, one window per tile");
+  __shared__ __attribute__((aligned(16))) float2 actss[ACT ? kActMaxCin : 1];   // (scale, shift) per channel
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
@@ -591,9 +600,33 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_halo_kernel(ConvLpArgs a, in
     for (int j = 0; j < G::NPL; ++j)
       hreg[j] = *(hpack[j] != ~0u ? src + ((size_t)(hpack[j] >> 3) * q8 + (hpack[j] & 7) + c8) : gzero);
   };
-  auto store_halo = [&](int buf) {
+  // the patch of chunk g into buffer buf (with ACT, first-source chunks are
+  // activated: in-image values only, the zero slots stay zero)
+  auto store_halo = [&](int buf, int g) {
 #pragma unroll
-    for (int j = 0; j < G::NPL; ++j) lds[buf * SLOTS + 64 * (wave + 4 * j) + lane] = hreg[j];
+    for (int j = 0; j < G::NPL; ++j) {
+      if constexpr (ACT) {
+        if (g < nch_a && hpack[j] != ~0u) {
+          const float4* ss = reinterpret_cast<const float4*>(&actss[32 * g + 8 * (hpack[j] & 7)]);
+          const uint32_t w[4] = {hreg[j][0], hreg[j][1], hreg[j][2], hreg[j][3]};
+          uint32_t o[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const float4 p = ss[k];                      // (scale, shift) of channels 2k, 2k + 1
+            float v0 = __uint_as_float(w[k] << 16), v1 = __uint_as_float(w[k] & 0xffff0000u);
+            v0 = v0 * p.x + p.y;
+            v1 = v1 * p.z + p.w;
+            v0 = v0 * __builtin_amdgcn_rcpf(1.0f + __expf(-v0));
+            v1 = v1 * __builtin_amdgcn_rcpf(1.0f + __expf(-v1));
+            typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+            const bf2 pk = {(__bf16)v0, (__bf16)v1};
+            o[k] = __builtin_bit_cast(uint32_t, pk);
+          }
+          hreg[j] = u4v{o[0], o[1], o[2], o[3]};
+        }
+      }
+      lds[buf * SLOTS + 64 * (wave + 4 * j) + lane] = hreg[j];
+    }
   };
 
   // ---- A operands: tile i of this wave, lane pixel (lane & 31); the base
@@ -636,7 +669,12 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_halo_kernel(ConvLpArgs a, in
       for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
 
   load_halo(0);
-  store_halo(0);
+  if constexpr (ACT) {
+    for (int c = tid; c < cin; c += 256)
+      actss[c] = make_float2(a.act_scale[(size_t)b0 * cin + c], a.act_shift[(size_t)b0 * cin + c]);
+    __syncthreads();
+  }
+  store_halo(0, 0);
 #pragma unroll
   for (int s = 0; s < P; ++s) issue_b(s, s);
   __syncthreads();
@@ -686,7 +724,7 @@ __global__ __launch_bounds__(256, 2) void conv_bf16_halo_kernel(ConvLpArgs a, in
     unroll<NSTEP>(step);
     // the next chunk's patch goes to the other buffer, which every wave
     // finished reading before the previous barrier
-    store_halo(buf ^ 1);
+    store_halo(buf ^ 1, g + 1);
     lds_barrier();
   };
   for (int g = 0; g < nch_a; ++g)
@@ -904,12 +942,20 @@ template <int L>
 void launch_halo(hipStream_t st, const ConvLpArgs& a) {
   const int M = a.nb << (2 * L);
   const int mt = (M + 255) / 256, nt = a.cout / 128;
+  const dim3 grid(mt * nt);
+  if constexpr (L >= 5) {
+    if (a.act_scale) {
+      hipLaunchKernelGGL((conv_bf16_halo_kernel<L, 2, 9, false, true>), grid, dim3(256), 0, st, a, nt);
+      TD_LAUNCHED();
+      return;
+    }
+  }
   if (a.taps == 9 && a.act2)
-    hipLaunchKernelGGL((conv_bf16_halo_kernel<L, 2, 9, true>), dim3(mt * nt), dim3(256), 0, st, a, nt);
+    hipLaunchKernelGGL((conv_bf16_halo_kernel<L, 2, 9, true, false>), grid, dim3(256), 0, st, a, nt);
   else if (a.taps == 9)
-    hipLaunchKernelGGL((conv_bf16_halo_kernel<L, 2, 9, false>), dim3(mt * nt), dim3(256), 0, st, a, nt);
+    hipLaunchKernelGGL((conv_bf16_halo_kernel<L, 2, 9, false, false>), grid, dim3(256), 0, st, a, nt);
   else
-    hipLaunchKernelGGL((conv_bf16_halo_kernel<L, 2, 1, false>), dim3(mt * nt), dim3(256), 0, st, a, nt);
+    hipLaunchKernelGGL((conv_bf16_halo_kernel<L, 2, 1, false, false>), grid, dim3(256), 0, st, a, nt);
   TD_LAUNCHED();
 }
 
@@ -949,6 +995,8 @@ bool conv_lp_fused_ok(const ConvLpArgs& a) {
   const bool halo = halo_shape(a);
   if (!halo || (a.out16 && a.res)) return false;
   if (a.act2 && (a.taps != 9 || a.cin2 < 32 || a.cin2 % 32 != 0)) return false;
+  if (a.act_scale && (!a.act_shift || a.taps != 9 || a.lw < 5 || a.cin > kActMaxCin || a.out16 || a.act2))
+    return false;
   if (a.chstats && (a.out16 || a.stats)) return false;
   if (!a.stats) return true;
   const int gs = a.groups > 0 && a.cout % a.groups == 0 ? a.cout / a.groups : 0;
@@ -973,8 +1021,8 @@ void launch_conv_lp(hipStream_t st, const ConvLpArgs& a) {
   // Other 3x3 shapes with C_in % 32 == 0: the direct-to-LDS ring; the rest
   // (and FP8 weights): the register-staged kernel.
   const bool halo = halo_shape(a);
-  TD_CHECK(!(a.out16 || a.stats || a.chstats || a.act2) || conv_lp_fused_ok(a), -5,
-           "bf16 conv: a BF16 output, GroupNorm sums or a fused 1x1 need the halo-staged kernel");
+  TD_CHECK(!(a.out16 || a.stats || a.chstats || a.act2 || a.act_scale) || conv_lp_fused_ok(a), -5,
+           "bf16 conv: a BF16 output, GroupNorm sums, a fused 1x1 or a staged activation need the halo-staged kernel");
   if (halo && a.lw == 6) launch_halo<6>(st, a);
   else if (halo && a.lw == 5) launch_halo<5>(st, a);
   else if (halo && a.lw == 4) launch_halo<4>(st, a);

@@ -589,8 +589,11 @@ void Model::gn_apply(hipStream_t st, const float* s0, int c0, int up0, const flo
 
 void Model::conv_lp(hipStream_t st, const uint16_t* act, int cin, int nb, int lr, int cout, int taps,
                     const uint16_t* wt, const uint8_t* w8, const float* w8s, int kp, const float* bias,
-                    const float* res, float* out, const uint16_t* wfrag, bool track) {
+                    const float* res, float* out, const uint16_t* wfrag, bool track, const float* act_scale,
+                    const float* act_shift) {
   ConvLpArgs a{};
+  a.act_scale = act_scale;
+  a.act_shift = act_shift;
   if (prec_ == 2) {
     a.wt = w8;
     a.w8 = 1;
@@ -656,6 +659,21 @@ bool Model::conv1_fused(hipStream_t st, const ResBlockW& w, const uint16_t* act,
   g.shift = gn_shift_;
   launch_gn_finalize(st, g, conv_lp_stat_slots(2 * lr));
   return true;
+}
+
+bool Model::conv2_act_ok(const ResBlockW& w, int nb, int lr) const {
+  if (prec_ != 1 || !w.w2_fr || w.has_skip) return false;
+  ConvLpArgs a{};   // the shape of the launch (conv_lp_fused_ok reads no data pointer but these)
+  a.cin = w.cout;
+  a.nb = nb;
+  a.lh = lr;
+  a.lw = lr;
+  a.cout = w.cout;
+  a.taps = 9;
+  a.wfrag = w.w2_fr;
+  a.act_scale = gn_scale_;
+  a.act_shift = gn_shift_;
+  return conv_lp_fused_ok(a);
 }
 
 bool Model::conv2_skip_fused(hipStream_t st, const ResBlockW& w, const uint16_t* act, const uint16_t* act2, int nb,
@@ -756,6 +774,14 @@ void Model::resblock(hipStream_t st, const ResBlockW& w, int k, const float* s0,
       if (!raw_in_apply) apply(st, s0, c0, up0, s1, c1, 0, nb, lr, B.A0);
     } else {
       TD_CHECK(c1 == 0 && !up0, -5, "identity skip needs a plain input");
+    }
+    // GroupNorm 2 + SiLU: staged by conv2 itself where the halo-staged kernel
+    // allows (an identity skip, windows of side 32 or 64), else a pass into B.A
+    const bool act_staged = fused && conv2_act_ok(w, nb, lr);
+    if (act_staged) {
+      conv_lp(st, T16, w.cout, nb, lr, w.cout, 9, w.w2_lp, w.w2_8, w.s2_8, w.kp2, w.b2, res, out, w.w2_fr, true,
+              gn_scale_, gn_shift_);
+      return;
     }
     if (fused) launch_apply_bf16(st, T16, w.cout, gn_scale_, gn_shift_, 2, nb, lr, lr, B.A);
     else gn_apply(st, B.T, w.cout, 0, nullptr, 0, nb, lr, w.gn2_g, w.gn2_b, 2, B.A, nullptr);

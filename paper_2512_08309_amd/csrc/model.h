@@ -175,7 +175,8 @@ class Model {
   // were.
   void conv_lp(hipStream_t st, const uint16_t* act, int cin, int nb, int lr, int cout, int taps,
                const uint16_t* wt, const uint8_t* w8, const float* w8s, int kp, const float* bias,
-               const float* res, float* out, const uint16_t* wfrag = nullptr, bool track = false);
+               const float* res, float* out, const uint16_t* wfrag = nullptr, bool track = false,
+               const float* act_scale = nullptr, const float* act_shift = nullptr);
   // conv1 of a BF16 residual block through the fused epilogue: BF16 output
   // into out16 and the GroupNorm sums of gn2 into gn_part_; false (nothing
   // launched) where the halo-staged kernel does not apply.
@@ -186,6 +187,9 @@ class Model {
   // per-channel sums; false (nothing launched) where that kernel does not apply
   bool conv2_skip_fused(hipStream_t st, const ResBlockW& w, const uint16_t* act, const uint16_t* act2, int nb, int lr,
                         float* out);
+  // conv2 of a BF16 residual block with an identity skip can stage GroupNorm 2
+  // + SiLU of conv1's raw BF16 output itself (gn_scale_ / gn_shift_)
+  bool conv2_act_ok(const ResBlockW& w, int nb, int lr) const;
   void apply(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int act, int nb,
              int lr, uint16_t* out, float* out32 = nullptr, uint16_t* raw = nullptr);
   void gn_apply(hipStream_t st, const float* s0, int c0, int up0, const float* s1, int c1, int nb, int lr,

@@ -176,7 +176,15 @@ struct ConvLpArgs {
   // cin2): a residual block's conv2 plus its skip projection in one pass.
   const uint16_t* act2;
   int cin2;
+  // set (3x3 without act2, halo-staged kernel, square windows of side 32 or
+  // 64, C_in <= kActMaxCin): act holds the raw tensor and the kernel stages SiLU(x *
+  // act_scale + act_shift) of it (per-window GroupNorm affine [nb][cin]),
+  // bit for bit as launch_apply_bf16 would have written it; out-of-image
+  // taps stay zero.
+  const float* act_scale;
+  const float* act_shift;
 };
+constexpr int kActMaxCin = 512;
 void launch_conv_lp(hipStream_t st, const ConvLpArgs& a);
 bool conv_lp_fused_ok(const ConvLpArgs& a);
 __host__ __device__ inline int conv_lp_stat_slots(int lhw) { return lhw > 8 ? 1 << (lhw - 8) : 1; }
